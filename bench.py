@@ -1,0 +1,169 @@
+"""Benchmark of the implicit-MPM hot path on one MI355X.
+
+Workload: the plane-strain Drucker-Prager footing configuration (256 x 128
+cells of 1/256 m, 131072 particles on 2x2 Gauss points, E = 10 MPa,
+nu = 0.3, friction 30 deg, cohesion 0, dilation 0), its geostatic load step
+(gravity on the soil layer).  A step is one load step: binning and pattern,
+Newton iterations (residual, Jacobian, block-Jacobi BiCGStab) to 1e-10, and
+the particle update; the input state is kept, so every step repeats it.
+
+Prints one JSON line: the metric is the residual + Jacobian assembly rate
+(Mparticles/s); it also carries ms per Newton iteration, the roofline of the
+dominant kernel (BSR SpMV inside the Krylov solve, timed with HIP events on
+the library's stream) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def spmv_bytes(n_row, nnzb, bs):
+    """Algorithmic HBM bytes of one BSR SpMV: values + column indices + row
+    pointers + one read of x and one write of y."""
+    return nnzb * (bs * bs * 8 + 4) + 4 * (n_row + 1) + 2 * n_row * bs * 8
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--krylov-rtol", type=float, default=1e-12)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU layout is a design "
+                                   "(domain slabs with halo exchange), not an implementation"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2507_09435_amd import mpm as M
+    from paper_2507_09435_amd import workloads as W
+
+    w = W.make_c2(n_steps=1)
+    P = w.prob
+    npart = w.particles.np
+    react = np.zeros((P.n_nodes, P.ndof), dtype=np.uint8)
+    react[w.footing_nodes(), 1] = 1
+    stream = torch.cuda.current_stream()
+    ctx = M.mpm_create(0, stream.cuda_stream)
+    dp = M.make_problem([(P, w.particles)], [w.bc(0)], react_masks=[react])
+    dim = P.dim
+    x_out = torch.empty_like(dp.tensors["x"])
+    F_out = torch.empty_like(dp.tensors["F"])
+    be_out = torch.empty_like(dp.tensors["be"])
+
+    def load_step(step):
+        # one pass of the whole path: binning + pattern, Newton (residual,
+        # Jacobian, block-Jacobi BiCGStab), end-of-step particle update; the
+        # input state is left untouched so every step repeats the same work
+        n_row, nnzb, nd = M.mpm_prepare(ctx, dp)
+        du = torch.zeros(n_row * nd, dtype=torch.float64, device="cuda")
+        rep = M.mpm_newton_step(ctx, dp, du, tol=w.tol, max_iter=25, commit=False, krylov_rtol=args.krylov_rtol,
+                                time_spmv=4)
+        M.mpm_update(ctx, dp, du, x_out, F_out, be_out)
+        print(f"[bench] step {step}: newton {rep['iters']} krylov {rep['krylov_iters']} "
+              f"{rep['ms_total']:.1f} ms", file=sys.stderr, flush=True)
+        return rep, (n_row, nnzb, nd), du
+
+    for step in range(args.warmup):
+        load_step(step)
+    torch.cuda.synchronize()
+
+    reps = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        rep, shape, du = load_step(args.warmup + k)
+        reps.append(rep)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    n_res = sum(r["iters"] + 1 for r in reps)
+    n_jac = sum(r["iters"] for r in reps)
+    ms_res = sum(r["ms_residual"] for r in reps)
+    ms_jac = sum(r["ms_jacobian"] for r in reps)
+    ms_kry = sum(r["ms_krylov"] for r in reps)
+    t_asm_ms = ms_res / n_res + ms_jac / max(n_jac, 1)
+    value = npart / (t_asm_ms * 1e-3) / 1e6
+    newton_ms = sum(r["ms_total"] for r in reps) / max(n_jac, 1)
+
+    # dominant kernel: the BSR SpMV of the Krylov loop; every 4th Krylov
+    # iteration of the timed steps brackets its SpMV launches with HIP events
+    # on the library's stream (the stream the kernel runs on)
+    n_row, nnzb, nd = shape
+    spmv_ms = sum(r["spmv_ms"] for r in reps)
+    spmv_n = sum(r["spmv_launches"] for r in reps)
+    spmv_us = spmv_ms * 1e3 / max(spmv_n, 1)
+    nbytes = spmv_bytes(n_row, nnzb, nd)
+    achieved = nbytes / (spmv_us * 1e-6) / 1e9
+
+    out = {
+        "metric": "Jacobian+residual assembly Mparticles/s",
+        "value": round(value, 3),
+        "unit": "Mparticles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2D plane-strain Drucker-Prager soil layer of the footing problem, 256x128 cells "
+                               "(h=1/256 m), 131072 particles, E=1e7 Pa, nu=0.3, friction 30 deg, c=0, "
+                               "geostatic load step",
+                   "particles": npart, "rows": n_row, "bsr_blocks": nnzb, "block": nd,
+                   "newton_tol": w.tol, "krylov": "block-Jacobi BiCGStab", "krylov_rtol": args.krylov_rtol},
+        "newton_step_ms": round(newton_ms, 3),
+        "newton_iters_per_step": [r["iters"] for r in reps],
+        "krylov_iters_per_step": [r["krylov_iters"] for r in reps],
+        "ms_residual_per_eval": round(ms_res / n_res, 4),
+        "ms_jacobian_per_eval": round(ms_jac / max(n_jac, 1), 4),
+        "ms_krylov_per_newton_iter": round(ms_kry / max(n_jac, 1), 3),
+        "roofline": {"kernel": "k_spmv<2,32> (BSR SpMV in BiCGStab)", "bound": "hbm",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "avg_launch_us": round(spmv_us, 3), "timed_launches": spmv_n,
+                     "algorithmic_bytes_per_launch": nbytes},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    M.mpm_destroy(ctx)
+    print(json.dumps(out))
+
+
+def cpu_baseline(w):
+    """The oracle as it stands: residual + dual-number Jacobian of the same
+    workload at its geostatic state, on the host cores."""
+    from oracle import oracle as O
+    P, st = w.prob, w.particles
+    pat = O.pattern(P, st)
+    rng = np.random.default_rng(0)
+    dof = np.zeros((P.n_nodes, P.ndof))
+    dof[pat.active] = rng.normal(size=(pat.n_row, P.ndof)) * 1e-4 * P.h
+    t0 = time.perf_counter()
+    O.forces(P, st, dof)
+    t1 = time.perf_counter()
+    O.jacobian_bsr(P, st, dof, pat)
+    t2 = time.perf_counter()
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(st.np / (t2 - t0) / 1e6, 4), "unit": "Mparticles/s", "cores": threads, "kind": "oracle",
+            "sample": f"one residual (serial) + one Jacobian (OpenMP) of the full {st.np}-particle footing; "
+                      f"{t1 - t0:.2f} s + {t2 - t1:.2f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -90,6 +90,11 @@ template <int N> inline Dual<N> cos(const Dual<N>& a) { return chain(a, std::cos
 template <int N> inline Dual<N> tan(const Dual<N>& a) { double c = std::cos(a.v); return chain(a, std::tan(a.v), 1.0 / (c * c)); }
 using std::sqrt; using std::log; using std::exp; using std::sin; using std::cos; using std::tan;
 
+// value of a, derivatives of b scaled by f (identity on plain doubles)
+inline double with_derivative(double a, double, double) { return a; }
+template <int N> inline Dual<N> with_derivative(const Dual<N>& a, const Dual<N>& b, double f) {
+  Dual<N> r; r.v = a.v; for (int k = 0; k < N; ++k) r.d[k] = f * b.d[k]; return r; }
+
 // ---------------------------------------------------------------- 3x3 -------
 template <class T>
 struct M3 {
@@ -198,6 +203,7 @@ struct Cfg {
   double E, nu, phi, c, psi;  // defaults when no per-particle array is given
   double rho0, g[3];
   double perm, mu_f, biot, rho_f, dt;
+  double apex_reg;   // tangent of an apex return = apex_reg * trial elastic tangent
 };
 
 struct Particles {
@@ -395,6 +401,14 @@ int hencky_dp(const Cfg& c, const T& E, const T& phi, const M3<T>& eps_tr, M3<T>
   for (int i = 0; i < 3; ++i) tau.a[i][i] += p_new;
   eps_e = scale(s_new, 1.0 / (2.0 * m.G));
   for (int i = 0; i < 3; ++i) eps_e.a[i][i] += p_new / (3.0 * m.K);
+  if (regime == 2) {
+    // The exact apex tangent of a cohesionless cone is zero, which leaves
+    // nodes held only by apex particles without stiffness.  Derivatives (not
+    // values) of an apex return are replaced by apex_reg times those of the
+    // trial elastic stress; the residual is unchanged.
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) tau.a[i][j] = with_derivative(tau.a[i][j], tau_tr.a[i][j], c.apex_reg);
+  }
   return regime;
 }
 

@@ -51,7 +51,7 @@ class _Cfg(C.Structure):
                 ("E", C.c_double), ("nu", C.c_double), ("phi", C.c_double), ("c", C.c_double),
                 ("psi", C.c_double), ("rho0", C.c_double), ("g", C.c_double * 3),
                 ("perm", C.c_double), ("mu_f", C.c_double), ("biot", C.c_double),
-                ("rho_f", C.c_double), ("dt", C.c_double)]
+                ("rho_f", C.c_double), ("dt", C.c_double), ("apex_reg", C.c_double)]
 
 
 class _Particles(C.Structure):
@@ -105,6 +105,7 @@ def cfg(prob) -> _Cfg:
     c.E, c.nu, c.phi, c.c, c.psi = (float(v) for v in (prob.E, prob.nu, prob.phi, prob.c, prob.psi))
     c.rho0, c.perm, c.mu_f, c.biot, c.rho_f, c.dt = (float(v) for v in (
         prob.rho0, prob.perm, prob.mu_f, prob.biot, prob.rho_f, prob.dt))
+    c.apex_reg = float(getattr(prob, "apex_reg", 0.0))
     return c
 
 
@@ -321,7 +322,7 @@ def _field_norms(prob, r):
 
 
 def newton(prob, st, mask_full, value_full, tol=1e-10, maxit=25, dof0_full=None, pat=None,
-           reaction_nodes=None, reaction_dof=None, solver="direct", stall_factor=1e3):
+           reaction_nodes=None, reaction_dof=None, solver="direct", stall_factor=1e3, line_search=0):
     """Newton iteration for one load step (Sec. 2.2).
 
     Unknowns start at ``dof0_full`` (zero if None) with the constrained ones
@@ -371,7 +372,24 @@ def newton(prob, st, mask_full, value_full, tol=1e-10, maxit=25, dof0_full=None,
             delta = spla.spsolve(A.tocsc(), rhs)
         else:
             delta = _bicgstab_bj(A, rhs, nd)
-        dof[pat.active] += delta.reshape(-1, nd)
+        step = delta.reshape(-1, nd)
+        alpha = 1.0
+        if line_search:
+            # backtracking on the residual norm: halve the step until
+            # ||r(u + a d)|| < (1 - 1e-4 a) ||r(u)||
+            base = dof.copy()
+            for _ in range(line_search):
+                dof[pat.active] = base[pat.active] + alpha * step
+                fi2, fe2 = forces(prob, st, dof)
+                r2 = (fi2 - fe2)[pat.active]
+                r2[cm] = 0.0
+                if np.linalg.norm(r2) < (1.0 - 1e-4 * alpha) * nrm[0]:
+                    break
+                alpha *= 0.5
+            else:
+                dof[pat.active] = base[pat.active] + step
+        else:
+            dof[pat.active] += step
     return dof, NewtonReport(it, norms, converged, reaction), pat
 
 

@@ -1,0 +1,543 @@
+// Residual, localized Jacobian and particle update kernels (one thread per
+// particle, particles sorted by stencil origin).
+//
+// Residual (Sec. 2.2): f_int,i = sum_p V0 P_p grad w_ip with P = tau dF^-T,
+// r = f_int - f_ext.  Jacobian (Sec. 3.2): every particle owns a dense local
+// block over its 3^d stencil nodes; here the block is the contraction
+//   K_ab = V0 (out-weights of a) . T . (in-weights of b)
+// of the particle's tangent table T (derivatives of its stress outputs with
+// respect to dF and, for u-p, to p and grad p), obtained by forward-mode
+// passes of the same stress code, then scattered into the BSR pattern.
+#include "mpm_internal.hpp"
+
+namespace mpm {
+
+struct AsmArgs {
+  int64_t np;
+  int nd, up, dp, match;
+  const double *xs, *vs, *Fs, *bes, *Es, *phis;   // sorted SoA (Es/phis may be null)
+  const int32_t* psim;
+  const SimDev* sims;
+  const int32_t* node_map;
+  double E, nu, phi, c, psi, apex_reg;
+  double biot, mob, dt, rho_f, g[3];
+};
+
+struct UpPar { double biot, mob, dt, rho_f, g[3]; };
+
+__device__ __forceinline__ UpPar up_par(const AsmArgs& A) {
+  return UpPar{A.biot, A.mob, A.dt, A.rho_f, {A.g[0], A.g[1], A.g[2]}};
+}
+
+// -------------------------------------------------------- 2-D particle -----
+template <class S>
+struct Out2 { S P[2][2]; S s1; S vv[2]; };
+
+template <class S>
+__device__ __forceinline__ int mech2(const Mat<S>& m, const S F[2][2], const Sym2<S>& be, S Jn, int up, const UpPar& u,
+                                     S pp, const S gp[2], Out2<S>& o, Sym2<S>* ee_out) {
+  S m00 = F[0][0] * be.xx + F[0][1] * be.xy, m01 = F[0][0] * be.xy + F[0][1] * be.yy;
+  S m10 = F[1][0] * be.xx + F[1][1] * be.xy, m11 = F[1][0] * be.xy + F[1][1] * be.yy;
+  Sym2<S> bt;
+  bt.xx = m00 * F[0][0] + m01 * F[0][1];
+  bt.yy = m10 * F[1][0] + m11 * F[1][1];
+  bt.xy = m00 * F[1][0] + m01 * F[1][1];
+  bt.zz = be.zz;
+  Sym2<S> eps = hencky2(bt);
+  Sym2<S> tau, ee;
+  int reg = stress2(m, eps, tau, ee);
+  S det = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+  S idet = 1.0 / det;
+  S it00 = F[1][1] * idet, it01 = -1.0 * F[1][0] * idet, it10 = -1.0 * F[0][1] * idet, it11 = F[0][0] * idet;
+  S J = det * Jn;
+  if (up) {
+    S bp = u.biot * J * pp;
+    tau.xx -= bp; tau.yy -= bp; tau.zz -= bp;
+  }
+  o.P[0][0] = tau.xx * it00 + tau.xy * it10;
+  o.P[0][1] = tau.xx * it01 + tau.xy * it11;
+  o.P[1][0] = tau.xy * it00 + tau.yy * it10;
+  o.P[1][1] = tau.xy * it01 + tau.yy * it11;
+  if (up) {
+    o.s1 = u.biot * s_log(det) * J;
+    S q0 = u.mob * (it00 * gp[0] + it01 * gp[1] - u.rho_f * u.g[0]);
+    S q1 = u.mob * (it10 * gp[0] + it11 * gp[1] - u.rho_f * u.g[1]);
+    o.vv[0] = u.dt * (it00 * q0 + it10 * q1) * J;
+    o.vv[1] = u.dt * (it01 * q0 + it11 * q1) * J;
+  }
+  if (ee_out) *ee_out = ee;
+  return reg;
+}
+
+// -------------------------------------------------------- 3-D particle -----
+template <class S>
+struct Out3 { S P[3][3]; };
+
+template <class S>
+__device__ __forceinline__ int mech3(const Mat<S>& m, const S F[3][3], const Sym3<S>& be, Out3<S>& o, Sym3<S>* ee_out,
+                                     int* range_err) {
+  S M[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) M[i][j] = F[i][0] * sget(be, 0, j) + F[i][1] * sget(be, 1, j) + F[i][2] * sget(be, 2, j);
+  Sym3<S> bt;
+  const int I[6] = {0, 1, 2, 1, 0, 0}, Jx[6] = {0, 1, 2, 2, 2, 1};
+#pragma unroll
+  for (int t = 0; t < 6; ++t)
+    bt.a[t] = M[I[t]][0] * F[Jx[t]][0] + M[I[t]][1] * F[Jx[t]][1] + M[I[t]][2] * F[Jx[t]][2];
+  Sym3<S> eps = hencky3(bt, range_err);
+  Sym3<S> tau, ee;
+  int reg = stress3(m, eps, tau, ee);
+  // dF^-T = cofactor(dF) / det
+  S cof[3][3];
+  cof[0][0] = F[1][1] * F[2][2] - F[1][2] * F[2][1];
+  cof[0][1] = F[1][2] * F[2][0] - F[1][0] * F[2][2];
+  cof[0][2] = F[1][0] * F[2][1] - F[1][1] * F[2][0];
+  cof[1][0] = F[0][2] * F[2][1] - F[0][1] * F[2][2];
+  cof[1][1] = F[0][0] * F[2][2] - F[0][2] * F[2][0];
+  cof[1][2] = F[0][1] * F[2][0] - F[0][0] * F[2][1];
+  cof[2][0] = F[0][1] * F[1][2] - F[0][2] * F[1][1];
+  cof[2][1] = F[0][2] * F[1][0] - F[0][0] * F[1][2];
+  cof[2][2] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+  S det = F[0][0] * cof[0][0] + F[0][1] * cof[0][1] + F[0][2] * cof[0][2];
+  S idet = 1.0 / det;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      o.P[i][j] = (sget(tau, i, 0) * cof[0][j] + sget(tau, i, 1) * cof[1][j] + sget(tau, i, 2) * cof[2][j]) * idet;
+  if (ee_out) *ee_out = ee;
+  return reg;
+}
+
+// ------------------------------------------------------ per-particle load ---
+template <int DIM>
+struct PLoad {
+  Stencil<DIM> st;
+  int32_t row[Stencil<DIM>::NN];
+  double dF[DIM][DIM];
+  double pp, gp[DIM];
+  double v0, Jn;
+  double E, phi;
+};
+
+template <int DIM>
+__device__ __forceinline__ void load_particle(const AsmArgs& A, int64_t i, const double* __restrict__ du, PLoad<DIM>& L) {
+  const SimDev& S = A.sims[A.psim[i]];
+  make_stencil<DIM>(S, A.xs, A.np, i, L.st);
+#pragma unroll
+  for (int r = 0; r < DIM; ++r)
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) L.dF[r][c] = (r == c) ? 1.0 : 0.0;
+  L.pp = 0.0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) L.gp[k] = 0.0;
+  const int nd = A.nd;
+  for (int a = 0; a < Stencil<DIM>::NN; ++a) {
+    int32_t r = A.node_map[L.st.node(S, a)];
+    L.row[a] = r;
+    double g[DIM];
+    L.st.grad(a, g);
+    const double* u = du + (int64_t)r * nd;
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) {
+      double uq = u[q];
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) L.dF[q][k] += uq * g[k];
+    }
+    if (DIM == 2 && A.up) {
+      double pa = u[2];
+      L.pp += L.st.weight(a) * pa;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) L.gp[k] += pa * g[k];
+    }
+  }
+  L.v0 = A.vs[i];
+  if (DIM == 2 && A.up) {
+    L.Jn = A.Fs[0 * A.np + i] * A.Fs[3 * A.np + i] - A.Fs[1 * A.np + i] * A.Fs[2 * A.np + i];
+  } else {
+    L.Jn = 1.0;
+  }
+  L.E = A.Es ? A.Es[i] : A.E;
+  L.phi = A.phis ? A.phis[i] : A.phi;
+}
+
+__device__ __forceinline__ Sym2<double> load_be2(const AsmArgs& A, int64_t i) {
+  return Sym2<double>{A.bes[0 * A.np + i], A.bes[1 * A.np + i], A.bes[2 * A.np + i], A.bes[3 * A.np + i]};
+}
+__device__ __forceinline__ Sym3<double> load_be3(const AsmArgs& A, int64_t i) {
+  Sym3<double> b;
+#pragma unroll
+  for (int t = 0; t < 6; ++t) b.a[t] = A.bes[t * A.np + i];
+  return b;
+}
+
+// ----------------------------------------------------------- residual ------
+template <int DIM>
+__global__ void __launch_bounds__(256) k_fint(AsmArgs A, const double* __restrict__ du, double* __restrict__ fint,
+                                              int32_t* __restrict__ flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.np) return;
+  PLoad<DIM> L;
+  load_particle<DIM>(A, i, du, L);
+  Mat<double> m = make_mat<double>(L.E, A.nu, L.phi, A.c, A.psi, A.dp, A.match, A.apex_reg);
+  const int nd = A.nd;
+  if constexpr (DIM == 2) {
+    Out2<double> o;
+    double F[2][2] = {{L.dF[0][0], L.dF[0][1]}, {L.dF[1][0], L.dF[1][1]}};
+    mech2<double>(m, F, load_be2(A, i), L.Jn, A.up, up_par(A), L.pp, L.gp, o, nullptr);
+    for (int a = 0; a < 9; ++a) {
+      double g[DIM];
+      L.st.grad(a, g);
+      double* f = fint + (int64_t)L.row[a] * nd;
+      atomicAdd(&f[0], L.v0 * (o.P[0][0] * g[0] + o.P[0][1] * g[1]));
+      atomicAdd(&f[1], L.v0 * (o.P[1][0] * g[0] + o.P[1][1] * g[1]));
+      if (A.up) atomicAdd(&f[2], L.v0 * (L.st.weight(a) * o.s1 + g[0] * o.vv[0] + g[1] * o.vv[1]));
+    }
+  } else {
+    Out3<double> o;
+    int rerr = 0;
+    mech3<double>(m, L.dF, load_be3(A, i), o, nullptr, &rerr);
+    if (rerr) atomicOr(flag, 4);
+    for (int a = 0; a < 27; ++a) {
+      double g[3];
+      L.st.grad(a, g);
+      double* f = fint + (int64_t)L.row[a] * nd;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) atomicAdd(&f[r], L.v0 * (o.P[r][0] * g[0] + o.P[r][1] * g[1] + o.P[r][2] * g[2]));
+    }
+  }
+}
+
+// r_raw = f_int - f_ext; r = r_raw with constrained unknowns zeroed.  Per-row-
+// block partials: [0] = ||r||^2, [1] = sum of r_raw over the reaction mask.
+__global__ void __launch_bounds__(64) k_res_final(const RowBlock* __restrict__ blocks, int nd,
+                                                  const double* __restrict__ fint, const double* __restrict__ fext,
+                                                  const uint8_t* __restrict__ cmask, const uint8_t* __restrict__ rmask,
+                                                  double* __restrict__ r, double* __restrict__ r_raw,
+                                                  double* __restrict__ part) {
+  RowBlock b = blocks[blockIdx.x];
+  int64_t row = b.row0 + threadIdx.x;
+  double sq = 0.0, re = 0.0;
+  if (row < b.row1) {
+    for (int c = 0; c < nd; ++c) {
+      int64_t k = row * nd + c;
+      double raw = fint[k] - fext[k];
+      if (r_raw) r_raw[k] = raw;
+      if (rmask[k]) re += raw;
+      double v = cmask[k] ? 0.0 : raw;
+      if (r) r[k] = v;
+      sq += v * v;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sq += __shfl_down(sq, off, 64);
+    re += __shfl_down(re, off, 64);
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x * NQ + 0] = sq;
+    part[blockIdx.x * NQ + 1] = re;
+  }
+}
+
+// Per sim: sum the row-block partials in block order (deterministic).
+__global__ void __launch_bounds__(64) k_sim_sum(int nsim, const int32_t* __restrict__ blk_first,
+                                                const double* __restrict__ part, int q, double* __restrict__ out,
+                                                int out_stride, int out_off) {
+  const int s = blockIdx.x;   // one wave per sim, fixed lane assignment and reduction order
+  double acc = 0.0;
+  for (int b = blk_first[s] + (int)threadIdx.x; b < blk_first[s + 1]; b += 64) acc += part[b * NQ + q];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (threadIdx.x == 0) out[s * out_stride + out_off] = acc;
+}
+
+// ----------------------------------------------------------- Jacobian ------
+// Tangent table of one 2-D particle: inputs dF (4), then for u-p p and
+// grad p (3); outputs P (4), then for u-p s1 and vv (3).
+template <int NIO>
+__device__ __forceinline__ void tangent2(const AsmArgs& A, const PLoad<2>& L, const Sym2<double>& be,
+                                         double T[NIO][NIO]) {
+  Mat<dnum> m = make_mat<dnum>(dnum(L.E), A.nu, dnum(L.phi), A.c, A.psi, A.dp, A.match, A.apex_reg);
+  UpPar u = up_par(A);
+  for (int q = 0; q < NIO; ++q) {
+    dnum F[2][2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) F[r][c] = dnum(L.dF[r][c], q == r * 2 + c ? 1.0 : 0.0);
+    dnum pp(L.pp, q == 4 ? 1.0 : 0.0);
+    dnum gp[2] = {dnum(L.gp[0], q == 5 ? 1.0 : 0.0), dnum(L.gp[1], q == 6 ? 1.0 : 0.0)};
+    Sym2<dnum> bd{dnum(be.xx), dnum(be.yy), dnum(be.xy), dnum(be.zz)};
+    Out2<dnum> o;
+    mech2<dnum>(m, F, bd, dnum(L.Jn), NIO == 7, u, pp, gp, o, nullptr);
+    T[0][q] = o.P[0][0].d; T[1][q] = o.P[0][1].d; T[2][q] = o.P[1][0].d; T[3][q] = o.P[1][1].d;
+    if constexpr (NIO == 7) { T[4][q] = o.s1.d; T[5][q] = o.vv[0].d; T[6][q] = o.vv[1].d; }
+  }
+}
+
+template <int NIO>
+__global__ void __launch_bounds__(128) k_jac2(AsmArgs A, const double* __restrict__ du,
+                                              const int32_t* __restrict__ rowptr, const int8_t* __restrict__ slot,
+                                              double* __restrict__ val) {
+  constexpr int ND = NIO == 7 ? 3 : 2;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.np) return;
+  PLoad<2> L;
+  load_particle<2>(A, i, du, L);
+  double T[NIO][NIO];
+  tangent2<NIO>(A, L, load_be2(A, i), T);
+  const double v0 = L.v0;
+  for (int b = 0; b < 9; ++b) {
+    double gb[2];
+    L.st.grad(b, gb);
+    double wb = L.st.weight(b);
+    // Tb[out][c]: in-weights of node b applied to the table
+    double Tb[NIO][ND];
+#pragma unroll
+    for (int o = 0; o < NIO; ++o) {
+#pragma unroll
+      for (int m = 0; m < 2; ++m) Tb[o][m] = T[o][m * 2 + 0] * gb[0] + T[o][m * 2 + 1] * gb[1];
+      if constexpr (ND == 3) Tb[o][2] = T[o][4] * wb + T[o][5] * gb[0] + T[o][6] * gb[1];
+    }
+    for (int a = 0; a < 9; ++a) {
+      double ga[2];
+      L.st.grad(a, ga);
+      double wa = L.st.weight(a);
+      int32_t ra = L.row[a];
+      int s = slot[(int64_t)ra * 25 + nb_index<2>(a, b)];
+      double* blk = val + ((int64_t)rowptr[ra] + s) * (ND * ND);
+#pragma unroll
+      for (int c = 0; c < ND; ++c) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) atomicAdd(&blk[r * ND + c], v0 * (ga[0] * Tb[r * 2 + 0][c] + ga[1] * Tb[r * 2 + 1][c]));
+        if constexpr (ND == 3)
+          atomicAdd(&blk[2 * ND + c], v0 * (wa * Tb[4][c] + ga[0] * Tb[5][c] + ga[1] * Tb[6][c]));
+      }
+    }
+  }
+}
+
+// 3-D: tangent A[(i,j)][(m,l)] = dP_ij / d dF_ml by nine forward passes.
+__global__ void __launch_bounds__(128) k_jac3(AsmArgs A, const double* __restrict__ du,
+                                              const int32_t* __restrict__ rowptr, const int8_t* __restrict__ slot,
+                                              double* __restrict__ val, int32_t* __restrict__ flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.np) return;
+  PLoad<3> L;
+  load_particle<3>(A, i, du, L);
+  Mat<dnum> m = make_mat<dnum>(dnum(L.E), A.nu, dnum(L.phi), A.c, A.psi, A.dp, A.match, A.apex_reg);
+  Sym3<double> be = load_be3(A, i);
+  double T[9][9];
+  int rerr = 0;
+  for (int q = 0; q < 9; ++q) {
+    dnum F[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) F[r][c] = dnum(L.dF[r][c], q == r * 3 + c ? 1.0 : 0.0);
+    Sym3<dnum> bd;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) bd.a[t] = dnum(be.a[t]);
+    Out3<dnum> o;
+    mech3<dnum>(m, F, bd, o, nullptr, &rerr);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) T[r * 3 + c][q] = o.P[r][c].d;
+  }
+  if (rerr) atomicOr(flag, 4);
+  const double v0 = L.v0;
+  for (int b = 0; b < 27; ++b) {
+    double gb[3];
+    L.st.grad(b, gb);
+    double Tb[9][3];
+#pragma unroll
+    for (int o = 0; o < 9; ++o)
+#pragma unroll
+      for (int mm = 0; mm < 3; ++mm)
+        Tb[o][mm] = T[o][mm * 3 + 0] * gb[0] + T[o][mm * 3 + 1] * gb[1] + T[o][mm * 3 + 2] * gb[2];
+    for (int a = 0; a < 27; ++a) {
+      double ga[3];
+      L.st.grad(a, ga);
+      int32_t ra = L.row[a];
+      int s = slot[(int64_t)ra * 125 + nb_index<3>(a, b)];
+      double* blk = val + ((int64_t)rowptr[ra] + s) * 9;
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          atomicAdd(&blk[r * 3 + c], v0 * (ga[0] * Tb[r * 3 + 0][c] + ga[1] * Tb[r * 3 + 1][c] + ga[2] * Tb[r * 3 + 2][c]));
+    }
+  }
+}
+
+// Dirichlet rows/columns: zero them, 1 on the diagonal (structure unchanged).
+__global__ void k_jac_bc(int64_t n_row, int nd, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+                         const uint8_t* __restrict__ cmask, double* __restrict__ val) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_row) return;
+  for (int32_t k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+    int32_t c = colind[k];
+    double* blk = val + (int64_t)k * nd * nd;
+    for (int i = 0; i < nd; ++i)
+      for (int j = 0; j < nd; ++j)
+        if (cmask[r * nd + i] || cmask[(int64_t)c * nd + j]) blk[i * nd + j] = (r == c && i == j) ? 1.0 : 0.0;
+  }
+}
+
+// ------------------------------------------------------------- update ------
+template <int DIM>
+__global__ void k_update(AsmArgs A, const double* __restrict__ du, const int32_t* __restrict__ perm,
+                         double* __restrict__ x_out, double* __restrict__ F_out, double* __restrict__ be_out,
+                         int32_t* __restrict__ flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.np) return;
+  PLoad<DIM> L;
+  load_particle<DIM>(A, i, du, L);
+  Mat<double> m = make_mat<double>(L.E, A.nu, L.phi, A.c, A.psi, A.dp, A.match, A.apex_reg);
+  const int64_t np = A.np, p = perm[i];
+  const SimDev& S = A.sims[A.psim[i]];
+  (void)S;
+  // x^{n+1} = x^n + sum_a w_a du_a
+  double dx[DIM];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) dx[k] = 0.0;
+  for (int a = 0; a < Stencil<DIM>::NN; ++a) {
+    double w = L.st.weight(a);
+    const double* u = du + (int64_t)L.row[a] * A.nd;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) dx[k] += w * u[k];
+  }
+  double xn[DIM], Fn[DIM * DIM];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) xn[k] = A.xs[k * np + i] + dx[k];
+#pragma unroll
+  for (int r = 0; r < DIM; ++r)
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) s += L.dF[r][k] * A.Fs[(k * DIM + c) * np + i];
+      Fn[r * DIM + c] = s;
+    }
+  if constexpr (DIM == 2) {
+    Out2<double> o;
+    Sym2<double> ee;
+    double F[2][2] = {{L.dF[0][0], L.dF[0][1]}, {L.dF[1][0], L.dF[1][1]}};
+    double gp0[2] = {0.0, 0.0};
+    mech2<double>(m, F, load_be2(A, i), L.Jn, 0, up_par(A), 0.0, gp0, o, &ee);
+    Sym2<double> b = exp2eps2(ee);
+    if (be_out) {
+      be_out[0 * np + p] = b.xx; be_out[1 * np + p] = b.yy; be_out[2 * np + p] = b.xy; be_out[3 * np + p] = b.zz;
+    }
+  } else {
+    Out3<double> o;
+    Sym3<double> ee;
+    int rerr = 0;
+    mech3<double>(m, L.dF, load_be3(A, i), o, &ee, &rerr);
+    if (rerr) atomicOr(flag, 4);
+    Sym3<double> b = exp2eps3(ee);
+    if (be_out)
+#pragma unroll
+      for (int t = 0; t < 6; ++t) be_out[t * np + p] = b.a[t];
+  }
+  if (x_out)
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) x_out[k * np + p] = xn[k];
+  if (F_out)
+#pragma unroll
+    for (int k = 0; k < DIM * DIM; ++k) F_out[k * np + p] = Fn[k];
+}
+
+}  // namespace mpm
+
+using namespace mpm;
+
+// ---------------------------------------------------------------- host -----
+static AsmArgs make_args(mpm_ctx* c, const mpm_problem* pb) {
+  AsmArgs A;
+  A.np = c->np;
+  A.nd = c->nd;
+  A.up = c->up;
+  A.dp = c->dp;
+  A.match = pb->mat.dp_match;
+  A.xs = c->xs.p; A.vs = c->vol0s.p; A.Fs = c->Fs.p; A.bes = c->bes.p;
+  A.Es = pb->P.E ? c->Es.p : nullptr;
+  A.phis = pb->P.phi ? c->phis.p : nullptr;
+  A.psim = c->psim.p;
+  A.sims = c->sims.p;
+  A.node_map = c->node_map.p;
+  A.E = pb->mat.E; A.nu = pb->mat.nu; A.phi = pb->mat.phi; A.c = pb->mat.c; A.psi = pb->mat.psi;
+  A.apex_reg = pb->mat.apex_reg;
+  A.biot = pb->mat.biot;
+  A.mob = pb->mat.mu_f > 0 ? pb->mat.perm / pb->mat.mu_f : 0.0;
+  A.dt = pb->mat.dt; A.rho_f = pb->mat.rho_f;
+  for (int k = 0; k < 3; ++k) A.g[k] = pb->mat.g[k];
+  return A;
+}
+
+static unsigned nb256(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + 255) / 256); }
+
+// f_int into c->fint (zeroed first).
+int launch_fint(mpm_ctx* c, const mpm_problem* pb, const double* du) {
+  AsmArgs A = make_args(c, pb);
+  HIPC(c, hipMemsetAsync(c->fint.p, 0, c->n_row * c->nd * sizeof(double), c->stream));
+  if (c->np == 0) return MPM_OK;
+  if (c->dim == 2) k_fint<2><<<nb256(c->np), 256, 0, c->stream>>>(A, du, c->fint.p, c->flag.p);
+  else k_fint<3><<<nb256(c->np), 256, 0, c->stream>>>(A, du, c->fint.p, c->flag.p);
+  LAUNCH_CHECK(c, "k_fint");
+  return MPM_OK;
+}
+
+// Residual with per-sim ||r||^2 -> simsc[s*16+0], reaction -> simsc[s*16+1].
+int launch_residual(mpm_ctx* c, const mpm_problem* pb, const double* du, double* r, double* r_raw) {
+  int rc = launch_fint(c, pb, du);
+  if (rc) return rc;
+  unsigned nbk = (unsigned)c->blocks_h.size();
+  if (nbk) {
+    k_res_final<<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->nd, c->fint.p, c->fext.p, c->cmask.p, c->rmask.p, r, r_raw,
+                                            c->part.p);
+    LAUNCH_CHECK(c, "k_res_final");
+  } else {
+    HIPC(c, hipMemsetAsync(c->part.p, 0, NQ * sizeof(double), c->stream));
+  }
+  k_sim_sum<<<c->nsim, 64, 0, c->stream>>>(c->nsim, c->blk_first.p, c->part.p, 0, c->simsc.p, 16, 0);
+  k_sim_sum<<<c->nsim, 64, 0, c->stream>>>(c->nsim, c->blk_first.p, c->part.p, 1, c->simsc.p, 16, 1);
+  LAUNCH_CHECK(c, "k_sim_sum");
+  return MPM_OK;
+}
+
+int sim_sum_launch(mpm_ctx* c, const double* part, int q, int off) {
+  k_sim_sum<<<c->nsim, 64, 0, c->stream>>>(c->nsim, c->blk_first.p, part, q, c->simsc.p, 16, off);
+  LAUNCH_CHECK(c, "k_sim_sum");
+  return MPM_OK;
+}
+
+int launch_jacobian(mpm_ctx* c, const mpm_problem* pb, const double* du, double* val, bool apply_bc) {
+  AsmArgs A = make_args(c, pb);
+  const int nd = c->nd;
+  HIPC(c, hipMemsetAsync(val, 0, c->nnzb * nd * nd * sizeof(double), c->stream));
+  if (c->np > 0) {
+    unsigned g = (unsigned)std::max<int64_t>(1, (c->np + 127) / 128);
+    if (c->dim == 2 && !c->up) k_jac2<4><<<g, 128, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val);
+    else if (c->dim == 2) k_jac2<7><<<g, 128, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val);
+    else k_jac3<<<g, 128, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val, c->flag.p);
+    LAUNCH_CHECK(c, "k_jac");
+  }
+  if (apply_bc && c->n_row > 0) {
+    k_jac_bc<<<nb256(c->n_row), 256, 0, c->stream>>>(c->n_row, nd, c->rowptr.p, c->colind.p, c->cmask.p, val);
+    LAUNCH_CHECK(c, "k_jac_bc");
+  }
+  return MPM_OK;
+}
+
+int launch_update(mpm_ctx* c, const mpm_problem* pb, const double* du, double* x, double* F, double* be) {
+  AsmArgs A = make_args(c, pb);
+  if (c->np == 0) return MPM_OK;
+  if (c->dim == 2) k_update<2><<<nb256(c->np), 256, 0, c->stream>>>(A, du, c->perm.p, x, F, be, c->flag.p);
+  else k_update<3><<<nb256(c->np), 256, 0, c->stream>>>(A, du, c->perm.p, x, F, be, c->flag.p);
+  LAUNCH_CHECK(c, "k_update");
+  return MPM_OK;
+}

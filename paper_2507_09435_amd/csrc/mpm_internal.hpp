@@ -1,0 +1,96 @@
+// Internal helpers shared by the library's translation units.
+#pragma once
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "mpm_kernels.hpp"
+
+#define HIPC(c, x)                                                                              \
+  do {                                                                                          \
+    hipError_t e_ = (x);                                                                        \
+    if (e_ != hipSuccess) return (c)->fail(MPM_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCH_CHECK(c, name)                                                                   \
+  do {                                                                                          \
+    hipError_t e_ = hipGetLastError();                                                          \
+    if (e_ != hipSuccess) return (c)->fail(MPM_E_HIP, std::string(name) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+namespace mpm {
+
+// B-spline stencil of one particle: per-axis origin, weights and gradients.
+template <int DIM>
+struct Stencil {
+  static constexpr int NN = DIM == 2 ? 9 : 27;
+  int32_t o[3];
+  double w[3][3], dw[3][3];
+
+  __device__ __forceinline__ int64_t node(const SimDev& S, int a) const {
+    int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
+    int64_t id = (o[0] + ax + 1) + (int64_t)S.nna[0] * (o[1] + ay + 1);
+    if (DIM == 3) id += (int64_t)S.nna[0] * S.nna[1] * (o[2] + az + 1);
+    return S.node_base + id;
+  }
+  __device__ __forceinline__ double weight(int a) const {
+    double v = w[0][a % 3] * w[1][(a / 3) % 3];
+    if (DIM == 3) v *= w[2][a / 9];
+    return v;
+  }
+  __device__ __forceinline__ void grad(int a, double g[DIM]) const {
+    int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
+    if (DIM == 2) {
+      g[0] = dw[0][ax] * w[1][ay];
+      g[1] = w[0][ax] * dw[1][ay];
+    } else {
+      g[0] = dw[0][ax] * w[1][ay] * w[2][az];
+      g[1] = w[0][ax] * dw[1][ay] * w[2][az];
+      g[2] = w[0][ax] * w[1][ay] * dw[2][az];
+    }
+  }
+};
+
+// Origin o = floor((x - x0)/h - 1/2) and xi = (x - x0)/h - o per axis.
+template <int DIM>
+__device__ __forceinline__ void make_stencil(const SimDev& S, const double* __restrict__ xs, int64_t np, int64_t i,
+                                             Stencil<DIM>& st) {
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    double u = (xs[k * np + i] - S.x0[k]) / S.h;
+    double of = floor(u - 0.5);
+    st.o[k] = (int32_t)of;
+    bspline3<double>(u - of, S.inv_h, st.w[k], st.dw[k]);
+  }
+  if (DIM == 2) {
+    st.o[2] = 0;
+    st.w[2][0] = st.w[2][1] = st.w[2][2] = 1.0;
+    st.dw[2][0] = st.dw[2][1] = st.dw[2][2] = 0.0;
+  }
+}
+
+// Offset index of node b relative to node a inside the 5^d neighbourhood.
+template <int DIM>
+__device__ __forceinline__ int nb_index(int a, int b) {
+  int dx = b % 3 - a % 3 + 2, dy = (b / 3) % 3 - (a / 3) % 3 + 2;
+  if (DIM == 2) return dx + 5 * dy;
+  int dz = b / 9 - a / 9 + 2;
+  return dx + 5 * dy + 25 * dz;
+}
+
+}  // namespace mpm
+
+int validate_problem(mpm_ctx* c, const mpm_problem* pb);
+int check_prepared(mpm_ctx* c, const mpm_problem* pb);
+int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row, int64_t* nnzb, int32_t* nd);
+namespace mpm {
+int scan_excl(mpm_ctx* c, const int32_t* in, int64_t n, int32_t* out, int32_t* total);
+}
+int sim_sum_launch(mpm_ctx* c, const double* part, int q, int off);
+int launch_fint(mpm_ctx* c, const mpm_problem* pb, const double* du);
+int launch_residual(mpm_ctx* c, const mpm_problem* pb, const double* du, double* r, double* r_raw);
+int launch_jacobian(mpm_ctx* c, const mpm_problem* pb, const double* du, double* val, bool apply_bc);
+int launch_update(mpm_ctx* c, const mpm_problem* pb, const double* du, double* x, double* F, double* be);
+int launch_bj_inv(mpm_ctx* c, const double* val);
+int launch_spmv(mpm_ctx* c, const double* val, const double* x, double* y);
+int krylov_solve(mpm_ctx* c, const double* val, double rtol, int max_iter, std::vector<int>& iters_out);

@@ -1,0 +1,104 @@
+// Shared declarations of the HIP kernels and the context of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mpm.h"
+#include "mpm_device.hpp"
+
+namespace mpm {
+
+// Per-simulation grid constants (device copy).
+struct SimDev {
+  int32_t n[3];        // cells per axis
+  int32_t nna[3];      // nodes per axis (n + 3)
+  int32_t noa[3];      // stencil origins per axis (n + 1): o in [-1, n-1]
+  int32_t dim;
+  double h, inv_h;
+  double x0[3];
+  int64_t node_base;   // first full-grid node id of this sim
+  int64_t okey_base;   // first origin key of this sim
+  int64_t row_base;    // first compact row of this sim (after prepare)
+  int64_t p_begin, p_end;
+};
+
+// Row blocks of the Krylov / elementwise kernels: a block never spans two sims.
+struct RowBlock {
+  int32_t sim;
+  int32_t row0, row1;  // [row0, row1)
+};
+
+constexpr int ROWS_PER_BLOCK = 64;
+constexpr int NQ = 4;               // reduction slots per row block
+
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  hipError_t ensure(size_t m) {
+    if (m <= n && p) return hipSuccess;
+    if (p) { (void)hipFree(p); p = nullptr; n = 0; }
+    size_t bytes = (m ? m : 1) * sizeof(T);
+    hipError_t e = hipMalloc((void**)&p, bytes);
+    if (e == hipSuccess) n = m;
+    return e;
+  }
+  void release() { if (p) (void)hipFree(p); p = nullptr; n = 0; }
+};
+
+}  // namespace mpm
+
+struct mpm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // identity of the prepared problem
+  bool prepared = false;
+  int dim = 0, nd = 0, nsim = 0, up = 0, dp = 0;
+  int64_t np = 0, n_nodes = 0, n_okeys = 0, n_row = 0, nnzb = 0;
+  const double* user_x = nullptr;
+  std::vector<mpm::SimDev> sims_h;
+  std::vector<int64_t> sim_row_start;   // [nsim+1]
+  std::vector<mpm::RowBlock> blocks_h;
+  std::vector<int32_t> sim_blk_first;   // [nsim+1]
+
+  // sorting / pattern
+  mpm::DBuf<mpm::SimDev> sims;
+  mpm::DBuf<int64_t> sim_start;
+  mpm::DBuf<int32_t> okey, gcount, gstart, cursor, perm, psim;
+  mpm::DBuf<int32_t> scan_tmp;
+  mpm::DBuf<int32_t> node_flag, node_map;      // node_map: full node -> row or -1
+  mpm::DBuf<int64_t> active_nodes;
+  mpm::DBuf<int32_t> row_sim, rowcnt, rowptr, colind;
+  mpm::DBuf<int8_t> slot;                      // [n_row][5^d] position in row or -1
+  mpm::DBuf<mpm::RowBlock> blocks;
+  mpm::DBuf<int32_t> blk_first;                // [nsim+1]
+  mpm::DBuf<int32_t> flag;                     // device error flags
+
+  // sorted particle copies
+  mpm::DBuf<double> xs, vol0s, Fs, bes, Es, phis;
+
+  // grid vectors (compact, n_row * nd)
+  mpm::DBuf<uint8_t> cmask, rmask;
+  mpm::DBuf<double> cval, fext, fint, nvol, work;
+  mpm::DBuf<double> val, dinv;
+  // Krylov
+  mpm::DBuf<double> kx, kr, krh, kp, kv, ks, kt, kph, ksh, kb;
+  mpm::DBuf<double> part;                      // [nblocks][NQ]
+  mpm::DBuf<double> simsc;                     // per-sim scalars [nsim][16]
+  mpm::DBuf<int32_t> simflag;                  // per-sim krylov state [nsim][2]
+  mpm::DBuf<double> du_base, alpha;            // line search
+  bool krylov_soft = false;                    // last solve stopped at its floor above rtol
+  int time_spmv = 0;                           // sample period of SpMV timing (0: off)
+  std::vector<hipEvent_t> spmv_events;
+  double spmv_ms = 0.0;
+  int64_t spmv_n = 0;
+  double* host_pinned = nullptr;               // small pinned staging
+  size_t host_pinned_n = 0;
+
+  int fail(int code, const std::string& msg) { err = msg; return code; }
+};

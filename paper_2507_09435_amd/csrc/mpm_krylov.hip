@@ -1,0 +1,472 @@
+// Linear solve of each Newton iteration, -J du = r (Sec. 2.2), on the GPU:
+// block-Jacobi preconditioned BiCGStab over the BSR Jacobian.  The paper
+// solves on the CPU (algebraic multigrid or a direct solver, Remark 2).
+//
+// A batch of independent simulations shares one block-diagonal matrix; every
+// simulation keeps its own Krylov scalars.  Row blocks never span two
+// simulations, so each per-simulation dot product is the sum, in block
+// order, of the partials of that simulation's row blocks (deterministic).
+#include "mpm_internal.hpp"
+
+namespace mpm {
+
+// per-sim scalar slots
+enum { SC_RN2 = 0, SC_REACT = 1, SC_BN2 = 2, SC_RHO = 3 /* 3,4 */, SC_ALPHA = 5, SC_OMEGA = 6, SC_TOL2 = 7,
+       SC_RR = 8 };
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum of part[b*NQ + q] over the row blocks of a sim, by one 64-lane wave.
+__device__ __forceinline__ double sim_sum(const double* __restrict__ part, int q, int b0, int b1) {
+  double acc = 0.0;
+  for (int b = b0 + (int)threadIdx.x % 64; b < b1; b += 64) acc += part[b * NQ + q];
+  return wave_sum(acc);
+}
+
+template <int BS>
+__device__ __forceinline__ void apply_dinv(const double* __restrict__ dinv, int64_t row, const double* __restrict__ in,
+                                           double* __restrict__ out) {
+  const double* D = dinv + row * BS * BS;
+  double v[BS];
+#pragma unroll
+  for (int j = 0; j < BS; ++j) v[j] = in[row * BS + j];
+#pragma unroll
+  for (int i = 0; i < BS; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < BS; ++j) s += D[i * BS + j] * v[j];
+    out[row * BS + i] = s;
+  }
+}
+
+// Inverse of each diagonal block (identity where singular; flag bit 8).
+template <int BS>
+__global__ void k_bj_inv(int64_t n_row, const int32_t* __restrict__ rowptr, const int8_t* __restrict__ slot,
+                         int nnb, int center, const double* __restrict__ val, double* __restrict__ dinv,
+                         int32_t* __restrict__ flag) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_row) return;
+  int s = slot[r * nnb + center];
+  double* D = dinv + r * BS * BS;
+  const double* A = val + ((int64_t)rowptr[r] + (s < 0 ? 0 : s)) * BS * BS;
+  if (s < 0) {
+    for (int k = 0; k < BS * BS; ++k) D[k] = (k % (BS + 1) == 0) ? 1.0 : 0.0;
+    atomicOr(flag, 8);
+    return;
+  }
+  if (BS == 2) {
+    double det = A[0] * A[3] - A[1] * A[2];
+    if (!(fabs(det) > 0.0) || !isfinite(det)) {
+      D[0] = 1.0; D[1] = 0.0; D[2] = 0.0; D[3] = 1.0;
+      atomicOr(flag, 8);
+      return;
+    }
+    double id = 1.0 / det;
+    D[0] = A[3] * id; D[1] = -A[1] * id; D[2] = -A[2] * id; D[3] = A[0] * id;
+  } else {
+    double c00 = A[4] * A[8] - A[5] * A[7], c01 = A[5] * A[6] - A[3] * A[8], c02 = A[3] * A[7] - A[4] * A[6];
+    double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+    if (!(fabs(det) > 0.0) || !isfinite(det)) {
+      for (int k = 0; k < 9; ++k) D[k] = (k % 4 == 0) ? 1.0 : 0.0;
+      atomicOr(flag, 8);
+      return;
+    }
+    double id = 1.0 / det;
+    D[0] = c00 * id; D[3] = c01 * id; D[6] = c02 * id;
+    D[1] = (A[2] * A[7] - A[1] * A[8]) * id;
+    D[4] = (A[0] * A[8] - A[2] * A[6]) * id;
+    D[7] = (A[1] * A[6] - A[0] * A[7]) * id;
+    D[2] = (A[1] * A[5] - A[2] * A[4]) * id;
+    D[5] = (A[2] * A[3] - A[0] * A[5]) * id;
+    D[8] = (A[0] * A[4] - A[1] * A[3]) * id;
+  }
+}
+
+// y = A x over one row block per workgroup; LPR lanes cooperate on a row.
+// Partials: part[blk][q1] = sum z1 . y (if z1), part[blk][q2] = sum y . y
+// (if q2 >= 0).  Skips sims whose Krylov solve is finished.
+template <int BS, int LPR>
+__global__ void __launch_bounds__(256) k_spmv(const RowBlock* __restrict__ blocks, const int32_t* __restrict__ simflag,
+                                              const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+                                              const double* __restrict__ val, const double* __restrict__ x,
+                                              double* __restrict__ y, const double* __restrict__ z1,
+                                              double* __restrict__ part, int q1, int q2) {
+  const RowBlock b = blocks[blockIdx.x];
+  if (simflag && simflag[2 * b.sim] >= 0) return;
+  constexpr int G = 256 / LPR;
+  const int lane = threadIdx.x % LPR, grp = threadIdx.x / LPR;
+  double d1 = 0.0, d2 = 0.0;
+  for (int row = b.row0 + grp; row < b.row1; row += G) {
+    double acc[BS];
+#pragma unroll
+    for (int i = 0; i < BS; ++i) acc[i] = 0.0;
+    const int k1 = rowptr[row + 1];
+    for (int k = rowptr[row] + lane; k < k1; k += LPR) {
+      const double* blk = val + (int64_t)k * (BS * BS);
+      const int64_t c = colind[k];
+      double xv[BS];
+#pragma unroll
+      for (int j = 0; j < BS; ++j) xv[j] = x[c * BS + j];
+#pragma unroll
+      for (int i = 0; i < BS; ++i)
+#pragma unroll
+        for (int j = 0; j < BS; ++j) acc[i] += blk[i * BS + j] * xv[j];
+    }
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1)
+#pragma unroll
+      for (int i = 0; i < BS; ++i) acc[i] += __shfl_xor(acc[i], off, LPR);
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < BS; ++i) {
+        y[(int64_t)row * BS + i] = acc[i];
+        if (z1) d1 += z1[(int64_t)row * BS + i] * acc[i];
+        d2 += acc[i] * acc[i];
+      }
+    }
+  }
+  if (q1 < 0 && q2 < 0) return;
+  __shared__ double sh[2][4];
+  d1 = wave_sum(d1);
+  d2 = wave_sum(d2);
+  if (threadIdx.x % 64 == 0) { sh[0][threadIdx.x / 64] = d1; sh[1][threadIdx.x / 64] = d2; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (q1 >= 0) part[blockIdx.x * NQ + q1] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+    if (q2 >= 0) part[blockIdx.x * NQ + q2] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+  }
+}
+
+// ---------------------------------------------------------- BiCGStab ------
+// Start (or restart) from x: r = b - t (t = A x, or x = 0 and t unused),
+// rhat = r, p = v = 0; partials (rhat, r) -> q0, (r, r) -> q1.
+template <int BS>
+__global__ void __launch_bounds__(64) k_bicg_init(const RowBlock* __restrict__ blocks, int from_zero,
+                                                  const double* __restrict__ bvec, const double* __restrict__ t,
+                                                  double* __restrict__ x, double* __restrict__ r,
+                                                  double* __restrict__ rh, double* __restrict__ p,
+                                                  double* __restrict__ v, double* __restrict__ part) {
+  const RowBlock b = blocks[blockIdx.x];
+  const int64_t row = b.row0 + threadIdx.x;
+  double rr = 0.0;
+  if (row < b.row1) {
+#pragma unroll
+    for (int i = 0; i < BS; ++i) {
+      int64_t k = row * BS + i;
+      double ri = from_zero ? bvec[k] : bvec[k] - t[k];
+      if (from_zero) x[k] = 0.0;
+      r[k] = ri; rh[k] = ri; p[k] = 0.0; v[k] = 0.0;
+      rr += ri * ri;
+    }
+  }
+  rr = wave_sum(rr);
+  if (threadIdx.x == 0) { part[blockIdx.x * NQ + 0] = rr; part[blockIdx.x * NQ + 1] = rr; }
+}
+
+// Per sim: reset scalars; record ||b||^2 on the first start.
+__global__ void k_bicg_sim_init(int nsim, const int32_t* __restrict__ blk_first, const double* __restrict__ part,
+                                double* __restrict__ sc, int32_t* __restrict__ flag, double rtol, int first) {
+  const int s = blockIdx.x;   // one wave per sim
+  double rr = 0.0;
+  for (int b = blk_first[s] + (int)threadIdx.x; b < blk_first[s + 1]; b += 64) rr += part[b * NQ + 1];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) rr += __shfl_xor(rr, off, 64);
+  if (threadIdx.x != 0) return;
+  double* S = sc + s * 16;
+  if (first) { S[SC_BN2] = rr; S[SC_TOL2] = rtol * rtol * rr; }
+  S[SC_RHO] = 1.0; S[SC_RHO + 1] = 1.0; S[SC_ALPHA] = 1.0; S[SC_OMEGA] = 1.0; S[SC_RR] = rr;
+  flag[2 * s] = (rr <= S[SC_TOL2]) ? 0 : -1;
+  flag[2 * s + 1] = 0;
+}
+
+// Step A of iteration it: convergence test, p = r + beta (p - omega v), phat = M^-1 p.
+template <int BS>
+__global__ void __launch_bounds__(64) k_bicg_a(const RowBlock* __restrict__ blocks, const int32_t* __restrict__ blk_first,
+                                               int it, const double* __restrict__ part, double* __restrict__ sc,
+                                               int32_t* __restrict__ flag, const double* __restrict__ r,
+                                               double* __restrict__ p, const double* __restrict__ v,
+                                               double* __restrict__ ph, const double* __restrict__ dinv) {
+  const RowBlock b = blocks[blockIdx.x];
+  const int s = b.sim;
+  if (flag[2 * s] >= 0) return;
+  const int b0 = blk_first[s], b1 = blk_first[s + 1];
+  double rho = sim_sum(part, 0, b0, b1);
+  double rr = sim_sum(part, 1, b0, b1);
+  double* S = sc + s * 16;
+  const bool lead = (blockIdx.x == (unsigned)b0) && threadIdx.x == 0;
+  if (rr <= S[SC_TOL2]) {
+    if (lead) { flag[2 * s] = it; S[SC_RR] = rr; }
+    return;
+  }
+  double rho_old = S[SC_RHO + ((it + 1) & 1)], alpha = S[SC_ALPHA], omega = S[SC_OMEGA];
+  if (!(rho != 0.0) || !isfinite(rho) || !isfinite(rr) || (it > 0 && omega == 0.0)) {
+    if (lead) { flag[2 * s] = it; flag[2 * s + 1] = 1; S[SC_RR] = rr; }
+    return;
+  }
+  double beta = (it == 0) ? 0.0 : (rho / rho_old) * (alpha / omega);
+  const int64_t row = b.row0 + threadIdx.x;
+  if (row < b.row1) {
+#pragma unroll
+    for (int i = 0; i < BS; ++i) {
+      int64_t k = row * BS + i;
+      p[k] = r[k] + beta * (p[k] - omega * v[k]);
+    }
+    apply_dinv<BS>(dinv, row, p, ph);
+  }
+  if (lead) S[SC_RHO + (it & 1)] = rho;
+}
+
+// Step C: alpha = rho / (rhat, v); s = r - alpha v; shat = M^-1 s.
+template <int BS>
+__global__ void __launch_bounds__(64) k_bicg_c(const RowBlock* __restrict__ blocks, const int32_t* __restrict__ blk_first,
+                                               int it, const double* __restrict__ part_rv, double* __restrict__ sc,
+                                               int32_t* __restrict__ flag, const double* __restrict__ r,
+                                               const double* __restrict__ v, double* __restrict__ s_,
+                                               double* __restrict__ sh, const double* __restrict__ dinv) {
+  const RowBlock b = blocks[blockIdx.x];
+  const int s = b.sim;
+  if (flag[2 * s] >= 0) return;
+  const int b0 = blk_first[s], b1 = blk_first[s + 1];
+  double rv = sim_sum(part_rv, 0, b0, b1);
+  double* S = sc + s * 16;
+  double rho = S[SC_RHO + (it & 1)];
+  double alpha = rv != 0.0 ? rho / rv : 0.0;
+  const int64_t row = b.row0 + threadIdx.x;
+  if (row < b.row1) {
+#pragma unroll
+    for (int i = 0; i < BS; ++i) {
+      int64_t k = row * BS + i;
+      s_[k] = r[k] - alpha * v[k];
+    }
+    apply_dinv<BS>(dinv, row, s_, sh);
+  }
+  if (blockIdx.x == (unsigned)b0 && threadIdx.x == 0) S[SC_ALPHA] = alpha;
+}
+
+// Step E: omega = (t, s)/(t, t); x += alpha phat + omega shat; r = s - omega t.
+template <int BS>
+__global__ void __launch_bounds__(64) k_bicg_e(const RowBlock* __restrict__ blocks, const int32_t* __restrict__ blk_first,
+                                               const double* __restrict__ part_ts, double* __restrict__ sc,
+                                               int32_t* __restrict__ flag, double* __restrict__ x,
+                                               double* __restrict__ r, const double* __restrict__ rh,
+                                               const double* __restrict__ ph, const double* __restrict__ sh,
+                                               const double* __restrict__ s_, const double* __restrict__ t,
+                                               double* __restrict__ part) {
+  const RowBlock b = blocks[blockIdx.x];
+  const int s = b.sim;
+  if (flag[2 * s] >= 0) return;
+  const int b0 = blk_first[s], b1 = blk_first[s + 1];
+  double ts = sim_sum(part_ts, 0, b0, b1);
+  double tt = sim_sum(part_ts, 1, b0, b1);
+  double* S = sc + s * 16;
+  double alpha = S[SC_ALPHA];
+  double omega = tt > 0.0 ? ts / tt : 0.0;
+  double d_rhr = 0.0, d_rr = 0.0;
+  const int64_t row = b.row0 + threadIdx.x;
+  if (row < b.row1) {
+#pragma unroll
+    for (int i = 0; i < BS; ++i) {
+      int64_t k = row * BS + i;
+      x[k] += alpha * ph[k] + omega * sh[k];
+      double rn = s_[k] - omega * t[k];
+      r[k] = rn;
+      d_rhr += rh[k] * rn;
+      d_rr += rn * rn;
+    }
+  }
+  d_rhr = wave_sum(d_rhr);
+  d_rr = wave_sum(d_rr);
+  if (threadIdx.x == 0) { part[blockIdx.x * NQ + 0] = d_rhr; part[blockIdx.x * NQ + 1] = d_rr; }
+  if (blockIdx.x == (unsigned)b0 && threadIdx.x == 0) S[SC_OMEGA] = omega;
+}
+
+// True residual norm per block: ||b - t||^2 -> part q2.
+template <int BS>
+__global__ void __launch_bounds__(64) k_true_res(const RowBlock* __restrict__ blocks, const double* __restrict__ bvec,
+                                                 const double* __restrict__ t, double* __restrict__ part) {
+  const RowBlock b = blocks[blockIdx.x];
+  const int64_t row = b.row0 + threadIdx.x;
+  double rr = 0.0;
+  if (row < b.row1)
+#pragma unroll
+    for (int i = 0; i < BS; ++i) { double d = bvec[row * BS + i] - t[row * BS + i]; rr += d * d; }
+  rr = wave_sum(rr);
+  if (threadIdx.x == 0) part[blockIdx.x * NQ + 2] = rr;
+}
+
+}  // namespace mpm
+
+using namespace mpm;
+
+// ---------------------------------------------------------------- host -----
+namespace {
+struct KBufs { double *part_rr, *part_rv, *part_ts; };
+}
+
+template <int BS, int LPR>
+static int spmv_launch(mpm_ctx* c, const int32_t* simflag, const double* val, const double* x, double* y,
+                       const double* z1, double* part, int q1, int q2) {
+  unsigned nbk = (unsigned)c->blocks_h.size();
+  if (!nbk) return MPM_OK;
+  k_spmv<BS, LPR><<<nbk, 256, 0, c->stream>>>(c->blocks.p, simflag, c->rowptr.p, c->colind.p, val, x, y, z1, part, q1,
+                                             q2);
+  LAUNCH_CHECK(c, "k_spmv");
+  return MPM_OK;
+}
+
+static int spmv(mpm_ctx* c, const int32_t* simflag, const double* val, const double* x, double* y, const double* z1,
+                double* part, int q1, int q2) {
+  if (c->nd == 2) return spmv_launch<2, 32>(c, simflag, val, x, y, z1, part, q1, q2);
+  if (c->dim == 2) return spmv_launch<3, 32>(c, simflag, val, x, y, z1, part, q1, q2);
+  return spmv_launch<3, 64>(c, simflag, val, x, y, z1, part, q1, q2);
+}
+
+int launch_spmv(mpm_ctx* c, const double* val, const double* x, double* y) {
+  return spmv(c, nullptr, val, x, y, nullptr, nullptr, -1, -1);
+}
+
+int launch_bj_inv(mpm_ctx* c, const double* val) {
+  const int nnb = c->dim == 3 ? 125 : 25, center = c->dim == 3 ? 62 : 12;
+  if (c->dinv.ensure(c->n_row * c->nd * c->nd) != hipSuccess) return c->fail(MPM_E_NOMEM, "dinv allocation failed");
+  if (!c->n_row) return MPM_OK;
+  unsigned g = (unsigned)((c->n_row + 255) / 256);
+  if (c->nd == 2) k_bj_inv<2><<<g, 256, 0, c->stream>>>(c->n_row, c->rowptr.p, c->slot.p, nnb, center, val, c->dinv.p, c->flag.p);
+  else k_bj_inv<3><<<g, 256, 0, c->stream>>>(c->n_row, c->rowptr.p, c->slot.p, nnb, center, val, c->dinv.p, c->flag.p);
+  LAUNCH_CHECK(c, "k_bj_inv");
+  return MPM_OK;
+}
+
+// Event pairs around sampled SpMV launches (kernel-duration measurement).
+static int spmv_timed(mpm_ctx* c, bool timed, const int32_t* simflag, const double* val, const double* x, double* y,
+                      const double* z1, double* part, int q1, int q2) {
+  if (!timed) return spmv(c, simflag, val, x, y, z1, part, q1, q2);
+  hipEvent_t e0, e1;
+  HIPC(c, hipEventCreate(&e0));
+  HIPC(c, hipEventCreate(&e1));
+  HIPC(c, hipEventRecord(e0, c->stream));
+  int rc = spmv(c, simflag, val, x, y, z1, part, q1, q2);
+  HIPC(c, hipEventRecord(e1, c->stream));
+  c->spmv_events.push_back(e0);
+  c->spmv_events.push_back(e1);
+  return rc;
+}
+
+template <int BS>
+static int bicg_iter(mpm_ctx* c, const double* val, int it, const KBufs& K) {
+  unsigned nbk = (unsigned)c->blocks_h.size();
+  int rc;
+  const bool timed = c->time_spmv > 0 && it % c->time_spmv == 0;
+  k_bicg_a<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->blk_first.p, it, K.part_rr, c->simsc.p, c->simflag.p, c->kr.p,
+                                         c->kp.p, c->kv.p, c->kph.p, c->dinv.p);
+  if ((rc = spmv_timed(c, timed, c->simflag.p, val, c->kph.p, c->kv.p, c->krh.p, K.part_rv, 0, -1))) return rc;
+  k_bicg_c<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->blk_first.p, it, K.part_rv, c->simsc.p, c->simflag.p, c->kr.p,
+                                         c->kv.p, c->ks.p, c->ksh.p, c->dinv.p);
+  if ((rc = spmv_timed(c, timed, c->simflag.p, val, c->ksh.p, c->kt.p, c->ks.p, K.part_ts, 0, 1))) return rc;
+  k_bicg_e<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->blk_first.p, K.part_ts, c->simsc.p, c->simflag.p, c->kx.p,
+                                         c->kr.p, c->krh.p, c->kph.p, c->ksh.p, c->ks.p, c->kt.p, K.part_rr);
+  LAUNCH_CHECK(c, "bicgstab step");
+  return MPM_OK;
+}
+
+// Solve val * x = b (compact vectors c->kb -> c->kx).  iters_out: host
+// [nsim] iterations per sim.  Returns MPM_E_KRYLOV on breakdown / limit.
+int krylov_solve(mpm_ctx* c, const double* val, double rtol, int max_iter, std::vector<int>& iters_out) {
+  const int64_t nv = c->n_row * c->nd;
+  const size_t nbk = c->blocks_h.size();
+  const int nsim = c->nsim;
+  bool ok = c->kx.ensure(nv) == hipSuccess && c->kr.ensure(nv) == hipSuccess && c->krh.ensure(nv) == hipSuccess &&
+            c->kp.ensure(nv) == hipSuccess && c->kv.ensure(nv) == hipSuccess && c->ks.ensure(nv) == hipSuccess &&
+            c->kt.ensure(nv) == hipSuccess && c->kph.ensure(nv) == hipSuccess && c->ksh.ensure(nv) == hipSuccess;
+  DBuf<double> parts;
+  ok = ok && parts.ensure(3 * (nbk + 1) * NQ) == hipSuccess;
+  if (!ok) { parts.release(); return c->fail(MPM_E_NOMEM, "Krylov vectors allocation failed"); }
+  KBufs K{parts.p, parts.p + (nbk + 1) * NQ, parts.p + 2 * (nbk + 1) * NQ};
+  iters_out.assign(nsim, 0);
+  std::vector<int32_t> hflag(2 * nsim);
+  std::vector<double> hsc(16 * nsim);
+  iters_out.assign(nsim, 0);
+  int used = 0;           // iterations spent over all (re)starts
+  const int CHUNK = 16;
+  bool good = false;
+  double last_worst = INFINITY;
+  for (int attempt = 0; attempt < 4 && !good && used < max_iter; ++attempt) {
+    unsigned g = (unsigned)nbk;
+    if (attempt > 0) {  // restart from the current x: r = b - A x
+      int rc = spmv(c, nullptr, val, c->kx.p, c->kt.p, nullptr, K.part_ts, -1, -1);
+      if (rc) { parts.release(); return rc; }
+    }
+    if (g) {
+      if (c->nd == 2)
+        k_bicg_init<2><<<g, 64, 0, c->stream>>>(c->blocks.p, attempt == 0, c->kb.p, c->kt.p, c->kx.p, c->kr.p, c->krh.p,
+                                                c->kp.p, c->kv.p, K.part_rr);
+      else
+        k_bicg_init<3><<<g, 64, 0, c->stream>>>(c->blocks.p, attempt == 0, c->kb.p, c->kt.p, c->kx.p, c->kr.p, c->krh.p,
+                                                c->kp.p, c->kv.p, K.part_rr);
+    }
+    k_bicg_sim_init<<<nsim, 64, 0, c->stream>>>(nsim, c->blk_first.p, K.part_rr, c->simsc.p, c->simflag.p, rtol,
+                                                 attempt == 0);
+    LAUNCH_CHECK(c, "bicgstab init");
+    int it = 0;
+    bool all_done = false;
+    while (!all_done && used + it < max_iter) {
+      for (int k = 0; k < CHUNK && used + it < max_iter; ++k, ++it) {
+        int rc = c->nd == 2 ? bicg_iter<2>(c, val, it, K) : bicg_iter<3>(c, val, it, K);
+        if (rc) { parts.release(); return rc; }
+      }
+      HIPC(c, hipMemcpyAsync(hflag.data(), c->simflag.p, 2 * nsim * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+      HIPC(c, hipStreamSynchronize(c->stream));
+      all_done = true;
+      for (int s = 0; s < nsim; ++s) all_done = all_done && hflag[2 * s] >= 0;
+    }
+    for (int s = 0; s < nsim; ++s) iters_out[s] += (hflag[2 * s] >= 0 ? hflag[2 * s] : it);
+    used += it;
+    // accept only on the true residual ||b - A x|| <= 10 rtol ||b|| of every sim
+    int rc = spmv(c, nullptr, val, c->kx.p, c->kt.p, nullptr, K.part_ts, -1, -1);
+    if (rc) { parts.release(); return rc; }
+    if (g) {
+      if (c->nd == 2) k_true_res<2><<<g, 64, 0, c->stream>>>(c->blocks.p, c->kb.p, c->kt.p, c->part.p);
+      else k_true_res<3><<<g, 64, 0, c->stream>>>(c->blocks.p, c->kb.p, c->kt.p, c->part.p);
+      LAUNCH_CHECK(c, "k_true_res");
+    }
+    rc = sim_sum_launch(c, c->part.p, 2, 9);
+    if (rc) { parts.release(); return rc; }
+    HIPC(c, hipMemcpyAsync(hsc.data(), c->simsc.p, 16 * nsim * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPC(c, hipStreamSynchronize(c->stream));
+    good = true;
+    double worst = 0.0;
+    for (int s = 0; s < nsim; ++s) {
+      double tr2 = hsc[s * 16 + 9], bn2 = hsc[s * 16 + SC_BN2];
+      double ratio = bn2 > 0.0 ? std::sqrt(tr2 / bn2) : 0.0;
+      if (!std::isfinite(ratio)) ratio = INFINITY;
+      worst = std::max(worst, ratio);
+      if (!(ratio <= 10.0 * rtol)) good = false;
+    }
+    // restarting only helps while the true residual still falls
+    if (!good && attempt > 0 && !(worst < 0.5 * last_worst)) { last_worst = std::min(last_worst, worst); break; }
+    last_worst = std::min(last_worst, worst);
+  }
+  // A solve that stalled above rtol at the FP64 floor of an ill-conditioned
+  // system is still a usable Newton direction when its true residual is at
+  // most 1e-6 ||b||; the Newton test on the nonlinear residual decides.
+  c->krylov_soft = !good && last_worst <= 1e-6;
+  const int status = (good || c->krylov_soft) ? MPM_OK : MPM_E_KRYLOV;
+  parts.release();
+  if (!c->spmv_events.empty()) {
+    HIPC(c, hipStreamSynchronize(c->stream));
+    for (size_t k = 0; k + 1 < c->spmv_events.size(); k += 2) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, c->spmv_events[k], c->spmv_events[k + 1]) == hipSuccess) {
+        c->spmv_ms += ms;
+        c->spmv_n += 1;
+      }
+    }
+    for (hipEvent_t e : c->spmv_events) (void)hipEventDestroy(e);
+    c->spmv_events.clear();
+  }
+  if (status != MPM_OK) return c->fail(MPM_E_KRYLOV, "Krylov solve did not reach its tolerance");
+  return MPM_OK;
+}

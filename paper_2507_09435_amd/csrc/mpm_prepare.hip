@@ -1,0 +1,563 @@
+// Particle binning by B-spline stencil origin and the block-sparse Jacobian
+// pattern of one load step (Sec. 3.2: every particle couples the 3^d nodes
+// of its stencil, so a node row couples at most 5^d nodes, Table 1).
+#include "mpm_kernels.hpp"
+#include "mpm_internal.hpp"
+
+namespace mpm {
+
+// -------------------------------------------------------------- scan ------
+// Exclusive prefix sum of int32 (n values) into out[0..n], out[n] = total.
+constexpr int SCAN_TPB = 256, SCAN_PER = 4, SCAN_TILE = SCAN_TPB * SCAN_PER;
+
+__global__ void k_scan_tiles(const int32_t* __restrict__ in, int64_t n, int32_t* __restrict__ tile_sum) {
+  __shared__ int32_t sh[SCAN_TPB];
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  int32_t s = 0;
+  for (int k = 0; k < SCAN_PER; ++k) {
+    int64_t i = base + (int64_t)k * SCAN_TPB + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = SCAN_TPB / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = sh[0];
+}
+
+// single block: exclusive scan of the tile sums in place
+__global__ void k_scan_sums(int32_t* __restrict__ tile_sum, int64_t ntiles) {
+  __shared__ int32_t sh[SCAN_TPB];
+  __shared__ int32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t b = 0; b < ntiles; b += SCAN_TPB) {
+    int64_t i = b + threadIdx.x;
+    int32_t v = (i < ntiles) ? tile_sum[i] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < SCAN_TPB; off <<= 1) {
+      int32_t t = (threadIdx.x >= off) ? sh[threadIdx.x - off] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < ntiles) tile_sum[i] = carry + sh[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == SCAN_TPB - 1) carry += sh[SCAN_TPB - 1];
+    __syncthreads();
+  }
+}
+
+__global__ void k_scan_apply(const int32_t* __restrict__ in, int64_t n, const int32_t* __restrict__ tile_off,
+                             int32_t* __restrict__ out) {
+  __shared__ int32_t sh[SCAN_TILE];
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  for (int k = 0; k < SCAN_PER; ++k) {
+    int idx = k * SCAN_TPB + threadIdx.x;
+    int64_t i = base + idx;
+    sh[idx] = (i < n) ? in[i] : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t run = tile_off[blockIdx.x];
+    for (int k = 0; k < SCAN_TILE; ++k) { int32_t v = sh[k]; sh[k] = run; run += v; }
+    if (base + SCAN_TILE >= n) out[n] = run;   // last tile writes the total
+  }
+  __syncthreads();
+  for (int k = 0; k < SCAN_PER; ++k) {
+    int idx = k * SCAN_TPB + threadIdx.x;
+    int64_t i = base + idx;
+    if (i < n) out[i] = sh[idx];
+  }
+}
+
+int scan_excl(mpm_ctx* c, const int32_t* in, int64_t n, int32_t* out, int32_t* total) {
+  int64_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+  if (ntiles < 1) ntiles = 1;
+  if (c->scan_tmp.ensure(ntiles) != hipSuccess) return c->fail(MPM_E_NOMEM, "scan scratch allocation failed");
+  k_scan_tiles<<<ntiles, SCAN_TPB, 0, c->stream>>>(in, n, c->scan_tmp.p);
+  k_scan_sums<<<1, SCAN_TPB, 0, c->stream>>>(c->scan_tmp.p, ntiles);
+  k_scan_apply<<<ntiles, SCAN_TPB, 0, c->stream>>>(in, n, c->scan_tmp.p, out);
+  LAUNCH_CHECK(c, "scan");
+  if (total) {
+    HIPC(c, hipMemcpyAsync(total, out + n, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPC(c, hipStreamSynchronize(c->stream));
+  }
+  return MPM_OK;
+}
+
+// ------------------------------------------------------------ binning -----
+__device__ __forceinline__ int find_sim(const int64_t* __restrict__ sim_start, int nsim, int64_t p) {
+  int lo = 0, hi = nsim - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (sim_start[mid] <= p) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Origin key of every particle (input order).  flag[0] |= 1 if a stencil
+// leaves the padded grid, 2 if a coordinate is not finite.
+__global__ void k_okeys(const double* __restrict__ x, int64_t np, const int64_t* __restrict__ sim_start, int nsim,
+                        const SimDev* __restrict__ sims, int dim, int32_t* __restrict__ okey,
+                        int32_t* __restrict__ psim_in, int32_t* __restrict__ flag) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  int s = find_sim(sim_start, nsim, p);
+  const SimDev& S = sims[s];
+  int64_t key = 0, stride = 1;
+  bool bad = false;
+  for (int k = 0; k < dim; ++k) {
+    double xv = x[(int64_t)k * np + p];
+    if (!isfinite(xv)) { atomicOr(flag, 2); bad = true; break; }
+    double t = (xv - S.x0[k]) / S.h - 0.5;
+    double of = floor(t);
+    if (!(of >= -1.0 && of <= (double)(S.n[k] - 1))) { bad = true; atomicOr(flag, 1); break; }
+    int64_t o = (int64_t)of;
+    key += (o + 1) * stride;
+    stride *= S.noa[k];
+  }
+  okey[p] = bad ? 0 : (int32_t)(S.okey_base + key);
+  psim_in[p] = s;
+}
+
+__global__ void k_hist(const int32_t* __restrict__ okey, int64_t np, int32_t* __restrict__ cnt) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < np) atomicAdd(&cnt[okey[p]], 1);
+}
+
+__global__ void k_scatter(const int32_t* __restrict__ okey, int64_t np, const int32_t* __restrict__ start,
+                          int32_t* __restrict__ cursor, int32_t* __restrict__ perm) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  int32_t k = okey[p];
+  int32_t pos = start[k] + atomicAdd(&cursor[k], 1);
+  perm[pos] = (int32_t)p;
+}
+
+// Deterministic order inside each stencil group: ascending input index.
+__global__ void k_group_sort(const int32_t* __restrict__ start, int64_t nkeys, int32_t* __restrict__ perm) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nkeys) return;
+  int32_t b = start[k], e = start[k + 1];
+  for (int32_t i = b + 1; i < e; ++i) {
+    int32_t v = perm[i];
+    int32_t j = i - 1;
+    while (j >= b && perm[j] > v) { perm[j + 1] = perm[j]; --j; }
+    perm[j + 1] = v;
+  }
+}
+
+// Sorted SoA copies of the particle state.
+__global__ void k_gather(int64_t np, int dim, const int32_t* __restrict__ perm, const int32_t* __restrict__ psim_in,
+                         const double* __restrict__ x, const double* __restrict__ vol0, const double* __restrict__ F,
+                         const double* __restrict__ be, const double* __restrict__ E, const double* __restrict__ phi,
+                         double* __restrict__ xs, double* __restrict__ vs, double* __restrict__ Fs,
+                         double* __restrict__ bs, double* __restrict__ Es, double* __restrict__ phis,
+                         int32_t* __restrict__ psim) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  int64_t p = perm[i];
+  for (int k = 0; k < dim; ++k) xs[k * np + i] = x[k * np + p];
+  vs[i] = vol0[p];
+  for (int k = 0; k < dim * dim; ++k) Fs[k * np + i] = F[k * np + p];
+  int nb = dim == 2 ? 4 : 6;
+  for (int k = 0; k < nb; ++k) bs[k * np + i] = be[k * np + p];
+  if (E) Es[i] = E[p];
+  if (phi) phis[i] = phi[p];
+  psim[i] = psim_in[p];
+}
+
+// --------------------------------------------------------- node activity --
+__device__ __forceinline__ int find_sim_node(const SimDev* __restrict__ sims, int nsim, int64_t node) {
+  int lo = 0, hi = nsim - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (sims[mid].node_base <= node) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Decompose a full-grid node id into (sim, per-axis node index -1..n+1).
+__device__ __forceinline__ int node_coords(const SimDev* __restrict__ sims, int nsim, int dim, int64_t node,
+                                           int32_t idx[3]) {
+  int s = find_sim_node(sims, nsim, node);
+  int64_t loc = node - sims[s].node_base;
+  for (int k = 0; k < 3; ++k) idx[k] = 0;
+  for (int k = 0; k < dim; ++k) { idx[k] = (int32_t)(loc % sims[s].nna[k]) - 1; loc /= sims[s].nna[k]; }
+  return s;
+}
+
+// Occupancy of the 3^d origins o = i - 2 .. i per axis as a bit mask
+// (bit a0 + 3 a1 + 9 a2 for o = i - 2 + a).
+__device__ __forceinline__ uint32_t occ_mask(const SimDev& S, int dim, const int32_t idx[3],
+                                             const int32_t* __restrict__ cnt) {
+  uint32_t m = 0;
+  int n2 = dim == 3 ? 3 : 1;
+  for (int a2 = 0; a2 < n2; ++a2)
+    for (int a1 = 0; a1 < 3; ++a1)
+      for (int a0 = 0; a0 < 3; ++a0) {
+        int a[3] = {a0, a1, a2};
+        bool ok = true;
+        int64_t key = 0, stride = 1;
+        for (int k = 0; k < dim; ++k) {
+          int o = idx[k] - 2 + a[k];
+          if (o < -1 || o > S.n[k] - 1) { ok = false; break; }
+          key += (int64_t)(o + 1) * stride;
+          stride *= S.noa[k];
+        }
+        if (ok && cnt[S.okey_base + key] > 0) m |= 1u << (a0 + 3 * a1 + 9 * a2);
+      }
+  return m;
+}
+
+__global__ void k_node_active(const SimDev* __restrict__ sims, int nsim, int dim, int64_t n_nodes,
+                              const int32_t* __restrict__ cnt, int32_t* __restrict__ flag_out) {
+  int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= n_nodes) return;
+  int32_t idx[3];
+  int s = node_coords(sims, nsim, dim, node, idx);
+  // the node is in the stencil of origin o iff o <= i <= o + 2, i.e. the
+  // origins i-2..i; those are exactly the mask bits
+  flag_out[node] = occ_mask(sims[s], dim, idx, cnt) != 0u ? 1 : 0;
+}
+
+__global__ void k_node_map(int64_t n_nodes, const int32_t* __restrict__ flag, const int32_t* __restrict__ scan,
+                           int32_t* __restrict__ node_map, int64_t* __restrict__ active, const SimDev* __restrict__ sims,
+                           int nsim, int32_t* __restrict__ row_sim) {
+  int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= n_nodes) return;
+  if (flag[node]) {
+    int32_t r = scan[node];
+    node_map[node] = r;
+    active[r] = node;
+    row_sim[r] = find_sim_node(sims, nsim, node);
+  } else {
+    node_map[node] = -1;
+  }
+}
+
+// Allowed-origin masks per neighbour offset delta in [-2, 2]^d: block (i, i+delta)
+// exists iff an occupied origin o satisfies max(i, j) - 2 <= o <= min(i, j) per
+// axis; with o = i - 2 + a this is max(0, delta) <= a <= 2 + min(0, delta).
+__device__ __forceinline__ uint32_t allowed_mask(int dim, const int d[3]) {
+  uint32_t m = 0;
+  int n2 = dim == 3 ? 3 : 1;
+  for (int a2 = 0; a2 < n2; ++a2)
+    for (int a1 = 0; a1 < 3; ++a1)
+      for (int a0 = 0; a0 < 3; ++a0) {
+        int a[3] = {a0, a1, a2};
+        bool ok = true;
+        for (int k = 0; k < dim; ++k) {
+          int lo = d[k] > 0 ? d[k] : 0, hi = 2 + (d[k] < 0 ? d[k] : 0);
+          if (a[k] < lo || a[k] > hi) { ok = false; break; }
+        }
+        if (ok) m |= 1u << (a0 + 3 * a1 + 9 * a2);
+      }
+  return m;
+}
+
+// mode 0: count blocks per row; mode 1: write colind and the slot table.
+__global__ void k_rows(int mode, int64_t n_row, int dim, const int64_t* __restrict__ active,
+                       const SimDev* __restrict__ sims, int nsim, const int32_t* __restrict__ cnt,
+                       const int32_t* __restrict__ node_map, int32_t* __restrict__ rowcnt,
+                       const int32_t* __restrict__ rowptr, int32_t* __restrict__ colind, int8_t* __restrict__ slot) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_row) return;
+  int32_t idx[3];
+  int64_t node = active[r];
+  int s = node_coords(sims, nsim, dim, node, idx);
+  const SimDev& S = sims[s];
+  uint32_t occ = occ_mask(S, dim, idx, cnt);
+  int nnb = dim == 3 ? 125 : 25;
+  int c = 0;
+  int64_t base = mode ? rowptr[r] : 0;
+  for (int t = 0; t < nnb; ++t) {
+    int d[3] = {t % 5 - 2, (t / 5) % 5 - 2, dim == 3 ? t / 25 - 2 : 0};
+    bool in = true;
+    int64_t nb = S.node_base, stride = 1;
+    for (int k = 0; k < dim; ++k) {
+      int j = idx[k] + d[k];
+      if (j < -1 || j > S.n[k] + 1) { in = false; break; }
+      nb += (int64_t)(j + 1) * stride;
+      stride *= S.nna[k];
+    }
+    bool exists = in && (occ & allowed_mask(dim, d)) != 0u;
+    if (mode == 1) {
+      slot[r * nnb + t] = exists ? (int8_t)c : (int8_t)-1;
+      if (exists) colind[base + c] = node_map[nb];
+    }
+    if (exists) ++c;
+  }
+  if (mode == 0) rowcnt[r] = c;
+}
+
+// Sum of w * V0 per row (a row whose sum is zero carries no material).
+template <int DIM>
+__global__ void k_node_volume(int64_t np, const double* __restrict__ xs, const double* __restrict__ vs,
+                              const int32_t* __restrict__ psim, const SimDev* __restrict__ sims,
+                              const int32_t* __restrict__ node_map, double* __restrict__ nvol) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const SimDev& S = sims[psim[i]];
+  Stencil<DIM> st;
+  make_stencil<DIM>(S, xs, np, i, st);
+  double v0 = vs[i];
+  for (int a = 0; a < Stencil<DIM>::NN; ++a) {
+    int32_t r = node_map[st.node(S, a)];
+    atomicAdd(&nvol[r], st.weight(a) * v0);
+  }
+}
+
+// Constrained unknowns per row: bc mask, or nodes without material.
+__global__ void k_cmask(int64_t n_row, int nd, const int64_t* __restrict__ active, const uint8_t* __restrict__ bc_mask,
+                        const double* __restrict__ bc_value, const uint8_t* __restrict__ react,
+                        const double* __restrict__ nvol, uint8_t* __restrict__ cmask, double* __restrict__ cval,
+                        uint8_t* __restrict__ rmask) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_row) return;
+  int64_t node = active[r];
+  bool empty = nvol[r] == 0.0;
+  for (int c = 0; c < nd; ++c) {
+    bool m = empty || bc_mask[node * nd + c] != 0;
+    cmask[r * nd + c] = m ? 1 : 0;
+    cval[r * nd + c] = (m && !empty) ? bc_value[node * nd + c] : 0.0;
+    rmask[r * nd + c] = react ? react[node * nd + c] : 0;
+  }
+}
+
+// External force: f_ext,i = sum_p w_ip (rho0 V0 g + f_p) (Sec. 2.2).
+template <int DIM>
+__global__ void k_fext(int64_t np, int nd, const double* __restrict__ xs, const double* __restrict__ vs,
+                       const double* __restrict__ fp_user, const int32_t* __restrict__ perm,
+                       const int32_t* __restrict__ psim, const SimDev* __restrict__ sims,
+                       const int32_t* __restrict__ node_map, double rho0, double gx, double gy, double gz,
+                       double* __restrict__ fext) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const SimDev& S = sims[psim[i]];
+  Stencil<DIM> st;
+  make_stencil<DIM>(S, xs, np, i, st);
+  double m = rho0 * vs[i];
+  double f[3] = {m * gx, m * gy, m * gz};
+  if (fp_user) {
+    int64_t p = perm[i];
+    for (int k = 0; k < DIM; ++k) f[k] += fp_user[k * np + p];
+  }
+  for (int a = 0; a < Stencil<DIM>::NN; ++a) {
+    int32_t r = node_map[st.node(S, a)];
+    double w = st.weight(a);
+    for (int k = 0; k < DIM; ++k) atomicAdd(&fext[(int64_t)r * nd + k], w * f[k]);
+  }
+}
+
+}  // namespace mpm
+
+using namespace mpm;
+
+// ======================================================================
+int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row_out, int64_t* nnzb_out, int32_t* nd_out) {
+  c->prepared = false;
+  int rc = validate_problem(c, pb);
+  if (rc) return rc;
+  const int dim = pb->grids[0].dim;
+  const int nsim = pb->nsim;
+  const int64_t np = pb->P.np;
+  c->dim = dim;
+  c->nsim = nsim;
+  c->up = pb->mat.up ? 1 : 0;
+  c->dp = pb->mat.dp ? 1 : 0;
+  c->nd = dim + c->up;
+  c->np = np;
+  const int nd = c->nd;
+
+  // per-sim constants
+  c->sims_h.assign(nsim, SimDev{});
+  int64_t nb = 0, ob = 0;
+  for (int s = 0; s < nsim; ++s) {
+    SimDev& S = c->sims_h[s];
+    const mpm_grid& g = pb->grids[s];
+    S.dim = dim;
+    S.h = g.h;
+    S.inv_h = 1.0 / g.h;
+    int64_t nn = 1, no = 1;
+    for (int k = 0; k < 3; ++k) {
+      S.n[k] = k < dim ? g.ncell[k] : 0;
+      S.nna[k] = k < dim ? g.ncell[k] + 3 : 1;
+      S.noa[k] = k < dim ? g.ncell[k] + 1 : 1;
+      S.x0[k] = k < dim ? g.origin[k] : 0.0;
+      nn *= S.nna[k];
+      no *= S.noa[k];
+    }
+    S.node_base = nb;
+    S.okey_base = ob;
+    S.p_begin = pb->sim_start ? pb->sim_start[s] : 0;
+    S.p_end = pb->sim_start ? pb->sim_start[s + 1] : np;
+    nb += nn;
+    ob += no;
+  }
+  if (nb > INT32_MAX || ob > INT32_MAX) return c->fail(MPM_E_INVALID, "grid too large for 32-bit node ids");
+  c->n_nodes = nb;
+  c->n_okeys = ob;
+
+  std::vector<int64_t> ss(nsim + 1);
+  for (int s = 0; s <= nsim; ++s) ss[s] = pb->sim_start ? pb->sim_start[s] : (s == 0 ? 0 : np);
+
+  // allocations
+  bool ok = c->sims.ensure(nsim) == hipSuccess && c->sim_start.ensure(nsim + 1) == hipSuccess &&
+            c->okey.ensure(np) == hipSuccess && c->gcount.ensure(ob + 1) == hipSuccess &&
+            c->gstart.ensure(ob + 1) == hipSuccess && c->cursor.ensure(ob + 1) == hipSuccess &&
+            c->perm.ensure(np) == hipSuccess && c->psim.ensure(2 * np) == hipSuccess &&
+            c->flag.ensure(8) == hipSuccess && c->node_flag.ensure(nb + 1) == hipSuccess &&
+            c->node_map.ensure(nb + 1) == hipSuccess && c->xs.ensure(dim * np) == hipSuccess &&
+            c->vol0s.ensure(np) == hipSuccess && c->Fs.ensure(dim * dim * np) == hipSuccess &&
+            c->bes.ensure((dim == 2 ? 4 : 6) * np) == hipSuccess &&
+            c->Es.ensure(pb->P.E ? np : 1) == hipSuccess && c->phis.ensure(pb->P.phi ? np : 1) == hipSuccess;
+  if (!ok) return c->fail(MPM_E_NOMEM, "device allocation failed in prepare");
+  HIPC(c, hipMemcpyAsync(c->sims.p, c->sims_h.data(), nsim * sizeof(SimDev), hipMemcpyHostToDevice, c->stream));
+  HIPC(c, hipMemcpyAsync(c->sim_start.p, ss.data(), (nsim + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+  HIPC(c, hipMemsetAsync(c->flag.p, 0, 8 * sizeof(int32_t), c->stream));
+
+  const int TPB = 256;
+  auto nblk = [](int64_t n) { return (unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); };
+  int32_t* psim_in = c->psim.p + np;   // second half: sim of each input particle
+  if (np > 0) {
+    k_okeys<<<nblk(np), TPB, 0, c->stream>>>(pb->P.x, np, c->sim_start.p, nsim, c->sims.p, dim, c->okey.p, psim_in,
+                                             c->flag.p);
+    LAUNCH_CHECK(c, "k_okeys");
+  }
+  int32_t hflag = 0;
+  HIPC(c, hipMemcpyAsync(&hflag, c->flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIPC(c, hipStreamSynchronize(c->stream));
+  if (hflag & 2) return c->fail(MPM_E_NONFINITE, "a particle coordinate is not finite");
+  if (hflag & 1) return c->fail(MPM_E_OUT_OF_GRID, "a particle stencil leaves the padded grid");
+
+  // counting sort by origin key
+  HIPC(c, hipMemsetAsync(c->gcount.p, 0, (ob + 1) * sizeof(int32_t), c->stream));
+  HIPC(c, hipMemsetAsync(c->cursor.p, 0, (ob + 1) * sizeof(int32_t), c->stream));
+  if (np > 0) {
+    k_hist<<<nblk(np), TPB, 0, c->stream>>>(c->okey.p, np, c->gcount.p);
+    LAUNCH_CHECK(c, "k_hist");
+  }
+  rc = scan_excl(c, c->gcount.p, ob, c->gstart.p, nullptr);
+  if (rc) return rc;
+  if (np > 0) {
+    k_scatter<<<nblk(np), TPB, 0, c->stream>>>(c->okey.p, np, c->gstart.p, c->cursor.p, c->perm.p);
+    k_group_sort<<<nblk(ob), TPB, 0, c->stream>>>(c->gstart.p, ob, c->perm.p);
+    k_gather<<<nblk(np), TPB, 0, c->stream>>>(np, dim, c->perm.p, psim_in, pb->P.x, pb->P.vol0, pb->P.F, pb->P.be,
+                                              pb->P.E, pb->P.phi, c->xs.p, c->vol0s.p, c->Fs.p, c->bes.p, c->Es.p,
+                                              c->phis.p, c->psim.p);
+    LAUNCH_CHECK(c, "sort/gather");
+  }
+
+  // active nodes and rows
+  k_node_active<<<nblk(nb), TPB, 0, c->stream>>>(c->sims.p, nsim, dim, nb, c->gcount.p, c->node_flag.p);
+  LAUNCH_CHECK(c, "k_node_active");
+  if (c->scan_tmp.ensure(1) != hipSuccess) return c->fail(MPM_E_NOMEM, "scan");
+  DBuf<int32_t> nscan;
+  if (nscan.ensure(nb + 1) != hipSuccess) return c->fail(MPM_E_NOMEM, "node scan");
+  int32_t n_row32 = 0;
+  rc = scan_excl(c, c->node_flag.p, nb, nscan.p, &n_row32);
+  if (rc) { nscan.release(); return rc; }
+  const int64_t n_row = n_row32;
+  c->n_row = n_row;
+  ok = c->active_nodes.ensure(n_row) == hipSuccess && c->row_sim.ensure(n_row) == hipSuccess &&
+       c->rowcnt.ensure(n_row + 1) == hipSuccess && c->rowptr.ensure(n_row + 1) == hipSuccess &&
+       c->slot.ensure(n_row * (dim == 3 ? 125 : 25)) == hipSuccess;
+  if (!ok) { nscan.release(); return c->fail(MPM_E_NOMEM, "device allocation failed (rows)"); }
+  k_node_map<<<nblk(nb), TPB, 0, c->stream>>>(nb, c->node_flag.p, nscan.p, c->node_map.p, c->active_nodes.p,
+                                              c->sims.p, nsim, c->row_sim.p);
+  LAUNCH_CHECK(c, "k_node_map");
+  // per-sim first row: the scan value at each sim's first node
+  c->sim_row_start.assign(nsim + 1, 0);
+  for (int s = 0; s < nsim; ++s) {
+    int32_t v = 0;
+    HIPC(c, hipMemcpyAsync(&v, nscan.p + c->sims_h[s].node_base, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPC(c, hipStreamSynchronize(c->stream));
+    c->sim_row_start[s] = v;
+    c->sims_h[s].row_base = v;
+  }
+  c->sim_row_start[nsim] = n_row;
+  nscan.release();
+  HIPC(c, hipMemcpyAsync(c->sims.p, c->sims_h.data(), nsim * sizeof(SimDev), hipMemcpyHostToDevice, c->stream));
+
+  if (n_row > 0) {
+    k_rows<<<nblk(n_row), TPB, 0, c->stream>>>(0, n_row, dim, c->active_nodes.p, c->sims.p, nsim, c->gcount.p,
+                                               c->node_map.p, c->rowcnt.p, nullptr, nullptr, nullptr);
+    LAUNCH_CHECK(c, "k_rows count");
+  }
+  int32_t nnzb32 = 0;
+  rc = scan_excl(c, c->rowcnt.p, n_row, c->rowptr.p, &nnzb32);
+  if (rc) return rc;
+  c->nnzb = nnzb32;
+  if (c->colind.ensure(c->nnzb) != hipSuccess) return c->fail(MPM_E_NOMEM, "colind allocation failed");
+  if (n_row > 0) {
+    k_rows<<<nblk(n_row), TPB, 0, c->stream>>>(1, n_row, dim, c->active_nodes.p, c->sims.p, nsim, c->gcount.p,
+                                               c->node_map.p, nullptr, c->rowptr.p, c->colind.p, c->slot.p);
+    LAUNCH_CHECK(c, "k_rows fill");
+  }
+
+  // grid vectors
+  const int64_t nv = n_row * nd;
+  ok = c->cmask.ensure(nv) == hipSuccess && c->rmask.ensure(nv) == hipSuccess && c->cval.ensure(nv) == hipSuccess &&
+       c->fext.ensure(nv) == hipSuccess && c->fint.ensure(nv) == hipSuccess && c->nvol.ensure(n_row) == hipSuccess &&
+       c->work.ensure(nv) == hipSuccess;
+  if (!ok) return c->fail(MPM_E_NOMEM, "device allocation failed (vectors)");
+  HIPC(c, hipMemsetAsync(c->nvol.p, 0, n_row * sizeof(double), c->stream));
+  HIPC(c, hipMemsetAsync(c->fext.p, 0, nv * sizeof(double), c->stream));
+  if (np > 0) {
+    if (dim == 2) {
+      k_node_volume<2><<<nblk(np), TPB, 0, c->stream>>>(np, c->xs.p, c->vol0s.p, c->psim.p, c->sims.p, c->node_map.p,
+                                                        c->nvol.p);
+      k_fext<2><<<nblk(np), TPB, 0, c->stream>>>(np, nd, c->xs.p, c->vol0s.p, pb->P.fp, c->perm.p, c->psim.p,
+                                                 c->sims.p, c->node_map.p, pb->mat.rho0, pb->mat.g[0], pb->mat.g[1],
+                                                 pb->mat.g[2], c->fext.p);
+    } else {
+      k_node_volume<3><<<nblk(np), TPB, 0, c->stream>>>(np, c->xs.p, c->vol0s.p, c->psim.p, c->sims.p, c->node_map.p,
+                                                        c->nvol.p);
+      k_fext<3><<<nblk(np), TPB, 0, c->stream>>>(np, nd, c->xs.p, c->vol0s.p, pb->P.fp, c->perm.p, c->psim.p,
+                                                 c->sims.p, c->node_map.p, pb->mat.rho0, pb->mat.g[0], pb->mat.g[1],
+                                                 pb->mat.g[2], c->fext.p);
+    }
+    LAUNCH_CHECK(c, "node volume / fext");
+  }
+  if (n_row > 0) {
+    k_cmask<<<nblk(n_row), TPB, 0, c->stream>>>(n_row, nd, c->active_nodes.p, pb->bc_mask, pb->bc_value,
+                                                pb->react_mask, c->nvol.p, c->cmask.p, c->cval.p, c->rmask.p);
+    LAUNCH_CHECK(c, "k_cmask");
+  }
+
+  // row blocks (never spanning two sims)
+  c->blocks_h.clear();
+  c->sim_blk_first.assign(nsim + 1, 0);
+  for (int s = 0; s < nsim; ++s) {
+    c->sim_blk_first[s] = (int32_t)c->blocks_h.size();
+    for (int64_t r = c->sim_row_start[s]; r < c->sim_row_start[s + 1]; r += ROWS_PER_BLOCK) {
+      RowBlock b;
+      b.sim = s;
+      b.row0 = (int32_t)r;
+      b.row1 = (int32_t)std::min<int64_t>(r + ROWS_PER_BLOCK, c->sim_row_start[s + 1]);
+      c->blocks_h.push_back(b);
+    }
+  }
+  c->sim_blk_first[nsim] = (int32_t)c->blocks_h.size();
+  size_t nbk = c->blocks_h.size();
+  ok = c->blocks.ensure(nbk) == hipSuccess && c->blk_first.ensure(nsim + 1) == hipSuccess &&
+       c->part.ensure((nbk + 1) * NQ) == hipSuccess && c->simsc.ensure(nsim * 16) == hipSuccess &&
+       c->simflag.ensure(nsim * 2) == hipSuccess;
+  if (!ok) return c->fail(MPM_E_NOMEM, "device allocation failed (blocks)");
+  if (nbk) HIPC(c, hipMemcpyAsync(c->blocks.p, c->blocks_h.data(), nbk * sizeof(RowBlock), hipMemcpyHostToDevice, c->stream));
+  HIPC(c, hipMemcpyAsync(c->blk_first.p, c->sim_blk_first.data(), (nsim + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
+                         c->stream));
+  HIPC(c, hipStreamSynchronize(c->stream));
+
+  c->user_x = pb->P.x;
+  c->prepared = true;
+  if (n_row_out) *n_row_out = n_row;
+  if (nnzb_out) *nnzb_out = c->nnzb;
+  if (nd_out) *nd_out = nd;
+  return MPM_OK;
+}

@@ -57,6 +57,7 @@ class Problem:
     biot: float = 1.0
     rho_f: float = 1000.0
     dt: float = 1.0
+    apex_reg: float = 1e-6          # tangent scale of apex returns (values are exact)
     name: str = ""
 
     @property

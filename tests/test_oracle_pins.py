@@ -313,6 +313,7 @@ def _tiny(dp=1, up=False, seed=4, amp=3e-3):
     else:
         w = W.small_footing(n_y=3, phi_deg=30.0)
         w.prob.dp = dp
+    w.prob.apex_reg = 0.0                     # exact derivative everywhere
     P, st = w.prob, w.particles
     rng = np.random.default_rng(seed)
     dof = rng.normal(size=(P.n_nodes, P.ndof)) * amp * P.h
@@ -358,6 +359,34 @@ def test_local_jacobian_equals_dense_and_fd(kind, golden):
         pass
     relfd = np.linalg.norm(Jfd - Jdc) / np.linalg.norm(Jdc)
     assert relfd < 1e-6, relfd
+
+
+def test_apex_regularisation_only_scales_apex_tangents():
+    """The apex tangent replacement is linear in apex_reg and touches only
+    blocks of nodes in the stencil of an apex particle; values are exact."""
+    P, st, dof = _tiny(dp=1, amp=2e-2)
+    reg = O.regimes(P, st, dof)
+    assert (reg == 2).sum() > 0
+    pat = O.pattern(P, st)
+    J = {}
+    for a in (0.0, 1e-3, 1.0):
+        P.apex_reg = a
+        J[a] = O.jacobian_bsr(P, st, dof, pat)
+    np.testing.assert_allclose(J[1e-3] - J[0.0], 1e-3 * (J[1.0] - J[0.0]), atol=1e-9 * np.abs(J[0.0]).max())
+    f1, _ = O.forces(P, st, dof)
+    P.apex_reg = 0.0
+    f0, _ = O.forces(P, st, dof)
+    np.testing.assert_array_equal(f0, f1)
+    o = O.origins(P, st)
+    npa = P.nodes_per_axis
+    touched = set()
+    for p in np.nonzero(reg == 2)[0]:
+        for b in range(3):
+            for a in range(3):
+                touched.add(int(pat.row_of_node[(o[0, p] + a + 1) + npa[0] * (o[1, p] + b + 1)]))
+    rows = np.repeat(np.arange(pat.n_row), np.diff(pat.rowptr))
+    diff = np.abs(J[1.0] - J[0.0]).reshape(pat.nnzb, -1).max(axis=1)
+    assert all(rows[k] in touched for k in np.nonzero(diff > 0)[0])
 
 
 def test_elastic_jacobian_symmetric():
