@@ -342,13 +342,13 @@ int mpm_newton_step(mpm_ctx* c, const mpm_problem* pb, const mpm_newton_opts* op
   return status;
 }
 
-int mpm_spmv(mpm_ctx* c, const double* val, const double* x, double* y) {
+int mpm_spmv(mpm_ctx* c, const double* val, const double* x, double* y, const double* z) {
   if (!c) return MPM_E_INVALID;
   c->err.clear();
   if (!c->prepared) return c->fail(MPM_E_INVALID, "mpm_prepare has not run");
-  if (!val || !x || !y || x == y) return c->fail(MPM_E_INVALID, "val, x, y are required and x, y must differ");
+  if (!val || !x || !y || x == y || z == y) return c->fail(MPM_E_INVALID, "val, x, y are required; y must not alias x or z");
   HIPC(c, hipSetDevice(c->device));
-  return launch_spmv(c, val, x, y);
+  return launch_spmv(c, val, x, y, z);
 }
 
 }  // extern "C"

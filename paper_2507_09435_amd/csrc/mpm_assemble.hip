@@ -277,45 +277,164 @@ __device__ __forceinline__ void tangent2(const AsmArgs& A, const PLoad<2>& L, co
   }
 }
 
+// ---------------------------------------------- group-cooperative 2-D ------
+// Particles of one stencil group (same origin) are adjacent after sorting.
+// A workgroup stages per-particle data in LDS, finds the group starts with a
+// ballot scan, and then one thread per (group, node) sums the group's
+// contributions in registers before a single atomic per entry.
+constexpr int GP = 128;   // particles (threads) per workgroup
+
+__device__ __forceinline__ int32_t origin_key2(const SimDev& S, const Stencil<2>& st) {
+  return (int32_t)(S.okey_base + (st.o[0] + 1) + (int64_t)S.noa[0] * (st.o[1] + 1));
+}
+
+// Group starts of the workgroup's particles (n valid).  Returns the number of
+// groups; gstart[g] = first local index of group g, gstart[G] = n.
+__device__ __forceinline__ int group_starts(const int32_t* key, int n, int32_t* gstart, int32_t* wave_cnt) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  bool head = t < n && (t == 0 || key[t] != key[t - 1]);
+  unsigned long long m = __ballot(head);
+  int before = __popcll(m & ((1ull << lane) - 1ull));
+  if (lane == 0) wave_cnt[wv] = __popcll(m);
+  __syncthreads();
+  int off = 0;
+  for (int w = 0; w < wv; ++w) off += wave_cnt[w];
+  if (head) gstart[off + before] = t;
+  int G = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) G += wave_cnt[w];
+  if (t == 0) gstart[G] = n;
+  __syncthreads();
+  return G;
+}
+
 template <int NIO>
-__global__ void __launch_bounds__(128) k_jac2(AsmArgs A, const double* __restrict__ du,
-                                              const int32_t* __restrict__ rowptr, const int8_t* __restrict__ slot,
-                                              double* __restrict__ val) {
+__global__ void __launch_bounds__(GP) k_jac2g(AsmArgs A, const double* __restrict__ du,
+                                             const int32_t* __restrict__ rowptr, const int8_t* __restrict__ slot,
+                                             double* __restrict__ val) {
   constexpr int ND = NIO == 7 ? 3 : 2;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A.np) return;
-  PLoad<2> L;
-  load_particle<2>(A, i, du, L);
-  double T[NIO][NIO];
-  tangent2<NIO>(A, L, load_be2(A, i), T);
-  const double v0 = L.v0;
-  for (int b = 0; b < 9; ++b) {
-    double gb[2];
-    L.st.grad(b, gb);
-    double wb = L.st.weight(b);
-    // Tb[out][c]: in-weights of node b applied to the table
-    double Tb[NIO][ND];
+  __shared__ double sT[GP][NIO * NIO];   // V0 * tangent table
+  __shared__ double sW[GP][2][3], sD[GP][2][3];
+  __shared__ int32_t sKey[GP], sRow[GP][9], sG[GP + 1], sWc[GP / 64];
+  const int64_t base = (int64_t)blockIdx.x * GP;
+  const int n = (int)min<int64_t>(GP, A.np - base);
+  const int t = threadIdx.x;
+  if (t < n) {
+    const int64_t i = base + t;
+    PLoad<2> L;
+    load_particle<2>(A, i, du, L);
+    double T[NIO][NIO];
+    tangent2<NIO>(A, L, load_be2(A, i), T);
 #pragma unroll
-    for (int o = 0; o < NIO; ++o) {
+    for (int o = 0; o < NIO; ++o)
 #pragma unroll
-      for (int m = 0; m < 2; ++m) Tb[o][m] = T[o][m * 2 + 0] * gb[0] + T[o][m * 2 + 1] * gb[1];
-      if constexpr (ND == 3) Tb[o][2] = T[o][4] * wb + T[o][5] * gb[0] + T[o][6] * gb[1];
-    }
-    for (int a = 0; a < 9; ++a) {
-      double ga[2];
-      L.st.grad(a, ga);
-      double wa = L.st.weight(a);
-      int32_t ra = L.row[a];
-      int s = slot[(int64_t)ra * 25 + nb_index<2>(a, b)];
-      double* blk = val + ((int64_t)rowptr[ra] + s) * (ND * ND);
+      for (int q = 0; q < NIO; ++q) sT[t][o * NIO + q] = L.v0 * T[o][q];
 #pragma unroll
-      for (int c = 0; c < ND; ++c) {
+    for (int k = 0; k < 2; ++k)
 #pragma unroll
-        for (int r = 0; r < 2; ++r) atomicAdd(&blk[r * ND + c], v0 * (ga[0] * Tb[r * 2 + 0][c] + ga[1] * Tb[r * 2 + 1][c]));
-        if constexpr (ND == 3)
-          atomicAdd(&blk[2 * ND + c], v0 * (wa * Tb[4][c] + ga[0] * Tb[5][c] + ga[1] * Tb[6][c]));
+      for (int a = 0; a < 3; ++a) { sW[t][k][a] = L.st.w[k][a]; sD[t][k][a] = L.st.dw[k][a]; }
+#pragma unroll
+    for (int a = 0; a < 9; ++a) sRow[t][a] = L.row[a];
+    sKey[t] = origin_key2(A.sims[A.psim[i]], L.st);
+  }
+  __syncthreads();
+  const int G = group_starts(sKey, n, sG, sWc);
+  for (int task = t; task < 9 * G; task += GP) {
+    const int g = task / 9, b = task % 9;
+    const int bx = b % 3, by = b / 3;
+    double acc[9][ND][ND];
+#pragma unroll
+    for (int a = 0; a < 9; ++a)
+#pragma unroll
+      for (int r = 0; r < ND; ++r)
+#pragma unroll
+        for (int c = 0; c < ND; ++c) acc[a][r][c] = 0.0;
+    for (int p = sG[g]; p < sG[g + 1]; ++p) {
+      const double* T = sT[p];
+      const double gb0 = sD[p][0][bx] * sW[p][1][by], gb1 = sW[p][0][bx] * sD[p][1][by];
+      double Tb[NIO][ND];
+#pragma unroll
+      for (int o = 0; o < NIO; ++o) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) Tb[o][m] = T[o * NIO + m * 2] * gb0 + T[o * NIO + m * 2 + 1] * gb1;
+        if constexpr (ND == 3) {
+          const double wb = sW[p][0][bx] * sW[p][1][by];
+          Tb[o][2] = T[o * NIO + 4] * wb + T[o * NIO + 5] * gb0 + T[o * NIO + 6] * gb1;
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        const int ax = a % 3, ay = a / 3;
+        const double ga0 = sD[p][0][ax] * sW[p][1][ay], ga1 = sW[p][0][ax] * sD[p][1][ay];
+#pragma unroll
+        for (int c = 0; c < ND; ++c) {
+#pragma unroll
+          for (int r = 0; r < 2; ++r) acc[a][r][c] += ga0 * Tb[r * 2][c] + ga1 * Tb[r * 2 + 1][c];
+          if constexpr (ND == 3) {
+            const double wa = sW[p][0][ax] * sW[p][1][ay];
+            acc[a][2][c] += wa * Tb[4][c] + ga0 * Tb[5][c] + ga1 * Tb[6][c];
+          }
+        }
       }
     }
+    const int p0 = sG[g];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      const int32_t ra = sRow[p0][a];
+      const int s = slot[(int64_t)ra * 25 + nb_index<2>(a, b)];
+      double* blk = val + ((int64_t)rowptr[ra] + s) * (ND * ND);
+#pragma unroll
+      for (int r = 0; r < ND; ++r)
+#pragma unroll
+        for (int c = 0; c < ND; ++c) atomicAdd(&blk[r * ND + c], acc[a][r][c]);
+    }
+  }
+}
+
+// Residual, 2-D, group-cooperative: per particle V0 P (and the u-p scalars),
+// then one thread per (group, node) sums the group and adds once.
+__global__ void __launch_bounds__(GP) k_fint2g(AsmArgs A, const double* __restrict__ du, double* __restrict__ fint) {
+  __shared__ double sP[GP][7];          // V0 P (4), V0 s1, V0 vv (2)
+  __shared__ double sW[GP][2][3], sD[GP][2][3];
+  __shared__ int32_t sKey[GP], sRow[GP][9], sG[GP + 1], sWc[GP / 64];
+  const int64_t base = (int64_t)blockIdx.x * GP;
+  const int n = (int)min<int64_t>(GP, A.np - base);
+  const int t = threadIdx.x;
+  if (t < n) {
+    const int64_t i = base + t;
+    PLoad<2> L;
+    load_particle<2>(A, i, du, L);
+    Mat<double> m = make_mat<double>(L.E, A.nu, L.phi, A.c, A.psi, A.dp, A.match, A.apex_reg);
+    Out2<double> o;
+    mech2<double>(m, L.dF, load_be2(A, i), L.Jn, A.up, up_par(A), L.pp, L.gp, o, nullptr);
+    sP[t][0] = L.v0 * o.P[0][0]; sP[t][1] = L.v0 * o.P[0][1];
+    sP[t][2] = L.v0 * o.P[1][0]; sP[t][3] = L.v0 * o.P[1][1];
+    sP[t][4] = A.up ? L.v0 * o.s1 : 0.0;
+    sP[t][5] = A.up ? L.v0 * o.vv[0] : 0.0;
+    sP[t][6] = A.up ? L.v0 * o.vv[1] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) { sW[t][k][a] = L.st.w[k][a]; sD[t][k][a] = L.st.dw[k][a]; }
+#pragma unroll
+    for (int a = 0; a < 9; ++a) sRow[t][a] = L.row[a];
+    sKey[t] = origin_key2(A.sims[A.psim[i]], L.st);
+  }
+  __syncthreads();
+  const int G = group_starts(sKey, n, sG, sWc);
+  const int nd = A.nd;
+  for (int task = t; task < 9 * G; task += GP) {
+    const int g = task / 9, a = task % 9, ax = a % 3, ay = a / 3;
+    double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+    for (int p = sG[g]; p < sG[g + 1]; ++p) {
+      const double ga0 = sD[p][0][ax] * sW[p][1][ay], ga1 = sW[p][0][ax] * sD[p][1][ay];
+      f0 += sP[p][0] * ga0 + sP[p][1] * ga1;
+      f1 += sP[p][2] * ga0 + sP[p][3] * ga1;
+      if (A.up) f2 += sW[p][0][ax] * sW[p][1][ay] * sP[p][4] + ga0 * sP[p][5] + ga1 * sP[p][6];
+    }
+    double* f = fint + (int64_t)sRow[sG[g]][a] * nd;
+    atomicAdd(&f[0], f0);
+    atomicAdd(&f[1], f1);
+    if (A.up) atomicAdd(&f[2], f2);
   }
 }
 
@@ -485,8 +604,12 @@ int launch_fint(mpm_ctx* c, const mpm_problem* pb, const double* du) {
   AsmArgs A = make_args(c, pb);
   HIPC(c, hipMemsetAsync(c->fint.p, 0, c->n_row * c->nd * sizeof(double), c->stream));
   if (c->np == 0) return MPM_OK;
-  if (c->dim == 2) k_fint<2><<<nb256(c->np), 256, 0, c->stream>>>(A, du, c->fint.p, c->flag.p);
-  else k_fint<3><<<nb256(c->np), 256, 0, c->stream>>>(A, du, c->fint.p, c->flag.p);
+  if (c->dim == 2) {
+    unsigned g = (unsigned)((c->np + GP - 1) / GP);
+    k_fint2g<<<g, GP, 0, c->stream>>>(A, du, c->fint.p);
+  } else {
+    k_fint<3><<<nb256(c->np), 256, 0, c->stream>>>(A, du, c->fint.p, c->flag.p);
+  }
   LAUNCH_CHECK(c, "k_fint");
   return MPM_OK;
 }
@@ -521,8 +644,9 @@ int launch_jacobian(mpm_ctx* c, const mpm_problem* pb, const double* du, double*
   HIPC(c, hipMemsetAsync(val, 0, c->nnzb * nd * nd * sizeof(double), c->stream));
   if (c->np > 0) {
     unsigned g = (unsigned)std::max<int64_t>(1, (c->np + 127) / 128);
-    if (c->dim == 2 && !c->up) k_jac2<4><<<g, 128, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val);
-    else if (c->dim == 2) k_jac2<7><<<g, 128, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val);
+    unsigned gg = (unsigned)((c->np + GP - 1) / GP);
+    if (c->dim == 2 && !c->up) k_jac2g<4><<<gg, GP, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val);
+    else if (c->dim == 2) k_jac2g<7><<<gg, GP, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val);
     else k_jac3<<<g, 128, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val, c->flag.p);
     LAUNCH_CHECK(c, "k_jac");
   }

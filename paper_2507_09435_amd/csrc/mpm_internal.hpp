@@ -92,5 +92,5 @@ int launch_residual(mpm_ctx* c, const mpm_problem* pb, const double* du, double*
 int launch_jacobian(mpm_ctx* c, const mpm_problem* pb, const double* du, double* val, bool apply_bc);
 int launch_update(mpm_ctx* c, const mpm_problem* pb, const double* du, double* x, double* F, double* be);
 int launch_bj_inv(mpm_ctx* c, const double* val);
-int launch_spmv(mpm_ctx* c, const double* val, const double* x, double* y);
+int launch_spmv(mpm_ctx* c, const double* val, const double* x, double* y, const double* z);
 int krylov_solve(mpm_ctx* c, const double* val, double rtol, int max_iter, std::vector<int>& iters_out);

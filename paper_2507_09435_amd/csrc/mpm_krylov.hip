@@ -20,11 +20,23 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum of part[b*NQ + q] over the row blocks of a sim, by one 64-lane wave.
+// Sum of part[b*NQ + q] (and q + 1) over the row blocks of a sim, by one
+// 64-lane wave; four independent accumulators keep several loads in flight,
+// and the lane assignment and combine order are fixed (deterministic).
+__device__ __forceinline__ double2 sim_sum2(const double* __restrict__ part, int q, int b0, int b1) {
+  double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0, y0 = 0.0, y1 = 0.0, y2 = 0.0, y3 = 0.0;
+  int b = b0 + (int)threadIdx.x % 64;
+  for (; b + 192 < b1; b += 256) {
+    x0 += part[b * NQ + q];          y0 += part[b * NQ + q + 1];
+    x1 += part[(b + 64) * NQ + q];   y1 += part[(b + 64) * NQ + q + 1];
+    x2 += part[(b + 128) * NQ + q];  y2 += part[(b + 128) * NQ + q + 1];
+    x3 += part[(b + 192) * NQ + q];  y3 += part[(b + 192) * NQ + q + 1];
+  }
+  for (; b < b1; b += 64) { x0 += part[b * NQ + q]; y0 += part[b * NQ + q + 1]; }
+  return make_double2(wave_sum((x0 + x1) + (x2 + x3)), wave_sum((y0 + y1) + (y2 + y3)));
+}
 __device__ __forceinline__ double sim_sum(const double* __restrict__ part, int q, int b0, int b1) {
-  double acc = 0.0;
-  for (int b = b0 + (int)threadIdx.x % 64; b < b1; b += 64) acc += part[b * NQ + q];
-  return wave_sum(acc);
+  return sim_sum2(part, q, b0, b1).x;
 }
 
 template <int BS>
@@ -194,8 +206,8 @@ __global__ void __launch_bounds__(64) k_bicg_a(const RowBlock* __restrict__ bloc
   const int s = b.sim;
   if (flag[2 * s] >= 0) return;
   const int b0 = blk_first[s], b1 = blk_first[s + 1];
-  double rho = sim_sum(part, 0, b0, b1);
-  double rr = sim_sum(part, 1, b0, b1);
+  const double2 sums = sim_sum2(part, 0, b0, b1);
+  const double rho = sums.x, rr = sums.y;
   double* S = sc + s * 16;
   const bool lead = (blockIdx.x == (unsigned)b0) && threadIdx.x == 0;
   if (rr <= S[SC_TOL2]) {
@@ -260,8 +272,8 @@ __global__ void __launch_bounds__(64) k_bicg_e(const RowBlock* __restrict__ bloc
   const int s = b.sim;
   if (flag[2 * s] >= 0) return;
   const int b0 = blk_first[s], b1 = blk_first[s + 1];
-  double ts = sim_sum(part_ts, 0, b0, b1);
-  double tt = sim_sum(part_ts, 1, b0, b1);
+  const double2 sums = sim_sum2(part_ts, 0, b0, b1);
+  const double ts = sums.x, tt = sums.y;
   double* S = sc + s * 16;
   double alpha = S[SC_ALPHA];
   double omega = tt > 0.0 ? ts / tt : 0.0;
@@ -325,8 +337,9 @@ static int spmv(mpm_ctx* c, const int32_t* simflag, const double* val, const dou
   return spmv_launch<3, 64>(c, simflag, val, x, y, z1, part, q1, q2);
 }
 
-int launch_spmv(mpm_ctx* c, const double* val, const double* x, double* y) {
-  return spmv(c, nullptr, val, x, y, nullptr, nullptr, -1, -1);
+int launch_spmv(mpm_ctx* c, const double* val, const double* x, double* y, const double* z) {
+  if (!z) return spmv(c, nullptr, val, x, y, nullptr, nullptr, -1, -1);
+  return spmv(c, nullptr, val, x, y, z, c->part.p, 2, 3);
 }
 
 int launch_bj_inv(mpm_ctx* c, const double* val) {

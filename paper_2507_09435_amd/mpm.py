@@ -93,7 +93,7 @@ def load():
         "mpm_newton_step": ([P, C.POINTER(mpm_problem), C.POINTER(mpm_newton_opts), P,
                              C.POINTER(mpm_newton_report)], C.c_int),
         "mpm_update": ([P, C.POINTER(mpm_problem), P, P, P, P], C.c_int),
-        "mpm_spmv": ([P, P, P, P], C.c_int),
+        "mpm_spmv": ([P, P, P, P, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -268,5 +268,5 @@ def mpm_update(ctx, dp: DeviceProblem, du, x_out, F_out, be_out):
     _check(ctx, load().mpm_update(ctx, C.byref(dp.struct), _ptr(du), _ptr(x_out), _ptr(F_out), _ptr(be_out)))
 
 
-def mpm_spmv(ctx, val, x, y):
-    _check(ctx, load().mpm_spmv(ctx, _ptr(val), _ptr(x), _ptr(y)))
+def mpm_spmv(ctx, val, x, y, z=None):
+    _check(ctx, load().mpm_spmv(ctx, _ptr(val), _ptr(x), _ptr(y), _ptr(z)))
