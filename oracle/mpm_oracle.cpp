@@ -528,6 +528,41 @@ int local_jacobian(const Cfg& c, const Particles& P, int64_t p, const double* do
   return reg;
 }
 
+// Particle state with forward tangents in two directions (for the
+// sensitivity of a whole simulation to two material parameters).
+struct Tangents {
+  const double* x;      // [2][dim][np]
+  const double* F;      // [2][dim*dim][np]
+  const double* be;     // [2][nb][np]
+  const double* theta;  // [2][2]: per direction, seeds of (E, phi)
+};
+
+inline PState<Dual<2>> load_particle_tan(const Cfg& c, const Particles& P, const Tangents& T, int64_t p) {
+  using D = Dual<2>;
+  PState<D> s = load_particle<D>(c, P, p);
+  const int d = c.dim, nb = d == 2 ? 4 : 6;
+  const int64_t np = P.np;
+  for (int k = 0; k < 2; ++k) {
+    for (int i = 0; i < d; ++i) s.x[i].d[k] = T.x[(k * d + i) * np + p];
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) s.F.a[i][j].d[k] = T.F[(k * d * d + i * d + j) * np + p];
+    double b[6];
+    for (int q = 0; q < nb; ++q) b[q] = T.be[(k * nb + q) * np + p];
+    if (d == 2) {
+      s.be.a[0][0].d[k] = b[0]; s.be.a[1][1].d[k] = b[1]; s.be.a[0][1].d[k] = s.be.a[1][0].d[k] = b[2];
+      s.be.a[2][2].d[k] = b[3];
+    } else {
+      s.be.a[0][0].d[k] = b[0]; s.be.a[1][1].d[k] = b[1]; s.be.a[2][2].d[k] = b[2];
+      s.be.a[1][2].d[k] = s.be.a[2][1].d[k] = b[3];
+      s.be.a[0][2].d[k] = s.be.a[2][0].d[k] = b[4];
+      s.be.a[0][1].d[k] = s.be.a[1][0].d[k] = b[5];
+    }
+    s.E.d[k] = T.theta[k * 2 + 0];
+    s.phi.d[k] = T.theta[k * 2 + 1];
+  }
+  return s;
+}
+
 }  // namespace orc
 
 using namespace orc;
@@ -693,6 +728,81 @@ int orc_stress(const Cfg* c, const Particles* P, const double* dof_full, double*
     int reg = hencky_dp(*c, s.E, s.phi, eps, tau, ee);
     for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) tau_out[(i * 3 + j) * P->np + p] = tau.a[i][j];
     if (regime) regime[p] = reg;
+  }
+  return 0;
+}
+
+// Forces and their tangents in two directions: the particle state carries
+// tangents T, the unknowns carry dof_t ([2][n_nodes*ndof]).
+// Outputs fint/fext (values) and fint_t/fext_t ([2][n_nodes*ndof]).
+int orc_forces_tan(const Cfg* c, const Particles* P, const Tangents* T, const double* dof_full, const double* dof_t,
+                   double* fint, double* fext, double* fint_t, double* fext_t) {
+  using D = Dual<2>;
+  const int nd = ndof_of(*c);
+  const int64_t ntot = n_nodes(*c) * nd;
+  std::memset(fint, 0, sizeof(double) * ntot);
+  std::memset(fext, 0, sizeof(double) * ntot);
+  std::memset(fint_t, 0, sizeof(double) * 2 * ntot);
+  std::memset(fext_t, 0, sizeof(double) * 2 * ntot);
+  for (int64_t p = 0; p < P->np; ++p) {
+    PState<D> s = load_particle_tan(*c, *P, *T, p);
+    Stencil<D> st = make_stencil(*c, s);
+    D du[27 * 4], fi[27 * 4], fe[27 * 4];
+    for (int a = 0; a < st.nn; ++a)
+      for (int k = 0; k < nd; ++k) {
+        int64_t gi = st.node[a] * nd + k;
+        du[a * nd + k] = D(dof_full[gi]);
+        du[a * nd + k].d[0] = dof_t[gi];
+        du[a * nd + k].d[1] = dof_t[ntot + gi];
+      }
+    eval_particle(*c, s, st, du, fi, fe, (PState<D>*)nullptr);
+    for (int a = 0; a < st.nn; ++a)
+      for (int k = 0; k < nd; ++k) {
+        int64_t gi = st.node[a] * nd + k;
+        fint[gi] += fi[a * nd + k].v;
+        fext[gi] += fe[a * nd + k].v;
+        for (int q = 0; q < 2; ++q) {
+          fint_t[q * ntot + gi] += fi[a * nd + k].d[q];
+          fext_t[q * ntot + gi] += fe[a * nd + k].d[q];
+        }
+      }
+  }
+  return 0;
+}
+
+// End-of-step update with tangents: new state and its two tangent sets.
+int orc_update_tan(const Cfg* c, const Particles* P, const Tangents* T, const double* dof_full, const double* dof_t,
+                   double* x_out, double* F_out, double* be_out, double* x_t, double* F_t, double* be_t) {
+  using D = Dual<2>;
+  const int nd = ndof_of(*c), d = c->dim, nb = d == 2 ? 4 : 6;
+  const int64_t ntot = n_nodes(*c) * nd, np = P->np;
+  for (int64_t p = 0; p < np; ++p) {
+    PState<D> s = load_particle_tan(*c, *P, *T, p);
+    Stencil<D> st = make_stencil(*c, s);
+    D du[27 * 4];
+    for (int a = 0; a < st.nn; ++a)
+      for (int k = 0; k < nd; ++k) {
+        int64_t gi = st.node[a] * nd + k;
+        du[a * nd + k] = D(dof_full[gi]);
+        du[a * nd + k].d[0] = dof_t[gi];
+        du[a * nd + k].d[1] = dof_t[ntot + gi];
+      }
+    PState<D> sn;
+    eval_particle(*c, s, st, du, (D*)nullptr, (D*)nullptr, &sn);
+    store_state(*c, sn, p, np, x_out, F_out, be_out);
+    for (int q = 0; q < 2; ++q) {
+      for (int i = 0; i < d; ++i) x_t[(q * d + i) * np + p] = sn.x[i].d[q];
+      for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) F_t[(q * d * d + i * d + j) * np + p] = sn.F.a[i][j].d[q];
+      double b[6];
+      if (d == 2) {
+        b[0] = sn.be.a[0][0].d[q]; b[1] = sn.be.a[1][1].d[q]; b[2] = sn.be.a[0][1].d[q]; b[3] = sn.be.a[2][2].d[q];
+      } else {
+        b[0] = sn.be.a[0][0].d[q]; b[1] = sn.be.a[1][1].d[q]; b[2] = sn.be.a[2][2].d[q];
+        b[3] = sn.be.a[1][2].d[q]; b[4] = sn.be.a[0][2].d[q]; b[5] = sn.be.a[0][1].d[q];
+      }
+      for (int k = 0; k < nb; ++k) be_t[(q * nb + k) * np + p] = b[k];
+    }
   }
   return 0;
 }

@@ -59,6 +59,10 @@ class _Particles(C.Structure):
                 ("be", C.c_void_p), ("fp", C.c_void_p), ("E", C.c_void_p), ("phi", C.c_void_p)]
 
 
+class _Tangents(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("F", C.c_void_p), ("be", C.c_void_p), ("theta", C.c_void_p)]
+
+
 _lib = None
 
 
@@ -79,6 +83,8 @@ def lib():
             ("orc_return_map", [P, C.c_double, C.c_double, P, P, P]),
             ("orc_return_map_dir", [P, C.c_double, C.c_double, P, P, P, P]),
             ("orc_bspline", [C.c_double, C.c_int64, P, P]),
+            ("orc_forces_tan", [P, P, P, P, P, P, P, P, P]),
+            ("orc_update_tan", [P, P, P, P, P, P, P, P, P, P, P]),
         ]:
             fn = getattr(_lib, name)
             fn.argtypes = args
@@ -415,3 +421,87 @@ def _block_diag_csr(inv):
     n, nd, _ = inv.shape
     indptr = np.arange(n + 1) * 1
     return sp.bsr_matrix((inv, np.arange(n), indptr), shape=(n * nd, n * nd)).tocsr()
+
+
+# ------------------------------------------------- forward sensitivity -----
+@dataclass
+class StateTangent:
+    """Tangents of the particle state in two directions (E, phi)."""
+    x: np.ndarray     # [2][dim][np]
+    F: np.ndarray     # [2][dim*dim][np]
+    be: np.ndarray    # [2][nb][np]
+
+    @staticmethod
+    def zeros(dim, np_):
+        nb = 4 if dim == 2 else 6
+        return StateTangent(np.zeros((2, dim, np_)), np.zeros((2, dim * dim, np_)), np.zeros((2, nb, np_)))
+
+
+_THETA = np.ascontiguousarray(np.eye(2))   # direction 0 seeds E, direction 1 seeds phi
+
+
+def _tan_struct(tan):
+    arrs = [np.ascontiguousarray(tan.x), np.ascontiguousarray(tan.F), np.ascontiguousarray(tan.be), _THETA]
+    return arrs, _Tangents(*[_ptr(a) for a in arrs])
+
+
+def forces_tan(prob, st, tan, dof_full, dof_t):
+    """f_int, f_ext and their tangents [2][n_nodes][ndof] (full grid)."""
+    nd = ndof(prob)
+    nn = n_nodes(prob) * nd
+    dof = np.ascontiguousarray(dof_full, dtype=np.float64).reshape(-1)
+    dt = np.ascontiguousarray(dof_t, dtype=np.float64).reshape(-1)
+    fi, fe = np.zeros(nn), np.zeros(nn)
+    fit, fet = np.zeros(2 * nn), np.zeros(2 * nn)
+    c, P = cfg(prob), _PartRef(st)
+    keep, T = _tan_struct(tan)
+    lib().orc_forces_tan(C.byref(c), C.byref(P.s), C.byref(T), _ptr(dof), _ptr(dt), _ptr(fi), _ptr(fe), _ptr(fit),
+                         _ptr(fet))
+    return fi.reshape(-1, nd), fe.reshape(-1, nd), fit.reshape(2, -1, nd), fet.reshape(2, -1, nd)
+
+
+def update_tan(prob, st, tan, dof_full, dof_t):
+    new = st.copy()
+    new.x = np.ascontiguousarray(new.x); new.F = np.ascontiguousarray(new.F); new.be = np.ascontiguousarray(new.be)
+    nt = StateTangent.zeros(prob.dim, st.vol0.shape[0])
+    dof = np.ascontiguousarray(dof_full, dtype=np.float64).reshape(-1)
+    dt = np.ascontiguousarray(dof_t, dtype=np.float64).reshape(-1)
+    c, P = cfg(prob), _PartRef(st)
+    keep, T = _tan_struct(tan)
+    lib().orc_update_tan(C.byref(c), C.byref(P.s), C.byref(T), _ptr(dof), _ptr(dt), _ptr(new.x), _ptr(new.F),
+                         _ptr(new.be), _ptr(nt.x), _ptr(nt.F), _ptr(nt.be))
+    return new, nt
+
+
+def simulate_sensitivity(prob, st0, bcs, react_nodes, react_dof, tol=1e-12, line_search=0):
+    """Run load steps with Newton and carry forward sensitivities of the
+    reaction to the two material parameters (E, phi) shared by all particles.
+
+    Per step: converged du; the tangent d(du)/d(theta) solves
+    J d(du) = -(dr/ds . ds/dtheta + dr/dtheta) on the free unknowns (the
+    implicit function of r(du; s, theta) = 0); the reaction and the state
+    update are then differentiated along (d(du), ds, e_theta).
+    Returns (reactions [n_steps], dR/dtheta [n_steps][2], final state)."""
+    import scipy.sparse.linalg as spla
+    nd = ndof(prob)
+    st = st0.copy()
+    tan = StateTangent.zeros(prob.dim, st.vol0.shape[0])
+    R, dR = [], []
+    for bc in bcs:
+        dof, rep, pat = newton(prob, st, bc.mask, bc.value, tol=tol, line_search=line_search)
+        if not rep.converged:
+            raise RuntimeError("oracle Newton did not converge in the sensitivity run")
+        cm = constrained(prob, st, pat, bc.mask)
+        A = apply_dirichlet(bsr_to_scipy(pat, jacobian_bsr(prob, st, dof, pat), nd), cm.reshape(-1)).tocsc()
+        zero_t = np.zeros((2, n_nodes(prob), nd))
+        _, _, fit, fet = forces_tan(prob, st, tan, dof, zero_t)
+        ddu = np.zeros((2, n_nodes(prob), nd))
+        for k in range(2):
+            rt = (fit[k] - fet[k])[pat.active]
+            rt[cm] = 0.0
+            ddu[k][pat.active] = spla.spsolve(A, -rt.reshape(-1)).reshape(-1, nd)
+        fi, fe, fit, fet = forces_tan(prob, st, tan, dof, ddu)
+        R.append(-(fi - fe)[react_nodes, react_dof].sum())
+        dR.append([-(fit[k] - fet[k])[react_nodes, react_dof].sum() for k in range(2)])
+        st, tan = update_tan(prob, st, tan, dof, ddu)
+    return np.array(R), np.array(dR), st

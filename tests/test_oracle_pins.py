@@ -585,3 +585,49 @@ def test_up_consolidation_paper_e4(golden):
             checks[step] = np.abs(pp - pt).max() / g["load_Pa"]
         st = O.update(P, st, dof)
     assert all(v < 0.02 for v in checks.values()), checks
+
+
+# ------------------------------------------------ forward sensitivity -------
+def _plastic_footing(n_y=6, E=1e7, phi_deg=30.0, steps=3):
+    """Footing reading used for gradients: cohesion 1 kPa, associated flow,
+    0.1 mm pushes (a path Newton follows; see the design notes)."""
+    w = W.small_footing(n_y=n_y, E=E, phi_deg=phi_deg)
+    w.prob.c = 1e3
+    w.prob.psi = w.prob.phi
+    w.footing = (w.footing[0], w.footing[1], w.footing[2], -1e-4)
+    bcs = [w.bc(k) for k in range(0, steps + 1)]
+    return w, bcs
+
+
+def _run_reactions(prob, st, bcs, fn, dof_):
+    R = []
+    regs = []
+    for bc in bcs:
+        dof, rep, _ = O.newton(prob, st, bc.mask, bc.value, tol=1e-13)
+        assert rep.converged
+        fint, fext = O.forces(prob, st, dof)
+        R.append(-(fint - fext)[fn, dof_].sum())
+        regs.append(O.regimes(prob, st, dof))
+        st = O.update(prob, st, dof)
+    return np.array(R), regs
+
+
+def test_forward_sensitivity_matches_central_fd():
+    """d(reaction_n)/d(E, phi) through geostatic + footing steps against
+    central differences of the whole run (regimes identical at +-delta)."""
+    import dataclasses
+    w, bcs = _plastic_footing()
+    P, st = w.prob, w.particles
+    fn = w.footing_nodes()
+    R, dR, _ = O.simulate_sensitivity(P, st, bcs, fn, 1)
+    R0, regs0 = _run_reactions(P, st, bcs, fn, 1)
+    np.testing.assert_allclose(R, R0, rtol=1e-9, atol=1e-9 * np.abs(R0).max())
+    assert any((r == 1).sum() > 0 for r in regs0)            # plasticity is active
+    for k, (name, delta) in enumerate([("E", 1e-6 * P.E), ("phi", 1e-6)]):
+        Rp, rp = _run_reactions(dataclasses.replace(P, **{name: getattr(P, name) + delta}), st, bcs, fn, 1)
+        Rm, rm = _run_reactions(dataclasses.replace(P, **{name: getattr(P, name) - delta}), st, bcs, fn, 1)
+        assert all(np.array_equal(a, b) for a, b in zip(rp, rm))
+        fd = (Rp - Rm) / (2 * delta)
+        scale = np.abs(fd).max()
+        assert scale > 0
+        np.testing.assert_allclose(dR[:, k], fd, rtol=1e-5, atol=1e-5 * scale)
