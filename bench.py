@@ -150,7 +150,7 @@ def main():
         "ms_residual_per_eval": round(ms_res / n_res, 4),
         "ms_jacobian_per_eval": round(ms_jac / max(n_jac, 1), 4),
         "ms_krylov_per_newton_iter": round(ms_kry / max(n_jac, 1), 3),
-        "roofline": {"kernel": "k_spmv<2,32> (BSR SpMV in BiCGStab)", "bound": "hbm",
+        "roofline": {"kernel": "k_spmv<2,8> (BSR SpMV in BiCGStab)", "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "avg_launch_us": round(spmv_us, 3), "timed_launches": nrep,

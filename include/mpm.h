@@ -195,6 +195,23 @@ int mpm_newton_step(mpm_ctx *ctx, const mpm_problem *prob, const mpm_newton_opts
 int mpm_update(mpm_ctx *ctx, const mpm_problem *prob, const double *du, double *x_out, double *F_out,
                double *be_out);
 
+/* Adjoint of one converged load step (plane strain, single-phase): the
+ * gradient the paper obtains by reverse AD through its whole-run tape
+ * (Sec. 4.5), here by one transposed solve per step.  prob: the state s_n
+ * at the start of the step, prepared with mpm_prepare; du: that step's
+ * converged compact increment.  Inputs: react_bar (host [nsim]) = dL/dR_n of
+ * the step's reaction (R = -sum of the raw residual over react_mask);
+ * sbar_next (device [10][np] in caller order: x (2), F (4), b^e (4)) =
+ * dL/ds_{n+1}, or NULL for zero.  Outputs: sbar_n (device [10][np], may be
+ * NULL) = dL/ds_n; theta_bar (device [nsim][2]) = this step's contribution
+ * to dL/dE and dL/dphi of each sim (E, phi per particle, summed per sim).
+ * The transposed system uses the step's Dirichlet-modified Jacobian; its
+ * solve runs to krylov_rtol (0: 1e-12); krylov_iters (host [nsim] or NULL).
+ * Errors: INVALID (not prepared, 3-D or u-p), NOMEM, KRYLOV, HIP. */
+int mpm_adjoint_step(mpm_ctx *ctx, const mpm_problem *prob, const double *du, const double *react_bar,
+                     const double *sbar_next, double *sbar_n, double *theta_bar, double krylov_rtol,
+                     int32_t *krylov_iters);
+
 /* y = J x with the BSR values val of this load step's pattern (the
  * matrix-vector product that drives the Krylov solve).  val [nnzb][ndof][ndof]
  * as returned by mpm_jacobian_bsr; x, y compact [n_row*ndof], must not

@@ -115,6 +115,8 @@ int mpm_destroy(mpm_ctx* c) {
   c->kx.release(); c->kr.release(); c->krh.release(); c->kp.release(); c->kv.release(); c->ks.release();
   c->kt.release(); c->kph.release(); c->ksh.release(); c->kb.release(); c->part.release(); c->simsc.release();
   c->simflag.release(); c->du_base.release(); c->alpha.release();
+  c->tpos.release(); c->dinvT.release(); c->adj_mu.release(); c->adj_nu.release(); c->adj_theta.release();
+  c->adj_rbar.release();
   delete c;
   return MPM_OK;
 }

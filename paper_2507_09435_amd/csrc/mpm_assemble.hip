@@ -23,92 +23,8 @@ struct AsmArgs {
   double biot, mob, dt, rho_f, g[3];
 };
 
-struct UpPar { double biot, mob, dt, rho_f, g[3]; };
-
 __device__ __forceinline__ UpPar up_par(const AsmArgs& A) {
   return UpPar{A.biot, A.mob, A.dt, A.rho_f, {A.g[0], A.g[1], A.g[2]}};
-}
-
-// -------------------------------------------------------- 2-D particle -----
-template <class S>
-struct Out2 { S P[2][2]; S s1; S vv[2]; };
-
-template <class S>
-__device__ __forceinline__ int mech2(const Mat<S>& m, const S F[2][2], const Sym2<S>& be, S Jn, int up, const UpPar& u,
-                                     S pp, const S gp[2], Out2<S>& o, Sym2<S>* ee_out) {
-  S m00 = F[0][0] * be.xx + F[0][1] * be.xy, m01 = F[0][0] * be.xy + F[0][1] * be.yy;
-  S m10 = F[1][0] * be.xx + F[1][1] * be.xy, m11 = F[1][0] * be.xy + F[1][1] * be.yy;
-  Sym2<S> bt;
-  bt.xx = m00 * F[0][0] + m01 * F[0][1];
-  bt.yy = m10 * F[1][0] + m11 * F[1][1];
-  bt.xy = m00 * F[1][0] + m01 * F[1][1];
-  bt.zz = be.zz;
-  Sym2<S> eps = hencky2(bt);
-  Sym2<S> tau, ee;
-  int reg = stress2(m, eps, tau, ee);
-  S det = F[0][0] * F[1][1] - F[0][1] * F[1][0];
-  S idet = 1.0 / det;
-  S it00 = F[1][1] * idet, it01 = -1.0 * F[1][0] * idet, it10 = -1.0 * F[0][1] * idet, it11 = F[0][0] * idet;
-  S J = det * Jn;
-  if (up) {
-    S bp = u.biot * J * pp;
-    tau.xx -= bp; tau.yy -= bp; tau.zz -= bp;
-  }
-  o.P[0][0] = tau.xx * it00 + tau.xy * it10;
-  o.P[0][1] = tau.xx * it01 + tau.xy * it11;
-  o.P[1][0] = tau.xy * it00 + tau.yy * it10;
-  o.P[1][1] = tau.xy * it01 + tau.yy * it11;
-  if (up) {
-    o.s1 = u.biot * s_log(det) * J;
-    S q0 = u.mob * (it00 * gp[0] + it01 * gp[1] - u.rho_f * u.g[0]);
-    S q1 = u.mob * (it10 * gp[0] + it11 * gp[1] - u.rho_f * u.g[1]);
-    o.vv[0] = u.dt * (it00 * q0 + it10 * q1) * J;
-    o.vv[1] = u.dt * (it01 * q0 + it11 * q1) * J;
-  }
-  if (ee_out) *ee_out = ee;
-  return reg;
-}
-
-// -------------------------------------------------------- 3-D particle -----
-template <class S>
-struct Out3 { S P[3][3]; };
-
-template <class S>
-__device__ __forceinline__ int mech3(const Mat<S>& m, const S F[3][3], const Sym3<S>& be, Out3<S>& o, Sym3<S>* ee_out,
-                                     int* range_err) {
-  S M[3][3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) M[i][j] = F[i][0] * sget(be, 0, j) + F[i][1] * sget(be, 1, j) + F[i][2] * sget(be, 2, j);
-  Sym3<S> bt;
-  const int I[6] = {0, 1, 2, 1, 0, 0}, Jx[6] = {0, 1, 2, 2, 2, 1};
-#pragma unroll
-  for (int t = 0; t < 6; ++t)
-    bt.a[t] = M[I[t]][0] * F[Jx[t]][0] + M[I[t]][1] * F[Jx[t]][1] + M[I[t]][2] * F[Jx[t]][2];
-  Sym3<S> eps = hencky3(bt, range_err);
-  Sym3<S> tau, ee;
-  int reg = stress3(m, eps, tau, ee);
-  // dF^-T = cofactor(dF) / det
-  S cof[3][3];
-  cof[0][0] = F[1][1] * F[2][2] - F[1][2] * F[2][1];
-  cof[0][1] = F[1][2] * F[2][0] - F[1][0] * F[2][2];
-  cof[0][2] = F[1][0] * F[2][1] - F[1][1] * F[2][0];
-  cof[1][0] = F[0][2] * F[2][1] - F[0][1] * F[2][2];
-  cof[1][1] = F[0][0] * F[2][2] - F[0][2] * F[2][0];
-  cof[1][2] = F[0][1] * F[2][0] - F[0][0] * F[2][1];
-  cof[2][0] = F[0][1] * F[1][2] - F[0][2] * F[1][1];
-  cof[2][1] = F[0][2] * F[1][0] - F[0][0] * F[1][2];
-  cof[2][2] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
-  S det = F[0][0] * cof[0][0] + F[0][1] * cof[0][1] + F[0][2] * cof[0][2];
-  S idet = 1.0 / det;
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-      o.P[i][j] = (sget(tau, i, 0) * cof[0][j] + sget(tau, i, 1) * cof[1][j] + sget(tau, i, 2) * cof[2][j]) * idet;
-  if (ee_out) *ee_out = ee;
-  return reg;
 }
 
 // ------------------------------------------------------ per-particle load ---
@@ -171,43 +87,6 @@ __device__ __forceinline__ Sym3<double> load_be3(const AsmArgs& A, int64_t i) {
 #pragma unroll
   for (int t = 0; t < 6; ++t) b.a[t] = A.bes[t * A.np + i];
   return b;
-}
-
-// ----------------------------------------------------------- residual ------
-template <int DIM>
-__global__ void __launch_bounds__(256) k_fint(AsmArgs A, const double* __restrict__ du, double* __restrict__ fint,
-                                              int32_t* __restrict__ flag) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A.np) return;
-  PLoad<DIM> L;
-  load_particle<DIM>(A, i, du, L);
-  Mat<double> m = make_mat<double>(L.E, A.nu, L.phi, A.c, A.psi, A.dp, A.match, A.apex_reg);
-  const int nd = A.nd;
-  if constexpr (DIM == 2) {
-    Out2<double> o;
-    double F[2][2] = {{L.dF[0][0], L.dF[0][1]}, {L.dF[1][0], L.dF[1][1]}};
-    mech2<double>(m, F, load_be2(A, i), L.Jn, A.up, up_par(A), L.pp, L.gp, o, nullptr);
-    for (int a = 0; a < 9; ++a) {
-      double g[DIM];
-      L.st.grad(a, g);
-      double* f = fint + (int64_t)L.row[a] * nd;
-      atomicAdd(&f[0], L.v0 * (o.P[0][0] * g[0] + o.P[0][1] * g[1]));
-      atomicAdd(&f[1], L.v0 * (o.P[1][0] * g[0] + o.P[1][1] * g[1]));
-      if (A.up) atomicAdd(&f[2], L.v0 * (L.st.weight(a) * o.s1 + g[0] * o.vv[0] + g[1] * o.vv[1]));
-    }
-  } else {
-    Out3<double> o;
-    int rerr = 0;
-    mech3<double>(m, L.dF, load_be3(A, i), o, nullptr, &rerr);
-    if (rerr) atomicOr(flag, 4);
-    for (int a = 0; a < 27; ++a) {
-      double g[3];
-      L.st.grad(a, g);
-      double* f = fint + (int64_t)L.row[a] * nd;
-#pragma unroll
-      for (int r = 0; r < 3; ++r) atomicAdd(&f[r], L.v0 * (o.P[r][0] * g[0] + o.P[r][1] * g[1] + o.P[r][2] * g[2]));
-    }
-  }
 }
 
 // r_raw = f_int - f_ext; r = r_raw with constrained unknowns zeroed.  Per-row-
@@ -438,56 +317,150 @@ __global__ void __launch_bounds__(GP) k_fint2g(AsmArgs A, const double* __restri
   }
 }
 
-// 3-D: tangent A[(i,j)][(m,l)] = dP_ij / d dF_ml by nine forward passes.
-__global__ void __launch_bounds__(128) k_jac3(AsmArgs A, const double* __restrict__ du,
+// ---------------------------------------------- group-cooperative 3-D ------
+constexpr int GP3 = 64;   // particles (threads) per workgroup in 3-D
+
+__device__ __forceinline__ int32_t origin_key3(const SimDev& S, const Stencil<3>& st) {
+  return (int32_t)(S.okey_base + (st.o[0] + 1) + (int64_t)S.noa[0] * ((st.o[1] + 1) + (int64_t)S.noa[1] * (st.o[2] + 1)));
+}
+
+__global__ void __launch_bounds__(GP3) k_fint3g(AsmArgs A, const double* __restrict__ du, double* __restrict__ fint,
+                                               int32_t* __restrict__ flag) {
+  __shared__ double sP[GP3][9];
+  __shared__ double sW[GP3][3][3], sD[GP3][3][3];
+  __shared__ int32_t sKey[GP3], sRow[GP3][27], sG[GP3 + 1], sWc[GP3 / 64];
+  const int64_t base = (int64_t)blockIdx.x * GP3;
+  const int n = (int)min<int64_t>(GP3, A.np - base);
+  const int t = threadIdx.x;
+  if (t < n) {
+    const int64_t i = base + t;
+    PLoad<3> L;
+    load_particle<3>(A, i, du, L);
+    Mat<double> m = make_mat<double>(L.E, A.nu, L.phi, A.c, A.psi, A.dp, A.match, A.apex_reg);
+    Out3<double> o;
+    int rerr = 0;
+    mech3<double>(m, L.dF, load_be3(A, i), o, nullptr, &rerr);
+    if (rerr) atomicOr(flag, 4);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sP[t][r * 3 + c] = L.v0 * o.P[r][c];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) { sW[t][k][a] = L.st.w[k][a]; sD[t][k][a] = L.st.dw[k][a]; }
+    for (int a = 0; a < 27; ++a) sRow[t][a] = L.row[a];
+    sKey[t] = origin_key3(A.sims[A.psim[i]], L.st);
+  }
+  __syncthreads();
+  const int G = group_starts(sKey, n, sG, sWc);
+  for (int task = t; task < 27 * G; task += GP3) {
+    const int g = task / 27, a = task % 27, ax = a % 3, ay = (a / 3) % 3, az = a / 9;
+    double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+    for (int p = sG[g]; p < sG[g + 1]; ++p) {
+      const double ga0 = sD[p][0][ax] * sW[p][1][ay] * sW[p][2][az];
+      const double ga1 = sW[p][0][ax] * sD[p][1][ay] * sW[p][2][az];
+      const double ga2 = sW[p][0][ax] * sW[p][1][ay] * sD[p][2][az];
+      f0 += sP[p][0] * ga0 + sP[p][1] * ga1 + sP[p][2] * ga2;
+      f1 += sP[p][3] * ga0 + sP[p][4] * ga1 + sP[p][5] * ga2;
+      f2 += sP[p][6] * ga0 + sP[p][7] * ga1 + sP[p][8] * ga2;
+    }
+    double* f = fint + (int64_t)sRow[sG[g]][a] * 3;
+    atomicAdd(&f[0], f0);
+    atomicAdd(&f[1], f1);
+    atomicAdd(&f[2], f2);
+  }
+}
+
+// 3-D Jacobian: nine forward passes per particle give its tangent table
+// (V0 dP_ij/d dF_ml) staged in LDS; one task per (group, node b, slab of a)
+// accumulates 9 blocks of 3x3 in registers.
+__global__ void __launch_bounds__(GP3) k_jac3g(AsmArgs A, const double* __restrict__ du,
                                               const int32_t* __restrict__ rowptr, const int8_t* __restrict__ slot,
                                               double* __restrict__ val, int32_t* __restrict__ flag) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A.np) return;
-  PLoad<3> L;
-  load_particle<3>(A, i, du, L);
-  Mat<dnum> m = make_mat<dnum>(dnum(L.E), A.nu, dnum(L.phi), A.c, A.psi, A.dp, A.match, A.apex_reg);
-  Sym3<double> be = load_be3(A, i);
-  double T[9][9];
-  int rerr = 0;
-  for (int q = 0; q < 9; ++q) {
-    dnum F[3][3];
+  __shared__ double sT[GP3][81];
+  __shared__ double sW[GP3][3][3], sD[GP3][3][3];
+  __shared__ int32_t sKey[GP3], sRow[GP3][27], sG[GP3 + 1], sWc[GP3 / 64];
+  const int64_t base = (int64_t)blockIdx.x * GP3;
+  const int n = (int)min<int64_t>(GP3, A.np - base);
+  const int t = threadIdx.x;
+  if (t < n) {
+    const int64_t i = base + t;
+    PLoad<3> L;
+    load_particle<3>(A, i, du, L);
+    Mat<dnum> m = make_mat<dnum>(dnum(L.E), A.nu, dnum(L.phi), A.c, A.psi, A.dp, A.match, A.apex_reg);
+    Sym3<double> be = load_be3(A, i);
+    int rerr = 0;
+    for (int q = 0; q < 9; ++q) {
+      dnum F[3][3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
+      for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) F[r][c] = dnum(L.dF[r][c], q == r * 3 + c ? 1.0 : 0.0);
-    Sym3<dnum> bd;
+        for (int c = 0; c < 3; ++c) F[r][c] = dnum(L.dF[r][c], q == r * 3 + c ? 1.0 : 0.0);
+      Sym3<dnum> bd;
 #pragma unroll
-    for (int t = 0; t < 6; ++t) bd.a[t] = dnum(be.a[t]);
-    Out3<dnum> o;
-    mech3<dnum>(m, F, bd, o, nullptr, &rerr);
+      for (int k = 0; k < 6; ++k) bd.a[k] = dnum(be.a[k]);
+      Out3<dnum> o;
+      mech3<dnum>(m, F, bd, o, nullptr, &rerr);
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
+      for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) T[r * 3 + c][q] = o.P[r][c].d;
+        for (int c = 0; c < 3; ++c) sT[t][(r * 3 + c) * 9 + q] = L.v0 * o.P[r][c].d;
+    }
+    if (rerr) atomicOr(flag, 4);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) { sW[t][k][a] = L.st.w[k][a]; sD[t][k][a] = L.st.dw[k][a]; }
+    for (int a = 0; a < 27; ++a) sRow[t][a] = L.row[a];
+    sKey[t] = origin_key3(A.sims[A.psim[i]], L.st);
   }
-  if (rerr) atomicOr(flag, 4);
-  const double v0 = L.v0;
-  for (int b = 0; b < 27; ++b) {
-    double gb[3];
-    L.st.grad(b, gb);
-    double Tb[9][3];
+  __syncthreads();
+  const int G = group_starts(sKey, n, sG, sWc);
+  for (int task = t; task < 81 * G; task += GP3) {
+    const int g = task / 81, rem = task % 81, b = rem / 3, az = rem % 3;
+    const int bx = b % 3, by = (b / 3) % 3, bz = b / 9;
+    double acc[9][3][3];
 #pragma unroll
-    for (int o = 0; o < 9; ++o)
+    for (int a = 0; a < 9; ++a)
 #pragma unroll
-      for (int mm = 0; mm < 3; ++mm)
-        Tb[o][mm] = T[o][mm * 3 + 0] * gb[0] + T[o][mm * 3 + 1] * gb[1] + T[o][mm * 3 + 2] * gb[2];
-    for (int a = 0; a < 27; ++a) {
-      double ga[3];
-      L.st.grad(a, ga);
-      int32_t ra = L.row[a];
-      int s = slot[(int64_t)ra * 125 + nb_index<3>(a, b)];
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[a][r][c] = 0.0;
+    for (int p = sG[g]; p < sG[g + 1]; ++p) {
+      const double* T = sT[p];
+      const double gb0 = sD[p][0][bx] * sW[p][1][by] * sW[p][2][bz];
+      const double gb1 = sW[p][0][bx] * sD[p][1][by] * sW[p][2][bz];
+      const double gb2 = sW[p][0][bx] * sW[p][1][by] * sD[p][2][bz];
+      double Tb[9][3];
+#pragma unroll
+      for (int o = 0; o < 9; ++o)
+#pragma unroll
+        for (int mm = 0; mm < 3; ++mm)
+          Tb[o][mm] = T[o * 9 + mm * 3] * gb0 + T[o * 9 + mm * 3 + 1] * gb1 + T[o * 9 + mm * 3 + 2] * gb2;
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        const int ax = a % 3, ay = a / 3;
+        const double ga0 = sD[p][0][ax] * sW[p][1][ay] * sW[p][2][az];
+        const double ga1 = sW[p][0][ax] * sD[p][1][ay] * sW[p][2][az];
+        const double ga2 = sW[p][0][ax] * sW[p][1][ay] * sD[p][2][az];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc[a][r][c] += ga0 * Tb[r * 3][c] + ga1 * Tb[r * 3 + 1][c] + ga2 * Tb[r * 3 + 2][c];
+      }
+    }
+    const int p0 = sG[g];
+#pragma unroll
+    for (int a9 = 0; a9 < 9; ++a9) {
+      const int a = a9 + 9 * az;
+      const int32_t ra = sRow[p0][a];
+      const int s = slot[(int64_t)ra * 125 + nb_index<3>(a, b)];
       double* blk = val + ((int64_t)rowptr[ra] + s) * 9;
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-          atomicAdd(&blk[r * 3 + c], v0 * (ga[0] * Tb[r * 3 + 0][c] + ga[1] * Tb[r * 3 + 1][c] + ga[2] * Tb[r * 3 + 2][c]));
+        for (int c = 0; c < 3; ++c) atomicAdd(&blk[r * 3 + c], acc[a9][r][c]);
     }
   }
 }
@@ -608,7 +581,8 @@ int launch_fint(mpm_ctx* c, const mpm_problem* pb, const double* du) {
     unsigned g = (unsigned)((c->np + GP - 1) / GP);
     k_fint2g<<<g, GP, 0, c->stream>>>(A, du, c->fint.p);
   } else {
-    k_fint<3><<<nb256(c->np), 256, 0, c->stream>>>(A, du, c->fint.p, c->flag.p);
+    unsigned g = (unsigned)((c->np + GP3 - 1) / GP3);
+    k_fint3g<<<g, GP3, 0, c->stream>>>(A, du, c->fint.p, c->flag.p);
   }
   LAUNCH_CHECK(c, "k_fint");
   return MPM_OK;
@@ -643,11 +617,11 @@ int launch_jacobian(mpm_ctx* c, const mpm_problem* pb, const double* du, double*
   const int nd = c->nd;
   HIPC(c, hipMemsetAsync(val, 0, c->nnzb * nd * nd * sizeof(double), c->stream));
   if (c->np > 0) {
-    unsigned g = (unsigned)std::max<int64_t>(1, (c->np + 127) / 128);
     unsigned gg = (unsigned)((c->np + GP - 1) / GP);
     if (c->dim == 2 && !c->up) k_jac2g<4><<<gg, GP, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val);
     else if (c->dim == 2) k_jac2g<7><<<gg, GP, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val);
-    else k_jac3<<<g, 128, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val, c->flag.p);
+    else k_jac3g<<<(unsigned)((c->np + GP3 - 1) / GP3), GP3, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val,
+                                                                              c->flag.p);
     LAUNCH_CHECK(c, "k_jac");
   }
   if (apply_bc && c->n_row > 0) {

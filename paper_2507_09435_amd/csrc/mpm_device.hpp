@@ -408,4 +408,92 @@ __device__ __forceinline__ int stress3(const Mat<S>& m, const Sym3<S>& eps, Sym3
   return reg;
 }
 
+// ------------------------------------------------ particle stress output ---
+// P = tau dF^-T per particle (the internal force is V0 P grad w), and the
+// u-p terms of the fluid row.
+struct UpPar { double biot, mob, dt, rho_f, g[3]; };
+
+
+// -------------------------------------------------------- 2-D particle -----
+template <class S>
+struct Out2 { S P[2][2]; S s1; S vv[2]; };
+
+template <class S>
+__device__ __forceinline__ int mech2(const Mat<S>& m, const S F[2][2], const Sym2<S>& be, S Jn, int up, const UpPar& u,
+                                     S pp, const S gp[2], Out2<S>& o, Sym2<S>* ee_out) {
+  S m00 = F[0][0] * be.xx + F[0][1] * be.xy, m01 = F[0][0] * be.xy + F[0][1] * be.yy;
+  S m10 = F[1][0] * be.xx + F[1][1] * be.xy, m11 = F[1][0] * be.xy + F[1][1] * be.yy;
+  Sym2<S> bt;
+  bt.xx = m00 * F[0][0] + m01 * F[0][1];
+  bt.yy = m10 * F[1][0] + m11 * F[1][1];
+  bt.xy = m00 * F[1][0] + m01 * F[1][1];
+  bt.zz = be.zz;
+  Sym2<S> eps = hencky2(bt);
+  Sym2<S> tau, ee;
+  int reg = stress2(m, eps, tau, ee);
+  S det = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+  S idet = 1.0 / det;
+  S it00 = F[1][1] * idet, it01 = -1.0 * F[1][0] * idet, it10 = -1.0 * F[0][1] * idet, it11 = F[0][0] * idet;
+  S J = det * Jn;
+  if (up) {
+    S bp = u.biot * J * pp;
+    tau.xx -= bp; tau.yy -= bp; tau.zz -= bp;
+  }
+  o.P[0][0] = tau.xx * it00 + tau.xy * it10;
+  o.P[0][1] = tau.xx * it01 + tau.xy * it11;
+  o.P[1][0] = tau.xy * it00 + tau.yy * it10;
+  o.P[1][1] = tau.xy * it01 + tau.yy * it11;
+  if (up) {
+    o.s1 = u.biot * s_log(det) * J;
+    S q0 = u.mob * (it00 * gp[0] + it01 * gp[1] - u.rho_f * u.g[0]);
+    S q1 = u.mob * (it10 * gp[0] + it11 * gp[1] - u.rho_f * u.g[1]);
+    o.vv[0] = u.dt * (it00 * q0 + it10 * q1) * J;
+    o.vv[1] = u.dt * (it01 * q0 + it11 * q1) * J;
+  }
+  if (ee_out) *ee_out = ee;
+  return reg;
+}
+
+// -------------------------------------------------------- 3-D particle -----
+template <class S>
+struct Out3 { S P[3][3]; };
+
+template <class S>
+__device__ __forceinline__ int mech3(const Mat<S>& m, const S F[3][3], const Sym3<S>& be, Out3<S>& o, Sym3<S>* ee_out,
+                                     int* range_err) {
+  S M[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) M[i][j] = F[i][0] * sget(be, 0, j) + F[i][1] * sget(be, 1, j) + F[i][2] * sget(be, 2, j);
+  Sym3<S> bt;
+  const int I[6] = {0, 1, 2, 1, 0, 0}, Jx[6] = {0, 1, 2, 2, 2, 1};
+#pragma unroll
+  for (int t = 0; t < 6; ++t)
+    bt.a[t] = M[I[t]][0] * F[Jx[t]][0] + M[I[t]][1] * F[Jx[t]][1] + M[I[t]][2] * F[Jx[t]][2];
+  Sym3<S> eps = hencky3(bt, range_err);
+  Sym3<S> tau, ee;
+  int reg = stress3(m, eps, tau, ee);
+  // dF^-T = cofactor(dF) / det
+  S cof[3][3];
+  cof[0][0] = F[1][1] * F[2][2] - F[1][2] * F[2][1];
+  cof[0][1] = F[1][2] * F[2][0] - F[1][0] * F[2][2];
+  cof[0][2] = F[1][0] * F[2][1] - F[1][1] * F[2][0];
+  cof[1][0] = F[0][2] * F[2][1] - F[0][1] * F[2][2];
+  cof[1][1] = F[0][0] * F[2][2] - F[0][2] * F[2][0];
+  cof[1][2] = F[0][1] * F[2][0] - F[0][0] * F[2][1];
+  cof[2][0] = F[0][1] * F[1][2] - F[0][2] * F[1][1];
+  cof[2][1] = F[0][2] * F[1][0] - F[0][0] * F[1][2];
+  cof[2][2] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+  S det = F[0][0] * cof[0][0] + F[0][1] * cof[0][1] + F[0][2] * cof[0][2];
+  S idet = 1.0 / det;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      o.P[i][j] = (sget(tau, i, 0) * cof[0][j] + sget(tau, i, 1) * cof[1][j] + sget(tau, i, 2) * cof[2][j]) * idet;
+  if (ee_out) *ee_out = ee;
+  return reg;
+}
+
 }  // namespace mpm

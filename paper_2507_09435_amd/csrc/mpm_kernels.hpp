@@ -92,6 +92,11 @@ struct mpm_ctx {
   mpm::DBuf<double> simsc;                     // per-sim scalars [nsim][16]
   mpm::DBuf<int32_t> simflag;                  // per-sim krylov state [nsim][2]
   mpm::DBuf<double> du_base, alpha;            // line search
+  // adjoint
+  mpm::DBuf<int32_t> tpos;                     // position of the transposed block
+  bool tpos_ready = false;
+  bool ktrans = false;                         // Krylov on J^T
+  mpm::DBuf<double> dinvT, adj_mu, adj_nu, adj_theta, adj_rbar;
   bool krylov_soft = false;                    // last solve stopped at its floor above rtol
   int time_spmv = 0;                           // sample period of SpMV timing (0: off)
   std::vector<hipEvent_t> spmv_events;

@@ -101,15 +101,17 @@ __global__ void k_bj_inv(int64_t n_row, const int32_t* __restrict__ rowptr, cons
 // y = A x over one row block per workgroup; LPR lanes cooperate on a row.
 // Partials: part[blk][q1] = sum z1 . y (if z1), part[blk][q2] = sum y . y
 // (if q2 >= 0).  Skips sims whose Krylov solve is finished.
-template <int BS, int LPR>
-__global__ void __launch_bounds__(256) k_spmv(const RowBlock* __restrict__ blocks, const int32_t* __restrict__ simflag,
+template <int BS, int LPR, bool TR>
+__global__ void __launch_bounds__(ROWS_PER_BLOCK * LPR) k_spmv(const RowBlock* __restrict__ blocks, const int32_t* __restrict__ simflag,
                                               const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+                                              const int32_t* __restrict__ tpos,
                                               const double* __restrict__ val, const double* __restrict__ x,
                                               double* __restrict__ y, const double* __restrict__ z1,
                                               double* __restrict__ part, int q1, int q2) {
   const RowBlock b = blocks[blockIdx.x];
   if (simflag && simflag[2 * b.sim] >= 0) return;
-  constexpr int G = 256 / LPR;
+  constexpr int G = ROWS_PER_BLOCK;   // one LPR-lane group per row: the whole block in flight at once
+  constexpr int NW = ROWS_PER_BLOCK * LPR / 64;
   const int lane = threadIdx.x % LPR, grp = threadIdx.x / LPR;
   double d1 = 0.0, d2 = 0.0;
   for (int row = b.row0 + grp; row < b.row1; row += G) {
@@ -118,7 +120,8 @@ __global__ void __launch_bounds__(256) k_spmv(const RowBlock* __restrict__ block
     for (int i = 0; i < BS; ++i) acc[i] = 0.0;
     const int k1 = rowptr[row + 1];
     for (int k = rowptr[row] + lane; k < k1; k += LPR) {
-      const double* blk = val + (int64_t)k * (BS * BS);
+      // transposed product: block (row, c) of J^T is block (c, row) of J, transposed
+      const double* blk = val + (int64_t)(TR ? tpos[k] : k) * (BS * BS);
       const int64_t c = colind[k];
       double xv[BS];
 #pragma unroll
@@ -126,7 +129,7 @@ __global__ void __launch_bounds__(256) k_spmv(const RowBlock* __restrict__ block
 #pragma unroll
       for (int i = 0; i < BS; ++i)
 #pragma unroll
-        for (int j = 0; j < BS; ++j) acc[i] += blk[i * BS + j] * xv[j];
+        for (int j = 0; j < BS; ++j) acc[i] += (TR ? blk[j * BS + i] : blk[i * BS + j]) * xv[j];
     }
 #pragma unroll
     for (int off = LPR / 2; off > 0; off >>= 1)
@@ -142,14 +145,17 @@ __global__ void __launch_bounds__(256) k_spmv(const RowBlock* __restrict__ block
     }
   }
   if (q1 < 0 && q2 < 0) return;
-  __shared__ double sh[2][4];
+  __shared__ double sh[2][NW];
   d1 = wave_sum(d1);
   d2 = wave_sum(d2);
   if (threadIdx.x % 64 == 0) { sh[0][threadIdx.x / 64] = d1; sh[1][threadIdx.x / 64] = d2; }
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (q1 >= 0) part[blockIdx.x * NQ + q1] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
-    if (q2 >= 0) part[blockIdx.x * NQ + q2] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) { s1 += sh[0][w]; s2 += sh[1][w]; }
+    if (q1 >= 0) part[blockIdx.x * NQ + q1] = s1;
+    if (q2 >= 0) part[blockIdx.x * NQ + q2] = s2;
   }
 }
 
@@ -324,17 +330,23 @@ static int spmv_launch(mpm_ctx* c, const int32_t* simflag, const double* val, co
                        const double* z1, double* part, int q1, int q2) {
   unsigned nbk = (unsigned)c->blocks_h.size();
   if (!nbk) return MPM_OK;
-  k_spmv<BS, LPR><<<nbk, 256, 0, c->stream>>>(c->blocks.p, simflag, c->rowptr.p, c->colind.p, val, x, y, z1, part, q1,
-                                             q2);
+  const unsigned threads = ROWS_PER_BLOCK * LPR;
+  if (c->ktrans)
+    k_spmv<BS, LPR, true><<<nbk, threads, 0, c->stream>>>(c->blocks.p, simflag, c->rowptr.p, c->colind.p, c->tpos.p,
+                                                          val, x, y, z1, part, q1, q2);
+  else
+    k_spmv<BS, LPR, false><<<nbk, threads, 0, c->stream>>>(c->blocks.p, simflag, c->rowptr.p, c->colind.p, nullptr,
+                                                           val, x, y, z1, part, q1, q2);
   LAUNCH_CHECK(c, "k_spmv");
   return MPM_OK;
 }
 
 static int spmv(mpm_ctx* c, const int32_t* simflag, const double* val, const double* x, double* y, const double* z1,
                 double* part, int q1, int q2) {
-  if (c->nd == 2) return spmv_launch<2, 32>(c, simflag, val, x, y, z1, part, q1, q2);
-  if (c->dim == 2) return spmv_launch<3, 32>(c, simflag, val, x, y, z1, part, q1, q2);
-  return spmv_launch<3, 64>(c, simflag, val, x, y, z1, part, q1, q2);
+  // lanes per row: 8 for the <= 25 blocks of a 2-D row, 16 for the <= 125 of a 3-D row
+  if (c->nd == 2) return spmv_launch<2, 8>(c, simflag, val, x, y, z1, part, q1, q2);
+  if (c->dim == 2) return spmv_launch<3, 8>(c, simflag, val, x, y, z1, part, q1, q2);
+  return spmv_launch<3, 16>(c, simflag, val, x, y, z1, part, q1, q2);
 }
 
 int launch_spmv(mpm_ctx* c, const double* val, const double* x, double* y, const double* z) {
@@ -371,13 +383,14 @@ static int spmv_timed(mpm_ctx* c, bool timed, const int32_t* simflag, const doub
 template <int BS>
 static int bicg_iter(mpm_ctx* c, const double* val, int it, const KBufs& K) {
   unsigned nbk = (unsigned)c->blocks_h.size();
+  const double* dinv = c->ktrans ? c->dinvT.p : c->dinv.p;
   int rc;
   const bool timed = c->time_spmv > 0 && it % c->time_spmv == 0;
   k_bicg_a<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->blk_first.p, it, K.part_rr, c->simsc.p, c->simflag.p, c->kr.p,
-                                         c->kp.p, c->kv.p, c->kph.p, c->dinv.p);
+                                         c->kp.p, c->kv.p, c->kph.p, dinv);
   if ((rc = spmv_timed(c, timed, c->simflag.p, val, c->kph.p, c->kv.p, c->krh.p, K.part_rv, 0, -1))) return rc;
   k_bicg_c<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->blk_first.p, it, K.part_rv, c->simsc.p, c->simflag.p, c->kr.p,
-                                         c->kv.p, c->ks.p, c->ksh.p, c->dinv.p);
+                                         c->kv.p, c->ks.p, c->ksh.p, dinv);
   if ((rc = spmv_timed(c, timed, c->simflag.p, val, c->ksh.p, c->kt.p, c->ks.p, K.part_ts, 0, 1))) return rc;
   k_bicg_e<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->blk_first.p, K.part_ts, c->simsc.p, c->simflag.p, c->kx.p,
                                          c->kr.p, c->krh.p, c->kph.p, c->ksh.p, c->ks.p, c->kt.p, K.part_rr);

@@ -361,6 +361,7 @@ using namespace mpm;
 // ======================================================================
 int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row_out, int64_t* nnzb_out, int32_t* nd_out) {
   c->prepared = false;
+  c->tpos_ready = false;
   int rc = validate_problem(c, pb);
   if (rc) return rc;
   const int dim = pb->grids[0].dim;

@@ -68,7 +68,7 @@ class mpm_newton_report(C.Structure):
 
 
 EXPORTS = ["mpm_create", "mpm_destroy", "mpm_last_error", "mpm_prepare", "mpm_residual", "mpm_jacobian_bsr",
-           "mpm_newton_step", "mpm_update", "mpm_spmv"]
+           "mpm_newton_step", "mpm_update", "mpm_spmv", "mpm_adjoint_step"]
 
 _lib = None
 
@@ -94,6 +94,8 @@ def load():
                              C.POINTER(mpm_newton_report)], C.c_int),
         "mpm_update": ([P, C.POINTER(mpm_problem), P, P, P, P], C.c_int),
         "mpm_spmv": ([P, P, P, P, P], C.c_int),
+        "mpm_adjoint_step": ([P, C.POINTER(mpm_problem), P, C.POINTER(C.c_double), P, P, P, C.c_double,
+                              C.POINTER(C.c_int32)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -270,3 +272,13 @@ def mpm_update(ctx, dp: DeviceProblem, du, x_out, F_out, be_out):
 
 def mpm_spmv(ctx, val, x, y, z=None):
     _check(ctx, load().mpm_spmv(ctx, _ptr(val), _ptr(x), _ptr(y), _ptr(z)))
+
+
+def mpm_adjoint_step(ctx, dp: DeviceProblem, du, react_bar, sbar_next, sbar_n, theta_bar, krylov_rtol=1e-12):
+    """One step's adjoint; react_bar is a host sequence [nsim].  Returns the
+    Krylov iterations of the transposed solve per sim."""
+    rb = (C.c_double * dp.nsim)(*[float(v) for v in react_bar])
+    it = (C.c_int32 * dp.nsim)()
+    _check(ctx, load().mpm_adjoint_step(ctx, C.byref(dp.struct), _ptr(du), rb, _ptr(sbar_next), _ptr(sbar_n),
+                                        _ptr(theta_bar), float(krylov_rtol), it))
+    return list(it)
