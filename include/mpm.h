@@ -74,7 +74,8 @@ typedef struct {
   int32_t up;         /* 1: u-p poromechanics (Sec. 2.2, Remark 1) */
   int32_t dp;         /* 1: Drucker-Prager return map on top of Hencky elasticity */
   int32_t dp_match;   /* 0: cone through the triaxial-compression meridian of Mohr-Coulomb,
-                         1: plane-strain match, 2: triaxial-extension meridian */
+                         1: plane-strain match, 2: triaxial-extension meridian;
+                         + 4: associated flow (dilation slope = friction slope, psi unused) */
   int32_t reserved;
   double E, nu;       /* Young's modulus [Pa], Poisson ratio */
   double phi, c, psi; /* friction angle [rad], cohesion [Pa], dilation angle [rad] */

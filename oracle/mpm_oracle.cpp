@@ -196,7 +196,7 @@ struct Cfg {
   int32_t dim;       // 2 (plane strain) or 3
   int32_t up;        // 1: u-p poromechanics (extra nodal pressure unknown)
   int32_t dp;        // 1: Drucker-Prager plasticity on top of Hencky
-  int32_t dp_match;  // 0 outer cone, 1 plane-strain match, 2 inner cone
+  int32_t dp_match;  // 0 outer cone, 1 plane-strain match, 2 inner cone (bit 4: associated flow)
   int32_t n[3];      // cells per axis; nodes are -1 .. n+1 per axis
   double h;          // cell size
   double x0[3];      // grid origin (coordinate of node 0)
@@ -334,7 +334,7 @@ Moduli<T> moduli(const T& E, double nu) {
 // Drucker-Prager coefficients: f = sqrt(J2) + eta p - xi c  (p = tr(tau)/3,
 // tension positive); plastic potential g = sqrt(J2) + etabar p.
 template <class T>
-void dp_coeffs(int match, const T& phi, double psi, T& eta, T& xi, double& etabar) {
+void dp_coeffs(int match, const T& phi, double psi, T& eta, T& xi, T& etabar) {
   const double r3 = std::sqrt(3.0);
   if (match == 1) {
     T t = tan(phi);
@@ -364,8 +364,9 @@ int hencky_dp(const Cfg& c, const T& E, const T& phi, const M3<T>& eps_tr, M3<T>
   for (int i = 0; i < 3; ++i) tau_tr.a[i][i] += m.lam * tr;
   tau = tau_tr; eps_e = eps_tr;
   if (!c.dp) return 0;
-  T eta, xi; double etabar;
-  dp_coeffs(c.dp_match, phi, c.psi, eta, xi, etabar);
+  T eta, xi, etabar;
+  dp_coeffs(c.dp_match & 3, phi, c.psi, eta, xi, etabar);
+  if (c.dp_match & 4) etabar = eta;   // associated flow: the potential is the yield function
   T p = trace(tau_tr) / 3.0;
   M3<T> s = tau_tr;
   for (int i = 0; i < 3; ++i) s.a[i][i] -= p;

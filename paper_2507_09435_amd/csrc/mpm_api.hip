@@ -66,7 +66,8 @@ int validate_problem(mpm_ctx* c, const mpm_problem* pb) {
   }
   if (!(pb->mat.E > 0.0) && !pb->P.E) return c->fail(MPM_E_INVALID, "Young's modulus must be positive");
   if (!(pb->mat.nu > -1.0 && pb->mat.nu < 0.5)) return c->fail(MPM_E_INVALID, "Poisson ratio out of range");
-  if (pb->mat.dp_match < 0 || pb->mat.dp_match > 2) return c->fail(MPM_E_INVALID, "dp_match must be 0, 1 or 2");
+  if ((pb->mat.dp_match & 3) > 2 || (pb->mat.dp_match & ~7) != 0)
+    return c->fail(MPM_E_INVALID, "dp_match must be 0, 1 or 2, plus 4 for associated flow");
   return MPM_OK;
 }
 

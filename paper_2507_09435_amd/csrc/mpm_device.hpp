@@ -87,7 +87,7 @@ template <class S>
 struct Mat {
   S K, G, lam;          // bulk, shear, Lame lambda
   S eta, xi;            // cone slope and cohesion factor
-  double etab;          // dilatancy slope of the plastic potential
+  S etab;               // dilatancy slope of the plastic potential
   double c;             // cohesion
   double apex_reg;      // apex-return tangent scale
   int dp;
@@ -104,6 +104,8 @@ __device__ __forceinline__ Mat<S> make_mat(S E, double nu, S phi, double c, doub
   m.dp = dp;
   m.c = c;
   const double r3 = 1.7320508075688772935;
+  const bool assoc = (match & 4) != 0;
+  match &= 3;
   if (match == 1) {
     S t = s_tan(phi);
     S den = s_sqrt(9.0 + 12.0 * t * t);
@@ -120,6 +122,7 @@ __device__ __forceinline__ Mat<S> make_mat(S E, double nu, S phi, double c, doub
     double spsi = sin(psi);
     m.etab = 6.0 * spsi / (r3 * (3.0 + sg * spsi));
   }
+  if (assoc) m.etab = m.eta;   // associated flow: the potential is the yield function
   return m;
 }
 

@@ -281,19 +281,32 @@ def c5_draws(seed: int, nsim: int = 64):
     return out
 
 
-def make_c5(nsim: int = 64, n_steps: int = 30, seed: int = 1005, target_seed: int = 2005):
-    """Batch of 2-D footings; returns (list of Workload, target (E, phi) list)."""
+def make_c5(nsim: int = 64, n_steps: int = 30, seed: int = 1005, target_seed: int = 2005, gradient: bool = True):
+    """Batch of 2-D footings; returns (list of Workload, target (E, phi) list).
+    gradient=True applies gradient_reading to every sim."""
     sims, targets = [], []
     draws = c5_draws(seed, nsim)
     tdraws = c5_draws(target_seed, nsim)
     for s, ((ns, E, phi), (_, Et, phit)) in enumerate(zip(draws, tdraws)):
         n_y = max(2, int(round(math.sqrt(ns / 8.0))))
         w = footing_2d(n_y, E, phi, n_steps, f"c5_{s}")
+        if gradient:
+            gradient_reading(w)
         w.particles.E = np.full(w.particles.np, E)
         w.particles.phi = np.full(w.particles.np, math.radians(phi))
         sims.append(w)
         targets.append((Et, math.radians(phit)))
     return sims, targets
+
+
+def gradient_reading(w: Workload, cohesion: float = 1e3, push: float = -1e-4) -> Workload:
+    """The footing reading used for gradients (a path Newton follows): a
+    small cohesion, associated flow and 0.1 mm footing pushes.  With zero
+    cohesion and zero dilation the footing path loses ellipticity."""
+    w.prob.c = cohesion
+    w.prob.dp_match = 4          # outer cone, associated flow
+    w.footing = (w.footing[0], w.footing[1], w.footing[2], push)
+    return w
 
 
 def small_footing(n_y: int = 8, n_steps: int = 3, E=1e7, phi_deg=30.0) -> Workload:

@@ -26,11 +26,7 @@ def ctx():
 def plastic_footing(n_y):
     """Footing reading used for gradients: cohesion 1 kPa, associated flow,
     0.1 mm pushes."""
-    w = W.small_footing(n_y=n_y)
-    w.prob.c = 1e3
-    w.prob.psi = w.prob.phi
-    w.footing = (w.footing[0], w.footing[1], w.footing[2], -1e-4)
-    return w
+    return W.gradient_reading(W.small_footing(n_y=n_y))
 
 
 CASES = [(5, 2e7, 28.0), (6, 1e7, 32.0), (4, 5e6, 25.0)]
@@ -38,11 +34,7 @@ STEPS = [0, 1, 2, 3]
 
 
 def _batch():
-    sims = [plastic_footing(n) for n, _, _ in CASES]
-    for w, (_, E, phi) in zip(sims, CASES):
-        # the psi = phi reading follows the per-sim friction angle
-        w.prob.psi = math.radians(phi)
-    return sims
+    return [plastic_footing(n) for n, _, _ in CASES]
 
 
 def test_batched_adjoint_matches_oracle_sensitivity(ctx):
@@ -50,11 +42,6 @@ def test_batched_adjoint_matches_oracle_sensitivity(ctx):
     sims = _batch()
     E = [c[1] for c in CASES]
     phi = [math.radians(c[2]) for c in CASES]
-    # one shared dilation angle for the batch (material constants other than
-    # E and phi are shared): use the mean friction angle for psi everywhere
-    psi = float(np.mean(phi))
-    for w in sims:
-        w.prob.psi = psi
     print("[adjoint] batch forward", flush=True)
     dp = AD.make_batch(sims, E, phi)
     run = AD.forward(ctx, dp, sims, STEPS, tol=1e-12)

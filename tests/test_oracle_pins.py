@@ -223,6 +223,50 @@ def test_dp_return_lands_on_surface_and_keeps_direction():
     assert n_plastic > 20
 
 
+def _sym_basis():
+    out = []
+    for i in range(3):
+        for j in range(i, 3):
+            e = np.zeros((3, 3))
+            e[i, j] = e[j, i] = 1.0 if i == j else math.sqrt(0.5)
+            out.append(e)
+    return out
+
+
+def test_dp_associated_flow_normality_and_symmetric_tangent():
+    """Associated flow (potential = yield function): the plastic log-strain
+    increment follows the yield-surface normal, so tr(d eps_p) /
+    |dev d eps_p| = sqrt(2) eta, and the consistent tangent of the return is
+    symmetric (closest-point projection in the energy norm).  The
+    non-associated default (psi = 0) gives a purely deviatoric increment and
+    a non-symmetric tangent."""
+    rng = np.random.default_rng(21)
+    E, nu, phi = 1e7, 0.3, math.radians(30)
+    eta, _ = _eta_xi(phi, 0)
+    assoc = _cfg(dp=1, nu=nu, dp_match=4, c=1e3)
+    nonassoc = _cfg(dp=1, nu=nu, dp_match=0, c=1e3)
+    basis = _sym_basis()
+    n_cone = 0
+    for _ in range(200):
+        eps = rng.normal(size=(3, 3)) * 2e-3
+        eps = 0.5 * (eps + eps.T) - 1e-3 * np.eye(3)
+        tau, ee, reg = ret(assoc, E, phi, eps)
+        if reg != 1:
+            continue
+        n_cone += 1
+        dp_ = eps - ee
+        dev = dp_ - np.trace(dp_) / 3 * np.eye(3)
+        assert abs(np.trace(dp_) / np.linalg.norm(dev) - math.sqrt(2) * eta) <= 1e-9 * eta
+        C_ = np.array([[(bk * ret_dir(assoc, E, phi, eps, bl)).sum() for bl in basis] for bk in basis])
+        assert np.abs(C_ - C_.T).max() <= 1e-9 * np.abs(C_).max()
+        _, ee_n, reg_n = ret(nonassoc, E, phi, eps)
+        if reg_n == 1:
+            assert abs(np.trace(eps - ee_n)) <= 1e-12
+            Cn = np.array([[(bk * ret_dir(nonassoc, E, phi, eps, bl)).sum() for bl in basis] for bk in basis])
+            assert np.abs(Cn - Cn.T).max() >= 1e-3 * np.abs(Cn).max()
+    assert n_cone > 20
+
+
 def test_dp_apex_for_tensile_trial():
     E, nu, phi = 1e7, 0.3, math.radians(30)
     tau, ee, reg = ret(_cfg(dp=1, nu=nu), E, phi, 1e-3 * np.eye(3) + np.diag([1e-4, 0, 0]))
@@ -591,10 +635,7 @@ def test_up_consolidation_paper_e4(golden):
 def _plastic_footing(n_y=6, E=1e7, phi_deg=30.0, steps=3):
     """Footing reading used for gradients: cohesion 1 kPa, associated flow,
     0.1 mm pushes (a path Newton follows; see the design notes)."""
-    w = W.small_footing(n_y=n_y, E=E, phi_deg=phi_deg)
-    w.prob.c = 1e3
-    w.prob.psi = w.prob.phi
-    w.footing = (w.footing[0], w.footing[1], w.footing[2], -1e-4)
+    w = W.gradient_reading(W.small_footing(n_y=n_y, E=E, phi_deg=phi_deg))
     bcs = [w.bc(k) for k in range(0, steps + 1)]
     return w, bcs
 
