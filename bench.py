@@ -41,6 +41,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--krylov-rtol", type=float, default=1e-12)
+    ap.add_argument("--batch-sims", type=int, default=16,
+                    help="sims of the batched footing set timed batched and one at a time (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=2, help="load steps of that comparison (incl. geostatic)")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="only the SpMV launches and a plain copy of known size, for counter passes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU layout is a design "
@@ -51,6 +56,10 @@ def main():
 
     from paper_2507_09435_amd import mpm as M
     from paper_2507_09435_amd import workloads as W
+
+    if args.pmc_probe:
+        pmc_probe(M, W, torch)
+        return
 
     w = W.make_c2(n_steps=1)
     P = w.prob
@@ -157,10 +166,78 @@ def main():
                      "in_loop_event_us": round(loop_ms * 1e3 / max(loop_n, 1), 3),
                      "algorithmic_bytes_per_launch": nbytes},
     }
+    if args.batch_sims > 0:
+        out["batched"] = batched_vs_sequential(ctx, args.batch_sims, args.batch_steps, args.krylov_rtol)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     M.mpm_destroy(ctx)
     print(json.dumps(out))
+
+
+def batched_vs_sequential(ctx, nsims, nsteps, krylov_rtol):
+    """Newton iterations per second summed over sims: the first nsims
+    footings of the batched set (uneven sizes, E and friction per sim; the
+    gradient reading of the footing) solved as one batch, against the same
+    sims solved one at a time, same steps and tolerances."""
+    import torch
+    from paper_2507_09435_amd import adjoint as AD
+    from paper_2507_09435_amd import workloads as W
+    sims, _ = W.make_c5(nsim=64)
+    sims = sims[:nsims]
+    E = [float(w.particles.E[0]) for w in sims]
+    phi = [float(w.particles.phi[0]) for w in sims]
+    steps = list(range(nsteps))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dp = AD.make_batch(sims, E, phi)
+    run = AD.forward(ctx, dp, sims, steps, krylov_rtol=krylov_rtol)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    print(f"[bench] batched {nsims} sims x {nsteps} steps: {t_b:.2f} s, newton {run.newton_iters}",
+          file=sys.stderr, flush=True)
+    iters = 0
+    t0 = time.perf_counter()
+    for k, w in enumerate(sims):
+        d1 = AD.make_batch([w], [E[k]], [phi[k]])
+        r1 = AD.forward(ctx, d1, [w], steps, krylov_rtol=krylov_rtol)
+        iters += sum(r1.newton_iters)
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t0
+    print(f"[bench] sequential: {t_s:.2f} s, {iters} Newton iterations", file=sys.stderr, flush=True)
+    particles = sum(w.particles.np for w in sims)
+    return {"sims": nsims, "load_steps": nsteps, "particles": particles,
+            "newton_iters": iters, "batched_s": round(t_b, 3), "sequential_s": round(t_s, 3),
+            "newton_iters_per_s_batched": round(iters / t_b, 2),
+            "newton_iters_per_s_sequential": round(iters / t_s, 2),
+            "speedup": round(t_s / t_b, 3),
+            "note": "the same Newton iterations counted on both sides: the sum over sims of each sim's own "
+                    "iterations when solved alone"}
+
+
+def pmc_probe(M, W, torch):
+    """SpMV launches on the 131072-particle footing's geostatic Jacobian and
+    a plain 256 MiB copy (the scale of the HBM byte counters)."""
+    w = W.make_c2(n_steps=1)
+    P = w.prob
+    ctx = M.mpm_create(0, torch.cuda.current_stream().cuda_stream)
+    dp = M.make_problem([(P, w.particles)], [w.bc(0)])
+    n_row, nnzb, nd = M.mpm_prepare(ctx, dp)
+    val = torch.zeros(nnzb * nd * nd, dtype=torch.float64, device="cuda")
+    du = torch.zeros(n_row * nd, dtype=torch.float64, device="cuda")
+    M.mpm_jacobian_bsr(ctx, dp, du, val=val)
+    xv = torch.randn(n_row * nd, dtype=torch.float64, device="cuda")
+    zv = torch.randn_like(xv)
+    yv = torch.empty_like(xv)
+    for _ in range(20):
+        M.mpm_spmv(ctx, val, xv, yv, zv)
+    a = torch.randn(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    M.mpm_destroy(ctx)
+    print(json.dumps({"pmc_probe": True, "spmv_algorithmic_bytes": spmv_bytes(n_row, nnzb, nd),
+                      "copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8}))
 
 
 def cpu_baseline(w):

@@ -164,7 +164,9 @@ typedef struct {
                              ||r(u + a du)|| < (1 - 1e-4 a) ||r(u)|| */
   int32_t time_spmv;      /* k > 0: time the SpMV launches of every k-th Krylov iteration with
                              HIP events on the context's stream (report fields spmv_*) */
-  int32_t reserved;
+  int32_t krylov_method;  /* 0: block-Jacobi BiCGStab (restarted while it improves) on up to half
+                             of krylov_max_iter, then restarted GMRES(100) with the same
+                             preconditioner for the sims still above tolerance; 1: GMRES only */
 } mpm_newton_opts;
 
 #define MPM_MAX_REPORT 32

@@ -287,6 +287,7 @@ extern "C" int mpm_adjoint_step(mpm_ctx* c, const mpm_problem* pb, const double*
   }
   std::vector<int> kit;
   c->ktrans = true;
+  c->kmethod = 0;
   rc = krylov_solve(c, c->val.p, krylov_rtol > 0 ? krylov_rtol : 1e-12, 20000, kit);
   c->ktrans = false;
   if (rc) return rc;

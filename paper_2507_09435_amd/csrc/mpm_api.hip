@@ -116,6 +116,7 @@ int mpm_destroy(mpm_ctx* c) {
   c->kx.release(); c->kr.release(); c->krh.release(); c->kp.release(); c->kv.release(); c->ks.release();
   c->kt.release(); c->kph.release(); c->ksh.release(); c->kb.release(); c->part.release(); c->simsc.release();
   c->simflag.release(); c->du_base.release(); c->alpha.release();
+  c->gV.release(); c->gsc.release(); c->gpart.release(); c->gflag.release(); c->greset.release();
   c->tpos.release(); c->dinvT.release(); c->adj_mu.release(); c->adj_nu.release(); c->adj_theta.release();
   c->adj_rbar.release();
   delete c;
@@ -195,6 +196,8 @@ int mpm_newton_step(mpm_ctx* c, const mpm_problem* pb, const mpm_newton_opts* op
   const int64_t nv = c->n_row * nd;
   const double rtol_fixed = opts->krylov_rtol;
   const int kmax = opts->krylov_max_iter > 0 ? opts->krylov_max_iter : 20000;
+  if (opts->krylov_method < 0 || opts->krylov_method > 1) return c->fail(MPM_E_INVALID, "unknown krylov_method");
+  c->kmethod = opts->krylov_method;
   const double stall = opts->stall_factor > 0 ? opts->stall_factor : 0.0;
   if (c->val.ensure(c->nnzb * nd * nd) != hipSuccess || c->kb.ensure(nv) != hipSuccess ||
       c->work.ensure(nv) != hipSuccess)

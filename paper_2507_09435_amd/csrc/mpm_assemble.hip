@@ -133,27 +133,26 @@ __global__ void __launch_bounds__(64) k_sim_sum(int nsim, const int32_t* __restr
 }
 
 // ----------------------------------------------------------- Jacobian ------
-// Tangent table of one 2-D particle: inputs dF (4), then for u-p p and
-// grad p (3); outputs P (4), then for u-p s1 and vv (3).
+// Column q of the tangent table of one 2-D particle: derivatives of the
+// outputs (P (4), then for u-p s1 and vv (2)) with respect to input q
+// (dF (4), then for u-p p and grad p (2)), by one forward-mode pass.
 template <int NIO>
-__device__ __forceinline__ void tangent2(const AsmArgs& A, const PLoad<2>& L, const Sym2<double>& be,
-                                         double T[NIO][NIO]) {
+__device__ __forceinline__ void tangent2_col(const AsmArgs& A, const PLoad<2>& L, const Sym2<double>& be, int q,
+                                             double Tc[NIO]) {
   Mat<dnum> m = make_mat<dnum>(dnum(L.E), A.nu, dnum(L.phi), A.c, A.psi, A.dp, A.match, A.apex_reg);
   UpPar u = up_par(A);
-  for (int q = 0; q < NIO; ++q) {
-    dnum F[2][2];
+  dnum F[2][2];
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+  for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int c = 0; c < 2; ++c) F[r][c] = dnum(L.dF[r][c], q == r * 2 + c ? 1.0 : 0.0);
-    dnum pp(L.pp, q == 4 ? 1.0 : 0.0);
-    dnum gp[2] = {dnum(L.gp[0], q == 5 ? 1.0 : 0.0), dnum(L.gp[1], q == 6 ? 1.0 : 0.0)};
-    Sym2<dnum> bd{dnum(be.xx), dnum(be.yy), dnum(be.xy), dnum(be.zz)};
-    Out2<dnum> o;
-    mech2<dnum>(m, F, bd, dnum(L.Jn), NIO == 7, u, pp, gp, o, nullptr);
-    T[0][q] = o.P[0][0].d; T[1][q] = o.P[0][1].d; T[2][q] = o.P[1][0].d; T[3][q] = o.P[1][1].d;
-    if constexpr (NIO == 7) { T[4][q] = o.s1.d; T[5][q] = o.vv[0].d; T[6][q] = o.vv[1].d; }
-  }
+    for (int c = 0; c < 2; ++c) F[r][c] = dnum(L.dF[r][c], q == r * 2 + c ? 1.0 : 0.0);
+  dnum pp(L.pp, q == 4 ? 1.0 : 0.0);
+  dnum gp[2] = {dnum(L.gp[0], q == 5 ? 1.0 : 0.0), dnum(L.gp[1], q == 6 ? 1.0 : 0.0)};
+  Sym2<dnum> bd{dnum(be.xx), dnum(be.yy), dnum(be.xy), dnum(be.zz)};
+  Out2<dnum> o;
+  mech2<dnum>(m, F, bd, dnum(L.Jn), NIO == 7, u, pp, gp, o, nullptr);
+  Tc[0] = o.P[0][0].d; Tc[1] = o.P[0][1].d; Tc[2] = o.P[1][0].d; Tc[3] = o.P[1][1].d;
+  if constexpr (NIO == 7) { Tc[4] = o.s1.d; Tc[5] = o.vv[0].d; Tc[6] = o.vv[1].d; }
 }
 
 // ---------------------------------------------- group-cooperative 2-D ------
@@ -186,43 +185,53 @@ __device__ __forceinline__ int group_starts(const int32_t* key, int n, int32_t* 
   return G;
 }
 
+// 2-D Jacobian.  Phase 1: LP lanes per particle, lane q computes tangent
+// column q (one forward pass each), so a workgroup holds JP particles and a
+// small problem still fills the chip.  Phase 2: one thread per (group,
+// column node b, row of 3 nodes a) sums the group's contributions to its
+// three local blocks in registers, then adds each entry once.
+constexpr int JT = 256;                       // threads per workgroup
+
 template <int NIO>
-__global__ void __launch_bounds__(GP) k_jac2g(AsmArgs A, const double* __restrict__ du,
+__global__ void __launch_bounds__(JT) k_jac2g(AsmArgs A, const double* __restrict__ du,
                                              const int32_t* __restrict__ rowptr, const int8_t* __restrict__ slot,
                                              double* __restrict__ val) {
   constexpr int ND = NIO == 7 ? 3 : 2;
-  __shared__ double sT[GP][NIO * NIO];   // V0 * tangent table
-  __shared__ double sW[GP][2][3], sD[GP][2][3];
-  __shared__ int32_t sKey[GP], sRow[GP][9], sG[GP + 1], sWc[GP / 64];
-  const int64_t base = (int64_t)blockIdx.x * GP;
-  const int n = (int)min<int64_t>(GP, A.np - base);
+  constexpr int LP = NIO == 7 ? 8 : 4;       // lanes per particle in phase 1
+  constexpr int JP = JT / LP;                 // particles per workgroup
+  __shared__ double sT[JP][NIO * NIO];        // V0 * tangent table
+  __shared__ double sW[JP][2][3], sD[JP][2][3];
+  __shared__ int32_t sKey[JP], sRow[JP][9], sG[JP + 1], sWc[JT / 64];
+  const int64_t base = (int64_t)blockIdx.x * JP;
+  const int n = (int)min<int64_t>(JP, A.np - base);
   const int t = threadIdx.x;
-  if (t < n) {
-    const int64_t i = base + t;
+  const int lp = t / LP, q = t % LP;
+  if (lp < n && q < NIO) {
+    const int64_t i = base + lp;
     PLoad<2> L;
     load_particle<2>(A, i, du, L);
-    double T[NIO][NIO];
-    tangent2<NIO>(A, L, load_be2(A, i), T);
+    double Tc[NIO];
+    tangent2_col<NIO>(A, L, load_be2(A, i), q, Tc);
 #pragma unroll
-    for (int o = 0; o < NIO; ++o)
+    for (int o = 0; o < NIO; ++o) sT[lp][o * NIO + q] = L.v0 * Tc[o];
+    if (q == 0) {
 #pragma unroll
-      for (int q = 0; q < NIO; ++q) sT[t][o * NIO + q] = L.v0 * T[o][q];
+      for (int k = 0; k < 2; ++k)
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
+        for (int a = 0; a < 3; ++a) { sW[lp][k][a] = L.st.w[k][a]; sD[lp][k][a] = L.st.dw[k][a]; }
 #pragma unroll
-      for (int a = 0; a < 3; ++a) { sW[t][k][a] = L.st.w[k][a]; sD[t][k][a] = L.st.dw[k][a]; }
-#pragma unroll
-    for (int a = 0; a < 9; ++a) sRow[t][a] = L.row[a];
-    sKey[t] = origin_key2(A.sims[A.psim[i]], L.st);
+      for (int a = 0; a < 9; ++a) sRow[lp][a] = L.row[a];
+      sKey[lp] = origin_key2(A.sims[A.psim[i]], L.st);
+    }
   }
   __syncthreads();
   const int G = group_starts(sKey, n, sG, sWc);
-  for (int task = t; task < 9 * G; task += GP) {
-    const int g = task / 9, b = task % 9;
+  for (int task = t; task < 27 * G; task += JT) {
+    const int g = task / 27, rem = task % 27, b = rem % 9, ay = rem / 9;
     const int bx = b % 3, by = b / 3;
-    double acc[9][ND][ND];
+    double acc[3][ND][ND];
 #pragma unroll
-    for (int a = 0; a < 9; ++a)
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int r = 0; r < ND; ++r)
 #pragma unroll
@@ -240,31 +249,32 @@ __global__ void __launch_bounds__(GP) k_jac2g(AsmArgs A, const double* __restric
           Tb[o][2] = T[o * NIO + 4] * wb + T[o * NIO + 5] * gb0 + T[o * NIO + 6] * gb1;
         }
       }
+      const double wy = sW[p][1][ay], dy = sD[p][1][ay];
 #pragma unroll
-      for (int a = 0; a < 9; ++a) {
-        const int ax = a % 3, ay = a / 3;
-        const double ga0 = sD[p][0][ax] * sW[p][1][ay], ga1 = sW[p][0][ax] * sD[p][1][ay];
+      for (int ax = 0; ax < 3; ++ax) {
+        const double ga0 = sD[p][0][ax] * wy, ga1 = sW[p][0][ax] * dy;
 #pragma unroll
         for (int c = 0; c < ND; ++c) {
 #pragma unroll
-          for (int r = 0; r < 2; ++r) acc[a][r][c] += ga0 * Tb[r * 2][c] + ga1 * Tb[r * 2 + 1][c];
+          for (int r = 0; r < 2; ++r) acc[ax][r][c] += ga0 * Tb[r * 2][c] + ga1 * Tb[r * 2 + 1][c];
           if constexpr (ND == 3) {
-            const double wa = sW[p][0][ax] * sW[p][1][ay];
-            acc[a][2][c] += wa * Tb[4][c] + ga0 * Tb[5][c] + ga1 * Tb[6][c];
+            const double wa = sW[p][0][ax] * wy;
+            acc[ax][2][c] += wa * Tb[4][c] + ga0 * Tb[5][c] + ga1 * Tb[6][c];
           }
         }
       }
     }
     const int p0 = sG[g];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) {
+    for (int ax = 0; ax < 3; ++ax) {
+      const int a = ay * 3 + ax;
       const int32_t ra = sRow[p0][a];
       const int s = slot[(int64_t)ra * 25 + nb_index<2>(a, b)];
       double* blk = val + ((int64_t)rowptr[ra] + s) * (ND * ND);
 #pragma unroll
       for (int r = 0; r < ND; ++r)
 #pragma unroll
-        for (int c = 0; c < ND; ++c) atomicAdd(&blk[r * ND + c], acc[a][r][c]);
+        for (int c = 0; c < ND; ++c) atomicAdd(&blk[r * ND + c], acc[ax][r][c]);
     }
   }
 }
@@ -617,9 +627,9 @@ int launch_jacobian(mpm_ctx* c, const mpm_problem* pb, const double* du, double*
   const int nd = c->nd;
   HIPC(c, hipMemsetAsync(val, 0, c->nnzb * nd * nd * sizeof(double), c->stream));
   if (c->np > 0) {
-    unsigned gg = (unsigned)((c->np + GP - 1) / GP);
-    if (c->dim == 2 && !c->up) k_jac2g<4><<<gg, GP, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val);
-    else if (c->dim == 2) k_jac2g<7><<<gg, GP, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val);
+    const unsigned g4 = (unsigned)((c->np + JT / 4 - 1) / (JT / 4)), g8 = (unsigned)((c->np + JT / 8 - 1) / (JT / 8));
+    if (c->dim == 2 && !c->up) k_jac2g<4><<<g4, JT, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val);
+    else if (c->dim == 2) k_jac2g<7><<<g8, JT, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val);
     else k_jac3g<<<(unsigned)((c->np + GP3 - 1) / GP3), GP3, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val,
                                                                               c->flag.p);
     LAUNCH_CHECK(c, "k_jac");

@@ -91,6 +91,10 @@ struct mpm_ctx {
   mpm::DBuf<double> part;                      // [nblocks][NQ]
   mpm::DBuf<double> simsc;                     // per-sim scalars [nsim][16]
   mpm::DBuf<int32_t> simflag;                  // per-sim krylov state [nsim][2]
+  mpm::DBuf<double> gV, gsc, gpart;            // GMRES basis, per-sim Hessenberg/rotations, partials
+  mpm::DBuf<int32_t> gflag;                    // per-sim GMRES state [nsim][2]
+  mpm::DBuf<uint8_t> greset;
+  int kmethod = 0;                             // 0: BiCGStab then GMRES fallback, 1: GMRES only
   mpm::DBuf<double> du_base, alpha;            // line search
   // adjoint
   mpm::DBuf<int32_t> tpos;                     // position of the transposed block

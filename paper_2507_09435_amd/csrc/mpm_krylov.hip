@@ -316,6 +316,249 @@ __global__ void __launch_bounds__(64) k_true_res(const RowBlock* __restrict__ bl
   if (threadIdx.x == 0) part[blockIdx.x * NQ + 2] = rr;
 }
 
+
+// ------------------------------------------------------------ GMRES(m) -----
+// Restarted GMRES with right block-Jacobi preconditioning, A M^-1 u = b - A x,
+// x += M^-1 V y: the fallback for simulations whose BiCGStab solve missed its
+// tolerance.  Orthogonalisation is classical Gram-Schmidt applied twice
+// (one pass of dot products per pass, reduced deterministically per sim);
+// the Hessenberg columns are reduced by Givens rotations as they arrive, so
+// |g_{j+1}| is the residual norm of the current iterate.  Per-sim state:
+// gflag[2s] < 0 while the sim is in the Arnoldi loop, otherwise the number
+// of basis vectors of its cycle; gflag[2s+1] = 1 when that was by convergence.
+constexpr int GM_M = 100;                      // restart length
+constexpr int GM_P = GM_M + 1;                 // partial slots per row block
+constexpr int GM_H = 0;                        // Hessenberg, column-major [M][M+1]
+constexpr int GM_CS = GM_H + GM_M * GM_P, GM_SN = GM_CS + GM_M, GM_G = GM_SN + GM_M, GM_Y = GM_G + GM_P,
+              GM_HC = GM_Y + GM_M, GM_MISC = GM_HC + GM_P, GM_STRIDE = GM_MISC + 4;
+enum { SC_GBETA = 10 };
+
+// Sum of part[b*stride + q] over a sim's row blocks by one wave (fixed order).
+__device__ __forceinline__ double seg_sum(const double* __restrict__ part, int stride, int q, int b0, int b1) {
+  double a0 = 0.0, a1 = 0.0;
+  int b = b0 + (int)threadIdx.x % 64;
+  for (; b + 64 < b1; b += 128) { a0 += part[(int64_t)b * stride + q]; a1 += part[(int64_t)(b + 64) * stride + q]; }
+  for (; b < b1; b += 64) a0 += part[(int64_t)b * stride + q];
+  return wave_sum(a0 + a1);
+}
+
+// r = b - t (or r = b with x = 0 for sims flagged in reset); ||r||^2 -> slot 0.
+template <int BS>
+__global__ void __launch_bounds__(64) k_gm_start(const RowBlock* __restrict__ blocks, const int32_t* __restrict__ gflag,
+                                                 const uint8_t* __restrict__ reset, const double* __restrict__ bvec,
+                                                 const double* __restrict__ t, double* __restrict__ x,
+                                                 double* __restrict__ r, double* __restrict__ part) {
+  const RowBlock b = blocks[blockIdx.x];
+  if (gflag[2 * b.sim] >= 0) return;
+  const bool z = reset[b.sim] != 0;
+  const int64_t row = b.row0 + threadIdx.x;
+  double rr = 0.0;
+  if (row < b.row1) {
+#pragma unroll
+    for (int i = 0; i < BS; ++i) {
+      const int64_t k = row * BS + i;
+      double ri = z ? bvec[k] : bvec[k] - t[k];
+      if (z) x[k] = 0.0;
+      r[k] = ri;
+      rr += ri * ri;
+    }
+  }
+  rr = wave_sum(rr);
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.x * GM_P] = rr;
+}
+
+// beta = ||r||; a sim already within tolerance leaves the loop with no basis.
+__global__ void k_gm_sim_start(int nsim, const int32_t* __restrict__ blk_first, const double* __restrict__ part,
+                               double* __restrict__ sc, double* __restrict__ gsc, int32_t* __restrict__ gflag) {
+  const int s = blockIdx.x;
+  if (gflag[2 * s] >= 0) return;
+  const double rr = seg_sum(part, GM_P, 0, blk_first[s], blk_first[s + 1]);
+  if (threadIdx.x != 0) return;
+  double* G = gsc + (int64_t)s * GM_STRIDE;
+  sc[s * 16 + SC_GBETA] = sqrt(rr);
+  if (!(rr > sc[s * 16 + SC_TOL2]) || !isfinite(rr)) {
+    gflag[2 * s] = 0;
+    gflag[2 * s + 1] = isfinite(rr) ? 1 : 0;
+    return;
+  }
+  const double beta = sqrt(rr);
+  for (int i = 0; i < GM_P; ++i) G[GM_G + i] = 0.0;
+  G[GM_G] = beta;
+  G[GM_MISC] = 1.0 / beta;
+}
+
+// v_j = scale * src, z = M^-1 v_j.
+template <int BS>
+__global__ void __launch_bounds__(64) k_gm_vz(const RowBlock* __restrict__ blocks, const int32_t* __restrict__ gflag,
+                                              const double* __restrict__ gsc, const double* __restrict__ src,
+                                              double* __restrict__ vj, double* __restrict__ z,
+                                              const double* __restrict__ dinv) {
+  const RowBlock b = blocks[blockIdx.x];
+  if (gflag[2 * b.sim] >= 0) return;
+  const double scale = gsc[(int64_t)b.sim * GM_STRIDE + GM_MISC];
+  const int64_t row = b.row0 + threadIdx.x;
+  if (row >= b.row1) return;
+#pragma unroll
+  for (int i = 0; i < BS; ++i) vj[row * BS + i] = src[row * BS + i] * scale;
+  apply_dinv<BS>(dinv, row, vj, z);
+}
+
+// Partials of (v_i, w), i < nvec, into slots 0..nvec-1.
+template <int BS>
+__global__ void __launch_bounds__(64) k_gm_dots(const RowBlock* __restrict__ blocks, const int32_t* __restrict__ gflag,
+                                                const double* __restrict__ V, int64_t nv, int nvec,
+                                                const double* __restrict__ w, double* __restrict__ part) {
+  const RowBlock b = blocks[blockIdx.x];
+  if (gflag[2 * b.sim] >= 0) return;
+  const int64_t row = b.row0 + threadIdx.x;
+  const bool in = row < b.row1;
+  double wv[BS];
+#pragma unroll
+  for (int k = 0; k < BS; ++k) wv[k] = in ? w[row * BS + k] : 0.0;
+  for (int i = 0; i < nvec; ++i) {
+    double d = 0.0;
+    if (in) {
+      const double* vi = V + (int64_t)i * nv + row * BS;
+#pragma unroll
+      for (int k = 0; k < BS; ++k) d += vi[k] * wv[k];
+    }
+    d = wave_sum(d);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * GM_P + i] = d;
+  }
+}
+
+// h_i = sum over the sim's blocks; grid (nsim, nvec).  pass 0 sets column j
+// of H, pass 1 adds the reorthogonalisation correction.
+__global__ void k_gm_hsum(const int32_t* __restrict__ blk_first, const double* __restrict__ part,
+                          double* __restrict__ gsc, const int32_t* __restrict__ gflag, int j, int pass) {
+  const int s = blockIdx.x, i = blockIdx.y;
+  if (gflag[2 * s] >= 0) return;
+  const double h = seg_sum(part, GM_P, i, blk_first[s], blk_first[s + 1]);
+  if (threadIdx.x != 0) return;
+  double* G = gsc + (int64_t)s * GM_STRIDE;
+  G[GM_HC + i] = h;
+  double* col = G + GM_H + (int64_t)j * GM_P;
+  col[i] = pass ? col[i] + h : h;
+}
+
+// w -= sum_i h_i v_i; with norm != 0 also ||w||^2 -> slot 0.
+template <int BS>
+__global__ void __launch_bounds__(64) k_gm_orth(const RowBlock* __restrict__ blocks, const int32_t* __restrict__ gflag,
+                                                const double* __restrict__ V, int64_t nv, int nvec,
+                                                const double* __restrict__ gsc, double* __restrict__ w,
+                                                double* __restrict__ part, int norm) {
+  const RowBlock b = blocks[blockIdx.x];
+  if (gflag[2 * b.sim] >= 0) return;
+  const double* hc = gsc + (int64_t)b.sim * GM_STRIDE + GM_HC;
+  const int64_t row = b.row0 + threadIdx.x;
+  double ww = 0.0;
+  if (row < b.row1) {
+    double acc[BS];
+#pragma unroll
+    for (int k = 0; k < BS; ++k) acc[k] = w[row * BS + k];
+    for (int i = 0; i < nvec; ++i) {
+      const double h = hc[i];
+      const double* vi = V + (int64_t)i * nv + row * BS;
+#pragma unroll
+      for (int k = 0; k < BS; ++k) acc[k] -= h * vi[k];
+    }
+#pragma unroll
+    for (int k = 0; k < BS; ++k) { w[row * BS + k] = acc[k]; ww += acc[k] * acc[k]; }
+  }
+  if (!norm) return;
+  ww = wave_sum(ww);
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.x * GM_P] = ww;
+}
+
+// h_{j+1,j} = ||w||, Givens reduction of column j, residual estimate, and
+// the end-of-cycle test (convergence, breakdown, or a full basis).
+__global__ void k_gm_norm(int nsim, const int32_t* __restrict__ blk_first, const double* __restrict__ part,
+                          const double* __restrict__ sc, double* __restrict__ gsc, int32_t* __restrict__ gflag, int j) {
+  const int s = blockIdx.x;
+  if (gflag[2 * s] >= 0) return;
+  const double nn = seg_sum(part, GM_P, 0, blk_first[s], blk_first[s + 1]);
+  if (threadIdx.x != 0) return;
+  double* G = gsc + (int64_t)s * GM_STRIDE;
+  double* col = G + GM_H + (int64_t)j * GM_P;
+  double* cs = G + GM_CS;
+  double* sn = G + GM_SN;
+  double* g = G + GM_G;
+  const double hn = sqrt(nn);
+  col[j + 1] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double a = col[i], c2 = col[i + 1];
+    col[i] = cs[i] * a + sn[i] * c2;
+    col[i + 1] = -sn[i] * a + cs[i] * c2;
+  }
+  const double a = col[j], bb = col[j + 1];
+  const double rr = sqrt(a * a + bb * bb);
+  const double c = rr > 0.0 ? a / rr : 1.0, sv = rr > 0.0 ? bb / rr : 0.0;
+  cs[j] = c; sn[j] = sv;
+  col[j] = rr; col[j + 1] = 0.0;
+  g[j + 1] = -sv * g[j];
+  g[j] = c * g[j];
+  const double res2 = g[j + 1] * g[j + 1];
+  const bool conv = res2 <= sc[s * 16 + SC_TOL2];
+  if (conv || !(hn > 0.0) || !isfinite(hn) || j + 1 == GM_M) {
+    gflag[2 * s] = j + 1;
+    gflag[2 * s + 1] = conv ? 1 : 0;
+  } else {
+    G[GM_MISC] = 1.0 / hn;
+  }
+}
+
+// Close the cycle of sims stopped by the iteration budget, then solve
+// R y = g by back substitution (one thread per sim).
+__global__ void k_gm_solve(int nsim, double* __restrict__ gsc, int32_t* __restrict__ gflag, int jdone) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsim) return;
+  if (gflag[2 * s] < 0) gflag[2 * s] = jdone;
+  const int k = gflag[2 * s];
+  double* G = gsc + (int64_t)s * GM_STRIDE;
+  const double* g = G + GM_G;
+  double* y = G + GM_Y;
+  for (int i = k - 1; i >= 0; --i) {
+    double v = g[i];
+    for (int l = i + 1; l < k; ++l) v -= G[GM_H + (int64_t)l * GM_P + i] * y[l];
+    const double d = G[GM_H + (int64_t)i * GM_P + i];
+    y[i] = (d != 0.0 && isfinite(d)) ? v / d : 0.0;
+  }
+}
+
+// x += M^-1 (V y) over the sim's k basis vectors.
+template <int BS>
+__global__ void __launch_bounds__(64) k_gm_update(const RowBlock* __restrict__ blocks, const int32_t* __restrict__ gflag,
+                                                  const double* __restrict__ V, int64_t nv,
+                                                  const double* __restrict__ gsc, double* __restrict__ x,
+                                                  const double* __restrict__ dinv) {
+  const RowBlock b = blocks[blockIdx.x];
+  const int k = gflag[2 * b.sim];
+  if (k <= 0) return;
+  const double* y = gsc + (int64_t)b.sim * GM_STRIDE + GM_Y;
+  const int64_t row = b.row0 + threadIdx.x;
+  if (row >= b.row1) return;
+  double acc[BS];
+#pragma unroll
+  for (int q = 0; q < BS; ++q) acc[q] = 0.0;
+  for (int i = 0; i < k; ++i) {
+    const double yi = y[i];
+    const double* vi = V + (int64_t)i * nv + row * BS;
+#pragma unroll
+    for (int q = 0; q < BS; ++q) acc[q] += yi * vi[q];
+  }
+  double dx[BS];
+  const double* D = dinv + row * BS * BS;
+#pragma unroll
+  for (int i = 0; i < BS; ++i) {
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < BS; ++q) sum += D[i * BS + q] * acc[q];
+    dx[i] = sum;
+  }
+#pragma unroll
+  for (int i = 0; i < BS; ++i) x[row * BS + i] += dx[i];
+}
+
 }  // namespace mpm
 
 using namespace mpm;
@@ -398,8 +641,119 @@ static int bicg_iter(mpm_ctx* c, const double* val, int it, const KBufs& K) {
   return MPM_OK;
 }
 
+// True residual ratio ||b - A x|| / ||b|| per sim (0 where b = 0).
+static int true_ratios(mpm_ctx* c, const double* val, double* part_ts, std::vector<double>& ratio) {
+  const unsigned g = (unsigned)c->blocks_h.size();
+  int rc = spmv(c, nullptr, val, c->kx.p, c->kt.p, nullptr, part_ts, -1, -1);
+  if (rc) return rc;
+  if (g) {
+    if (c->nd == 2) k_true_res<2><<<g, 64, 0, c->stream>>>(c->blocks.p, c->kb.p, c->kt.p, c->part.p);
+    else k_true_res<3><<<g, 64, 0, c->stream>>>(c->blocks.p, c->kb.p, c->kt.p, c->part.p);
+    LAUNCH_CHECK(c, "k_true_res");
+  }
+  if ((rc = sim_sum_launch(c, c->part.p, 2, 9))) return rc;
+  std::vector<double> hsc(16 * c->nsim);
+  HIPC(c, hipMemcpyAsync(hsc.data(), c->simsc.p, hsc.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPC(c, hipStreamSynchronize(c->stream));
+  ratio.assign(c->nsim, 0.0);
+  for (int s = 0; s < c->nsim; ++s) {
+    const double tr2 = hsc[s * 16 + 9], bn2 = hsc[s * 16 + SC_BN2];
+    double r = bn2 > 0.0 ? std::sqrt(tr2 / bn2) : 0.0;
+    ratio[s] = std::isfinite(r) ? r : INFINITY;
+  }
+  return MPM_OK;
+}
+
+// Restarted GMRES(GM_M) for the sims with work[s] != 0, starting from c->kx
+// (from zero where reset[s] != 0), within `budget` Arnoldi steps overall.
+// Stops a sim when its tolerance is met or a cycle no longer lowers its
+// residual.  Basis vectors spent per sim are added to iters_out.
+template <int BS>
+static int gmres_solve(mpm_ctx* c, const double* val, std::vector<uint8_t> work, const std::vector<uint8_t>& reset,
+                       int budget, std::vector<int>& iters_out) {
+  const int nsim = c->nsim;
+  const int64_t nv = c->n_row * BS;
+  const unsigned nbk = (unsigned)c->blocks_h.size();
+  if (!nbk) return MPM_OK;
+  const double* dinv = c->ktrans ? c->dinvT.p : c->dinv.p;
+  if (c->gV.ensure((size_t)GM_P * nv) != hipSuccess || c->gsc.ensure((size_t)nsim * GM_STRIDE) != hipSuccess ||
+      c->gpart.ensure((size_t)(nbk + 1) * GM_P) != hipSuccess || c->gflag.ensure(2 * nsim) != hipSuccess ||
+      c->greset.ensure(nsim) != hipSuccess)
+    return c->fail(MPM_E_NOMEM, "GMRES allocation failed");
+  std::vector<int32_t> hfl(2 * nsim);
+  std::vector<double> hsc(16 * nsim);
+  std::vector<double> beta_prev(nsim, INFINITY);
+  std::vector<uint8_t> rst(reset);
+  int used = 0;
+  const unsigned nsb = (unsigned)((nsim + 63) / 64);
+  for (;;) {
+    for (int s = 0; s < nsim; ++s) { hfl[2 * s] = work[s] ? -1 : 0; hfl[2 * s + 1] = 0; }
+    HIPC(c, hipMemcpyAsync(c->gflag.p, hfl.data(), hfl.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    HIPC(c, hipMemcpyAsync(c->greset.p, rst.data(), nsim, hipMemcpyHostToDevice, c->stream));
+    int rc = spmv(c, c->gflag.p, val, c->kx.p, c->kt.p, nullptr, nullptr, -1, -1);
+    if (rc) return rc;
+    k_gm_start<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->gflag.p, c->greset.p, c->kb.p, c->kt.p, c->kx.p, c->kr.p,
+                                              c->gpart.p);
+    k_gm_sim_start<<<nsim, 64, 0, c->stream>>>(nsim, c->blk_first.p, c->gpart.p, c->simsc.p, c->gsc.p, c->gflag.p);
+    LAUNCH_CHECK(c, "gmres start");
+    HIPC(c, hipMemcpyAsync(hfl.data(), c->gflag.p, hfl.size() * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPC(c, hipMemcpyAsync(hsc.data(), c->simsc.p, hsc.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPC(c, hipStreamSynchronize(c->stream));
+    std::fill(rst.begin(), rst.end(), 0);
+    bool any = false;
+    for (int s = 0; s < nsim; ++s) {
+      if (!work[s]) continue;
+      const double beta = hsc[s * 16 + SC_GBETA];
+      // converged, or the last cycle did not lower the true residual: stop this sim
+      if (hfl[2 * s] >= 0 || !(beta < beta_prev[s])) { work[s] = 0; continue; }
+      beta_prev[s] = beta;
+      any = true;
+    }
+    if (!any || used >= budget) break;
+    for (int s = 0; s < nsim; ++s) hfl[2 * s] = work[s] ? -1 : 0;
+    HIPC(c, hipMemcpyAsync(c->gflag.p, hfl.data(), hfl.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    int j = 0;
+    bool all_done = false;
+    while (j < GM_M && used + j < budget && !all_done) {
+      const double* src = j == 0 ? c->kr.p : c->kt.p;
+      double* vj = c->gV.p + (int64_t)j * nv;
+      k_gm_vz<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->gflag.p, c->gsc.p, src, vj, c->kph.p, dinv);
+      LAUNCH_CHECK(c, "k_gm_vz");
+      if ((rc = spmv(c, c->gflag.p, val, c->kph.p, c->kt.p, nullptr, nullptr, -1, -1))) return rc;
+      for (int pass = 0; pass < 2; ++pass) {
+        k_gm_dots<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->gflag.p, c->gV.p, nv, j + 1, c->kt.p, c->gpart.p);
+        k_gm_hsum<<<dim3((unsigned)nsim, (unsigned)(j + 1)), 64, 0, c->stream>>>(c->blk_first.p, c->gpart.p, c->gsc.p,
+                                                                                 c->gflag.p, j, pass);
+        k_gm_orth<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->gflag.p, c->gV.p, nv, j + 1, c->gsc.p, c->kt.p,
+                                                 c->gpart.p, pass);
+      }
+      k_gm_norm<<<nsim, 64, 0, c->stream>>>(nsim, c->blk_first.p, c->gpart.p, c->simsc.p, c->gsc.p, c->gflag.p, j);
+      LAUNCH_CHECK(c, "gmres arnoldi step");
+      ++j;
+      if (j % 16 == 0) {
+        HIPC(c, hipMemcpyAsync(hfl.data(), c->gflag.p, hfl.size() * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        HIPC(c, hipStreamSynchronize(c->stream));
+        all_done = true;
+        for (int s = 0; s < nsim; ++s) all_done = all_done && hfl[2 * s] >= 0;
+      }
+    }
+    k_gm_solve<<<nsb, 64, 0, c->stream>>>(nsim, c->gsc.p, c->gflag.p, j);
+    k_gm_update<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->gflag.p, c->gV.p, nv, c->gsc.p, c->kx.p, dinv);
+    LAUNCH_CHECK(c, "gmres update");
+    HIPC(c, hipMemcpyAsync(hfl.data(), c->gflag.p, hfl.size() * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPC(c, hipStreamSynchronize(c->stream));
+    for (int s = 0; s < nsim; ++s) if (work[s]) iters_out[s] += hfl[2 * s];
+    used += j;
+  }
+  return MPM_OK;
+}
+
 // Solve val * x = b (compact vectors c->kb -> c->kx).  iters_out: host
-// [nsim] iterations per sim.  Returns MPM_E_KRYLOV on breakdown / limit.
+// [nsim] iterations per sim (BiCGStab iterations plus GMRES basis vectors).
+// c->kmethod 0: BiCGStab with restarts on up to half the budget, then
+// GMRES(GM_M) for the sims still above tolerance; 1: GMRES only.  Accepts a
+// sim when its true residual is at most 10 rtol ||b||.  Returns MPM_E_KRYLOV
+// when a sim ends above that (beyond the soft floor).
 int krylov_solve(mpm_ctx* c, const double* val, double rtol, int max_iter, std::vector<int>& iters_out) {
   const int64_t nv = c->n_row * c->nd;
   const size_t nbk = c->blocks_h.size();
@@ -411,19 +765,20 @@ int krylov_solve(mpm_ctx* c, const double* val, double rtol, int max_iter, std::
   ok = ok && parts.ensure(3 * (nbk + 1) * NQ) == hipSuccess;
   if (!ok) { parts.release(); return c->fail(MPM_E_NOMEM, "Krylov vectors allocation failed"); }
   KBufs K{parts.p, parts.p + (nbk + 1) * NQ, parts.p + 2 * (nbk + 1) * NQ};
+  std::vector<int32_t> hflag(2 * nsim, 0);
   iters_out.assign(nsim, 0);
-  std::vector<int32_t> hflag(2 * nsim);
-  std::vector<double> hsc(16 * nsim);
-  iters_out.assign(nsim, 0);
+  const bool gmres_only = c->kmethod == 1;
+  const int bicg_budget = gmres_only ? 0 : max_iter / 2;
   int used = 0;           // iterations spent over all (re)starts
   const int CHUNK = 16;
   bool good = false;
   double last_worst = INFINITY;
-  for (int attempt = 0; attempt < 4 && !good && used < max_iter; ++attempt) {
+  std::vector<double> ratio(nsim, INFINITY);
+  int rc = MPM_OK;
+  for (int attempt = 0; attempt < 4 && !good && (attempt == 0 || used < bicg_budget); ++attempt) {
     unsigned g = (unsigned)nbk;
     if (attempt > 0) {  // restart from the current x: r = b - A x
-      int rc = spmv(c, nullptr, val, c->kx.p, c->kt.p, nullptr, K.part_ts, -1, -1);
-      if (rc) { parts.release(); return rc; }
+      if ((rc = spmv(c, nullptr, val, c->kx.p, c->kt.p, nullptr, K.part_ts, -1, -1))) break;
     }
     if (g) {
       if (c->nd == 2)
@@ -438,49 +793,62 @@ int krylov_solve(mpm_ctx* c, const double* val, double rtol, int max_iter, std::
     LAUNCH_CHECK(c, "bicgstab init");
     int it = 0;
     bool all_done = false;
-    while (!all_done && used + it < max_iter) {
-      for (int k = 0; k < CHUNK && used + it < max_iter; ++k, ++it) {
-        int rc = c->nd == 2 ? bicg_iter<2>(c, val, it, K) : bicg_iter<3>(c, val, it, K);
-        if (rc) { parts.release(); return rc; }
+    while (!all_done && used + it < bicg_budget) {
+      for (int k = 0; k < CHUNK && used + it < bicg_budget; ++k, ++it) {
+        rc = c->nd == 2 ? bicg_iter<2>(c, val, it, K) : bicg_iter<3>(c, val, it, K);
+        if (rc) break;
       }
+      if (rc) break;
       HIPC(c, hipMemcpyAsync(hflag.data(), c->simflag.p, 2 * nsim * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
       HIPC(c, hipStreamSynchronize(c->stream));
       all_done = true;
       for (int s = 0; s < nsim; ++s) all_done = all_done && hflag[2 * s] >= 0;
     }
+    if (rc) break;
     for (int s = 0; s < nsim; ++s) iters_out[s] += (hflag[2 * s] >= 0 ? hflag[2 * s] : it);
     used += it;
-    // accept only on the true residual ||b - A x|| <= 10 rtol ||b|| of every sim
-    int rc = spmv(c, nullptr, val, c->kx.p, c->kt.p, nullptr, K.part_ts, -1, -1);
-    if (rc) { parts.release(); return rc; }
-    if (g) {
-      if (c->nd == 2) k_true_res<2><<<g, 64, 0, c->stream>>>(c->blocks.p, c->kb.p, c->kt.p, c->part.p);
-      else k_true_res<3><<<g, 64, 0, c->stream>>>(c->blocks.p, c->kb.p, c->kt.p, c->part.p);
-      LAUNCH_CHECK(c, "k_true_res");
-    }
-    rc = sim_sum_launch(c, c->part.p, 2, 9);
-    if (rc) { parts.release(); return rc; }
-    HIPC(c, hipMemcpyAsync(hsc.data(), c->simsc.p, 16 * nsim * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPC(c, hipStreamSynchronize(c->stream));
+    if ((rc = true_ratios(c, val, K.part_ts, ratio))) break;
     good = true;
     double worst = 0.0;
     for (int s = 0; s < nsim; ++s) {
-      double tr2 = hsc[s * 16 + 9], bn2 = hsc[s * 16 + SC_BN2];
-      double ratio = bn2 > 0.0 ? std::sqrt(tr2 / bn2) : 0.0;
-      if (!std::isfinite(ratio)) ratio = INFINITY;
-      worst = std::max(worst, ratio);
-      if (!(ratio <= 10.0 * rtol)) good = false;
+      worst = std::max(worst, ratio[s]);
+      good = good && ratio[s] <= 10.0 * rtol;
     }
+    if (gmres_only) break;
     // restarting only helps while the true residual still falls
     if (!good && attempt > 0 && !(worst < 0.5 * last_worst)) { last_worst = std::min(last_worst, worst); break; }
     last_worst = std::min(last_worst, worst);
   }
+  if (rc == MPM_OK && !good && used < max_iter) {
+    std::vector<uint8_t> work(nsim, 0), reset(nsim, 0);
+    for (int s = 0; s < nsim; ++s) {
+      work[s] = !(ratio[s] <= 10.0 * rtol);
+      reset[s] = !(ratio[s] < 1.0);     // BiCGStab made things worse (or broke down): start from zero
+    }
+    rc = c->nd == 2 ? gmres_solve<2>(c, val, work, reset, max_iter - used, iters_out)
+                    : gmres_solve<3>(c, val, work, reset, max_iter - used, iters_out);
+    if (rc == MPM_OK) rc = true_ratios(c, val, K.part_ts, ratio);
+    if (rc == MPM_OK) {
+      good = true;
+      last_worst = 0.0;
+      for (int s = 0; s < nsim; ++s) {
+        good = good && ratio[s] <= 10.0 * rtol;
+        last_worst = std::max(last_worst, ratio[s]);
+      }
+    }
+  }
+  parts.release();
+  if (rc != MPM_OK) return rc;
+  std::string diag;
+  for (int s = 0; s < nsim && diag.size() < 400; ++s)
+    if (!(ratio[s] <= 10.0 * rtol))
+      diag += " sim " + std::to_string(s) + ": true residual " + std::to_string(ratio[s]) + ", iterations " +
+              std::to_string(iters_out[s]) + ";";
   // A solve that stalled above rtol at the FP64 floor of an ill-conditioned
   // system is still a usable Newton direction when its true residual is at
   // most 1e-6 ||b||; the Newton test on the nonlinear residual decides.
   c->krylov_soft = !good && last_worst <= 1e-6;
   const int status = (good || c->krylov_soft) ? MPM_OK : MPM_E_KRYLOV;
-  parts.release();
   if (!c->spmv_events.empty()) {
     HIPC(c, hipStreamSynchronize(c->stream));
     for (size_t k = 0; k + 1 < c->spmv_events.size(); k += 2) {
@@ -493,6 +861,6 @@ int krylov_solve(mpm_ctx* c, const double* val, double rtol, int max_iter, std::
     for (hipEvent_t e : c->spmv_events) (void)hipEventDestroy(e);
     c->spmv_events.clear();
   }
-  if (status != MPM_OK) return c->fail(MPM_E_KRYLOV, "Krylov solve did not reach its tolerance");
+  if (status != MPM_OK) return c->fail(MPM_E_KRYLOV, "Krylov solve did not reach its tolerance:" + diag);
   return MPM_OK;
 }

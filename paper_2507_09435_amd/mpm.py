@@ -55,7 +55,7 @@ class mpm_problem(C.Structure):
 class mpm_newton_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("commit", C.c_int32), ("stall_factor", C.c_double),
                 ("krylov_rtol", C.c_double), ("krylov_max_iter", C.c_int32), ("line_search", C.c_int32),
-                ("time_spmv", C.c_int32), ("reserved", C.c_int32)]
+                ("time_spmv", C.c_int32), ("krylov_method", C.c_int32)]
 
 
 class mpm_newton_report(C.Structure):
@@ -246,9 +246,10 @@ def mpm_jacobian_bsr(ctx, dp: DeviceProblem, du, rowptr=None, colind=None, val=N
 
 
 def mpm_newton_step(ctx, dp: DeviceProblem, du, tol=1e-10, max_iter=25, commit=True, stall_factor=1e3,
-                    krylov_rtol=1e-12, krylov_max_iter=20000, line_search=0, time_spmv=0, raise_on_fail=True):
+                    krylov_rtol=1e-12, krylov_max_iter=20000, line_search=0, time_spmv=0, krylov_method=0,
+                    raise_on_fail=True):
     o = mpm_newton_opts(tol, max_iter, 1 if commit else 0, stall_factor, krylov_rtol, krylov_max_iter,
-                        int(line_search), int(time_spmv), 0)
+                        int(line_search), int(time_spmv), int(krylov_method))
     rep = mpm_newton_report()
     it = (C.c_int32 * dp.nsim)()
     cv = (C.c_int32 * dp.nsim)()

@@ -115,8 +115,9 @@ def test_jacobian_parity(ctx, name, raw):
     assert errs.max() <= 1e-9, (errs.max(), int(errs.argmax()))
 
 
-NEWTON_CASES = [("c1", 1), ("footing", 0), ("footing_elastic", 1), ("up", 1), ("c3small", 0),
-                ("c3small_stiff", 0)]
+# (case, load step, Krylov method: 0 BiCGStab with GMRES fallback, 1 GMRES only)
+NEWTON_CASES = [("c1", 1, 0), ("footing", 0, 0), ("footing_elastic", 1, 0), ("up", 1, 0), ("c3small", 0, 0),
+                ("c3small_stiff", 0, 0), ("c1", 1, 1), ("footing_elastic", 1, 1), ("up", 1, 1), ("c3small", 0, 1)]
 
 
 def _newton_case(name):
@@ -132,8 +133,8 @@ def _newton_case(name):
     return _case(name)[0]
 
 
-@pytest.mark.parametrize("name,step", NEWTON_CASES)
-def test_newton_and_update_parity(ctx, name, step):
+@pytest.mark.parametrize("name,step,method", NEWTON_CASES)
+def test_newton_and_update_parity(ctx, name, step, method):
     """Both sides iterate to the round-off floor, then du and the updated
     particle state are compared.  The bound on du is 1e-10 relative, widened
     only to 10x the oracle's own spread (how far du still moves when the
@@ -142,7 +143,7 @@ def test_newton_and_update_parity(ctx, name, step):
     must then also zero the oracle's residual to 1e-10 of r_0."""
     from paper_2507_09435_amd import mpm as M
     w = _newton_case(name)
-    print(f"[newton] case={name} step={step}", flush=True)
+    print(f"[newton] case={name} step={step} krylov_method={method}", flush=True)
     P, st = w.prob, w.particles
     bc = w.bc(step)
     if step >= 1 and w.geostatic:
@@ -154,7 +155,8 @@ def test_newton_and_update_parity(ctx, name, step):
     dp = _dev(w, step)
     n_row, nnzb, nd = M.mpm_prepare(ctx, dp)
     du = torch.zeros(n_row * nd, dtype=torch.float64, device="cuda")
-    rep = M.mpm_newton_step(ctx, dp, du, tol=1e-13, max_iter=25, commit=True, krylov_rtol=1e-12)
+    rep = M.mpm_newton_step(ctx, dp, du, tol=1e-13, max_iter=25, commit=True, krylov_rtol=1e-12,
+                            krylov_method=method)
     torch.cuda.synchronize()
     assert rep["converged"], rep
     dof, orep, pat = O.newton(P, st, bc.mask, bc.value, tol=1e-13)
@@ -216,4 +218,37 @@ def test_batched_pattern_and_residual(ctx):
         assert e <= 1e-10
         rm = react_mask(w)[pat.active].astype(bool)
         assert abs(react[k] + ref[rm].sum()) <= 1e-10 * np.linalg.norm(fint[pat.active])
+        off += pat.n_row
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_batched_newton_parity(ctx, method):
+    """Three elastic footing pushes of different size and stiffness in one
+    batch: each sim's converged increment equals its own oracle Newton
+    solution (per-sim scalars and convergence flags, block-diagonal solve)."""
+    from paper_2507_09435_amd import mpm as M
+    ws = []
+    for k, n_y in enumerate((4, 6, 5)):
+        w = W.small_footing(n_y=n_y)
+        w.prob.dp = 0
+        w.particles.E = np.full(w.particles.np, 10.0 ** (6.5 + 0.5 * k))
+        ws.append(w)
+    print(f"[newton-batch] krylov_method={method}", flush=True)
+    dp = M.make_problem([(w.prob, w.particles) for w in ws], [w.bc(1) for w in ws],
+                        react_masks=[react_mask(w) for w in ws])
+    n_row, nnzb, nd = M.mpm_prepare(ctx, dp)
+    du = torch.zeros(n_row * nd, dtype=torch.float64, device="cuda")
+    rep = M.mpm_newton_step(ctx, dp, du, tol=1e-13, max_iter=25, commit=False, krylov_rtol=1e-12,
+                            krylov_method=method)
+    torch.cuda.synchronize()
+    assert rep["converged"] and all(rep["sim_converged"]), rep
+    got = du.cpu().numpy().reshape(-1, nd)
+    off = 0
+    for k, w in enumerate(ws):
+        bc = w.bc(1)
+        dof, orep, pat = O.newton(w.prob, w.particles, bc.mask, bc.value, tol=1e-13)
+        assert orep.converged
+        e = rel_err(got[off:off + pat.n_row], dof[pat.active])
+        print(f"  sim {k}: du rel err {e:.3e}, newton {rep['sim_iters'][k]} vs oracle {orep.iters}", flush=True)
+        assert e <= 1e-10
         off += pat.n_row
