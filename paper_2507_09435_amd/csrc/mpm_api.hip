@@ -115,7 +115,7 @@ int mpm_destroy(mpm_ctx* c) {
   c->work.release(); c->val.release(); c->dinv.release();
   c->kx.release(); c->kr.release(); c->krh.release(); c->kp.release(); c->kv.release(); c->ks.release();
   c->kt.release(); c->kph.release(); c->ksh.release(); c->kb.release(); c->part.release(); c->simsc.release();
-  c->simflag.release(); c->du_base.release(); c->alpha.release();
+  c->simflag.release(); c->kcnt.release(); c->du_base.release(); c->alpha.release();
   c->gV.release(); c->gsc.release(); c->gpart.release(); c->gflag.release(); c->greset.release();
   c->tpos.release(); c->dinvT.release(); c->adj_mu.release(); c->adj_nu.release(); c->adj_theta.release();
   c->adj_rbar.release();

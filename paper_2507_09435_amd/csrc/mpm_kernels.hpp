@@ -91,6 +91,7 @@ struct mpm_ctx {
   mpm::DBuf<double> part;                      // [nblocks][NQ]
   mpm::DBuf<double> simsc;                     // per-sim scalars [nsim][16]
   mpm::DBuf<int32_t> simflag;                  // per-sim krylov state [nsim][2]
+  mpm::DBuf<int32_t> kcnt;                     // per-sim arrival counters of fused reductions (kept 0)
   mpm::DBuf<double> gV, gsc, gpart;            // GMRES basis, per-sim Hessenberg/rotations, partials
   mpm::DBuf<int32_t> gflag;                    // per-sim GMRES state [nsim][2]
   mpm::DBuf<uint8_t> greset;

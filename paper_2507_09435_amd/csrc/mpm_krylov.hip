@@ -12,7 +12,7 @@ namespace mpm {
 
 // per-sim scalar slots
 enum { SC_RN2 = 0, SC_REACT = 1, SC_BN2 = 2, SC_RHO = 3 /* 3,4 */, SC_ALPHA = 5, SC_OMEGA = 6, SC_TOL2 = 7,
-       SC_RR = 8 };
+       SC_RR = 8, SC_TRUE = 9, SC_GBETA = 10, SC_RV = 11, SC_TS = 12, SC_TT = 13, SC_RHR = 14, SC_RRN = 15 };
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -35,8 +35,32 @@ __device__ __forceinline__ double2 sim_sum2(const double* __restrict__ part, int
   for (; b < b1; b += 64) { x0 += part[b * NQ + q]; y0 += part[b * NQ + q + 1]; }
   return make_double2(wave_sum((x0 + x1) + (x2 + x3)), wave_sum((y0 + y1) + (y2 + y3)));
 }
-__device__ __forceinline__ double sim_sum(const double* __restrict__ part, int q, int b0, int b1) {
-  return sim_sum2(part, q, b0, b1).x;
+
+// Fused per-sim reduction: every row block of a sim has written its partials
+// part[blk*NQ + q] and [q + 1]; the block that arrives last (counted with a
+// device-scope atomic, no waiting) sums them in block order and stores the
+// per-sim scalars sc[s*16 + o1] (and o2 if >= 0), then clears the counter.
+// Called by every thread of the block.
+__device__ __forceinline__ void finish_sim_sum(const RowBlock& b, const int32_t* __restrict__ blk_first,
+                                               int32_t* __restrict__ cnt, const double* __restrict__ part, int q,
+                                               double* __restrict__ sc, int o1, int o2) {
+  __shared__ int last;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const int nb = blk_first[b.sim + 1] - blk_first[b.sim];
+    last = atomicAdd(&cnt[b.sim], 1) == nb - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (threadIdx.x < 64) {
+    const double2 v = sim_sum2(part, q, blk_first[b.sim], blk_first[b.sim + 1]);
+    if (threadIdx.x == 0) {
+      sc[b.sim * 16 + o1] = v.x;
+      if (o2 >= 0) sc[b.sim * 16 + o2] = v.y;
+      cnt[b.sim] = 0;
+    }
+  }
 }
 
 template <int BS>
@@ -100,14 +124,18 @@ __global__ void k_bj_inv(int64_t n_row, const int32_t* __restrict__ rowptr, cons
 
 // y = A x over one row block per workgroup; LPR lanes cooperate on a row.
 // Partials: part[blk][q1] = sum z1 . y (if z1), part[blk][q2] = sum y . y
-// (if q2 >= 0).  Skips sims whose Krylov solve is finished.
+// (if q2 >= 0; then q2 = q1 + 1).  With cnt, the last block of each sim also
+// reduces them into sc[s*16 + o1], sc[s*16 + o2].  Skips sims whose Krylov
+// solve is finished.
 template <int BS, int LPR, bool TR>
 __global__ void __launch_bounds__(ROWS_PER_BLOCK * LPR) k_spmv(const RowBlock* __restrict__ blocks, const int32_t* __restrict__ simflag,
                                               const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
                                               const int32_t* __restrict__ tpos,
                                               const double* __restrict__ val, const double* __restrict__ x,
                                               double* __restrict__ y, const double* __restrict__ z1,
-                                              double* __restrict__ part, int q1, int q2) {
+                                              double* __restrict__ part, int q1, int q2,
+                                              const int32_t* __restrict__ blk_first, int32_t* __restrict__ cnt,
+                                              double* __restrict__ sc, int o1, int o2) {
   const RowBlock b = blocks[blockIdx.x];
   if (simflag && simflag[2 * b.sim] >= 0) return;
   constexpr int G = ROWS_PER_BLOCK;   // one LPR-lane group per row: the whole block in flight at once
@@ -157,6 +185,7 @@ __global__ void __launch_bounds__(ROWS_PER_BLOCK * LPR) k_spmv(const RowBlock* _
     if (q1 >= 0) part[blockIdx.x * NQ + q1] = s1;
     if (q2 >= 0) part[blockIdx.x * NQ + q2] = s2;
   }
+  if (cnt) finish_sim_sum(b, blk_first, cnt, part, q1 >= 0 ? q1 : q2, sc, o1, o2);
 }
 
 // ---------------------------------------------------------- BiCGStab ------
@@ -197,6 +226,8 @@ __global__ void k_bicg_sim_init(int nsim, const int32_t* __restrict__ blk_first,
   double* S = sc + s * 16;
   if (first) { S[SC_BN2] = rr; S[SC_TOL2] = rtol * rtol * rr; }
   S[SC_RHO] = 1.0; S[SC_RHO + 1] = 1.0; S[SC_ALPHA] = 1.0; S[SC_OMEGA] = 1.0; S[SC_RR] = rr;
+  S[SC_RHR] = rr;   // rhat = r at a (re)start
+  S[SC_RRN] = rr;
   flag[2 * s] = (rr <= S[SC_TOL2]) ? 0 : -1;
   flag[2 * s + 1] = 0;
 }
@@ -204,17 +235,16 @@ __global__ void k_bicg_sim_init(int nsim, const int32_t* __restrict__ blk_first,
 // Step A of iteration it: convergence test, p = r + beta (p - omega v), phat = M^-1 p.
 template <int BS>
 __global__ void __launch_bounds__(64) k_bicg_a(const RowBlock* __restrict__ blocks, const int32_t* __restrict__ blk_first,
-                                               int it, const double* __restrict__ part, double* __restrict__ sc,
+                                               int it, double* __restrict__ sc,
                                                int32_t* __restrict__ flag, const double* __restrict__ r,
                                                double* __restrict__ p, const double* __restrict__ v,
                                                double* __restrict__ ph, const double* __restrict__ dinv) {
   const RowBlock b = blocks[blockIdx.x];
   const int s = b.sim;
   if (flag[2 * s] >= 0) return;
-  const int b0 = blk_first[s], b1 = blk_first[s + 1];
-  const double2 sums = sim_sum2(part, 0, b0, b1);
-  const double rho = sums.x, rr = sums.y;
+  const int b0 = blk_first[s];
   double* S = sc + s * 16;
+  const double rho = S[SC_RHR], rr = S[SC_RRN];
   const bool lead = (blockIdx.x == (unsigned)b0) && threadIdx.x == 0;
   if (rr <= S[SC_TOL2]) {
     if (lead) { flag[2 * s] = it; S[SC_RR] = rr; }
@@ -241,16 +271,16 @@ __global__ void __launch_bounds__(64) k_bicg_a(const RowBlock* __restrict__ bloc
 // Step C: alpha = rho / (rhat, v); s = r - alpha v; shat = M^-1 s.
 template <int BS>
 __global__ void __launch_bounds__(64) k_bicg_c(const RowBlock* __restrict__ blocks, const int32_t* __restrict__ blk_first,
-                                               int it, const double* __restrict__ part_rv, double* __restrict__ sc,
+                                               int it, double* __restrict__ sc,
                                                int32_t* __restrict__ flag, const double* __restrict__ r,
                                                const double* __restrict__ v, double* __restrict__ s_,
                                                double* __restrict__ sh, const double* __restrict__ dinv) {
   const RowBlock b = blocks[blockIdx.x];
   const int s = b.sim;
   if (flag[2 * s] >= 0) return;
-  const int b0 = blk_first[s], b1 = blk_first[s + 1];
-  double rv = sim_sum(part_rv, 0, b0, b1);
+  const int b0 = blk_first[s];
   double* S = sc + s * 16;
+  const double rv = S[SC_RV];
   double rho = S[SC_RHO + (it & 1)];
   double alpha = rv != 0.0 ? rho / rv : 0.0;
   const int64_t row = b.row0 + threadIdx.x;
@@ -268,7 +298,7 @@ __global__ void __launch_bounds__(64) k_bicg_c(const RowBlock* __restrict__ bloc
 // Step E: omega = (t, s)/(t, t); x += alpha phat + omega shat; r = s - omega t.
 template <int BS>
 __global__ void __launch_bounds__(64) k_bicg_e(const RowBlock* __restrict__ blocks, const int32_t* __restrict__ blk_first,
-                                               const double* __restrict__ part_ts, double* __restrict__ sc,
+                                               int32_t* __restrict__ cnt, double* __restrict__ sc,
                                                int32_t* __restrict__ flag, double* __restrict__ x,
                                                double* __restrict__ r, const double* __restrict__ rh,
                                                const double* __restrict__ ph, const double* __restrict__ sh,
@@ -277,11 +307,10 @@ __global__ void __launch_bounds__(64) k_bicg_e(const RowBlock* __restrict__ bloc
   const RowBlock b = blocks[blockIdx.x];
   const int s = b.sim;
   if (flag[2 * s] >= 0) return;
-  const int b0 = blk_first[s], b1 = blk_first[s + 1];
-  const double2 sums = sim_sum2(part_ts, 0, b0, b1);
-  const double ts = sums.x, tt = sums.y;
+  const int b0 = blk_first[s];
   double* S = sc + s * 16;
-  double alpha = S[SC_ALPHA];
+  const double ts = S[SC_TS], tt = S[SC_TT];
+  const double alpha = S[SC_ALPHA];
   double omega = tt > 0.0 ? ts / tt : 0.0;
   double d_rhr = 0.0, d_rr = 0.0;
   const int64_t row = b.row0 + threadIdx.x;
@@ -300,6 +329,7 @@ __global__ void __launch_bounds__(64) k_bicg_e(const RowBlock* __restrict__ bloc
   d_rr = wave_sum(d_rr);
   if (threadIdx.x == 0) { part[blockIdx.x * NQ + 0] = d_rhr; part[blockIdx.x * NQ + 1] = d_rr; }
   if (blockIdx.x == (unsigned)b0 && threadIdx.x == 0) S[SC_OMEGA] = omega;
+  finish_sim_sum(b, blk_first, cnt, part, 0, sc, SC_RHR, SC_RRN);
 }
 
 // True residual norm per block: ||b - t||^2 -> part q2.
@@ -331,7 +361,6 @@ constexpr int GM_P = GM_M + 1;                 // partial slots per row block
 constexpr int GM_H = 0;                        // Hessenberg, column-major [M][M+1]
 constexpr int GM_CS = GM_H + GM_M * GM_P, GM_SN = GM_CS + GM_M, GM_G = GM_SN + GM_M, GM_Y = GM_G + GM_P,
               GM_HC = GM_Y + GM_M, GM_MISC = GM_HC + GM_P, GM_STRIDE = GM_MISC + 4;
-enum { SC_GBETA = 10 };
 
 // Sum of part[b*stride + q] over a sim's row blocks by one wave (fixed order).
 __device__ __forceinline__ double seg_sum(const double* __restrict__ part, int stride, int q, int b0, int b1) {
@@ -570,31 +599,35 @@ struct KBufs { double *part_rr, *part_rv, *part_ts; };
 
 template <int BS, int LPR>
 static int spmv_launch(mpm_ctx* c, const int32_t* simflag, const double* val, const double* x, double* y,
-                       const double* z1, double* part, int q1, int q2) {
+                       const double* z1, double* part, int q1, int q2, int o1, int o2) {
   unsigned nbk = (unsigned)c->blocks_h.size();
   if (!nbk) return MPM_OK;
   const unsigned threads = ROWS_PER_BLOCK * LPR;
+  int32_t* cnt = o1 >= 0 ? c->kcnt.p : nullptr;
   if (c->ktrans)
     k_spmv<BS, LPR, true><<<nbk, threads, 0, c->stream>>>(c->blocks.p, simflag, c->rowptr.p, c->colind.p, c->tpos.p,
-                                                          val, x, y, z1, part, q1, q2);
+                                                          val, x, y, z1, part, q1, q2, c->blk_first.p, cnt,
+                                                          c->simsc.p, o1, o2);
   else
     k_spmv<BS, LPR, false><<<nbk, threads, 0, c->stream>>>(c->blocks.p, simflag, c->rowptr.p, c->colind.p, nullptr,
-                                                           val, x, y, z1, part, q1, q2);
+                                                           val, x, y, z1, part, q1, q2, c->blk_first.p, cnt,
+                                                           c->simsc.p, o1, o2);
   LAUNCH_CHECK(c, "k_spmv");
   return MPM_OK;
 }
 
 static int spmv(mpm_ctx* c, const int32_t* simflag, const double* val, const double* x, double* y, const double* z1,
-                double* part, int q1, int q2) {
+                double* part, int q1, int q2, int o1 = -1, int o2 = -1) {
   // lanes per row: 8 for the <= 25 blocks of a 2-D row, 16 for the <= 125 of a 3-D row
-  if (c->nd == 2) return spmv_launch<2, 8>(c, simflag, val, x, y, z1, part, q1, q2);
-  if (c->dim == 2) return spmv_launch<3, 8>(c, simflag, val, x, y, z1, part, q1, q2);
-  return spmv_launch<3, 16>(c, simflag, val, x, y, z1, part, q1, q2);
+  if (c->nd == 2) return spmv_launch<2, 8>(c, simflag, val, x, y, z1, part, q1, q2, o1, o2);
+  if (c->dim == 2) return spmv_launch<3, 8>(c, simflag, val, x, y, z1, part, q1, q2, o1, o2);
+  return spmv_launch<3, 16>(c, simflag, val, x, y, z1, part, q1, q2, o1, o2);
 }
 
 int launch_spmv(mpm_ctx* c, const double* val, const double* x, double* y, const double* z) {
   if (!z) return spmv(c, nullptr, val, x, y, nullptr, nullptr, -1, -1);
-  return spmv(c, nullptr, val, x, y, z, c->part.p, 2, 3);
+  // the in-loop form: product, both partial dot products and their per-sim reduction
+  return spmv(c, nullptr, val, x, y, z, c->part.p, 2, 3, SC_TS, SC_TT);
 }
 
 int launch_bj_inv(mpm_ctx* c, const double* val) {
@@ -610,13 +643,13 @@ int launch_bj_inv(mpm_ctx* c, const double* val) {
 
 // Event pairs around sampled SpMV launches (kernel-duration measurement).
 static int spmv_timed(mpm_ctx* c, bool timed, const int32_t* simflag, const double* val, const double* x, double* y,
-                      const double* z1, double* part, int q1, int q2) {
-  if (!timed) return spmv(c, simflag, val, x, y, z1, part, q1, q2);
+                      const double* z1, double* part, int q1, int q2, int o1, int o2) {
+  if (!timed) return spmv(c, simflag, val, x, y, z1, part, q1, q2, o1, o2);
   hipEvent_t e0, e1;
   HIPC(c, hipEventCreate(&e0));
   HIPC(c, hipEventCreate(&e1));
   HIPC(c, hipEventRecord(e0, c->stream));
-  int rc = spmv(c, simflag, val, x, y, z1, part, q1, q2);
+  int rc = spmv(c, simflag, val, x, y, z1, part, q1, q2, o1, o2);
   HIPC(c, hipEventRecord(e1, c->stream));
   c->spmv_events.push_back(e0);
   c->spmv_events.push_back(e1);
@@ -629,13 +662,15 @@ static int bicg_iter(mpm_ctx* c, const double* val, int it, const KBufs& K) {
   const double* dinv = c->ktrans ? c->dinvT.p : c->dinv.p;
   int rc;
   const bool timed = c->time_spmv > 0 && it % c->time_spmv == 0;
-  k_bicg_a<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->blk_first.p, it, K.part_rr, c->simsc.p, c->simflag.p, c->kr.p,
+  k_bicg_a<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->blk_first.p, it, c->simsc.p, c->simflag.p, c->kr.p,
                                          c->kp.p, c->kv.p, c->kph.p, dinv);
-  if ((rc = spmv_timed(c, timed, c->simflag.p, val, c->kph.p, c->kv.p, c->krh.p, K.part_rv, 0, -1))) return rc;
-  k_bicg_c<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->blk_first.p, it, K.part_rv, c->simsc.p, c->simflag.p, c->kr.p,
+  if ((rc = spmv_timed(c, timed, c->simflag.p, val, c->kph.p, c->kv.p, c->krh.p, K.part_rv, 0, -1, SC_RV, -1)))
+    return rc;
+  k_bicg_c<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->blk_first.p, it, c->simsc.p, c->simflag.p, c->kr.p,
                                          c->kv.p, c->ks.p, c->ksh.p, dinv);
-  if ((rc = spmv_timed(c, timed, c->simflag.p, val, c->ksh.p, c->kt.p, c->ks.p, K.part_ts, 0, 1))) return rc;
-  k_bicg_e<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->blk_first.p, K.part_ts, c->simsc.p, c->simflag.p, c->kx.p,
+  if ((rc = spmv_timed(c, timed, c->simflag.p, val, c->ksh.p, c->kt.p, c->ks.p, K.part_ts, 0, 1, SC_TS, SC_TT)))
+    return rc;
+  k_bicg_e<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->blk_first.p, c->kcnt.p, c->simsc.p, c->simflag.p, c->kx.p,
                                          c->kr.p, c->krh.p, c->kph.p, c->ksh.p, c->ks.p, c->kt.p, K.part_rr);
   LAUNCH_CHECK(c, "bicgstab step");
   return MPM_OK;
