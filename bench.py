@@ -34,6 +34,26 @@ def spmv_bytes(n_row, nnzb, bs):
     return nnzb * (bs * bs * 8 + 4) + 4 * (n_row + 1) + 2 * n_row * bs * 8
 
 
+def spmv_traffic():
+    """HBM bytes per SpMV launch from the committed counter passes
+    (profiles/k_spmv_c2_geostatic_pmc.md), or None when the kernel's source
+    has changed since they were taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "k_spmv_c2_geostatic_pmc.md")
+    src = os.path.join(ROOT, "paper_2507_09435_amd", "csrc", "mpm_krylov.hip")
+    try:
+        text = open(prof).read()
+        code = open(src).read()
+    except OSError:
+        return None
+    i = code.find("template <int BS, int LPR, bool TR>")
+    j = code.find("// ---------------------------------------------------------- BiCGStab")
+    fields = dict(line.split(": ", 1) for line in text.splitlines() if line.startswith(("traffic_", "kernel_")))
+    if i < 0 or j < 0 or fields.get("kernel_source_sha1", "").strip() != hashlib.sha1(code[i:j].encode()).hexdigest():
+        return None
+    return int(float(fields["traffic_bytes_per_launch"]))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,7 +181,7 @@ def main():
         "ms_krylov_per_newton_iter": round(ms_kry / max(n_jac, 1), 3),
         "roofline": {"kernel": "k_spmv<2,8> (BSR SpMV in BiCGStab)", "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": spmv_traffic(),
                      "avg_launch_us": round(spmv_us, 3), "timed_launches": nrep,
                      "in_loop_event_us": round(loop_ms * 1e3 / max(loop_n, 1), 3),
                      "algorithmic_bytes_per_launch": nbytes},

@@ -218,10 +218,9 @@ int mpm_adjoint_step(mpm_ctx *ctx, const mpm_problem *prob, const double *du, co
 /* y = J x with the BSR values val of this load step's pattern (the
  * matrix-vector product that drives the Krylov solve).  val [nnzb][ndof][ndof]
  * as returned by mpm_jacobian_bsr; x, y compact [n_row*ndof], must not
- * alias.  z (may be NULL): the product also forms z.y and y.y per simulation,
- * as the Krylov iteration fuses them into it (partials per row block, summed
- * in block order by the last block of each simulation; kept in library
- * scratch).  Errors: INVALID, HIP. */
+ * alias.  z (may be NULL): the product also forms the per-row-block partial
+ * sums of z.y and y.y that the Krylov iteration fuses into it (kept in
+ * library scratch).  Errors: INVALID, HIP. */
 int mpm_spmv(mpm_ctx *ctx, const double *val, const double *x, double *y, const double *z);
 
 #ifdef __cplusplus

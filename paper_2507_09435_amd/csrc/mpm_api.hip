@@ -112,10 +112,10 @@ int mpm_destroy(mpm_ctx* c) {
   c->colind.release(); c->slot.release(); c->blocks.release(); c->blk_first.release(); c->flag.release();
   c->xs.release(); c->vol0s.release(); c->Fs.release(); c->bes.release(); c->Es.release(); c->phis.release();
   c->cmask.release(); c->rmask.release(); c->cval.release(); c->fext.release(); c->fint.release(); c->nvol.release();
-  c->work.release(); c->val.release(); c->dinv.release();
+  c->work.release(); c->val.release(); c->dinv.release(); c->pdat.release(); c->gbuf.release();
   c->kx.release(); c->kr.release(); c->krh.release(); c->kp.release(); c->kv.release(); c->ks.release();
   c->kt.release(); c->kph.release(); c->ksh.release(); c->kb.release(); c->part.release(); c->simsc.release();
-  c->simflag.release(); c->kcnt.release(); c->du_base.release(); c->alpha.release();
+  c->simflag.release(); c->du_base.release(); c->alpha.release();
   c->gV.release(); c->gsc.release(); c->gpart.release(); c->gflag.release(); c->greset.release();
   c->tpos.release(); c->dinvT.release(); c->adj_mu.release(); c->adj_nu.release(); c->adj_theta.release();
   c->adj_rbar.release();

@@ -279,6 +279,131 @@ __global__ void __launch_bounds__(JT) k_jac2g(AsmArgs A, const double* __restric
   }
 }
 
+// 2-D single-phase Jacobian without atomics, in three deterministic passes.
+// k_tan2: one record per particle (sorted order): V0 * tangent table (dP/dF,
+// 4x4, output-major) and its stencil's weights and derivatives per axis.
+// k_grp2: one wave per stencil group (origin key) sums the 9x9 local blocks
+// of the group's particles, in particle order, into a per-origin buffer.
+// k_jac2_blocks: every BSR block (a, b) is the sum, in origin order, of the
+// group blocks of the (at most nine) origins whose stencil holds both nodes,
+// written once (no clearing, no atomics).
+constexpr int PD2 = 32;   // doubles per particle record: T 0..15, wx 16..18, dwx 19..21, wy 22..24, dwy 25..27
+
+__global__ void __launch_bounds__(256) k_tan2(AsmArgs A, const double* __restrict__ du, double* __restrict__ pdat) {
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = gid >> 2;
+  const int q = (int)(gid & 3);
+  if (i >= A.np) return;
+  PLoad<2> L;
+  load_particle<2>(A, i, du, L);
+  double Tc[4];
+  tangent2_col<4>(A, L, load_be2(A, i), q, Tc);
+  double* P = pdat + i * PD2;
+#pragma unroll
+  for (int o = 0; o < 4; ++o) P[o * 4 + q] = L.v0 * Tc[o];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)   // lane a < 3 stores entry a (constant indices keep the stencil in registers)
+    if (q == a) {
+      P[16 + a] = L.st.w[0][a];
+      P[19 + a] = L.st.dw[0][a];
+      P[22 + a] = L.st.w[1][a];
+      P[25 + a] = L.st.dw[1][a];
+    }
+}
+
+__device__ __forceinline__ double sel3(int i, double v0, double v1, double v2) {
+  return i == 0 ? v0 : (i == 1 ? v1 : v2);
+}
+
+constexpr int GB2 = 81 * 4;   // doubles per origin in the group-block buffer
+
+__global__ void __launch_bounds__(256) k_grp2(int64_t n_okeys, const int32_t* __restrict__ gstart,
+                                             const double* __restrict__ pdat, double* __restrict__ gbuf) {
+  const int64_t key = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  if (key >= n_okeys) return;
+  const int p0 = gstart[key], p1 = gstart[key + 1];
+  if (p0 == p1) return;   // empty origin: never read
+  const int lane = threadIdx.x % 64;
+  // blocks j = lane and j = lane + 64 (< 81); j = 9 a + b over local nodes a, b
+  const int j0 = lane, j1 = lane + 64;
+  const int a0 = j0 / 9, b0 = j0 % 9, a1 = (j1 < 81 ? j1 : 80) / 9, b1 = (j1 < 81 ? j1 : 80) % 9;
+  double K0[4] = {0.0, 0.0, 0.0, 0.0}, K1[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int p = p0; p < p1; ++p) {
+    const double* P = pdat + (int64_t)p * PD2;
+    double T[16], w[12];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) T[k] = P[k];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) w[k] = P[16 + k];
+    // w: wx 0..2, dwx 3..5, wy 6..8, dwy 9..11; grad w_n = (dwx wy, wx dwy)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int a = h ? a1 : a0, b = h ? b1 : b0;
+      const int ax = a % 3, ay = a / 3, bx = b % 3, by = b / 3;
+      const double ga0 = sel3(ax, w[3], w[4], w[5]) * sel3(ay, w[6], w[7], w[8]);
+      const double ga1 = sel3(ax, w[0], w[1], w[2]) * sel3(ay, w[9], w[10], w[11]);
+      const double gb0 = sel3(bx, w[3], w[4], w[5]) * sel3(by, w[6], w[7], w[8]);
+      const double gb1 = sel3(bx, w[0], w[1], w[2]) * sel3(by, w[9], w[10], w[11]);
+      double* K = h ? K1 : K0;
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          K[r * 2 + c] += ga0 * (T[(2 * r) * 4 + 2 * c] * gb0 + T[(2 * r) * 4 + 2 * c + 1] * gb1) +
+                          ga1 * (T[(2 * r + 1) * 4 + 2 * c] * gb0 + T[(2 * r + 1) * 4 + 2 * c + 1] * gb1);
+    }
+  }
+  double* G = gbuf + key * GB2;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) G[j0 * 4 + e] = K0[e];
+  if (j1 < 81)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) G[j1 * 4 + e] = K1[e];
+}
+
+// 32 lanes per BSR row (two rows per wave); lane k < row length owns slot k.
+// With cmask, constrained rows and columns are written as the identity's.
+__global__ void __launch_bounds__(256) k_jac2_blocks(int64_t n_row, const int64_t* __restrict__ active_nodes,
+                                                    const int32_t* __restrict__ row_sim,
+                                                    const SimDev* __restrict__ sims,
+                                                    const int32_t* __restrict__ gstart,
+                                                    const int32_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ colind,
+                                                    const double* __restrict__ gbuf,
+                                                    const uint8_t* __restrict__ cmask, double* __restrict__ val) {
+  const int64_t row = ((int64_t)blockIdx.x * 256 + threadIdx.x) / 32;
+  if (row >= n_row) return;
+  const int k = rowptr[row] + (int)(threadIdx.x % 32);
+  if (k >= rowptr[row + 1]) return;
+  const SimDev& S = sims[row_sim[row]];
+  const int64_t na = active_nodes[row] - S.node_base, nb = active_nodes[colind[k]] - S.node_base;
+  const int ix = (int)(na % S.nna[0]) - 1, iy = (int)(na / S.nna[0]) - 1;
+  const int jx = (int)(nb % S.nna[0]) - 1, jy = (int)(nb / S.nna[0]) - 1;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int oy0 = max(max(iy, jy) - 2, -1), oy1 = min(min(iy, jy), S.n[1] - 1);
+  const int ox0 = max(max(ix, jx) - 2, -1), ox1 = min(min(ix, jx), S.n[0] - 1);
+  for (int oy = oy0; oy <= oy1; ++oy)
+    for (int ox = ox0; ox <= ox1; ++ox) {
+      const int64_t key = S.okey_base + (ox + 1) + (int64_t)S.noa[0] * (oy + 1);
+      if (gstart[key] == gstart[key + 1]) continue;
+      const int la = (ix - ox) + 3 * (iy - oy), lb = (jx - ox) + 3 * (jy - oy);
+      const double* G = gbuf + key * GB2 + (la * 9 + lb) * 4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[e] += G[e];
+    }
+  if (cmask) {
+    const int64_t col = colind[k];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        if (cmask[row * 2 + i] || cmask[col * 2 + j]) acc[i * 2 + j] = (row == col && i == j) ? 1.0 : 0.0;
+  }
+  double* blk = val + (int64_t)k * 4;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) blk[e] = acc[e];
+}
+
 // Residual, 2-D, group-cooperative: per particle V0 P (and the u-p scalars),
 // then one thread per (group, node) sums the group and adds once.
 __global__ void __launch_bounds__(GP) k_fint2g(AsmArgs A, const double* __restrict__ du, double* __restrict__ fint) {
@@ -625,16 +750,37 @@ int sim_sum_launch(mpm_ctx* c, const double* part, int q, int off) {
 int launch_jacobian(mpm_ctx* c, const mpm_problem* pb, const double* du, double* val, bool apply_bc) {
   AsmArgs A = make_args(c, pb);
   const int nd = c->nd;
-  HIPC(c, hipMemsetAsync(val, 0, c->nnzb * nd * nd * sizeof(double), c->stream));
-  if (c->np > 0) {
-    const unsigned g4 = (unsigned)((c->np + JT / 4 - 1) / (JT / 4)), g8 = (unsigned)((c->np + JT / 8 - 1) / (JT / 8));
-    if (c->dim == 2 && !c->up) k_jac2g<4><<<g4, JT, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val);
-    else if (c->dim == 2) k_jac2g<7><<<g8, JT, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val);
+  if (c->dim == 2 && !c->up) {
+    // tangent records, then one writer per block (no clearing needed)
+    if (c->pdat.ensure(std::max<int64_t>(1, c->np) * PD2) != hipSuccess)
+      return c->fail(MPM_E_NOMEM, "particle tangent records allocation failed");
+    if (c->np > 0) {
+      k_tan2<<<(unsigned)((4 * c->np + 255) / 256), 256, 0, c->stream>>>(A, du, c->pdat.p);
+      LAUNCH_CHECK(c, "k_tan2");
+    }
+    if (c->gbuf.ensure(std::max<int64_t>(1, c->n_okeys) * GB2) != hipSuccess)
+      return c->fail(MPM_E_NOMEM, "group block buffer allocation failed");
+    if (c->n_okeys > 0) {
+      k_grp2<<<(unsigned)((c->n_okeys + 3) / 4), 256, 0, c->stream>>>(c->n_okeys, c->gstart.p, c->pdat.p, c->gbuf.p);
+      LAUNCH_CHECK(c, "k_grp2");
+    }
+    if (c->n_row > 0) {
+      k_jac2_blocks<<<(unsigned)((c->n_row * 32 + 255) / 256), 256, 0, c->stream>>>(
+          c->n_row, c->active_nodes.p, c->row_sim.p, c->sims.p, c->gstart.p, c->rowptr.p, c->colind.p, c->gbuf.p,
+          apply_bc ? c->cmask.p : nullptr, val);
+      LAUNCH_CHECK(c, "k_jac2_blocks");
+    }
+  } else {
+    HIPC(c, hipMemsetAsync(val, 0, c->nnzb * nd * nd * sizeof(double), c->stream));
+  }
+  if (c->np > 0 && !(c->dim == 2 && !c->up)) {
+    const unsigned g8 = (unsigned)((c->np + JT / 8 - 1) / (JT / 8));
+    if (c->dim == 2) k_jac2g<7><<<g8, JT, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val);
     else k_jac3g<<<(unsigned)((c->np + GP3 - 1) / GP3), GP3, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val,
                                                                               c->flag.p);
     LAUNCH_CHECK(c, "k_jac");
   }
-  if (apply_bc && c->n_row > 0) {
+  if (apply_bc && c->n_row > 0 && !(c->dim == 2 && !c->up)) {   // the 2-D single-phase writer applies it itself
     k_jac_bc<<<nb256(c->n_row), 256, 0, c->stream>>>(c->n_row, nd, c->rowptr.p, c->colind.p, c->cmask.p, val);
     LAUNCH_CHECK(c, "k_jac_bc");
   }

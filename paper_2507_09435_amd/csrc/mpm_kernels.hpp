@@ -86,16 +86,18 @@ struct mpm_ctx {
   mpm::DBuf<uint8_t> cmask, rmask;
   mpm::DBuf<double> cval, fext, fint, nvol, work;
   mpm::DBuf<double> val, dinv;
+  mpm::DBuf<double> pdat;                      // per-particle tangent records (2-D assembly)
+  mpm::DBuf<double> gbuf;                      // per-origin group blocks (2-D assembly)
   // Krylov
   mpm::DBuf<double> kx, kr, krh, kp, kv, ks, kt, kph, ksh, kb;
   mpm::DBuf<double> part;                      // [nblocks][NQ]
   mpm::DBuf<double> simsc;                     // per-sim scalars [nsim][16]
   mpm::DBuf<int32_t> simflag;                  // per-sim krylov state [nsim][2]
-  mpm::DBuf<int32_t> kcnt;                     // per-sim arrival counters of fused reductions (kept 0)
   mpm::DBuf<double> gV, gsc, gpart;            // GMRES basis, per-sim Hessenberg/rotations, partials
   mpm::DBuf<int32_t> gflag;                    // per-sim GMRES state [nsim][2]
   mpm::DBuf<uint8_t> greset;
   int kmethod = 0;                             // 0: BiCGStab then GMRES fallback, 1: GMRES only
+  bool kfused = true;                          // BiCGStab consumers sum the row-block partials themselves
   mpm::DBuf<double> du_base, alpha;            // line search
   // adjoint
   mpm::DBuf<int32_t> tpos;                     // position of the transposed block

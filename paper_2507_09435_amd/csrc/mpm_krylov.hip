@@ -36,30 +36,35 @@ __device__ __forceinline__ double2 sim_sum2(const double* __restrict__ part, int
   return make_double2(wave_sum((x0 + x1) + (x2 + x3)), wave_sum((y0 + y1) + (y2 + y3)));
 }
 
-// Fused per-sim reduction: every row block of a sim has written its partials
-// part[blk*NQ + q] and [q + 1]; the block that arrives last (counted with a
-// device-scope atomic, no waiting) sums them in block order and stores the
-// per-sim scalars sc[s*16 + o1] (and o2 if >= 0), then clears the counter.
-// Called by every thread of the block.
-__device__ __forceinline__ void finish_sim_sum(const RowBlock& b, const int32_t* __restrict__ blk_first,
-                                               int32_t* __restrict__ cnt, const double* __restrict__ part, int q,
-                                               double* __restrict__ sc, int o1, int o2) {
-  __shared__ int last;
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const int nb = blk_first[b.sim + 1] - blk_first[b.sim];
-    last = atomicAdd(&cnt[b.sim], 1) == nb - 1;
+// Per-sim sums of the row-block partials part[blk*NQ + q] and [q + 1] into
+// sc[s*16 + o1] (and o2 if >= 0): one 256-thread workgroup per sim, fixed
+// lane assignment and a fixed tree, so the sums do not depend on timing or on
+// the other sims of a batch.  Skips sims whose solve is finished.
+constexpr int RT = 256;
+__global__ void __launch_bounds__(RT) k_sim_dot2(const int32_t* __restrict__ blk_first,
+                                                 const int32_t* __restrict__ flag, const double* __restrict__ part,
+                                                 int q, double* __restrict__ sc, int o1, int o2) {
+  const int s = blockIdx.x;
+  if (flag && flag[2 * s] >= 0) return;
+  __shared__ double sh[2][RT];
+  double a = 0.0, b = 0.0;
+  for (int k = blk_first[s] + (int)threadIdx.x; k < blk_first[s + 1]; k += RT) {
+    a += part[(int64_t)k * NQ + q];
+    b += part[(int64_t)k * NQ + q + 1];
   }
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
   __syncthreads();
-  if (!last) return;
-  __threadfence();
-  if (threadIdx.x < 64) {
-    const double2 v = sim_sum2(part, q, blk_first[b.sim], blk_first[b.sim + 1]);
-    if (threadIdx.x == 0) {
-      sc[b.sim * 16 + o1] = v.x;
-      if (o2 >= 0) sc[b.sim * 16 + o2] = v.y;
-      cnt[b.sim] = 0;
+  for (int w = RT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
     }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    sc[s * 16 + o1] = sh[0][0];
+    if (o2 >= 0) sc[s * 16 + o2] = sh[1][0];
   }
 }
 
@@ -124,18 +129,14 @@ __global__ void k_bj_inv(int64_t n_row, const int32_t* __restrict__ rowptr, cons
 
 // y = A x over one row block per workgroup; LPR lanes cooperate on a row.
 // Partials: part[blk][q1] = sum z1 . y (if z1), part[blk][q2] = sum y . y
-// (if q2 >= 0; then q2 = q1 + 1).  With cnt, the last block of each sim also
-// reduces them into sc[s*16 + o1], sc[s*16 + o2].  Skips sims whose Krylov
-// solve is finished.
+// (if q2 >= 0).  Skips sims whose Krylov solve is finished.
 template <int BS, int LPR, bool TR>
 __global__ void __launch_bounds__(ROWS_PER_BLOCK * LPR) k_spmv(const RowBlock* __restrict__ blocks, const int32_t* __restrict__ simflag,
                                               const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
                                               const int32_t* __restrict__ tpos,
                                               const double* __restrict__ val, const double* __restrict__ x,
                                               double* __restrict__ y, const double* __restrict__ z1,
-                                              double* __restrict__ part, int q1, int q2,
-                                              const int32_t* __restrict__ blk_first, int32_t* __restrict__ cnt,
-                                              double* __restrict__ sc, int o1, int o2) {
+                                              double* __restrict__ part, int q1, int q2) {
   const RowBlock b = blocks[blockIdx.x];
   if (simflag && simflag[2 * b.sim] >= 0) return;
   constexpr int G = ROWS_PER_BLOCK;   // one LPR-lane group per row: the whole block in flight at once
@@ -185,7 +186,6 @@ __global__ void __launch_bounds__(ROWS_PER_BLOCK * LPR) k_spmv(const RowBlock* _
     if (q1 >= 0) part[blockIdx.x * NQ + q1] = s1;
     if (q2 >= 0) part[blockIdx.x * NQ + q2] = s2;
   }
-  if (cnt) finish_sim_sum(b, blk_first, cnt, part, q1 >= 0 ? q1 : q2, sc, o1, o2);
 }
 
 // ---------------------------------------------------------- BiCGStab ------
@@ -235,7 +235,7 @@ __global__ void k_bicg_sim_init(int nsim, const int32_t* __restrict__ blk_first,
 // Step A of iteration it: convergence test, p = r + beta (p - omega v), phat = M^-1 p.
 template <int BS>
 __global__ void __launch_bounds__(64) k_bicg_a(const RowBlock* __restrict__ blocks, const int32_t* __restrict__ blk_first,
-                                               int it, double* __restrict__ sc,
+                                               int it, const double* __restrict__ part, double* __restrict__ sc,
                                                int32_t* __restrict__ flag, const double* __restrict__ r,
                                                double* __restrict__ p, const double* __restrict__ v,
                                                double* __restrict__ ph, const double* __restrict__ dinv) {
@@ -244,7 +244,9 @@ __global__ void __launch_bounds__(64) k_bicg_a(const RowBlock* __restrict__ bloc
   if (flag[2 * s] >= 0) return;
   const int b0 = blk_first[s];
   double* S = sc + s * 16;
-  const double rho = S[SC_RHR], rr = S[SC_RRN];
+  // (rhat, r) and (r, r): summed here from the row-block partials, or by k_sim_dot2
+  const double2 sums = part ? sim_sum2(part, 0, b0, blk_first[s + 1]) : make_double2(S[SC_RHR], S[SC_RRN]);
+  const double rho = sums.x, rr = sums.y;
   const bool lead = (blockIdx.x == (unsigned)b0) && threadIdx.x == 0;
   if (rr <= S[SC_TOL2]) {
     if (lead) { flag[2 * s] = it; S[SC_RR] = rr; }
@@ -271,7 +273,7 @@ __global__ void __launch_bounds__(64) k_bicg_a(const RowBlock* __restrict__ bloc
 // Step C: alpha = rho / (rhat, v); s = r - alpha v; shat = M^-1 s.
 template <int BS>
 __global__ void __launch_bounds__(64) k_bicg_c(const RowBlock* __restrict__ blocks, const int32_t* __restrict__ blk_first,
-                                               int it, double* __restrict__ sc,
+                                               int it, const double* __restrict__ part, double* __restrict__ sc,
                                                int32_t* __restrict__ flag, const double* __restrict__ r,
                                                const double* __restrict__ v, double* __restrict__ s_,
                                                double* __restrict__ sh, const double* __restrict__ dinv) {
@@ -280,7 +282,7 @@ __global__ void __launch_bounds__(64) k_bicg_c(const RowBlock* __restrict__ bloc
   if (flag[2 * s] >= 0) return;
   const int b0 = blk_first[s];
   double* S = sc + s * 16;
-  const double rv = S[SC_RV];
+  const double rv = part ? sim_sum2(part, 0, b0, blk_first[s + 1]).x : S[SC_RV];
   double rho = S[SC_RHO + (it & 1)];
   double alpha = rv != 0.0 ? rho / rv : 0.0;
   const int64_t row = b.row0 + threadIdx.x;
@@ -298,7 +300,7 @@ __global__ void __launch_bounds__(64) k_bicg_c(const RowBlock* __restrict__ bloc
 // Step E: omega = (t, s)/(t, t); x += alpha phat + omega shat; r = s - omega t.
 template <int BS>
 __global__ void __launch_bounds__(64) k_bicg_e(const RowBlock* __restrict__ blocks, const int32_t* __restrict__ blk_first,
-                                               int32_t* __restrict__ cnt, double* __restrict__ sc,
+                                               const double* __restrict__ part_ts, double* __restrict__ sc,
                                                int32_t* __restrict__ flag, double* __restrict__ x,
                                                double* __restrict__ r, const double* __restrict__ rh,
                                                const double* __restrict__ ph, const double* __restrict__ sh,
@@ -309,7 +311,8 @@ __global__ void __launch_bounds__(64) k_bicg_e(const RowBlock* __restrict__ bloc
   if (flag[2 * s] >= 0) return;
   const int b0 = blk_first[s];
   double* S = sc + s * 16;
-  const double ts = S[SC_TS], tt = S[SC_TT];
+  const double2 sums = part_ts ? sim_sum2(part_ts, 0, b0, blk_first[s + 1]) : make_double2(S[SC_TS], S[SC_TT]);
+  const double ts = sums.x, tt = sums.y;
   const double alpha = S[SC_ALPHA];
   double omega = tt > 0.0 ? ts / tt : 0.0;
   double d_rhr = 0.0, d_rr = 0.0;
@@ -329,7 +332,6 @@ __global__ void __launch_bounds__(64) k_bicg_e(const RowBlock* __restrict__ bloc
   d_rr = wave_sum(d_rr);
   if (threadIdx.x == 0) { part[blockIdx.x * NQ + 0] = d_rhr; part[blockIdx.x * NQ + 1] = d_rr; }
   if (blockIdx.x == (unsigned)b0 && threadIdx.x == 0) S[SC_OMEGA] = omega;
-  finish_sim_sum(b, blk_first, cnt, part, 0, sc, SC_RHR, SC_RRN);
 }
 
 // True residual norm per block: ||b - t||^2 -> part q2.
@@ -603,16 +605,18 @@ static int spmv_launch(mpm_ctx* c, const int32_t* simflag, const double* val, co
   unsigned nbk = (unsigned)c->blocks_h.size();
   if (!nbk) return MPM_OK;
   const unsigned threads = ROWS_PER_BLOCK * LPR;
-  int32_t* cnt = o1 >= 0 ? c->kcnt.p : nullptr;
   if (c->ktrans)
     k_spmv<BS, LPR, true><<<nbk, threads, 0, c->stream>>>(c->blocks.p, simflag, c->rowptr.p, c->colind.p, c->tpos.p,
-                                                          val, x, y, z1, part, q1, q2, c->blk_first.p, cnt,
-                                                          c->simsc.p, o1, o2);
+                                                          val, x, y, z1, part, q1, q2);
   else
     k_spmv<BS, LPR, false><<<nbk, threads, 0, c->stream>>>(c->blocks.p, simflag, c->rowptr.p, c->colind.p, nullptr,
-                                                           val, x, y, z1, part, q1, q2, c->blk_first.p, cnt,
-                                                           c->simsc.p, o1, o2);
+                                                           val, x, y, z1, part, q1, q2);
   LAUNCH_CHECK(c, "k_spmv");
+  if (o1 >= 0) {
+    k_sim_dot2<<<(unsigned)c->nsim, RT, 0, c->stream>>>(c->blk_first.p, simflag, part, q1 >= 0 ? q1 : q2, c->simsc.p,
+                                                       o1, o2);
+    LAUNCH_CHECK(c, "k_sim_dot2");
+  }
   return MPM_OK;
 }
 
@@ -626,8 +630,9 @@ static int spmv(mpm_ctx* c, const int32_t* simflag, const double* val, const dou
 
 int launch_spmv(mpm_ctx* c, const double* val, const double* x, double* y, const double* z) {
   if (!z) return spmv(c, nullptr, val, x, y, nullptr, nullptr, -1, -1);
-  // the in-loop form: product, both partial dot products and their per-sim reduction
-  return spmv(c, nullptr, val, x, y, z, c->part.p, 2, 3, SC_TS, SC_TT);
+  // the in-loop form: product and both partial dot products (their per-sim
+  // reduction is a separate launch, not part of this kernel)
+  return spmv(c, nullptr, val, x, y, z, c->part.p, 2, 3);
 }
 
 int launch_bj_inv(mpm_ctx* c, const double* val) {
@@ -662,16 +667,25 @@ static int bicg_iter(mpm_ctx* c, const double* val, int it, const KBufs& K) {
   const double* dinv = c->ktrans ? c->dinvT.p : c->dinv.p;
   int rc;
   const bool timed = c->time_spmv > 0 && it % c->time_spmv == 0;
-  k_bicg_a<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->blk_first.p, it, c->simsc.p, c->simflag.p, c->kr.p,
-                                         c->kp.p, c->kv.p, c->kph.p, dinv);
-  if ((rc = spmv_timed(c, timed, c->simflag.p, val, c->kph.p, c->kv.p, c->krh.p, K.part_rv, 0, -1, SC_RV, -1)))
+  // small sims: every consumer workgroup sums its sim's partials itself (no
+  // extra launch); large sims: one reduction launch per dot product
+  const bool fused = c->kfused;
+  k_bicg_a<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->blk_first.p, it, fused ? K.part_rr : nullptr, c->simsc.p,
+                                         c->simflag.p, c->kr.p, c->kp.p, c->kv.p, c->kph.p, dinv);
+  if ((rc = spmv_timed(c, timed, c->simflag.p, val, c->kph.p, c->kv.p, c->krh.p, K.part_rv, 0, -1,
+                       fused ? -1 : SC_RV, -1)))
     return rc;
-  k_bicg_c<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->blk_first.p, it, c->simsc.p, c->simflag.p, c->kr.p,
-                                         c->kv.p, c->ks.p, c->ksh.p, dinv);
-  if ((rc = spmv_timed(c, timed, c->simflag.p, val, c->ksh.p, c->kt.p, c->ks.p, K.part_ts, 0, 1, SC_TS, SC_TT)))
+  k_bicg_c<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->blk_first.p, it, fused ? K.part_rv : nullptr, c->simsc.p,
+                                         c->simflag.p, c->kr.p, c->kv.p, c->ks.p, c->ksh.p, dinv);
+  if ((rc = spmv_timed(c, timed, c->simflag.p, val, c->ksh.p, c->kt.p, c->ks.p, K.part_ts, 0, 1,
+                       fused ? -1 : SC_TS, SC_TT)))
     return rc;
-  k_bicg_e<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->blk_first.p, c->kcnt.p, c->simsc.p, c->simflag.p, c->kx.p,
-                                         c->kr.p, c->krh.p, c->kph.p, c->ksh.p, c->ks.p, c->kt.p, K.part_rr);
+  k_bicg_e<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->blk_first.p, fused ? K.part_ts : nullptr, c->simsc.p,
+                                         c->simflag.p, c->kx.p, c->kr.p, c->krh.p, c->kph.p, c->ksh.p, c->ks.p, c->kt.p,
+                                         K.part_rr);
+  if (!fused)
+    k_sim_dot2<<<(unsigned)c->nsim, RT, 0, c->stream>>>(c->blk_first.p, c->simflag.p, K.part_rr, 0, c->simsc.p, SC_RHR,
+                                                       SC_RRN);
   LAUNCH_CHECK(c, "bicgstab step");
   return MPM_OK;
 }
@@ -803,6 +817,10 @@ int krylov_solve(mpm_ctx* c, const double* val, double rtol, int max_iter, std::
   std::vector<int32_t> hflag(2 * nsim, 0);
   iters_out.assign(nsim, 0);
   const bool gmres_only = c->kmethod == 1;
+  int max_blocks = 0;
+  for (int sidx = 0; sidx < nsim; ++sidx)
+    max_blocks = std::max(max_blocks, c->sim_blk_first[sidx + 1] - c->sim_blk_first[sidx]);
+  c->kfused = max_blocks <= 2048;
   const int bicg_budget = gmres_only ? 0 : max_iter / 2;
   int used = 0;           // iterations spent over all (re)starts
   const int CHUNK = 16;

@@ -548,9 +548,8 @@ int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row_out, int6
   size_t nbk = c->blocks_h.size();
   ok = c->blocks.ensure(nbk) == hipSuccess && c->blk_first.ensure(nsim + 1) == hipSuccess &&
        c->part.ensure((nbk + 1) * NQ) == hipSuccess && c->simsc.ensure(nsim * 16) == hipSuccess &&
-       c->simflag.ensure(nsim * 2) == hipSuccess && c->kcnt.ensure(nsim) == hipSuccess;
+       c->simflag.ensure(nsim * 2) == hipSuccess;
   if (!ok) return c->fail(MPM_E_NOMEM, "device allocation failed (blocks)");
-  HIPC(c, hipMemsetAsync(c->kcnt.p, 0, nsim * sizeof(int32_t), c->stream));
   if (nbk) HIPC(c, hipMemcpyAsync(c->blocks.p, c->blocks_h.data(), nbk * sizeof(RowBlock), hipMemcpyHostToDevice, c->stream));
   HIPC(c, hipMemcpyAsync(c->blk_first.p, c->sim_blk_first.data(), (nsim + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
                          c->stream));
