@@ -26,6 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KRYLOV_NAMES = {0: "block-Jacobi BiCGStab, GMRES(100) fallback", 1: "block-Jacobi GMRES(100)",
+                2: "BiCGStab preconditioned by a geometric multigrid V-cycle, GMRES(100) fallback"}
 
 
 def spmv_bytes(n_row, nnzb, bs):
@@ -61,6 +63,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--krylov-rtol", type=float, default=1e-12)
+    ap.add_argument("--krylov-method", type=int, default=2,
+                    help="0 block-Jacobi BiCGStab (GMRES fallback), 1 GMRES, 2 multigrid-preconditioned BiCGStab")
     ap.add_argument("--batch-sims", type=int, default=16,
                     help="sims of the batched footing set timed batched and one at a time (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=2, help="load steps of that comparison (incl. geostatic)")
@@ -101,7 +105,7 @@ def main():
         n_row, nnzb, nd = M.mpm_prepare(ctx, dp)
         du = torch.zeros(n_row * nd, dtype=torch.float64, device="cuda")
         rep = M.mpm_newton_step(ctx, dp, du, tol=w.tol, max_iter=25, commit=False, krylov_rtol=args.krylov_rtol,
-                                time_spmv=4)
+                                time_spmv=4, krylov_method=args.krylov_method)
         M.mpm_update(ctx, dp, du, x_out, F_out, be_out)
         print(f"[bench] step {step}: newton {rep['iters']} krylov {rep['krylov_iters']} "
               f"{rep['ms_total']:.1f} ms", file=sys.stderr, flush=True)
@@ -172,7 +176,8 @@ def main():
                                "(h=1/256 m), 131072 particles, E=1e7 Pa, nu=0.3, friction 30 deg, c=0, "
                                "geostatic load step",
                    "particles": npart, "rows": n_row, "bsr_blocks": nnzb, "block": nd,
-                   "newton_tol": w.tol, "krylov": "block-Jacobi BiCGStab", "krylov_rtol": args.krylov_rtol},
+                   "newton_tol": w.tol, "krylov": KRYLOV_NAMES[args.krylov_method],
+                   "krylov_rtol": args.krylov_rtol},
         "newton_step_ms": round(newton_ms, 3),
         "newton_iters_per_step": [r["iters"] for r in reps],
         "krylov_iters_per_step": [r["krylov_iters"] for r in reps],
@@ -187,14 +192,15 @@ def main():
                      "algorithmic_bytes_per_launch": nbytes},
     }
     if args.batch_sims > 0:
-        out["batched"] = batched_vs_sequential(ctx, args.batch_sims, args.batch_steps, args.krylov_rtol)
+        out["batched"] = batched_vs_sequential(ctx, args.batch_sims, args.batch_steps, args.krylov_rtol,
+                                               args.krylov_method)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     M.mpm_destroy(ctx)
     print(json.dumps(out))
 
 
-def batched_vs_sequential(ctx, nsims, nsteps, krylov_rtol):
+def batched_vs_sequential(ctx, nsims, nsteps, krylov_rtol, krylov_method):
     """Newton iterations per second summed over sims: the first nsims
     footings of the batched set (uneven sizes, E and friction per sim; the
     gradient reading of the footing) solved as one batch, against the same
@@ -210,7 +216,7 @@ def batched_vs_sequential(ctx, nsims, nsteps, krylov_rtol):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     dp = AD.make_batch(sims, E, phi)
-    run = AD.forward(ctx, dp, sims, steps, krylov_rtol=krylov_rtol)
+    run = AD.forward(ctx, dp, sims, steps, krylov_rtol=krylov_rtol, krylov_method=krylov_method)
     torch.cuda.synchronize()
     t_b = time.perf_counter() - t0
     print(f"[bench] batched {nsims} sims x {nsteps} steps: {t_b:.2f} s, newton {run.newton_iters}",
@@ -219,13 +225,13 @@ def batched_vs_sequential(ctx, nsims, nsteps, krylov_rtol):
     t0 = time.perf_counter()
     for k, w in enumerate(sims):
         d1 = AD.make_batch([w], [E[k]], [phi[k]])
-        r1 = AD.forward(ctx, d1, [w], steps, krylov_rtol=krylov_rtol)
+        r1 = AD.forward(ctx, d1, [w], steps, krylov_rtol=krylov_rtol, krylov_method=krylov_method)
         iters += sum(r1.newton_iters)
     torch.cuda.synchronize()
     t_s = time.perf_counter() - t0
     print(f"[bench] sequential: {t_s:.2f} s, {iters} Newton iterations", file=sys.stderr, flush=True)
     particles = sum(w.particles.np for w in sims)
-    return {"sims": nsims, "load_steps": nsteps, "particles": particles,
+    return {"sims": nsims, "load_steps": nsteps, "particles": particles, "krylov": KRYLOV_NAMES[krylov_method],
             "newton_iters": iters, "batched_s": round(t_b, 3), "sequential_s": round(t_s, 3),
             "newton_iters_per_s_batched": round(iters / t_b, 2),
             "newton_iters_per_s_sequential": round(iters / t_s, 2),

@@ -166,7 +166,12 @@ typedef struct {
                              HIP events on the context's stream (report fields spmv_*) */
   int32_t krylov_method;  /* 0: block-Jacobi BiCGStab (restarted while it improves) on up to half
                              of krylov_max_iter, then restarted GMRES(100) with the same
-                             preconditioner for the sims still above tolerance; 1: GMRES only */
+                             preconditioner for the sims still above tolerance; 1: GMRES only;
+                             2: as 0, with a geometric multigrid V-cycle (coarse levels
+                             rediscretized from the particles on grids of 2^l h) preconditioning
+                             BiCGStab, replayed from a captured HIP graph; 3: as 2 with the
+                             V-cycle launched kernel by kernel (same arithmetic); 2 and 3 are
+                             2-D single-phase only (else INVALID) */
 } mpm_newton_opts;
 
 #define MPM_MAX_REPORT 32

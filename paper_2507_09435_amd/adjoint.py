@@ -54,7 +54,7 @@ def set_params(dp, sims, E, phi):
     dp.tensors["phi"].copy_(torch.from_numpy(Pp))
 
 
-def forward(ctx, dp, sims, steps, tol=1e-10, krylov_rtol=1e-12, max_iter=25, line_search=0):
+def forward(ctx, dp, sims, steps, tol=1e-10, krylov_rtol=1e-12, max_iter=25, line_search=0, krylov_method=0):
     import torch
     T = dp.tensors
     R, cps, dus, nit, kit = [], [], [], [], []
@@ -64,7 +64,7 @@ def forward(ctx, dp, sims, steps, tol=1e-10, krylov_rtol=1e-12, max_iter=25, lin
         n_row, nnzb, nd = M.mpm_prepare(ctx, dp)
         du = torch.zeros(n_row * nd, dtype=torch.float64, device=T["x"].device)
         rep = M.mpm_newton_step(ctx, dp, du, tol=tol, max_iter=max_iter, commit=True, krylov_rtol=krylov_rtol,
-                                line_search=line_search)
+                                line_search=line_search, krylov_method=krylov_method)
         R.append(rep["sim_reaction"])
         dus.append(du)
         nit.append(rep["iters"])

@@ -80,11 +80,23 @@ int check_prepared(mpm_ctx* c, const mpm_problem* pb) {
   return MPM_OK;
 }
 
-#define GUARD(expr)          \
-  do {                       \
-    int rc_ = (expr);        \
-    if (rc_) return rc_;     \
-  } while (0)
+// Device buffers of a context and of its multigrid levels.
+void ctx_release(mpm_ctx* c) {
+  mg_release(c);
+  c->sims.release(); c->sim_start.release(); c->okey.release(); c->gcount.release(); c->gstart.release();
+  c->cursor.release(); c->okey_sorted.release(); c->sort_tmp.release(); c->perm.release(); c->psim.release(); c->scan_tmp.release(); c->node_flag.release();
+  c->node_map.release(); c->active_nodes.release(); c->row_sim.release(); c->rowcnt.release(); c->rowptr.release();
+  c->colind.release(); c->slot.release(); c->blocks.release(); c->blk_first.release(); c->flag.release();
+  c->xs.release(); c->vol0s.release(); c->Fs.release(); c->bes.release(); c->Es.release(); c->phis.release();
+  c->cmask.release(); c->rmask.release(); c->cval.release(); c->fext.release(); c->fint.release(); c->nvol.release();
+  c->work.release(); c->val.release(); c->dinv.release(); c->pdat.release(); c->gbuf.release(); c->rrec.release();
+  c->kx.release(); c->kr.release(); c->krh.release(); c->kp.release(); c->kv.release(); c->ks.release();
+  c->kt.release(); c->kph.release(); c->ksh.release(); c->kb.release(); c->part.release(); c->simsc.release();
+  c->simflag.release(); c->du_base.release(); c->alpha.release();
+  c->gV.release(); c->gsc.release(); c->gpart.release(); c->gflag.release(); c->greset.release();
+  c->tpos.release(); c->dinvT.release(); c->adj_mu.release(); c->adj_nu.release(); c->adj_theta.release();
+  c->adj_rbar.release();
+}
 
 extern "C" {
 
@@ -106,19 +118,7 @@ int mpm_destroy(mpm_ctx* c) {
   if (!c) return MPM_OK;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  c->sims.release(); c->sim_start.release(); c->okey.release(); c->gcount.release(); c->gstart.release();
-  c->cursor.release(); c->perm.release(); c->psim.release(); c->scan_tmp.release(); c->node_flag.release();
-  c->node_map.release(); c->active_nodes.release(); c->row_sim.release(); c->rowcnt.release(); c->rowptr.release();
-  c->colind.release(); c->slot.release(); c->blocks.release(); c->blk_first.release(); c->flag.release();
-  c->xs.release(); c->vol0s.release(); c->Fs.release(); c->bes.release(); c->Es.release(); c->phis.release();
-  c->cmask.release(); c->rmask.release(); c->cval.release(); c->fext.release(); c->fint.release(); c->nvol.release();
-  c->work.release(); c->val.release(); c->dinv.release(); c->pdat.release(); c->gbuf.release();
-  c->kx.release(); c->kr.release(); c->krh.release(); c->kp.release(); c->kv.release(); c->ks.release();
-  c->kt.release(); c->kph.release(); c->ksh.release(); c->kb.release(); c->part.release(); c->simsc.release();
-  c->simflag.release(); c->du_base.release(); c->alpha.release();
-  c->gV.release(); c->gsc.release(); c->gpart.release(); c->gflag.release(); c->greset.release();
-  c->tpos.release(); c->dinvT.release(); c->adj_mu.release(); c->adj_nu.release(); c->adj_theta.release();
-  c->adj_rbar.release();
+  ctx_release(c);
   delete c;
   return MPM_OK;
 }
@@ -196,8 +196,12 @@ int mpm_newton_step(mpm_ctx* c, const mpm_problem* pb, const mpm_newton_opts* op
   const int64_t nv = c->n_row * nd;
   const double rtol_fixed = opts->krylov_rtol;
   const int kmax = opts->krylov_max_iter > 0 ? opts->krylov_max_iter : 20000;
-  if (opts->krylov_method < 0 || opts->krylov_method > 1) return c->fail(MPM_E_INVALID, "unknown krylov_method");
+  if (opts->krylov_method < 0 || opts->krylov_method > 3) return c->fail(MPM_E_INVALID, "unknown krylov_method");
+  const bool use_mg = opts->krylov_method >= 2;
+  if (use_mg && (c->dim != 2 || c->up))
+    return c->fail(MPM_E_INVALID, "krylov_method 2 and 3 (multigrid) cover 2-D single-phase problems");
   c->kmethod = opts->krylov_method;
+  if (use_mg && !c->mg_ready) GUARD(mg_build(c, pb));
   const double stall = opts->stall_factor > 0 ? opts->stall_factor : 0.0;
   if (c->val.ensure(c->nnzb * nd * nd) != hipSuccess || c->kb.ensure(nv) != hipSuccess ||
       c->work.ensure(nv) != hipSuccess)
@@ -258,8 +262,10 @@ int mpm_newton_step(mpm_ctx* c, const mpm_problem* pb, const mpm_newton_opts* op
     // Jacobian and linear solve for the sims still iterating
     HIPC(c, hipEventRecord(ev[2], c->stream));
     GUARD(launch_jacobian(c, pb, du, c->val.p, true));
-    GUARD(launch_bj_inv(c, c->val.p));
     HIPC(c, hipEventRecord(ev[3], c->stream));
+    // preconditioner setup belongs to the linear solve's time
+    GUARD(launch_bj_inv(c, c->val.p));
+    if (use_mg) GUARD(mg_setup(c));
     HIPC(c, hipMemcpyAsync(active.p, act.data(), nsim, hipMemcpyHostToDevice, c->stream));
     if (!c->blocks_h.empty()) {
       k_rhs<<<(unsigned)c->blocks_h.size(), 64, 0, c->stream>>>(c->blocks.p, nd, active.p, c->work.p, c->kb.p);

@@ -287,7 +287,6 @@ __global__ void __launch_bounds__(JT) k_jac2g(AsmArgs A, const double* __restric
 // k_jac2_blocks: every BSR block (a, b) is the sum, in origin order, of the
 // group blocks of the (at most nine) origins whose stencil holds both nodes,
 // written once (no clearing, no atomics).
-constexpr int PD2 = 32;   // doubles per particle record: T 0..15, wx 16..18, dwx 19..21, wy 22..24, dwy 25..27
 
 __global__ void __launch_bounds__(256) k_tan2(AsmArgs A, const double* __restrict__ du, double* __restrict__ pdat) {
   const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -315,7 +314,6 @@ __device__ __forceinline__ double sel3(int i, double v0, double v1, double v2) {
   return i == 0 ? v0 : (i == 1 ? v1 : v2);
 }
 
-constexpr int GB2 = 81 * 4;   // doubles per origin in the group-block buffer
 
 __global__ void __launch_bounds__(256) k_grp2(int64_t n_okeys, const int32_t* __restrict__ gstart,
                                              const double* __restrict__ pdat, double* __restrict__ gbuf) {
@@ -404,52 +402,68 @@ __global__ void __launch_bounds__(256) k_jac2_blocks(int64_t n_row, const int64_
   for (int e = 0; e < 4; ++e) blk[e] = acc[e];
 }
 
-// Residual, 2-D, group-cooperative: per particle V0 P (and the u-p scalars),
-// then one thread per (group, node) sums the group and adds once.
-__global__ void __launch_bounds__(GP) k_fint2g(AsmArgs A, const double* __restrict__ du, double* __restrict__ fint) {
-  __shared__ double sP[GP][7];          // V0 P (4), V0 s1, V0 vv (2)
-  __shared__ double sW[GP][2][3], sD[GP][2][3];
-  __shared__ int32_t sKey[GP], sRow[GP][9], sG[GP + 1], sWc[GP / 64];
-  const int64_t base = (int64_t)blockIdx.x * GP;
-  const int n = (int)min<int64_t>(GP, A.np - base);
-  const int t = threadIdx.x;
-  if (t < n) {
-    const int64_t i = base + t;
-    PLoad<2> L;
-    load_particle<2>(A, i, du, L);
-    Mat<double> m = make_mat<double>(L.E, A.nu, L.phi, A.c, A.psi, A.dp, A.match, A.apex_reg);
-    Out2<double> o;
-    mech2<double>(m, L.dF, load_be2(A, i), L.Jn, A.up, up_par(A), L.pp, L.gp, o, nullptr);
-    sP[t][0] = L.v0 * o.P[0][0]; sP[t][1] = L.v0 * o.P[0][1];
-    sP[t][2] = L.v0 * o.P[1][0]; sP[t][3] = L.v0 * o.P[1][1];
-    sP[t][4] = A.up ? L.v0 * o.s1 : 0.0;
-    sP[t][5] = A.up ? L.v0 * o.vv[0] : 0.0;
-    sP[t][6] = A.up ? L.v0 * o.vv[1] : 0.0;
+// 2-D residual P2G without atomics.  k_fint2_rec writes one record per
+// particle (sorted order): V0 P (4), for u-p V0 s1 and V0 vv (3), then the
+// stencil's weights and derivatives per axis.  k_fint2_rows gives each row
+// (node a) to one thread, which sums f_a = sum_p V0 P_p grad w_a(x_p) (and the
+// u-p row) over the particles of the (at most nine) stencil groups whose
+// stencil holds a, in group then particle order: deterministic, written once.
+constexpr int RD2 = 20;   // doubles per residual record: V0 P 0..3, u-p 4..6, wx 8..10, dwx 11..13, wy 14..16, dwy 17..19
+
+__global__ void __launch_bounds__(256) k_fint2_rec(AsmArgs A, const double* __restrict__ du, double* __restrict__ rec) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= A.np) return;
+  PLoad<2> L;
+  load_particle<2>(A, i, du, L);
+  Mat<double> m = make_mat<double>(L.E, A.nu, L.phi, A.c, A.psi, A.dp, A.match, A.apex_reg);
+  Out2<double> o;
+  mech2<double>(m, L.dF, load_be2(A, i), L.Jn, A.up, up_par(A), L.pp, L.gp, o, nullptr);
+  double* R = rec + i * RD2;
+  R[0] = L.v0 * o.P[0][0]; R[1] = L.v0 * o.P[0][1];
+  R[2] = L.v0 * o.P[1][0]; R[3] = L.v0 * o.P[1][1];
+  R[4] = A.up ? L.v0 * o.s1 : 0.0;
+  R[5] = A.up ? L.v0 * o.vv[0] : 0.0;
+  R[6] = A.up ? L.v0 * o.vv[1] : 0.0;
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) { sW[t][k][a] = L.st.w[k][a]; sD[t][k][a] = L.st.dw[k][a]; }
-#pragma unroll
-    for (int a = 0; a < 9; ++a) sRow[t][a] = L.row[a];
-    sKey[t] = origin_key2(A.sims[A.psim[i]], L.st);
+  for (int a = 0; a < 3; ++a) {
+    R[8 + a] = L.st.w[0][a];
+    R[11 + a] = L.st.dw[0][a];
+    R[14 + a] = L.st.w[1][a];
+    R[17 + a] = L.st.dw[1][a];
   }
-  __syncthreads();
-  const int G = group_starts(sKey, n, sG, sWc);
-  const int nd = A.nd;
-  for (int task = t; task < 9 * G; task += GP) {
-    const int g = task / 9, a = task % 9, ax = a % 3, ay = a / 3;
-    double f0 = 0.0, f1 = 0.0, f2 = 0.0;
-    for (int p = sG[g]; p < sG[g + 1]; ++p) {
-      const double ga0 = sD[p][0][ax] * sW[p][1][ay], ga1 = sW[p][0][ax] * sD[p][1][ay];
-      f0 += sP[p][0] * ga0 + sP[p][1] * ga1;
-      f1 += sP[p][2] * ga0 + sP[p][3] * ga1;
-      if (A.up) f2 += sW[p][0][ax] * sW[p][1][ay] * sP[p][4] + ga0 * sP[p][5] + ga1 * sP[p][6];
+}
+
+__global__ void __launch_bounds__(256) k_fint2_rows(int64_t n_row, int nd, int up,
+                                                   const int64_t* __restrict__ active_nodes,
+                                                   const int32_t* __restrict__ row_sim,
+                                                   const SimDev* __restrict__ sims,
+                                                   const int32_t* __restrict__ gstart,
+                                                   const double* __restrict__ rec, double* __restrict__ fint) {
+  const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (row >= n_row) return;
+  const SimDev& S = sims[row_sim[row]];
+  const int64_t nid = active_nodes[row] - S.node_base;
+  const int ix = (int)(nid % S.nna[0]) - 1, iy = (int)(nid / S.nna[0]) - 1;
+  double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+  for (int oy = max(iy - 2, -1); oy <= min(iy, S.n[1] - 1); ++oy) {
+    const int ay = iy - oy;
+    for (int ox = max(ix - 2, -1); ox <= min(ix, S.n[0] - 1); ++ox) {
+      const int ax = ix - ox;
+      const int64_t key = S.okey_base + (ox + 1) + (int64_t)S.noa[0] * (oy + 1);
+      const int p1 = gstart[key + 1];
+      for (int p = gstart[key]; p < p1; ++p) {
+        const double* R = rec + (int64_t)p * RD2;
+        const double wx = R[8 + ax], dwx = R[11 + ax], wy = R[14 + ay], dwy = R[17 + ay];
+        const double ga0 = dwx * wy, ga1 = wx * dwy;
+        f0 += R[0] * ga0 + R[1] * ga1;
+        f1 += R[2] * ga0 + R[3] * ga1;
+        if (up) f2 += wx * wy * R[4] + ga0 * R[5] + ga1 * R[6];
+      }
     }
-    double* f = fint + (int64_t)sRow[sG[g]][a] * nd;
-    atomicAdd(&f[0], f0);
-    atomicAdd(&f[1], f1);
-    if (A.up) atomicAdd(&f[2], f2);
   }
+  fint[row * nd] = f0;
+  fint[row * nd + 1] = f1;
+  if (up) fint[row * nd + 2] = f2;
 }
 
 // ---------------------------------------------- group-cooperative 3-D ------
@@ -710,16 +724,26 @@ static unsigned nb256(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + 25
 // f_int into c->fint (zeroed first).
 int launch_fint(mpm_ctx* c, const mpm_problem* pb, const double* du) {
   AsmArgs A = make_args(c, pb);
+  if (c->dim == 2) {
+    // particle records, then one writer per row (deterministic, no clearing)
+    if (c->rrec.ensure(std::max<int64_t>(1, c->np) * RD2) != hipSuccess)
+      return c->fail(MPM_E_NOMEM, "residual records allocation failed");
+    if (c->np > 0) {
+      k_fint2_rec<<<(unsigned)((c->np + 255) / 256), 256, 0, c->stream>>>(A, du, c->rrec.p);
+      LAUNCH_CHECK(c, "k_fint2_rec");
+    }
+    if (c->n_row > 0) {
+      k_fint2_rows<<<(unsigned)((c->n_row + 255) / 256), 256, 0, c->stream>>>(
+          c->n_row, c->nd, c->up, c->active_nodes.p, c->row_sim.p, c->sims.p, c->gstart.p, c->rrec.p, c->fint.p);
+      LAUNCH_CHECK(c, "k_fint2_rows");
+    }
+    return MPM_OK;
+  }
   HIPC(c, hipMemsetAsync(c->fint.p, 0, c->n_row * c->nd * sizeof(double), c->stream));
   if (c->np == 0) return MPM_OK;
-  if (c->dim == 2) {
-    unsigned g = (unsigned)((c->np + GP - 1) / GP);
-    k_fint2g<<<g, GP, 0, c->stream>>>(A, du, c->fint.p);
-  } else {
-    unsigned g = (unsigned)((c->np + GP3 - 1) / GP3);
-    k_fint3g<<<g, GP3, 0, c->stream>>>(A, du, c->fint.p, c->flag.p);
-  }
-  LAUNCH_CHECK(c, "k_fint");
+  unsigned g = (unsigned)((c->np + GP3 - 1) / GP3);
+  k_fint3g<<<g, GP3, 0, c->stream>>>(A, du, c->fint.p, c->flag.p);
+  LAUNCH_CHECK(c, "k_fint3g");
   return MPM_OK;
 }
 
@@ -747,6 +771,30 @@ int sim_sum_launch(mpm_ctx* c, const double* part, int q, int off) {
   return MPM_OK;
 }
 
+// Group blocks and BSR blocks from the particle records already in c->pdat
+// (2-D single-phase); apply_bc writes constrained rows and columns as the
+// identity's.
+int launch_jac2_records(mpm_ctx* c, double* val, bool apply_bc) {
+  if (c->gbuf.ensure(std::max<int64_t>(1, c->n_okeys) * GB2) != hipSuccess)
+    return c->fail(MPM_E_NOMEM, "group block buffer allocation failed");
+  if (c->n_okeys > 0) {
+    k_grp2<<<(unsigned)((c->n_okeys + 3) / 4), 256, 0, c->stream>>>(c->n_okeys, c->gstart.p, c->pdat.p, c->gbuf.p);
+    LAUNCH_CHECK(c, "k_grp2");
+  }
+  return launch_jac2_blocks(c, val, apply_bc);
+}
+
+// BSR blocks from the group blocks already in c->gbuf.
+int launch_jac2_blocks(mpm_ctx* c, double* val, bool apply_bc) {
+  if (c->n_row > 0) {
+    k_jac2_blocks<<<(unsigned)((c->n_row * 32 + 255) / 256), 256, 0, c->stream>>>(
+        c->n_row, c->active_nodes.p, c->row_sim.p, c->sims.p, c->gstart.p, c->rowptr.p, c->colind.p, c->gbuf.p,
+        apply_bc ? c->cmask.p : nullptr, val);
+    LAUNCH_CHECK(c, "k_jac2_blocks");
+  }
+  return MPM_OK;
+}
+
 int launch_jacobian(mpm_ctx* c, const mpm_problem* pb, const double* du, double* val, bool apply_bc) {
   AsmArgs A = make_args(c, pb);
   const int nd = c->nd;
@@ -758,18 +806,7 @@ int launch_jacobian(mpm_ctx* c, const mpm_problem* pb, const double* du, double*
       k_tan2<<<(unsigned)((4 * c->np + 255) / 256), 256, 0, c->stream>>>(A, du, c->pdat.p);
       LAUNCH_CHECK(c, "k_tan2");
     }
-    if (c->gbuf.ensure(std::max<int64_t>(1, c->n_okeys) * GB2) != hipSuccess)
-      return c->fail(MPM_E_NOMEM, "group block buffer allocation failed");
-    if (c->n_okeys > 0) {
-      k_grp2<<<(unsigned)((c->n_okeys + 3) / 4), 256, 0, c->stream>>>(c->n_okeys, c->gstart.p, c->pdat.p, c->gbuf.p);
-      LAUNCH_CHECK(c, "k_grp2");
-    }
-    if (c->n_row > 0) {
-      k_jac2_blocks<<<(unsigned)((c->n_row * 32 + 255) / 256), 256, 0, c->stream>>>(
-          c->n_row, c->active_nodes.p, c->row_sim.p, c->sims.p, c->gstart.p, c->rowptr.p, c->colind.p, c->gbuf.p,
-          apply_bc ? c->cmask.p : nullptr, val);
-      LAUNCH_CHECK(c, "k_jac2_blocks");
-    }
+    GUARD(launch_jac2_records(c, val, apply_bc));
   } else {
     HIPC(c, hipMemsetAsync(val, 0, c->nnzb * nd * nd * sizeof(double), c->stream));
   }

@@ -12,6 +12,12 @@
     if (e_ != hipSuccess) return (c)->fail(MPM_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+#define GUARD(expr)          \
+  do {                       \
+    int rc_ = (expr);        \
+    if (rc_) return rc_;     \
+  } while (0)
+
 #define LAUNCH_CHECK(c, name)                                                                   \
   do {                                                                                          \
     hipError_t e_ = hipGetLastError();                                                          \
@@ -80,6 +86,11 @@ __device__ __forceinline__ int nb_index(int a, int b) {
 
 }  // namespace mpm
 
+namespace mpm {
+constexpr int PD2 = 32;       // doubles per 2-D particle record: V0 T 0..15, wx 16..18, dwx 19..21, wy 22..24, dwy 25..27
+constexpr int GB2 = 81 * 4;   // doubles per origin in the 2-D group-block buffer
+}  // namespace mpm
+
 int validate_problem(mpm_ctx* c, const mpm_problem* pb);
 int check_prepared(mpm_ctx* c, const mpm_problem* pb);
 int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row, int64_t* nnzb, int32_t* nd);
@@ -94,3 +105,12 @@ int launch_update(mpm_ctx* c, const mpm_problem* pb, const double* du, double* x
 int launch_bj_inv(mpm_ctx* c, const double* val);
 int launch_spmv(mpm_ctx* c, const double* val, const double* x, double* y, const double* z);
 int krylov_solve(mpm_ctx* c, const double* val, double rtol, int max_iter, std::vector<int>& iters_out);
+int launch_jac2_records(mpm_ctx* c, double* val, bool apply_bc);
+int launch_jac2_blocks(mpm_ctx* c, double* val, bool apply_bc);
+void ctx_release(mpm_ctx* c);
+// multigrid preconditioner (2-D single-phase)
+int mg_build(mpm_ctx* c, const mpm_problem* pb);
+int mg_setup(mpm_ctx* c);
+int mg_vcycle(mpm_ctx* c, const double* b, double* x);
+void mg_release(mpm_ctx* c);
+void mg_drop_graphs(mpm_ctx* c);

@@ -51,6 +51,25 @@ struct DBuf {
 
 }  // namespace mpm
 
+struct mpm_ctx;
+namespace mpm {
+// One coarse multigrid level: a child context on the coarsened grids, its
+// Dirichlet mask, the map to the finest particle records, its vectors and
+// the chunks (at most MG_CHUNK particles of one stencil group) of its
+// group-block assembly.
+struct MgLevel {
+  mpm_ctx* sub = nullptr;
+  std::vector<mpm_grid> grids;
+  DBuf<uint8_t> mask;        // full coarse grid [nodes][2]
+  DBuf<int32_t> pmap;        // child-sorted particle -> finest-sorted particle
+  DBuf<double> vec;          // sweep partner, residual, solution, right-hand side (4 * n_row * 2)
+  DBuf<int32_t> chunk;       // per chunk: first particle, count
+  DBuf<int32_t> key_chunk;   // per origin key: first chunk (n_okeys + 1)
+  DBuf<double> part;         // per chunk: 81 partial 2x2 blocks
+  int64_t n_chunks = 0;
+};
+}  // namespace mpm
+
 struct mpm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -69,7 +88,9 @@ struct mpm_ctx {
   // sorting / pattern
   mpm::DBuf<mpm::SimDev> sims;
   mpm::DBuf<int64_t> sim_start;
-  mpm::DBuf<int32_t> okey, gcount, gstart, cursor, perm, psim;
+  mpm::DBuf<int32_t> okey, gcount, gstart, cursor, perm, psim;   // cursor: 0..np-1 for the key sort
+  mpm::DBuf<int32_t> okey_sorted;
+  mpm::DBuf<uint8_t> sort_tmp;
   mpm::DBuf<int32_t> scan_tmp;
   mpm::DBuf<int32_t> node_flag, node_map;      // node_map: full node -> row or -1
   mpm::DBuf<int64_t> active_nodes;
@@ -88,6 +109,7 @@ struct mpm_ctx {
   mpm::DBuf<double> val, dinv;
   mpm::DBuf<double> pdat;                      // per-particle tangent records (2-D assembly)
   mpm::DBuf<double> gbuf;                      // per-origin group blocks (2-D assembly)
+  mpm::DBuf<double> rrec;                      // per-particle residual records (2-D)
   // Krylov
   mpm::DBuf<double> kx, kr, krh, kp, kv, ks, kt, kph, ksh, kb;
   mpm::DBuf<double> part;                      // [nblocks][NQ]
@@ -111,6 +133,26 @@ struct mpm_ctx {
   int64_t spmv_n = 0;
   double* host_pinned = nullptr;               // small pinned staging
   size_t host_pinned_n = 0;
+
+  // multigrid hierarchy (levels 1..L are child contexts on grids of 2^l h)
+  std::vector<mpm::MgLevel*> mgl;
+  mpm::DBuf<double> mg_zero;                   // zero prescribed values for the child problems
+  mpm::DBuf<int32_t> mg_inv;                   // finest sorted index of each original particle
+  mpm::DBuf<double> mg_fine;                   // finest level: sweep partner and residual (2 * n_row * nd)
+  mpm::DBuf<double> mg_dense;                  // coarsest level: per sim dense matrix and inverse
+  mpm::DBuf<int32_t> mg_doff;                  // per sim: first coarsest row, rows
+  mpm::DBuf<mpm::SimDev> mg_sims;              // staging of a child level's descriptors
+  int mg_nmax = 0;                             // largest coarsest system (unknowns)
+  bool mg_ready = false;                       // hierarchy built for the current prepare
+  bool mg_on = false;                          // precondition the current solve with a V-cycle
+  bool mg_level = false;                       // this context is a coarse multigrid level
+  bool mg_graph = true;                        // replay captured V-cycles (false: launch them eagerly)
+  uint64_t mg_gen = 0;                         // bumped whenever the hierarchy is rebuilt
+  hipStream_t lstream = nullptr;               // stream the V-cycle kernels are launched on
+  hipStream_t cap_stream = nullptr;            // private stream for graph capture
+  struct MgGraph { hipGraphExec_t exec = nullptr; const void* key[5] = {}; uint64_t gen = 0; };
+  MgGraph mg_exec[2];                          // V-cycles of BiCGStab's two preconditioner applications
+  int mg_next = 0;
 
   int fail(int code, const std::string& msg) { err = msg; return code; }
 };

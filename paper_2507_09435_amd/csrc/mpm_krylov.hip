@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(64) k_bicg_a(const RowBlock* __restrict__ bloc
       int64_t k = row * BS + i;
       p[k] = r[k] + beta * (p[k] - omega * v[k]);
     }
-    apply_dinv<BS>(dinv, row, p, ph);
+    if (dinv) apply_dinv<BS>(dinv, row, p, ph);   // else the multigrid V-cycle follows
   }
   if (lead) S[SC_RHO + (it & 1)] = rho;
 }
@@ -292,7 +292,7 @@ __global__ void __launch_bounds__(64) k_bicg_c(const RowBlock* __restrict__ bloc
       int64_t k = row * BS + i;
       s_[k] = r[k] - alpha * v[k];
     }
-    apply_dinv<BS>(dinv, row, s_, sh);
+    if (dinv) apply_dinv<BS>(dinv, row, s_, sh);
   }
   if (blockIdx.x == (unsigned)b0 && threadIdx.x == 0) S[SC_ALPHA] = alpha;
 }
@@ -670,13 +670,16 @@ static int bicg_iter(mpm_ctx* c, const double* val, int it, const KBufs& K) {
   // small sims: every consumer workgroup sums its sim's partials itself (no
   // extra launch); large sims: one reduction launch per dot product
   const bool fused = c->kfused;
+  const bool mg = c->mg_on;   // preconditioner: multigrid V-cycle instead of block-Jacobi
   k_bicg_a<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->blk_first.p, it, fused ? K.part_rr : nullptr, c->simsc.p,
-                                         c->simflag.p, c->kr.p, c->kp.p, c->kv.p, c->kph.p, dinv);
+                                         c->simflag.p, c->kr.p, c->kp.p, c->kv.p, c->kph.p, mg ? nullptr : dinv);
+  if (mg && (rc = mg_vcycle(c, c->kp.p, c->kph.p))) return rc;
   if ((rc = spmv_timed(c, timed, c->simflag.p, val, c->kph.p, c->kv.p, c->krh.p, K.part_rv, 0, -1,
                        fused ? -1 : SC_RV, -1)))
     return rc;
   k_bicg_c<BS><<<nbk, 64, 0, c->stream>>>(c->blocks.p, c->blk_first.p, it, fused ? K.part_rv : nullptr, c->simsc.p,
-                                         c->simflag.p, c->kr.p, c->kv.p, c->ks.p, c->ksh.p, dinv);
+                                         c->simflag.p, c->kr.p, c->kv.p, c->ks.p, c->ksh.p, mg ? nullptr : dinv);
+  if (mg && (rc = mg_vcycle(c, c->ks.p, c->ksh.p))) return rc;
   if ((rc = spmv_timed(c, timed, c->simflag.p, val, c->ksh.p, c->kt.p, c->ks.p, K.part_ts, 0, 1,
                        fused ? -1 : SC_TS, SC_TT)))
     return rc;
@@ -800,7 +803,9 @@ static int gmres_solve(mpm_ctx* c, const double* val, std::vector<uint8_t> work,
 // Solve val * x = b (compact vectors c->kb -> c->kx).  iters_out: host
 // [nsim] iterations per sim (BiCGStab iterations plus GMRES basis vectors).
 // c->kmethod 0: BiCGStab with restarts on up to half the budget, then
-// GMRES(GM_M) for the sims still above tolerance; 1: GMRES only.  Accepts a
+// GMRES(GM_M) for the sims still above tolerance; 1: GMRES only; 2: as 0
+// with the multigrid V-cycle preconditioning BiCGStab (c->mg_on), replayed
+// from captured graphs; 3: as 2 with the V-cycle launched eagerly.  Accepts a
 // sim when its true residual is at most 10 rtol ||b||.  Returns MPM_E_KRYLOV
 // when a sim ends above that (beyond the soft floor).
 int krylov_solve(mpm_ctx* c, const double* val, double rtol, int max_iter, std::vector<int>& iters_out) {
@@ -817,6 +822,8 @@ int krylov_solve(mpm_ctx* c, const double* val, double rtol, int max_iter, std::
   std::vector<int32_t> hflag(2 * nsim, 0);
   iters_out.assign(nsim, 0);
   const bool gmres_only = c->kmethod == 1;
+  c->mg_on = (c->kmethod == 2 || c->kmethod == 3) && !c->ktrans;
+  c->mg_graph = c->kmethod == 2;
   int max_blocks = 0;
   for (int sidx = 0; sidx < nsim; ++sidx)
     max_blocks = std::max(max_blocks, c->sim_blk_first[sidx + 1] - c->sim_blk_first[sidx]);
@@ -872,6 +879,7 @@ int krylov_solve(mpm_ctx* c, const double* val, double rtol, int max_iter, std::
     if (!good && attempt > 0 && !(worst < 0.5 * last_worst)) { last_worst = std::min(last_worst, worst); break; }
     last_worst = std::min(last_worst, worst);
   }
+  c->mg_on = false;   // the GMRES fallback is block-Jacobi preconditioned
   if (rc == MPM_OK && !good && used < max_iter) {
     std::vector<uint8_t> work(nsim, 0), reset(nsim, 0);
     for (int s = 0; s < nsim; ++s) {

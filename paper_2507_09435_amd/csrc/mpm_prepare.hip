@@ -1,6 +1,8 @@
 // Particle binning by B-spline stencil origin and the block-sparse Jacobian
 // pattern of one load step (Sec. 3.2: every particle couples the 3^d nodes
 // of its stencil, so a node row couples at most 5^d nodes, Table 1).
+#include <hipcub/hipcub.hpp>
+
 #include "mpm_kernels.hpp"
 #include "mpm_internal.hpp"
 
@@ -124,31 +126,23 @@ __global__ void k_okeys(const double* __restrict__ x, int64_t np, const int64_t*
   psim_in[p] = s;
 }
 
+// Particles per origin key.  A wave whose particles share one key (large
+// stencil groups on coarse grids) adds its count with one atomic.
 __global__ void k_hist(const int32_t* __restrict__ okey, int64_t np, int32_t* __restrict__ cnt) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < np) atomicAdd(&cnt[okey[p]], 1);
-}
-
-__global__ void k_scatter(const int32_t* __restrict__ okey, int64_t np, const int32_t* __restrict__ start,
-                          int32_t* __restrict__ cursor, int32_t* __restrict__ perm) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= np) return;
-  int32_t k = okey[p];
-  int32_t pos = start[k] + atomicAdd(&cursor[k], 1);
-  perm[pos] = (int32_t)p;
-}
-
-// Deterministic order inside each stencil group: ascending input index.
-__global__ void k_group_sort(const int32_t* __restrict__ start, int64_t nkeys, int32_t* __restrict__ perm) {
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nkeys) return;
-  int32_t b = start[k], e = start[k + 1];
-  for (int32_t i = b + 1; i < e; ++i) {
-    int32_t v = perm[i];
-    int32_t j = i - 1;
-    while (j >= b && perm[j] > v) { perm[j + 1] = perm[j]; --j; }
-    perm[j + 1] = v;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = p < np;
+  const int32_t k = okey[valid ? p : np - 1];
+  if (__all(k == __shfl(k, 0))) {
+    const int n = __popcll(__ballot(valid));
+    if (threadIdx.x % 64 == 0) atomicAdd(&cnt[k], n);
+  } else if (valid) {
+    atomicAdd(&cnt[k], 1);
   }
+}
+
+__global__ void k_iota(int64_t np, int32_t* __restrict__ v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < np) v[i] = (int32_t)i;
 }
 
 // Sorted SoA copies of the particle state.
@@ -300,15 +294,25 @@ template <int DIM>
 __global__ void k_node_volume(int64_t np, const double* __restrict__ xs, const double* __restrict__ vs,
                               const int32_t* __restrict__ psim, const SimDev* __restrict__ sims,
                               const int32_t* __restrict__ node_map, double* __restrict__ nvol) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= np) return;
+  // particles are sorted by stencil origin: a wave whose particles share one
+  // stencil (coarse grids) sums its weights first and adds once per node
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i0 < np;
+  const int64_t i = valid ? i0 : np - 1;
   const SimDev& S = sims[psim[i]];
   Stencil<DIM> st;
   make_stencil<DIM>(S, xs, np, i, st);
-  double v0 = vs[i];
-  for (int a = 0; a < Stencil<DIM>::NN; ++a) {
-    int32_t r = node_map[st.node(S, a)];
-    atomicAdd(&nvol[r], st.weight(a) * v0);
+  const double v0 = valid ? vs[i] : 0.0;
+  const int64_t n0 = st.node(S, 0);
+  if (__all(n0 == __shfl(n0, 0))) {
+    for (int a = 0; a < Stencil<DIM>::NN; ++a) {
+      double w = st.weight(a) * v0;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
+      if (threadIdx.x % 64 == 0) atomicAdd(&nvol[node_map[st.node(S, a)]], w);
+    }
+  } else if (valid) {
+    for (int a = 0; a < Stencil<DIM>::NN; ++a) atomicAdd(&nvol[node_map[st.node(S, a)]], st.weight(a) * v0);
   }
 }
 
@@ -352,6 +356,44 @@ __global__ void k_fext(int64_t np, int nd, const double* __restrict__ xs, const 
     double w = st.weight(a);
     for (int k = 0; k < DIM; ++k) atomicAdd(&fext[(int64_t)r * nd + k], w * f[k]);
   }
+}
+
+// 2-D external force as a row gather (deterministic, no atomics): f_ext at
+// node a sums w_a(x_p) (rho0 V0 g + f_p) over the particles of the stencil
+// groups whose stencil holds a, in group then particle order.
+__global__ void k_fext2_rows(int64_t n_row, int nd, const int64_t* __restrict__ active_nodes,
+                             const int32_t* __restrict__ row_sim, const SimDev* __restrict__ sims,
+                             const int32_t* __restrict__ gstart, int64_t np, const double* __restrict__ xs,
+                             const double* __restrict__ vs, const double* __restrict__ fp_user,
+                             const int32_t* __restrict__ perm, double rho0, double gx, double gy,
+                             double* __restrict__ fext) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n_row) return;
+  const SimDev& S = sims[row_sim[row]];
+  const int64_t nid = active_nodes[row] - S.node_base;
+  const int ix = (int)(nid % S.nna[0]) - 1, iy = (int)(nid / S.nna[0]) - 1;
+  double f0 = 0.0, f1 = 0.0;
+  for (int oy = max(iy - 2, -1); oy <= min(iy, S.n[1] - 1); ++oy)
+    for (int ox = max(ix - 2, -1); ox <= min(ix, S.n[0] - 1); ++ox) {
+      const int64_t key = S.okey_base + (ox + 1) + (int64_t)S.noa[0] * (oy + 1);
+      const int p1 = gstart[key + 1];
+      for (int p = gstart[key]; p < p1; ++p) {
+        Stencil<2> st;
+        make_stencil<2>(S, xs, np, p, st);
+        const double w = st.w[0][ix - ox] * st.w[1][iy - oy];
+        const double m = rho0 * vs[p];
+        double fx = m * gx, fy = m * gy;
+        if (fp_user) {
+          const int64_t q = perm[p];
+          fx += fp_user[q];
+          fy += fp_user[np + q];
+        }
+        f0 += w * fx;
+        f1 += w * fy;
+      }
+    }
+  fext[row * nd] = f0;
+  fext[row * nd + 1] = f1;
 }
 
 }  // namespace mpm
@@ -410,7 +452,8 @@ int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row_out, int6
   // allocations
   bool ok = c->sims.ensure(nsim) == hipSuccess && c->sim_start.ensure(nsim + 1) == hipSuccess &&
             c->okey.ensure(np) == hipSuccess && c->gcount.ensure(ob + 1) == hipSuccess &&
-            c->gstart.ensure(ob + 1) == hipSuccess && c->cursor.ensure(ob + 1) == hipSuccess &&
+            c->gstart.ensure(ob + 1) == hipSuccess && c->cursor.ensure(std::max<int64_t>(1, np)) == hipSuccess &&
+            c->okey_sorted.ensure(std::max<int64_t>(1, np)) == hipSuccess &&
             c->perm.ensure(np) == hipSuccess && c->psim.ensure(2 * np) == hipSuccess &&
             c->flag.ensure(8) == hipSuccess && c->node_flag.ensure(nb + 1) == hipSuccess &&
             c->node_map.ensure(nb + 1) == hipSuccess && c->xs.ensure(dim * np) == hipSuccess &&
@@ -438,7 +481,6 @@ int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row_out, int6
 
   // counting sort by origin key
   HIPC(c, hipMemsetAsync(c->gcount.p, 0, (ob + 1) * sizeof(int32_t), c->stream));
-  HIPC(c, hipMemsetAsync(c->cursor.p, 0, (ob + 1) * sizeof(int32_t), c->stream));
   if (np > 0) {
     k_hist<<<nblk(np), TPB, 0, c->stream>>>(c->okey.p, np, c->gcount.p);
     LAUNCH_CHECK(c, "k_hist");
@@ -446,8 +488,19 @@ int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row_out, int6
   rc = scan_excl(c, c->gcount.p, ob, c->gstart.p, nullptr);
   if (rc) return rc;
   if (np > 0) {
-    k_scatter<<<nblk(np), TPB, 0, c->stream>>>(c->okey.p, np, c->gstart.p, c->cursor.p, c->perm.p);
-    k_group_sort<<<nblk(ob), TPB, 0, c->stream>>>(c->gstart.p, ob, c->perm.p);
+    // stable radix sort of (origin key, input index): each stencil group is
+    // contiguous, ascending input index inside it (deterministic order)
+    k_iota<<<nblk(np), TPB, 0, c->stream>>>(np, c->cursor.p);
+    LAUNCH_CHECK(c, "k_iota");
+    int bits = 1;
+    while (bits < 31 && (int64_t(1) << bits) < ob) ++bits;
+    size_t tmp_bytes = 0;
+    HIPC(c, hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, c->okey.p, c->okey_sorted.p, c->cursor.p,
+                                               c->perm.p, (int)np, 0, bits, c->stream));
+    if (c->sort_tmp.ensure(std::max<size_t>(1, tmp_bytes)) != hipSuccess)
+      return c->fail(MPM_E_NOMEM, "sort scratch allocation failed");
+    HIPC(c, hipcub::DeviceRadixSort::SortPairs(c->sort_tmp.p, tmp_bytes, c->okey.p, c->okey_sorted.p, c->cursor.p,
+                                               c->perm.p, (int)np, 0, bits, c->stream));
     k_gather<<<nblk(np), TPB, 0, c->stream>>>(np, dim, c->perm.p, psim_in, pb->P.x, pb->P.vol0, pb->P.F, pb->P.be,
                                               pb->P.E, pb->P.phi, c->xs.p, c->vol0s.p, c->Fs.p, c->bes.p, c->Es.p,
                                               c->phis.p, c->psim.p);
@@ -513,9 +566,10 @@ int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row_out, int6
     if (dim == 2) {
       k_node_volume<2><<<nblk(np), TPB, 0, c->stream>>>(np, c->xs.p, c->vol0s.p, c->psim.p, c->sims.p, c->node_map.p,
                                                         c->nvol.p);
-      k_fext<2><<<nblk(np), TPB, 0, c->stream>>>(np, nd, c->xs.p, c->vol0s.p, pb->P.fp, c->perm.p, c->psim.p,
-                                                 c->sims.p, c->node_map.p, pb->mat.rho0, pb->mat.g[0], pb->mat.g[1],
-                                                 pb->mat.g[2], c->fext.p);
+      if (!c->mg_level && n_row > 0)   // a multigrid level needs no external force
+        k_fext2_rows<<<nblk(n_row), TPB, 0, c->stream>>>(n_row, nd, c->active_nodes.p, c->row_sim.p, c->sims.p,
+                                                         c->gstart.p, np, c->xs.p, c->vol0s.p, pb->P.fp, c->perm.p,
+                                                         pb->mat.rho0, pb->mat.g[0], pb->mat.g[1], c->fext.p);
     } else {
       k_node_volume<3><<<nblk(np), TPB, 0, c->stream>>>(np, c->xs.p, c->vol0s.p, c->psim.p, c->sims.p, c->node_map.p,
                                                         c->nvol.p);
@@ -556,6 +610,7 @@ int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row_out, int6
   HIPC(c, hipStreamSynchronize(c->stream));
 
   c->user_x = pb->P.x;
+  c->mg_ready = false;   // a multigrid hierarchy belongs to one prepare
   c->prepared = true;
   if (n_row_out) *n_row_out = n_row;
   if (nnzb_out) *nnzb_out = c->nnzb;

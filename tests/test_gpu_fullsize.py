@@ -64,13 +64,15 @@ def test_full_residual_and_jacobian(c2):
     assert errs.max() <= 1e-9, errs.max()
 
 
-def test_full_geostatic_newton(c2):
+@pytest.mark.parametrize("method", [0, 2])
+def test_full_geostatic_newton(c2, method):
     from paper_2507_09435_amd import mpm as M
     w, ctx, dp, (n_row, nnzb, nd), pat = c2
     P, st = w.prob, w.particles
-    print("[fullsize] geostatic newton", flush=True)
+    print(f"[fullsize] geostatic newton, krylov_method={method}", flush=True)
     du = torch.zeros(n_row * nd, dtype=torch.float64, device="cuda")
-    rep = M.mpm_newton_step(ctx, dp, du, tol=1e-12, commit=False, krylov_rtol=1e-12)
+    rep = M.mpm_newton_step(ctx, dp, du, tol=1e-12, commit=False, krylov_rtol=1e-12, krylov_method=method)
+    print(f"  newton {rep['iters']} krylov {rep['krylov']} ms {rep['ms_total']:.1f}", flush=True)
     torch.cuda.synchronize()
     assert rep["converged"]
     bc = w.bc(0)
