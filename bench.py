@@ -65,9 +65,14 @@ def main():
     ap.add_argument("--krylov-rtol", type=float, default=1e-12)
     ap.add_argument("--krylov-method", type=int, default=2,
                     help="0 block-Jacobi BiCGStab (GMRES fallback), 1 GMRES, 2 multigrid-preconditioned BiCGStab")
-    ap.add_argument("--batch-sims", type=int, default=16,
+    ap.add_argument("--batch-sims", type=int, default=64,
                     help="sims of the batched footing set timed batched and one at a time (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=2, help="load steps of that comparison (incl. geostatic)")
+    ap.add_argument("--c5-full", action="store_true",
+                    help="only the batched footing set with its adjoint gradient checked by central differences")
+    ap.add_argument("--c5-sims", type=int, default=64)
+    ap.add_argument("--c5-steps", type=int, default=30)
+    ap.add_argument("--c5-fd-steps", type=int, default=10)
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only the SpMV launches and a plain copy of known size, for counter passes")
     args = ap.parse_args()
@@ -83,6 +88,9 @@ def main():
 
     if args.pmc_probe:
         pmc_probe(M, W, torch)
+        return
+    if args.c5_full:
+        print(json.dumps(c5_full(M, W, torch, args)))
         return
 
     w = W.make_c2(n_steps=1)
@@ -216,7 +224,8 @@ def batched_vs_sequential(ctx, nsims, nsteps, krylov_rtol, krylov_method):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     dp = AD.make_batch(sims, E, phi)
-    run = AD.forward(ctx, dp, sims, steps, krylov_rtol=krylov_rtol, krylov_method=krylov_method)
+    run = AD.forward(ctx, dp, sims, steps, krylov_rtol=krylov_rtol, krylov_method=krylov_method, line_search=4,
+                     max_iter=50)
     torch.cuda.synchronize()
     t_b = time.perf_counter() - t0
     print(f"[bench] batched {nsims} sims x {nsteps} steps: {t_b:.2f} s, newton {run.newton_iters}",
@@ -225,7 +234,8 @@ def batched_vs_sequential(ctx, nsims, nsteps, krylov_rtol, krylov_method):
     t0 = time.perf_counter()
     for k, w in enumerate(sims):
         d1 = AD.make_batch([w], [E[k]], [phi[k]])
-        r1 = AD.forward(ctx, d1, [w], steps, krylov_rtol=krylov_rtol, krylov_method=krylov_method)
+        r1 = AD.forward(ctx, d1, [w], steps, krylov_rtol=krylov_rtol, krylov_method=krylov_method, line_search=4,
+                        max_iter=50)
         iters += sum(r1.newton_iters)
     torch.cuda.synchronize()
     t_s = time.perf_counter() - t0
@@ -238,6 +248,79 @@ def batched_vs_sequential(ctx, nsims, nsteps, krylov_rtol, krylov_method):
             "speedup": round(t_s / t_b, 3),
             "note": "the same Newton iterations counted on both sides: the sum over sims of each sim's own "
                     "iterations when solved alone"}
+
+
+def c5_full(M, W, torch, args):
+    """The batched footing set at full size: every sim's load steps in one
+    batch, the squared misfit of each sim's footing reaction curve against
+    the curve of its target (E, friction), and its gradient with respect to
+    (E, friction) from the step adjoints behind torch.autograd.  The gradient
+    is checked against central differences of the same losses over the first
+    --c5-fd-steps steps (all sims perturbed at once: they are independent)."""
+    from paper_2507_09435_amd import adjoint as AD
+    sims, targets = W.make_c5(nsim=args.c5_sims, n_steps=args.c5_steps)
+    ctx = M.mpm_create(0, torch.cuda.current_stream().cuda_stream)
+
+    def progress(step, rep):
+        print(f"[c5]   step {step}: newton {rep['iters']} krylov {rep['krylov_iters']} {rep['ms_total']:.0f} ms",
+              file=sys.stderr, flush=True)
+
+    def adjoint_progress(step, kit):
+        print(f"[c5]   adjoint step {step}: krylov max {max(kit)}", file=sys.stderr, flush=True)
+
+    # backtracking line search: cone/elastic switching can make full Newton steps cycle
+    opts = dict(tol=1e-11, krylov_rtol=1e-12, max_iter=50, krylov_method=2, line_search=4, progress=progress,
+                adjoint_progress=adjoint_progress)
+    E0 = torch.tensor([float(w.particles.E[0]) for w in sims], dtype=torch.float64)
+    phi0 = torch.tensor([float(w.particles.phi[0]) for w in sims], dtype=torch.float64)
+    Et = torch.tensor([t[0] for t in targets], dtype=torch.float64)
+    phit = torch.tensor([t[1] for t in targets], dtype=torch.float64)
+
+    def timed(f, label):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = f()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        print(f"[c5] {label}: {dt:.2f} s", file=sys.stderr, flush=True)
+        return out, dt
+
+    def gradient(nsteps, label):
+        curves = AD.ReactionCurves(ctx, sims, list(range(nsteps + 1)), **opts)
+        with torch.no_grad():
+            Rt, _ = timed(lambda: curves(Et, phit), f"{label} target curves")
+        E = E0.clone().requires_grad_(True)
+        phi = phi0.clone().requires_grad_(True)
+        R, t_f = timed(lambda: curves(E, phi), f"{label} forward")
+        per_sim = ((R - Rt) ** 2).sum(dim=0)
+        _, t_b = timed(lambda: per_sim.sum().backward(), f"{label} backward")
+        return curves, Rt, E.grad.detach(), phi.grad.detach(), t_f, t_b, float(per_sim.sum())
+
+    _, _, _, _, t_fwd, t_bwd, loss_total = gradient(args.c5_steps, "full")
+    curves, Rt, gE, gphi, _, _, _ = gradient(args.c5_fd_steps, "fd horizon")
+
+    def loss(Ev, pv, label):
+        with torch.no_grad():
+            Rv, _ = timed(lambda: curves(Ev, pv), label)
+            return ((Rv - Rt) ** 2).sum(dim=0)
+
+    dE, dphi = 1e-5, 1e-5
+    fd_E = (loss(E0 * (1 + dE), phi0, "E+") - loss(E0 * (1 - dE), phi0, "E-")) / (2 * dE * E0)
+    fd_phi = (loss(E0, phi0 + dphi, "phi+") - loss(E0, phi0 - dphi, "phi-")) / (2 * dphi)
+
+    def rel(a, b):
+        a, b = a.numpy(), b.numpy()
+        return np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+
+    eE, ep = rel(gE, fd_E), rel(gphi, fd_phi)
+    M.mpm_destroy(ctx)
+    return {"mode": "batched footing set, forward + adjoint gradient", "sims": len(sims),
+            "load_steps": args.c5_steps + 1, "particles": sum(w.particles.np for w in sims),
+            "newton_tol": opts["tol"], "krylov": KRYLOV_NAMES[opts["krylov_method"]],
+            "forward_s": round(t_fwd, 3), "backward_s": round(t_bwd, 3), "loss_total": loss_total,
+            "grad_vs_central_fd": {"load_steps": args.c5_fd_steps + 1, "dE_rel": dE, "dphi_rad": dphi,
+                                   "E_rel_err_max": float(eE.max()), "E_rel_err_median": float(np.median(eE)),
+                                   "phi_rel_err_max": float(ep.max()), "phi_rel_err_median": float(np.median(ep))}}
 
 
 def pmc_probe(M, W, torch):

@@ -54,7 +54,10 @@ def set_params(dp, sims, E, phi):
     dp.tensors["phi"].copy_(torch.from_numpy(Pp))
 
 
-def forward(ctx, dp, sims, steps, tol=1e-10, krylov_rtol=1e-12, max_iter=25, line_search=0, krylov_method=0):
+def forward(ctx, dp, sims, steps, tol=1e-10, krylov_rtol=1e-12, max_iter=25, line_search=0, krylov_method=0,
+            progress=None):
+    """Run the load steps of a batch, keeping checkpoints; progress(step,
+    report) is called after each step when given."""
     import torch
     T = dp.tensors
     R, cps, dus, nit, kit = [], [], [], [], []
@@ -68,12 +71,15 @@ def forward(ctx, dp, sims, steps, tol=1e-10, krylov_rtol=1e-12, max_iter=25, lin
         R.append(rep["sim_reaction"])
         dus.append(du)
         nit.append(rep["iters"])
+        if progress is not None:
+            progress(step, rep)
         kit.append(rep["krylov_iters"])
     return Run(dp, sims, list(steps), np.array(R), cps, dus, nit, kit)
 
 
-def backward(ctx, run: Run, react_bar, krylov_rtol=1e-12):
-    """dL/d(E, phi) per sim given dL/dR (array [n_steps][nsim])."""
+def backward(ctx, run: Run, react_bar, krylov_rtol=1e-12, progress=None):
+    """dL/d(E, phi) per sim given dL/dR (array [n_steps][nsim]);
+    progress(step, krylov_iters) is called after each step when given."""
     import torch
     dp = run.dp
     T = dp.tensors
@@ -89,7 +95,9 @@ def backward(ctx, run: Run, react_bar, krylov_rtol=1e-12):
         M.set_bc(dp, [w.bc(run.steps[k]) for w in run.sims])
         M.mpm_prepare(ctx, dp)
         sbar_n = torch.empty(10 * np_, dtype=torch.float64, device=T["x"].device)
-        M.mpm_adjoint_step(ctx, dp, run.increments[k], react_bar[k], sbar, sbar_n, step_theta, krylov_rtol)
+        kit = M.mpm_adjoint_step(ctx, dp, run.increments[k], react_bar[k], sbar, sbar_n, step_theta, krylov_rtol)
+        if progress is not None:
+            progress(run.steps[k], kit)
         theta += step_theta
         sbar = sbar_n
     return theta.reshape(dp.nsim, 2)
@@ -114,13 +122,16 @@ class ReactionCurves:
                 for w in outer.sims:
                     w.particles = w.particles.copy()
                 dp = make_batch(outer.sims, e, f)
-                run = forward(outer.ctx, dp, outer.sims, outer.steps, **outer.opts)
+                fopts = {k: v for k, v in outer.opts.items() if k != "adjoint_progress"}
+                run = forward(outer.ctx, dp, outer.sims, outer.steps, **fopts)
                 fctx.run = run
                 return torch.from_numpy(run.reactions.copy()).to(E.device)
 
             @staticmethod
             def backward(fctx, gR):
-                th = backward(outer.ctx, fctx.run, gR.detach().cpu().numpy())
+                th = backward(outer.ctx, fctx.run, gR.detach().cpu().numpy(),
+                              krylov_rtol=outer.opts.get("krylov_rtol", 1e-12),
+                              progress=outer.opts.get("adjoint_progress"))
                 return th[:, 0].to(gR.device), th[:, 1].to(gR.device)
 
         return _F

@@ -281,9 +281,26 @@ def c5_draws(seed: int, nsim: int = 64):
     return out
 
 
+def footing_push(E: float, phi: float, c: float, n_steps: int, B: float = 0.1, nu: float = 0.3,
+                 rho0: float = 2000.0, g: float = 9.81, frac: float = 0.5) -> float:
+    """Per-step footing displacement (negative = down) whose total over
+    n_steps is frac times the elastic settlement of a strip of width B at
+    its bearing capacity q = c Nc + gamma B N_gamma / 2 (surface footing,
+    Vesic factors), s = q B (1 - nu^2) / E: the path stays below the limit
+    load, where perfect plasticity has no unique solution."""
+    t = math.tan(phi)
+    nq = math.exp(math.pi * t) * math.tan(math.pi / 4 + phi / 2) ** 2
+    nc = (nq - 1.0) / t
+    ng = 2.0 * (nq + 1.0) * t
+    q = c * nc + 0.5 * rho0 * g * B * ng
+    return -frac * q * B * (1.0 - nu * nu) / E / n_steps
+
+
 def make_c5(nsim: int = 64, n_steps: int = 30, seed: int = 1005, target_seed: int = 2005, gradient: bool = True):
     """Batch of 2-D footings; returns (list of Workload, target (E, phi) list).
-    gradient=True applies gradient_reading to every sim."""
+    gradient=True applies gradient_reading to every sim, with a push per sim
+    sized (footing_push) for the softer-capacity of its drawn and its target
+    (E, friction), so both runs stay below the limit load."""
     sims, targets = [], []
     draws = c5_draws(seed, nsim)
     tdraws = c5_draws(target_seed, nsim)
@@ -291,7 +308,9 @@ def make_c5(nsim: int = 64, n_steps: int = 30, seed: int = 1005, target_seed: in
         n_y = max(2, int(round(math.sqrt(ns / 8.0))))
         w = footing_2d(n_y, E, phi, n_steps, f"c5_{s}")
         if gradient:
-            gradient_reading(w)
+            c = 1e3
+            push = max(footing_push(E, math.radians(phi), c, n_steps), footing_push(Et, math.radians(phit), c, n_steps))
+            gradient_reading(w, cohesion=c, push=push)
         w.particles.E = np.full(w.particles.np, E)
         w.particles.phi = np.full(w.particles.np, math.radians(phi))
         sims.append(w)
