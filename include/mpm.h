@@ -228,6 +228,12 @@ int mpm_adjoint_step(mpm_ctx *ctx, const mpm_problem *prob, const double *du, co
  * library scratch).  Errors: INVALID, HIP. */
 int mpm_spmv(mpm_ctx *ctx, const double *val, const double *x, double *y, const double *z);
 
+/* Lanes per BSR row of the SpMV launch shape that the autotuner picked for
+ * the current pattern (the product is timed on the live matrix with 4, 8 and
+ * 16 lanes per row at the first product after mpm_prepare); 0 before that.
+ * No errors. */
+int mpm_spmv_lanes(const mpm_ctx *ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -354,6 +354,8 @@ int mpm_newton_step(mpm_ctx* c, const mpm_problem* pb, const mpm_newton_opts* op
   return status;
 }
 
+int mpm_spmv_lanes(const mpm_ctx* c) { return c ? c->spmv_lanes : 0; }
+
 int mpm_spmv(mpm_ctx* c, const double* val, const double* x, double* y, const double* z) {
   if (!c) return MPM_E_INVALID;
   c->err.clear();

@@ -620,12 +620,57 @@ static int spmv_launch(mpm_ctx* c, const int32_t* simflag, const double* val, co
   return MPM_OK;
 }
 
+static int spmv_lpr(mpm_ctx* c, int lpr, const int32_t* simflag, const double* val, const double* x, double* y,
+                    const double* z1, double* part, int q1, int q2, int o1, int o2) {
+  if (c->dim == 2) {   // rows of at most 25 blocks
+    if (c->nd == 2) {
+      if (lpr == 4) return spmv_launch<2, 4>(c, simflag, val, x, y, z1, part, q1, q2, o1, o2);
+      if (lpr == 16) return spmv_launch<2, 16>(c, simflag, val, x, y, z1, part, q1, q2, o1, o2);
+      return spmv_launch<2, 8>(c, simflag, val, x, y, z1, part, q1, q2, o1, o2);
+    }
+    if (lpr == 4) return spmv_launch<3, 4>(c, simflag, val, x, y, z1, part, q1, q2, o1, o2);
+    if (lpr == 16) return spmv_launch<3, 16>(c, simflag, val, x, y, z1, part, q1, q2, o1, o2);
+    return spmv_launch<3, 8>(c, simflag, val, x, y, z1, part, q1, q2, o1, o2);
+  }
+  // 3-D rows of at most 125 blocks (64 rows x 16 lanes is the largest workgroup)
+  if (lpr == 4) return spmv_launch<3, 4>(c, simflag, val, x, y, z1, part, q1, q2, o1, o2);
+  if (lpr == 8) return spmv_launch<3, 8>(c, simflag, val, x, y, z1, part, q1, q2, o1, o2);
+  return spmv_launch<3, 16>(c, simflag, val, x, y, z1, part, q1, q2, o1, o2);
+}
+
+// Launch-shape autotuner: on the first product after a prepare, time the
+// product (with its two fused partial dot products, as in the Krylov loop)
+// for each candidate number of lanes per row on the live matrix and keep
+// the fastest for this pattern.
+static int spmv_tune(mpm_ctx* c, const double* val, const double* x, double* y) {
+  const int cand[3] = {4, 8, 16};   // 64 rows per workgroup: at most 1024 threads
+  hipEvent_t e0, e1;
+  HIPC(c, hipEventCreate(&e0));
+  HIPC(c, hipEventCreate(&e1));
+  float best = INFINITY;
+  int pick = cand[1];
+  for (int k = 0; k < 3; ++k) {
+    int rc = MPM_OK;
+    for (int w = 0; w < 3 && !rc; ++w) rc = spmv_lpr(c, cand[k], nullptr, val, x, y, x, c->part.p, 2, 3, -1, -1);
+    HIPC(c, hipEventRecord(e0, c->stream));
+    for (int w = 0; w < 10 && !rc; ++w) rc = spmv_lpr(c, cand[k], nullptr, val, x, y, x, c->part.p, 2, 3, -1, -1);
+    HIPC(c, hipEventRecord(e1, c->stream));
+    HIPC(c, hipEventSynchronize(e1));
+    if (rc) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return rc; }
+    float ms = 0.0f;
+    HIPC(c, hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) { best = ms; pick = cand[k]; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->spmv_lanes = pick;
+  return MPM_OK;
+}
+
 static int spmv(mpm_ctx* c, const int32_t* simflag, const double* val, const double* x, double* y, const double* z1,
                 double* part, int q1, int q2, int o1 = -1, int o2 = -1) {
-  // lanes per row: 8 for the <= 25 blocks of a 2-D row, 16 for the <= 125 of a 3-D row
-  if (c->nd == 2) return spmv_launch<2, 8>(c, simflag, val, x, y, z1, part, q1, q2, o1, o2);
-  if (c->dim == 2) return spmv_launch<3, 8>(c, simflag, val, x, y, z1, part, q1, q2, o1, o2);
-  return spmv_launch<3, 16>(c, simflag, val, x, y, z1, part, q1, q2, o1, o2);
+  if (c->spmv_lanes == 0 && !c->blocks_h.empty()) GUARD(spmv_tune(c, val, x, y));
+  return spmv_lpr(c, c->spmv_lanes, simflag, val, x, y, z1, part, q1, q2, o1, o2);
 }
 
 int launch_spmv(mpm_ctx* c, const double* val, const double* x, double* y, const double* z) {

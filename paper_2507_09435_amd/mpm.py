@@ -68,7 +68,7 @@ class mpm_newton_report(C.Structure):
 
 
 EXPORTS = ["mpm_create", "mpm_destroy", "mpm_last_error", "mpm_prepare", "mpm_residual", "mpm_jacobian_bsr",
-           "mpm_newton_step", "mpm_update", "mpm_spmv", "mpm_adjoint_step"]
+           "mpm_newton_step", "mpm_update", "mpm_spmv", "mpm_spmv_lanes", "mpm_adjoint_step"]
 
 _lib = None
 
@@ -273,6 +273,11 @@ def mpm_update(ctx, dp: DeviceProblem, du, x_out, F_out, be_out):
 
 def mpm_spmv(ctx, val, x, y, z=None):
     _check(ctx, load().mpm_spmv(ctx, _ptr(val), _ptr(x), _ptr(y), _ptr(z)))
+
+
+def mpm_spmv_lanes(ctx):
+    """Lanes per BSR row the SpMV autotuner picked (0 before the first product)."""
+    return int(load().mpm_spmv_lanes(ctx))
 
 
 def mpm_adjoint_step(ctx, dp: DeviceProblem, du, react_bar, sbar_next, sbar_n, theta_bar, krylov_rtol=1e-12):
