@@ -148,17 +148,38 @@ __global__ void __launch_bounds__(ROWS_PER_BLOCK * LPR) k_spmv(const RowBlock* _
 #pragma unroll
     for (int i = 0; i < BS; ++i) acc[i] = 0.0;
     const int k1 = rowptr[row + 1];
-    for (int k = rowptr[row] + lane; k < k1; k += LPR) {
-      // transposed product: block (row, c) of J^T is block (c, row) of J, transposed
-      const double* blk = val + (int64_t)(TR ? tpos[k] : k) * (BS * BS);
-      const int64_t c = colind[k];
-      double xv[BS];
+    // four blocks per lane and pass: all their column indices, then all
+    // their values and x entries, then the products (loads in flight
+    // together).  Slots past the row end re-read the pass's first block and
+    // are left out of the sum.
+    for (int k0 = rowptr[row] + lane; k0 < k1; k0 += 4 * LPR) {
+      constexpr int U = 4;
+      int kc[U];
+      bool vu[U];
+      int64_t cu[U];
 #pragma unroll
-      for (int j = 0; j < BS; ++j) xv[j] = x[c * BS + j];
+      for (int u = 0; u < U; ++u) {
+        vu[u] = k0 + u * LPR < k1;
+        kc[u] = vu[u] ? k0 + u * LPR : k0;
+        cu[u] = colind[kc[u]];
+      }
+      double bv[U][BS * BS], xv[U][BS];
 #pragma unroll
-      for (int i = 0; i < BS; ++i)
+      for (int u = 0; u < U; ++u) {
+        // transposed product: block (row, c) of J^T is block (c, row) of J, transposed
+        const double* blk = val + (int64_t)(TR ? tpos[kc[u]] : kc[u]) * (BS * BS);
 #pragma unroll
-        for (int j = 0; j < BS; ++j) acc[i] += (TR ? blk[j * BS + i] : blk[i * BS + j]) * xv[j];
+        for (int e = 0; e < BS * BS; ++e) bv[u][e] = blk[e];
+#pragma unroll
+        for (int j = 0; j < BS; ++j) xv[u][j] = x[cu[u] * BS + j];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (vu[u])
+#pragma unroll
+          for (int i = 0; i < BS; ++i)
+#pragma unroll
+            for (int j = 0; j < BS; ++j) acc[i] += (TR ? bv[u][j * BS + i] : bv[u][i * BS + j]) * xv[u][j];
     }
 #pragma unroll
     for (int off = LPR / 2; off > 0; off >>= 1)
@@ -647,20 +668,24 @@ static int spmv_tune(mpm_ctx* c, const double* val, const double* x, double* y) 
   hipEvent_t e0, e1;
   HIPC(c, hipEventCreate(&e0));
   HIPC(c, hipEventCreate(&e1));
-  float best = INFINITY;
+  float best, mid;
   int pick = cand[1];
+  float t[3];
   for (int k = 0; k < 3; ++k) {
     int rc = MPM_OK;
     for (int w = 0; w < 3 && !rc; ++w) rc = spmv_lpr(c, cand[k], nullptr, val, x, y, x, c->part.p, 2, 3, -1, -1);
     HIPC(c, hipEventRecord(e0, c->stream));
-    for (int w = 0; w < 10 && !rc; ++w) rc = spmv_lpr(c, cand[k], nullptr, val, x, y, x, c->part.p, 2, 3, -1, -1);
+    for (int w = 0; w < 20 && !rc; ++w) rc = spmv_lpr(c, cand[k], nullptr, val, x, y, x, c->part.p, 2, 3, -1, -1);
     HIPC(c, hipEventRecord(e1, c->stream));
     HIPC(c, hipEventSynchronize(e1));
     if (rc) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return rc; }
-    float ms = 0.0f;
-    HIPC(c, hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best) { best = ms; pick = cand[k]; }
+    HIPC(c, hipEventElapsedTime(&t[k], e0, e1));
   }
+  // keep the middle shape unless another is clearly faster (stable choice)
+  mid = t[1];
+  best = mid;
+  for (int k = 0; k < 3; ++k)
+    if (k != 1 && t[k] < 0.95f * mid && t[k] < best) { best = t[k]; pick = cand[k]; }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->spmv_lanes = pick;
