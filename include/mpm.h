@@ -131,15 +131,18 @@ const char *mpm_last_error(const mpm_ctx *ctx);
  * lies in an occupied stencil; block (i, j) exists iff one occupied stencil
  * holds both nodes.  Outputs (host, may be NULL): n_row, nnzb (blocks), ndof.
  * The particle arrays and grids must stay unchanged until the next call.
- * Errors: INVALID, OUT_OF_GRID, NOMEM, HIP.  Synchronises the stream. */
+ * Zero particles (or a sim without any) is valid: such a sim has no rows.
+ * Errors: INVALID, NONFINITE (a coordinate is NaN or infinite), OUT_OF_GRID
+ * (an origin outside -1..ncell-1 on some axis), NOMEM, HIP; the context keeps
+ * no prepared problem after an error.  Synchronises the stream. */
 int mpm_prepare(mpm_ctx *ctx, const mpm_problem *prob, int64_t *n_row, int64_t *nnzb, int32_t *ndof);
 
 /* Residual at compact unknowns du (Sec. 2.2): r = f_int - f_ext with the
  * constrained unknowns (bc_mask, and nodes without material) set to zero.
  * r_raw (may be NULL) receives f_int - f_ext before that.  reaction (host,
  * may be NULL) receives per sim -sum(r_raw over react_mask).  du, r, r_raw
- * are compact [n_row*ndof].  Errors: INVALID (no prepare / different
- * problem), HIP. */
+ * are compact [n_row*ndof] (du may be NULL only when n_row is 0).
+ * Errors: INVALID (no prepare / different problem), HIP. */
 int mpm_residual(mpm_ctx *ctx, const mpm_problem *prob, const double *du, double *r, double *r_raw,
                  double *reaction);
 
@@ -148,7 +151,8 @@ int mpm_residual(mpm_ctx *ctx, const mpm_problem *prob, const double *du, double
  * blocks, active_nodes [n_row] full-grid node id of each row.  Each output
  * may be NULL to skip it.  flags & MPM_JAC_RAW: return the raw derivative of
  * f_int; otherwise constrained rows and columns are zeroed with 1 on the
- * diagonal (the matrix Newton solves).  Errors: INVALID, HIP. */
+ * diagonal (the matrix Newton solves).  du is needed for val unless n_row
+ * is 0.  Errors: INVALID, HIP. */
 #define MPM_JAC_RAW 1
 int mpm_jacobian_bsr(mpm_ctx *ctx, const mpm_problem *prob, const double *du, int32_t *rowptr,
                      int32_t *colind, double *val, int64_t *active_nodes, int32_t flags);
@@ -191,7 +195,8 @@ typedef struct {
 
 /* One load step of Newton's method (Sec. 2.2).  du: compact unknowns,
  * in = initial guess (constrained entries are overwritten by bc_value),
- * out = converged solution.  Requires mpm_prepare for this problem.
+ * out = converged solution (NULL allowed when n_row is 0).  Requires
+ * mpm_prepare for this problem.
  * Errors: NOT_CONVERGED (du holds the last iterate, nothing committed),
  * KRYLOV, NONFINITE, INVALID, HIP.  Synchronises the stream. */
 int mpm_newton_step(mpm_ctx *ctx, const mpm_problem *prob, const mpm_newton_opts *opts, double *du,
@@ -199,7 +204,8 @@ int mpm_newton_step(mpm_ctx *ctx, const mpm_problem *prob, const mpm_newton_opts
 
 /* End-of-step particle update at compact du (x += sum w du, F = dF F,
  * b^e = exp(2 eps^e)), written to x_out, F_out, be_out (may alias the
- * problem's arrays).  Errors: INVALID, HIP. */
+ * problem's arrays).  du may be NULL when n_row is 0.  Errors: INVALID,
+ * RANGE, HIP. */
 int mpm_update(mpm_ctx *ctx, const mpm_problem *prob, const double *du, double *x_out, double *F_out,
                double *be_out);
 
@@ -228,11 +234,20 @@ int mpm_adjoint_step(mpm_ctx *ctx, const mpm_problem *prob, const double *du, co
  * library scratch).  Errors: INVALID, HIP. */
 int mpm_spmv(mpm_ctx *ctx, const double *val, const double *x, double *y, const double *z);
 
-/* Lanes per BSR row of the SpMV launch shape that the autotuner picked for
- * the current pattern (the product is timed on the live matrix with 4, 8 and
- * 16 lanes per row at the first product after mpm_prepare); 0 before that.
- * No errors. */
+/* Lanes per BSR row of the SpMV launch shape in use: the pinned one (see
+ * mpm_spmv_set_lanes), else the one the autotuner picked for the current
+ * pattern (the product is timed on the live matrix with 4, 8 and 16 lanes
+ * per row at the first product after mpm_prepare); 0 before that.  No errors. */
 int mpm_spmv_lanes(const mpm_ctx *ctx);
+
+/* Pin the SpMV launch shape to lanes = 4, 8 or 16 lanes per BSR row for this
+ * context, kept across mpm_prepare calls; lanes = 0 returns to autotuning at
+ * the next product.  Every shape sums each row in the same order (block k of
+ * a row into partial sum k mod 16, the 16 partial sums in a fixed tree), so
+ * products, Krylov iterates and Newton results are bitwise identical for any
+ * shape: the pin only fixes the speed, e.g. for timing one shape.
+ * Errors: INVALID (another lanes value). */
+int mpm_spmv_set_lanes(mpm_ctx *ctx, int32_t lanes);
 
 #ifdef __cplusplus
 }

@@ -136,7 +136,7 @@ int mpm_residual(mpm_ctx* c, const mpm_problem* pb, const double* du, double* r,
   if (!c) return MPM_E_INVALID;
   c->err.clear();
   GUARD(check_prepared(c, pb));
-  if (!du) return c->fail(MPM_E_INVALID, "du is NULL");
+  if (!du && c->n_row) return c->fail(MPM_E_INVALID, "du is NULL");
   HIPC(c, hipSetDevice(c->device));
   GUARD(launch_residual(c, pb, du, r, r_raw));
   if (reaction) {
@@ -162,7 +162,7 @@ int mpm_jacobian_bsr(mpm_ctx* c, const mpm_problem* pb, const double* du, int32_
     HIPC(c, hipMemcpyAsync(active_nodes, c->active_nodes.p, c->n_row * sizeof(int64_t), hipMemcpyDeviceToDevice,
                            c->stream));
   if (val) {
-    if (!du) return c->fail(MPM_E_INVALID, "du is NULL");
+    if (!du && c->n_row) return c->fail(MPM_E_INVALID, "du is NULL");
     GUARD(launch_jacobian(c, pb, du, val, (flags & MPM_JAC_RAW) == 0));
   }
   return MPM_OK;
@@ -172,7 +172,7 @@ int mpm_update(mpm_ctx* c, const mpm_problem* pb, const double* du, double* x_ou
   if (!c) return MPM_E_INVALID;
   c->err.clear();
   GUARD(check_prepared(c, pb));
-  if (!du) return c->fail(MPM_E_INVALID, "du is NULL");
+  if (!du && c->n_row) return c->fail(MPM_E_INVALID, "du is NULL");
   HIPC(c, hipSetDevice(c->device));
   HIPC(c, hipMemsetAsync(c->flag.p, 0, sizeof(int32_t), c->stream));
   GUARD(launch_update(c, pb, du, x_out, F_out, be_out));
@@ -188,7 +188,7 @@ int mpm_newton_step(mpm_ctx* c, const mpm_problem* pb, const mpm_newton_opts* op
   if (!c) return MPM_E_INVALID;
   c->err.clear();
   GUARD(check_prepared(c, pb));
-  if (!du || !opts) return c->fail(MPM_E_INVALID, "du and opts are required");
+  if (!opts || (!du && c->n_row)) return c->fail(MPM_E_INVALID, "du and opts are required");
   if (!(opts->tol > 0.0) || opts->max_iter < 0 || opts->max_iter > 1000)
     return c->fail(MPM_E_INVALID, "Newton options out of range");
   HIPC(c, hipSetDevice(c->device));
@@ -355,6 +355,16 @@ int mpm_newton_step(mpm_ctx* c, const mpm_problem* pb, const mpm_newton_opts* op
 }
 
 int mpm_spmv_lanes(const mpm_ctx* c) { return c ? c->spmv_lanes : 0; }
+
+int mpm_spmv_set_lanes(mpm_ctx* c, int32_t lanes) {
+  if (!c) return MPM_E_INVALID;
+  c->err.clear();
+  if (lanes != 0 && lanes != 4 && lanes != 8 && lanes != 16)
+    return c->fail(MPM_E_INVALID, "lanes per row must be 0, 4, 8 or 16");
+  c->spmv_pin = lanes;
+  c->spmv_lanes = lanes;
+  return MPM_OK;
+}
 
 int mpm_spmv(mpm_ctx* c, const double* val, const double* x, double* y, const double* z) {
   if (!c) return MPM_E_INVALID;

@@ -121,6 +121,7 @@ struct mpm_ctx {
   int kmethod = 0;                             // 0: BiCGStab then GMRES fallback, 1: GMRES only
   bool kfused = true;                          // BiCGStab consumers sum the row-block partials themselves
   int spmv_lanes = 0;                          // lanes per BSR row picked by the autotuner (0: not yet)
+  int spmv_pin = 0;                            // lanes per BSR row fixed by the caller (0: autotune)
   mpm::DBuf<double> du_base, alpha;            // line search
   // adjoint
   mpm::DBuf<int32_t> tpos;                     // position of the transposed block

@@ -140,18 +140,30 @@ __global__ void __launch_bounds__(ROWS_PER_BLOCK * LPR) k_spmv(const RowBlock* _
   const RowBlock b = blocks[blockIdx.x];
   if (simflag && simflag[2 * b.sim] >= 0) return;
   constexpr int G = ROWS_PER_BLOCK;   // one LPR-lane group per row: the whole block in flight at once
-  constexpr int NW = ROWS_PER_BLOCK * LPR / 64;
+  // The arithmetic does not depend on LPR: block k of a row (counted from
+  // the row start) adds into virtual lane k mod VL in ascending k, and the VL
+  // partial sums meet in one fixed butterfly (offsets VL/2 .. 1).  A lane
+  // holds NA = VL/LPR virtual lanes; the butterfly levels at offsets >= LPR
+  // are additions inside the lane, the rest are shuffles.  The per-row dot
+  // products are summed over the block's rows in one fixed tree.
+  constexpr int VL = 16;
+  constexpr int NA = VL / LPR;
+  static_assert(NA >= 1 && (4 % NA) == 0, "LPR must be 4, 8 or 16");
   const int lane = threadIdx.x % LPR, grp = threadIdx.x / LPR;
   double d1 = 0.0, d2 = 0.0;
   for (int row = b.row0 + grp; row < b.row1; row += G) {
-    double acc[BS];
+    double acc[NA][BS];
 #pragma unroll
-    for (int i = 0; i < BS; ++i) acc[i] = 0.0;
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int i = 0; i < BS; ++i) acc[a][i] = 0.0;
     const int k1 = rowptr[row + 1];
     // four blocks per lane and pass: all their column indices, then all
     // their values and x entries, then the products (loads in flight
     // together).  Slots past the row end re-read the pass's first block and
-    // are left out of the sum.
+    // are left out of the sum.  The lane's u-th block of a pass belongs to
+    // its virtual lane u mod NA (a pass spans 4 LPR blocks, a multiple of VL
+    // when NA divides 4).
     for (int k0 = rowptr[row] + lane; k0 < k1; k0 += 4 * LPR) {
       constexpr int U = 4;
       int kc[U];
@@ -179,33 +191,40 @@ __global__ void __launch_bounds__(ROWS_PER_BLOCK * LPR) k_spmv(const RowBlock* _
 #pragma unroll
           for (int i = 0; i < BS; ++i)
 #pragma unroll
-            for (int j = 0; j < BS; ++j) acc[i] += (TR ? bv[u][j * BS + i] : bv[u][i * BS + j]) * xv[u][j];
+            for (int j = 0; j < BS; ++j)
+              acc[u % NA][i] += (TR ? bv[u][j * BS + i] : bv[u][i * BS + j]) * xv[u][j];
     }
+    // butterfly levels inside the lane: virtual lanes a and a + m (offset m LPR)
+#pragma unroll
+    for (int m = NA / 2; m > 0; m >>= 1)
+#pragma unroll
+      for (int a = 0; a < m; ++a)
+#pragma unroll
+        for (int i = 0; i < BS; ++i) acc[a][i] += acc[a + m][i];
 #pragma unroll
     for (int off = LPR / 2; off > 0; off >>= 1)
 #pragma unroll
-      for (int i = 0; i < BS; ++i) acc[i] += __shfl_xor(acc[i], off, LPR);
+      for (int i = 0; i < BS; ++i) acc[0][i] += __shfl_xor(acc[0][i], off, LPR);
     if (lane == 0) {
 #pragma unroll
       for (int i = 0; i < BS; ++i) {
-        y[(int64_t)row * BS + i] = acc[i];
-        if (z1) d1 += z1[(int64_t)row * BS + i] * acc[i];
-        d2 += acc[i] * acc[i];
+        y[(int64_t)row * BS + i] = acc[0][i];
+        if (z1) d1 += z1[(int64_t)row * BS + i] * acc[0][i];
+        d2 += acc[0][i] * acc[0][i];
       }
     }
   }
   if (q1 < 0 && q2 < 0) return;
-  __shared__ double sh[2][NW];
-  d1 = wave_sum(d1);
-  d2 = wave_sum(d2);
-  if (threadIdx.x % 64 == 0) { sh[0][threadIdx.x / 64] = d1; sh[1][threadIdx.x / 64] = d2; }
+  __shared__ double sh[2][G];
+  if (lane == 0) { sh[0][grp] = d1; sh[1][grp] = d2; }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) { s1 += sh[0][w]; s2 += sh[1][w]; }
-    if (q1 >= 0) part[blockIdx.x * NQ + q1] = s1;
-    if (q2 >= 0) part[blockIdx.x * NQ + q2] = s2;
+  if (threadIdx.x < 64) {   // one wave sums the G = 64 row values (lane = row in the block)
+    const double s1 = wave_sum(sh[0][threadIdx.x]);
+    const double s2 = wave_sum(sh[1][threadIdx.x]);
+    if (threadIdx.x == 0) {
+      if (q1 >= 0) part[blockIdx.x * NQ + q1] = s1;
+      if (q2 >= 0) part[blockIdx.x * NQ + q2] = s2;
+    }
   }
 }
 

@@ -313,9 +313,10 @@ __global__ void __launch_bounds__(64) k_mg_dense_apply(const int32_t* __restrict
   const double* Vt = dense + (int64_t)s * 2 * nmax * nmax + (int64_t)nmax * nmax;
   const double* bs = b + (int64_t)r0 * 2;
   const int i = threadIdx.x;
+  if (i >= n) return;   // lanes past this sim's unknowns (nmax may be < 64) read nothing
   double acc = 0.0;
   for (int j = 0; j < n; ++j) acc += Vt[(int64_t)j * nmax + i] * bs[j];
-  if (i < n) x[(int64_t)r0 * 2 + i] = acc;
+  x[(int64_t)r0 * 2 + i] = acc;
 }
 
 // Coarse-level group blocks in chunks: coarse stencil groups hold 4^l times

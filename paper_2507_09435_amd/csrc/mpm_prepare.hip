@@ -611,7 +611,7 @@ int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row_out, int6
 
   c->user_x = pb->P.x;
   c->mg_ready = false;   // a multigrid hierarchy belongs to one prepare
-  c->spmv_lanes = 0;     // the SpMV launch shape is tuned again on the new pattern
+  c->spmv_lanes = c->spmv_pin;   // unless pinned, the SpMV launch shape is tuned again on the new pattern
   c->prepared = true;
   if (n_row_out) *n_row_out = n_row;
   if (nnzb_out) *nnzb_out = c->nnzb;

@@ -68,7 +68,8 @@ class mpm_newton_report(C.Structure):
 
 
 EXPORTS = ["mpm_create", "mpm_destroy", "mpm_last_error", "mpm_prepare", "mpm_residual", "mpm_jacobian_bsr",
-           "mpm_newton_step", "mpm_update", "mpm_spmv", "mpm_spmv_lanes", "mpm_adjoint_step"]
+           "mpm_newton_step", "mpm_update", "mpm_spmv", "mpm_spmv_lanes", "mpm_spmv_set_lanes",
+           "mpm_adjoint_step"]
 
 _lib = None
 
@@ -94,6 +95,8 @@ def load():
                              C.POINTER(mpm_newton_report)], C.c_int),
         "mpm_update": ([P, C.POINTER(mpm_problem), P, P, P, P], C.c_int),
         "mpm_spmv": ([P, P, P, P, P], C.c_int),
+        "mpm_spmv_lanes": ([P], C.c_int),
+        "mpm_spmv_set_lanes": ([P, C.c_int32], C.c_int),
         "mpm_adjoint_step": ([P, C.POINTER(mpm_problem), P, C.POINTER(C.c_double), P, P, P, C.c_double,
                               C.POINTER(C.c_int32)], C.c_int),
     }
@@ -278,6 +281,12 @@ def mpm_spmv(ctx, val, x, y, z=None):
 def mpm_spmv_lanes(ctx):
     """Lanes per BSR row the SpMV autotuner picked (0 before the first product)."""
     return int(load().mpm_spmv_lanes(ctx))
+
+
+def mpm_spmv_set_lanes(ctx, lanes):
+    """Pin the SpMV launch shape (4, 8, 16 lanes per row; 0: autotune).
+    Results do not depend on it."""
+    _check(ctx, load().mpm_spmv_set_lanes(ctx, int(lanes)))
 
 
 def mpm_adjoint_step(ctx, dp: DeviceProblem, du, react_bar, sbar_next, sbar_n, theta_bar, krylov_rtol=1e-12):

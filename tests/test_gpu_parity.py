@@ -155,6 +155,70 @@ def test_multigrid_graph_replays_match_eager(ctx, name):
         assert np.array_equal(du, outs[0][0])
 
 
+@pytest.mark.parametrize("name", ["footing_elastic", "c3small", "up"])
+def test_spmv_does_not_depend_on_its_shape(ctx, name):
+    """y = J x on one assembled matrix is bitwise the same for 4, 8 and 16
+    lanes per row (block sizes 2 and 3)."""
+    from paper_2507_09435_amd import mpm as M
+    w = _newton_case(name)
+    P, st = w.prob, w.particles
+    dp = _dev(w, 1)
+    n_row, nnzb, nd = M.mpm_prepare(ctx, dp)
+    pat = O.pattern(P, st)
+    dut = torch.from_numpy(seeded_du(P, pat, seed=13).reshape(-1)).cuda()
+    val = torch.zeros(nnzb * nd * nd, dtype=torch.float64, device="cuda")
+    M.mpm_jacobian_bsr(ctx, dp, dut, val=val)
+    x = torch.from_numpy(np.random.default_rng(14).normal(size=n_row * nd)).cuda()
+    ys = []
+    try:
+        for lanes in (4, 8, 16):
+            print(f"[spmv-shape] case={name} lanes={lanes}", flush=True)
+            M.mpm_spmv_set_lanes(ctx, lanes)
+            y = torch.zeros_like(x)
+            M.mpm_spmv(ctx, val, x, y)
+            torch.cuda.synchronize()
+            assert M.mpm_spmv_lanes(ctx) == lanes
+            ys.append(y.cpu().numpy())
+    finally:
+        M.mpm_spmv_set_lanes(ctx, 0)
+    for y in ys[1:]:
+        assert np.array_equal(y, ys[0])
+    with pytest.raises(M.MPMError):
+        M.mpm_spmv_set_lanes(ctx, 32)
+
+
+@pytest.mark.parametrize("name,method", [("footing_big", 2), ("footing_elastic", 0), ("footing_elastic", 1)])
+def test_newton_does_not_depend_on_spmv_shape(ctx, name, method):
+    """Plane-strain single-phase solves (assembled without atomics, so each
+    prepare rebuilds the same matrix bits): the Newton increments and the
+    Newton and Krylov iteration counts are bitwise the same for every SpMV
+    shape, including the Krylov dot products the product fuses."""
+    from paper_2507_09435_amd import mpm as M
+    w = _newton_case(name)
+    P = w.prob
+    P.dp = 0
+    step = 1 if name == "footing_elastic" else 0
+    outs = []
+    try:
+        for lanes in (4, 8, 16):
+            print(f"[newton-shape] case={name} lanes={lanes} krylov_method={method}", flush=True)
+            M.mpm_spmv_set_lanes(ctx, lanes)
+            dp = _dev(w, step)
+            n_row, nnzb, nd = M.mpm_prepare(ctx, dp)
+            du = torch.zeros(n_row * nd, dtype=torch.float64, device="cuda")
+            rep = M.mpm_newton_step(ctx, dp, du, tol=1e-12, max_iter=25, commit=False, krylov_rtol=1e-12,
+                                    krylov_method=method)
+            torch.cuda.synchronize()
+            assert rep["converged"], rep
+            assert M.mpm_spmv_lanes(ctx) == lanes
+            outs.append((du.cpu().numpy(), rep["krylov"], rep["iters"]))
+    finally:
+        M.mpm_spmv_set_lanes(ctx, 0)
+    for du, kr, it in outs[1:]:
+        assert kr == outs[0][1] and it == outs[0][2]
+        assert np.array_equal(du, outs[0][0])
+
+
 def _newton_case(name):
     if name == "c3small_stiff":
         w = W.make_c3(n=8, n_steps=1)
