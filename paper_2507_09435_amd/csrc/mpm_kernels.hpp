@@ -57,6 +57,24 @@ namespace mpm {
 // Dirichlet mask, the map to the finest particle records, its vectors and
 // the chunks (at most MG_CHUNK particles of one stencil group) of its
 // group-block assembly.
+// Device view of one level for the fused coarse tail of the V-cycle.
+struct MgTailLevel {
+  const int32_t* rowptr;
+  const int32_t* colind;
+  const double* val;        // level operator (BSR, 2x2 blocks)
+  const double* dinv;       // inverted diagonal blocks
+  const int64_t* active;    // full-grid node of each row
+  const SimDev* sims;       // per sim: grid and first row
+  const int32_t* node_map;  // full-grid node -> row (-1 inactive)
+  const uint8_t* cmask;     // constrained unknowns
+  double* y;                // sweep partner
+  double* r;                // residual
+  double* x;                // solution (coarse levels)
+  double* b;                // right-hand side (coarse levels)
+  int32_t n_row;
+  int32_t nsim;
+};
+
 struct MgLevel {
   mpm_ctx* sub = nullptr;
   std::vector<mpm_grid> grids;
@@ -122,6 +140,7 @@ struct mpm_ctx {
   bool kfused = true;                          // BiCGStab consumers sum the row-block partials themselves
   int spmv_lanes = 0;                          // lanes per BSR row picked by the autotuner (0: not yet)
   int spmv_pin = 0;                            // lanes per BSR row fixed by the caller (0: autotune)
+  int kprev = 0;                               // BiCGStab iterations of the previous solve (slowest sim)
   mpm::DBuf<double> du_base, alpha;            // line search
   // adjoint
   mpm::DBuf<int32_t> tpos;                     // position of the transposed block
@@ -155,6 +174,10 @@ struct mpm_ctx {
   struct MgGraph { hipGraphExec_t exec = nullptr; const void* key[5] = {}; uint64_t gen = 0; };
   MgGraph mg_exec[2];                          // V-cycles of BiCGStab's two preconditioner applications
   int mg_next = 0;
+  int mg_tail_first = -1;                      // first level of the fused coarse tail (-1: none)
+  bool mg_fuse = true;                         // run the coarse tail in one launch
+  mpm::DBuf<mpm::MgTailLevel> mg_tail;         // tail levels' device views (first .. coarsest)
+  std::vector<mpm::MgTailLevel> mg_tail_h;     // host staging of mg_tail
 
   int fail(int code, const std::string& msg) { err = msg; return code; }
 };

@@ -913,13 +913,22 @@ int krylov_solve(mpm_ctx* c, const double* val, double rtol, int max_iter, std::
   const bool gmres_only = c->kmethod == 1;
   c->mg_on = (c->kmethod == 2 || c->kmethod == 3) && !c->ktrans;
   c->mg_graph = c->kmethod == 2;
+  c->mg_fuse = c->kmethod == 2;   // method 3 launches every level's kernels
   int max_blocks = 0;
   for (int sidx = 0; sidx < nsim; ++sidx)
     max_blocks = std::max(max_blocks, c->sim_blk_first[sidx + 1] - c->sim_blk_first[sidx]);
   c->kfused = max_blocks <= 2048;
   const int bicg_budget = gmres_only ? 0 : max_iter / 2;
   int used = 0;           // iterations spent over all (re)starts
-  const int CHUNK = 16;
+  // Iterations are launched in chunks between host checks of the per-sim
+  // convergence flags; iterations past a sim's convergence change nothing
+  // but still cost their launches.  The first chunk runs up to one short of
+  // the previous solve's count, later chunks a sixteenth of it (at least
+  // 2): a check costs far less than a preconditioned iteration.
+  auto next_chunk = [&](int done) {
+    const int ref = c->kprev > 0 ? c->kprev : done;
+    return std::max(2, ref / (c->kprev > 0 ? 16 : 4));
+  };
   bool good = false;
   double last_worst = INFINITY;
   std::vector<double> ratio(nsim, INFINITY);
@@ -942,8 +951,9 @@ int krylov_solve(mpm_ctx* c, const double* val, double rtol, int max_iter, std::
     LAUNCH_CHECK(c, "bicgstab init");
     int it = 0;
     bool all_done = false;
+    int chunk = attempt == 0 && c->kprev > 0 ? std::max(1, c->kprev - 1) : 16;
     while (!all_done && used + it < bicg_budget) {
-      for (int k = 0; k < CHUNK && used + it < bicg_budget; ++k, ++it) {
+      for (int k = 0; k < chunk && used + it < bicg_budget; ++k, ++it) {
         rc = c->nd == 2 ? bicg_iter<2>(c, val, it, K) : bicg_iter<3>(c, val, it, K);
         if (rc) break;
       }
@@ -952,9 +962,16 @@ int krylov_solve(mpm_ctx* c, const double* val, double rtol, int max_iter, std::
       HIPC(c, hipStreamSynchronize(c->stream));
       all_done = true;
       for (int s = 0; s < nsim; ++s) all_done = all_done && hflag[2 * s] >= 0;
+      chunk = next_chunk(it);
     }
     if (rc) break;
-    for (int s = 0; s < nsim; ++s) iters_out[s] += (hflag[2 * s] >= 0 ? hflag[2 * s] : it);
+    int slowest = 0;
+    for (int s = 0; s < nsim; ++s) {
+      const int its = hflag[2 * s] >= 0 ? hflag[2 * s] : it;
+      iters_out[s] += its;
+      slowest = std::max(slowest, its);
+    }
+    if (attempt == 0) c->kprev = slowest;
     used += it;
     if ((rc = true_ratios(c, val, K.part_ts, ratio))) break;
     good = true;

@@ -24,6 +24,7 @@ constexpr int MG_NU1 = 2, MG_NU2 = 2;   // pre- and post-smoothing sweeps
 constexpr double MG_OMEGA = 0.6;        // damping of the block-Jacobi sweeps
 constexpr int MG_MAX_LEVELS = 12;
 constexpr int MG_DENSE_MAX = 64;        // coarsest unknowns per simulation (inverted in LDS)
+constexpr int MG_TAIL_ROWS = 256;       // levels with at most this many rows per sim run in one launch
 
 __device__ __forceinline__ int sim_of_node(const SimDev* sims, int nsim, int64_t node) {
   int s = 0;
@@ -80,9 +81,48 @@ __global__ void k_mg_rec2(int64_t np, const double* __restrict__ xs, const int32
   }
 }
 
-// One sweep over the row blocks of a level (LPR lanes per row):
+// One block-Jacobi step on one row (LPR lanes per row):
 // mode 0: x_out = w D^-1 b;  mode 1: x_out = x_in + w D^-1 (b - A x_in);
-// mode 2: x_out = b - A x_in.  Skips sims whose Krylov solve is finished.
+// mode 2: x_out = b - A x_in.
+template <int LPR>
+__device__ __forceinline__ void mg_sweep_row(int row, int lane, const int32_t* __restrict__ rowptr,
+                                             const int32_t* __restrict__ colind, const double* __restrict__ val,
+                                             const double* __restrict__ dinv, const double* __restrict__ b,
+                                             const double* __restrict__ x_in, double* __restrict__ x_out,
+                                             double omega, int mode) {
+  double a0 = 0.0, a1 = 0.0;
+  if (mode != 0) {
+    const int k1 = rowptr[row + 1];
+    for (int k = rowptr[row] + lane; k < k1; k += LPR) {
+      const double* blk = val + (int64_t)k * 4;
+      const int64_t c = colind[k];
+      const double x0 = x_in[c * 2], x1 = x_in[c * 2 + 1];
+      a0 += blk[0] * x0 + blk[1] * x1;
+      a1 += blk[2] * x0 + blk[3] * x1;
+    }
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) {
+      a0 += __shfl_xor(a0, off, LPR);
+      a1 += __shfl_xor(a1, off, LPR);
+    }
+  }
+  if (lane == 0) {
+    const double r0 = b[(int64_t)row * 2] - a0, r1 = b[(int64_t)row * 2 + 1] - a1;
+    if (mode == 2) {
+      x_out[(int64_t)row * 2] = r0;
+      x_out[(int64_t)row * 2 + 1] = r1;
+    } else {
+      const double* D = dinv + (int64_t)row * 4;
+      const double base0 = mode == 1 ? x_in[(int64_t)row * 2] : 0.0;
+      const double base1 = mode == 1 ? x_in[(int64_t)row * 2 + 1] : 0.0;
+      x_out[(int64_t)row * 2] = base0 + omega * (D[0] * r0 + D[1] * r1);
+      x_out[(int64_t)row * 2 + 1] = base1 + omega * (D[2] * r0 + D[3] * r1);
+    }
+  }
+}
+
+// One sweep over the row blocks of a level; skips sims whose Krylov solve
+// is finished.
 template <int LPR>
 __global__ void __launch_bounds__(ROWS_PER_BLOCK * LPR) k_mg_sweep(
     const RowBlock* __restrict__ blocks, const int32_t* __restrict__ simflag, const int32_t* __restrict__ rowptr,
@@ -92,49 +132,17 @@ __global__ void __launch_bounds__(ROWS_PER_BLOCK * LPR) k_mg_sweep(
   const RowBlock B = blocks[blockIdx.x];
   if (simflag && simflag[2 * B.sim] >= 0) return;
   const int lane = threadIdx.x % LPR, grp = threadIdx.x / LPR;
-  for (int row = B.row0 + grp; row < B.row1; row += ROWS_PER_BLOCK) {
-    double a0 = 0.0, a1 = 0.0;
-    if (mode != 0) {
-      const int k1 = rowptr[row + 1];
-      for (int k = rowptr[row] + lane; k < k1; k += LPR) {
-        const double* blk = val + (int64_t)k * 4;
-        const int64_t c = colind[k];
-        const double x0 = x_in[c * 2], x1 = x_in[c * 2 + 1];
-        a0 += blk[0] * x0 + blk[1] * x1;
-        a1 += blk[2] * x0 + blk[3] * x1;
-      }
-#pragma unroll
-      for (int off = LPR / 2; off > 0; off >>= 1) {
-        a0 += __shfl_xor(a0, off, LPR);
-        a1 += __shfl_xor(a1, off, LPR);
-      }
-    }
-    if (lane == 0) {
-      const double r0 = b[(int64_t)row * 2] - a0, r1 = b[(int64_t)row * 2 + 1] - a1;
-      if (mode == 2) {
-        x_out[(int64_t)row * 2] = r0;
-        x_out[(int64_t)row * 2 + 1] = r1;
-      } else {
-        const double* D = dinv + (int64_t)row * 4;
-        const double base0 = mode == 1 ? x_in[(int64_t)row * 2] : 0.0;
-        const double base1 = mode == 1 ? x_in[(int64_t)row * 2 + 1] : 0.0;
-        x_out[(int64_t)row * 2] = base0 + omega * (D[0] * r0 + D[1] * r1);
-        x_out[(int64_t)row * 2 + 1] = base1 + omega * (D[2] * r0 + D[3] * r1);
-      }
-    }
-  }
+  for (int row = B.row0 + grp; row < B.row1; row += ROWS_PER_BLOCK)
+    mg_sweep_row<LPR>(row, lane, rowptr, colind, val, dinv, b, x_in, x_out, omega, mode);
 }
 
-// b_c = R r_f on one coarse row per thread (R = transpose of the linear
+// b_c = R r_f on coarse row R of sim s (R = transpose of the linear
 // interpolation); constrained coarse unknowns get 0.
-__global__ void k_mg_restrict(int64_t n_crow, const int64_t* __restrict__ c_active,
-                              const int32_t* __restrict__ c_rowsim, const SimDev* __restrict__ csims,
-                              const SimDev* __restrict__ fsims, const int32_t* __restrict__ f_node_map,
-                              const double* __restrict__ rf, const uint8_t* __restrict__ c_cmask,
-                              double* __restrict__ bc) {
-  const int64_t R = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (R >= n_crow) return;
-  const int s = c_rowsim[R];
+__device__ __forceinline__ void mg_restrict_row(int64_t R, int s, const int64_t* __restrict__ c_active,
+                                                const SimDev* __restrict__ csims, const SimDev* __restrict__ fsims,
+                                                const int32_t* __restrict__ f_node_map,
+                                                const double* __restrict__ rf, const uint8_t* __restrict__ c_cmask,
+                                                double* __restrict__ bc) {
   const SimDev& C = csims[s];
   const SimDev& F = fsims[s];
   const int64_t loc = c_active[R] - C.node_base;
@@ -158,16 +166,24 @@ __global__ void k_mg_restrict(int64_t n_crow, const int64_t* __restrict__ c_acti
   bc[R * 2 + 1] = c_cmask[R * 2 + 1] ? 0.0 : a1;
 }
 
-// x_f += P x_c on one fine row per thread; constrained fine unknowns keep
+// The restriction on one coarse row per thread.
+__global__ void k_mg_restrict(int64_t n_crow, const int64_t* __restrict__ c_active,
+                              const int32_t* __restrict__ c_rowsim, const SimDev* __restrict__ csims,
+                              const SimDev* __restrict__ fsims, const int32_t* __restrict__ f_node_map,
+                              const double* __restrict__ rf, const uint8_t* __restrict__ c_cmask,
+                              double* __restrict__ bc) {
+  const int64_t R = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (R >= n_crow) return;
+  mg_restrict_row(R, c_rowsim[R], c_active, csims, fsims, f_node_map, rf, c_cmask, bc);
+}
+
+// x_f += P x_c on fine row r of sim s; constrained fine unknowns keep
 // their value.
-__global__ void k_mg_prolong(int64_t n_frow, const int64_t* __restrict__ f_active,
-                             const int32_t* __restrict__ f_rowsim, const SimDev* __restrict__ fsims,
-                             const SimDev* __restrict__ csims, const int32_t* __restrict__ c_node_map,
-                             const double* __restrict__ xc, const uint8_t* __restrict__ f_cmask,
-                             double* __restrict__ xf) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n_frow) return;
-  const int s = f_rowsim[r];
+__device__ __forceinline__ void mg_prolong_row(int64_t r, int s, const int64_t* __restrict__ f_active,
+                                               const SimDev* __restrict__ fsims, const SimDev* __restrict__ csims,
+                                               const int32_t* __restrict__ c_node_map,
+                                               const double* __restrict__ xc, const uint8_t* __restrict__ f_cmask,
+                                               double* __restrict__ xf) {
   const SimDev& F = fsims[s];
   const SimDev& C = csims[s];
   const int64_t loc = f_active[r] - F.node_base;
@@ -189,6 +205,17 @@ __global__ void k_mg_prolong(int64_t n_frow, const int64_t* __restrict__ f_activ
   }
   if (!f_cmask[r * 2]) xf[r * 2] += a0;
   if (!f_cmask[r * 2 + 1]) xf[r * 2 + 1] += a1;
+}
+
+// The prolongation on one fine row per thread.
+__global__ void k_mg_prolong(int64_t n_frow, const int64_t* __restrict__ f_active,
+                             const int32_t* __restrict__ f_rowsim, const SimDev* __restrict__ fsims,
+                             const SimDev* __restrict__ csims, const int32_t* __restrict__ c_node_map,
+                             const double* __restrict__ xc, const uint8_t* __restrict__ f_cmask,
+                             double* __restrict__ xf) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_frow) return;
+  mg_prolong_row(r, f_rowsim[r], f_active, fsims, csims, c_node_map, xc, f_cmask, xf);
 }
 
 // Coarsest level: dense matrix of each sim (n_s = 2 * rows, stride nmax),
@@ -303,20 +330,94 @@ __global__ void __launch_bounds__(GJ) k_mg_gauss_jordan(const int32_t* __restric
   }
 }
 
-// x = A^-1 b per sim on the coarsest level: one wave per sim, lane i owns
-// unknown i (n <= 64), reading the transposed inverse column by column.
-__global__ void __launch_bounds__(64) k_mg_dense_apply(const int32_t* __restrict__ doff, int nmax,
-                                                       const double* __restrict__ dense,
-                                                       const double* __restrict__ b, double* __restrict__ x) {
-  const int s = blockIdx.x;
+// x = A^-1 b for sim s on the coarsest level: lane i (one wave, n <= 64)
+// owns unknown i and reads the transposed inverse column by column.
+__device__ __forceinline__ void mg_dense_lane(int s, int i, const int32_t* __restrict__ doff, int nmax,
+                                              const double* __restrict__ dense, const double* __restrict__ b,
+                                              double* __restrict__ x) {
   const int r0 = doff[2 * s], n = 2 * doff[2 * s + 1];
+  if (i >= n) return;   // lanes past this sim's unknowns (nmax may be < 64) read nothing
   const double* Vt = dense + (int64_t)s * 2 * nmax * nmax + (int64_t)nmax * nmax;
   const double* bs = b + (int64_t)r0 * 2;
-  const int i = threadIdx.x;
-  if (i >= n) return;   // lanes past this sim's unknowns (nmax may be < 64) read nothing
   double acc = 0.0;
   for (int j = 0; j < n; ++j) acc += Vt[(int64_t)j * nmax + i] * bs[j];
   x[(int64_t)r0 * 2 + i] = acc;
+}
+
+__global__ void __launch_bounds__(64) k_mg_dense_apply(const int32_t* __restrict__ doff, int nmax,
+                                                       const double* __restrict__ dense,
+                                                       const double* __restrict__ b, double* __restrict__ x) {
+  mg_dense_lane(blockIdx.x, threadIdx.x, doff, nmax, dense, b, x);
+}
+
+// The coarse tail of the V-cycle in one launch: one workgroup per sim runs
+// the levels from the first one with at most MG_TAIL_ROWS rows per sim
+// down to the dense solve and back, with the same row operations in the
+// same order as the level-by-level launches (so the same arithmetic), a
+// workgroup barrier standing in for each launch boundary.  Coarse levels
+// are launch-latency bound: this replaces 7 launches per level.
+constexpr int MG_TAIL_THREADS = 1024;
+constexpr int MG_TAIL_LPR = 8;
+__global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const MgTailLevel* __restrict__ lv, int nlev,
+                                                             const int32_t* __restrict__ simflag,
+                                                             const int32_t* __restrict__ doff, int nmax,
+                                                             const double* __restrict__ dense,
+                                                             const double* __restrict__ b_top,
+                                                             double* __restrict__ x_top) {
+  const int s = blockIdx.x;
+  if (simflag && simflag[2 * s] >= 0) return;   // whole workgroup: the sim's solve is finished
+  constexpr int LPR = MG_TAIL_LPR, NG = MG_TAIL_THREADS / LPR;
+  const int lane = threadIdx.x % LPR, grp = threadIdx.x / LPR;
+  auto rows = [&](const MgTailLevel& L, int& r0, int& r1) {
+    r0 = L.sims[s].row_base;
+    r1 = s + 1 < L.nsim ? L.sims[s + 1].row_base : L.n_row;
+  };
+  auto sweep = [&](const MgTailLevel& L, const double* b, const double* xin, double* xout, int mode) {
+    int r0, r1;
+    rows(L, r0, r1);
+    for (int row = r0 + grp; row < r1; row += NG)
+      mg_sweep_row<LPR>(row, lane, L.rowptr, L.colind, L.val, L.dinv, b, xin, xout, MG_OMEGA, mode);
+    __syncthreads();
+  };
+  // down: pre-smoothing, residual, restriction
+  for (int m = 0; m < nlev; ++m) {
+    const MgTailLevel& L = lv[m];
+    const MgTailLevel& Cl = lv[m + 1];
+    const double* b = m == 0 ? b_top : L.b;
+    double* out = m == 0 ? x_top : L.x;
+    const bool odd = (MG_NU1 - 1 + MG_NU2) % 2 == 1;
+    double* xa = odd ? L.y : out;
+    double* xb = odd ? out : L.y;
+    sweep(L, b, nullptr, xa, 0);
+    for (int k = 1; k < MG_NU1; ++k) { sweep(L, b, xa, xb, 1); double* t = xa; xa = xb; xb = t; }
+    sweep(L, b, xa, L.r, 2);
+    int c0, c1;
+    rows(Cl, c0, c1);
+    for (int R = c0 + (int)threadIdx.x; R < c1; R += MG_TAIL_THREADS)
+      mg_restrict_row(R, s, Cl.active, Cl.sims, L.sims, L.node_map, L.r, Cl.cmask, Cl.b);
+    __syncthreads();
+  }
+  // coarsest: dense solve
+  if (threadIdx.x < 64) mg_dense_lane(s, threadIdx.x, doff, nmax, dense, lv[nlev].b, lv[nlev].x);
+  __syncthreads();
+  // up: prolongation, post-smoothing
+  for (int m = nlev - 1; m >= 0; --m) {
+    const MgTailLevel& L = lv[m];
+    const MgTailLevel& Cl = lv[m + 1];
+    const double* b = m == 0 ? b_top : L.b;
+    double* out = m == 0 ? x_top : L.x;
+    // the pre-smoothing iterate: the sweeps alternate from (odd ? y : out)
+    const bool odd = (MG_NU1 - 1 + MG_NU2) % 2 == 1;
+    const bool pre_in_out = odd == ((MG_NU1 - 1) % 2 == 1);
+    double* xa = pre_in_out ? out : L.y;
+    double* xb = pre_in_out ? L.y : out;
+    int r0, r1;
+    rows(L, r0, r1);
+    for (int r = r0 + (int)threadIdx.x; r < r1; r += MG_TAIL_THREADS)
+      mg_prolong_row(r, s, L.active, L.sims, Cl.sims, Cl.node_map, Cl.x, L.cmask, xa);
+    __syncthreads();
+    for (int k = 0; k < MG_NU2; ++k) { sweep(L, b, xa, xb, 1); double* t = xa; xa = xb; xb = t; }
+  }
 }
 
 // Coarse-level group blocks in chunks: coarse stencil groups hold 4^l times
@@ -398,7 +499,8 @@ void mg_release(mpm_ctx* c) {
   for (MgLevel* L : c->mgl) level_release(L);
   c->mgl.clear();
   c->mg_zero.release(); c->mg_inv.release(); c->mg_fine.release(); c->mg_dense.release(); c->mg_doff.release();
-  c->mg_sims.release();
+  c->mg_sims.release(); c->mg_tail.release();
+  c->mg_tail_first = -1;
   mg_drop_graphs(c);
   if (c->cap_stream) { (void)hipStreamDestroy(c->cap_stream); c->cap_stream = nullptr; }
   c->mg_ready = false;
@@ -522,6 +624,17 @@ int mg_build(mpm_ctx* c, const mpm_problem* pb) {
     nl = l;
   }
   while (c->mgl.size() > nl) { level_release(c->mgl.back()); c->mgl.pop_back(); }
+  // fused coarse tail: from the first level whose sims all have at most
+  // MG_TAIL_ROWS rows, when at least one smoothed level lies above the dense solve
+  c->mg_tail_first = -1;
+  for (size_t l = 0; l < nl && c->mg_tail_first < 0; ++l) {
+    const mpm_ctx* L = l == 0 ? c : c->mgl[l - 1]->sub;
+    int64_t mx = 0;
+    for (int s = 0; s < nsim; ++s) mx = std::max<int64_t>(mx, L->sim_row_start[s + 1] - L->sim_row_start[s]);
+    if (mx <= MG_TAIL_ROWS) c->mg_tail_first = (int)l;
+  }
+  if (c->mg_tail_first >= 0 && c->mg_tail.ensure(nl - c->mg_tail_first + 1) != hipSuccess)
+    return c->fail(MPM_E_NOMEM, "multigrid tail allocation failed");
   // coarsest: dense per sim
   const mpm_ctx* C = nl ? c->mgl.back()->sub : c;
   std::vector<int32_t> doff(2 * nsim);
@@ -580,6 +693,34 @@ int mg_setup(mpm_ctx* c) {
   }
   k_mg_gauss_jordan<<<(unsigned)c->nsim, GJ, 0, c->stream>>>(c->mg_doff.p, nmax, c->mg_dense.p, c->flag.p);
   LAUNCH_CHECK(c, "k_mg_gauss_jordan");
+  if (c->mg_tail_first >= 0) {
+    // device views of the tail levels (the operators' buffers are final here)
+    const size_t nl = c->mgl.size();
+    c->mg_tail_h.clear();
+    for (size_t l = (size_t)c->mg_tail_first; l <= nl; ++l) {
+      const mpm_ctx* L = l == 0 ? c : c->mgl[l - 1]->sub;
+      double* v = l == 0 ? c->mg_fine.p : c->mgl[l - 1]->vec.p;
+      const int64_t nv = L->n_row * 2;
+      MgTailLevel d;
+      d.rowptr = L->rowptr.p;
+      d.colind = L->colind.p;
+      d.val = l == 0 ? c->val.p : L->val.p;
+      d.dinv = l == 0 ? c->dinv.p : L->dinv.p;
+      d.active = L->active_nodes.p;
+      d.sims = L->sims.p;
+      d.node_map = L->node_map.p;
+      d.cmask = L->cmask.p;
+      d.y = v;
+      d.r = v + nv;
+      d.x = l == 0 ? nullptr : v + 2 * nv;   // the finest level's vectors are the caller's
+      d.b = l == 0 ? nullptr : v + 3 * nv;
+      d.n_row = (int32_t)L->n_row;
+      d.nsim = c->nsim;
+      c->mg_tail_h.push_back(d);
+    }
+    HIPC(c, hipMemcpyAsync(c->mg_tail.p, c->mg_tail_h.data(), c->mg_tail_h.size() * sizeof(MgTailLevel),
+                           hipMemcpyHostToDevice, c->stream));
+  }
   return MPM_OK;
 }
 
@@ -605,6 +746,12 @@ static int sweep(mpm_ctx* c, const LevelView& L, const double* b, const double* 
 // x = M^-1 b on level l (vectors of that level); result written to out.
 static int vcycle(mpm_ctx* c, size_t l, const double* b, double* out) {
   const size_t nl = c->mgl.size();
+  if (c->mg_fuse && c->mg_tail_first >= 0 && l == (size_t)c->mg_tail_first) {
+    k_mg_tail<<<(unsigned)c->nsim, MG_TAIL_THREADS, 0, c->lstream>>>(
+        c->mg_tail.p, (int)(nl - l), c->simflag.p, c->mg_doff.p, c->mg_nmax, c->mg_dense.p, b, out);
+    LAUNCH_CHECK(c, "k_mg_tail");
+    return MPM_OK;
+  }
   if (l == nl) {
     k_mg_dense_apply<<<(unsigned)c->nsim, 64, 0, c->lstream>>>(c->mg_doff.p, c->mg_nmax, c->mg_dense.p, b, out);
     LAUNCH_CHECK(c, "k_mg_dense_apply");
