@@ -85,6 +85,7 @@ struct MgLevel {
   DBuf<int32_t> key_chunk;   // per origin key: first chunk (n_okeys + 1)
   DBuf<double> part;         // per chunk: 81 partial 2x2 blocks
   int64_t n_chunks = 0;
+  int32_t max_key_chunks = 0;   // most chunks of one origin key
 };
 }  // namespace mpm
 

@@ -83,23 +83,40 @@ __global__ void k_mg_rec2(int64_t np, const double* __restrict__ xs, const int32
 
 // One block-Jacobi step on one row (LPR lanes per row):
 // mode 0: x_out = w D^-1 b;  mode 1: x_out = x_in + w D^-1 (b - A x_in);
-// mode 2: x_out = b - A x_in.
+// mode 2: x_out = b - A x_in.  The row product does not depend on LPR
+// (4 or 8): block k of the row adds into partial sum k mod 8 in ascending
+// k, and the 8 partial sums meet in a fixed butterfly (offsets 4, 2, 1),
+// the levels at offsets >= LPR inside the lane.
 template <int LPR>
 __device__ __forceinline__ void mg_sweep_row(int row, int lane, const int32_t* __restrict__ rowptr,
                                              const int32_t* __restrict__ colind, const double* __restrict__ val,
                                              const double* __restrict__ dinv, const double* __restrict__ b,
                                              const double* __restrict__ x_in, double* __restrict__ x_out,
                                              double omega, int mode) {
+  constexpr int VL = 8, NA = VL / LPR;
+  static_assert(NA == 1 || NA == 2, "LPR must be 4 or 8");
   double a0 = 0.0, a1 = 0.0;
   if (mode != 0) {
+    double p0[NA], p1[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) p0[a] = p1[a] = 0.0;
     const int k1 = rowptr[row + 1];
-    for (int k = rowptr[row] + lane; k < k1; k += LPR) {
-      const double* blk = val + (int64_t)k * 4;
-      const int64_t c = colind[k];
-      const double x0 = x_in[c * 2], x1 = x_in[c * 2 + 1];
-      a0 += blk[0] * x0 + blk[1] * x1;
-      a1 += blk[2] * x0 + blk[3] * x1;
+    for (int k0 = rowptr[row] + lane; k0 < k1; k0 += VL) {
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        const int k = k0 + a * LPR;
+        if (k < k1) {
+          const double* blk = val + (int64_t)k * 4;
+          const int64_t c = colind[k];
+          const double x0 = x_in[c * 2], x1 = x_in[c * 2 + 1];
+          p0[a] += blk[0] * x0 + blk[1] * x1;
+          p1[a] += blk[2] * x0 + blk[3] * x1;
+        }
+      }
     }
+    if (NA == 2) { p0[0] += p0[NA - 1]; p1[0] += p1[NA - 1]; }
+    a0 = p0[0];
+    a1 = p1[0];
 #pragma unroll
     for (int off = LPR / 2; off > 0; off >>= 1) {
       a0 += __shfl_xor(a0, off, LPR);
@@ -357,7 +374,7 @@ __global__ void __launch_bounds__(64) k_mg_dense_apply(const int32_t* __restrict
 // workgroup barrier standing in for each launch boundary.  Coarse levels
 // are launch-latency bound: this replaces 7 launches per level.
 constexpr int MG_TAIL_THREADS = 1024;
-constexpr int MG_TAIL_LPR = 8;
+constexpr int MG_TAIL_LPR = 4;   // 256 rows per pass
 __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const MgTailLevel* __restrict__ lv, int nlev,
                                                              const int32_t* __restrict__ simflag,
                                                              const int32_t* __restrict__ doff, int nmax,
@@ -482,6 +499,36 @@ __global__ void __launch_bounds__(256) k_mg_grp_sum(int64_t n_okeys, const int32
   }
 }
 
+// The same sums for levels whose groups hold many chunks: one workgroup per
+// key, wave w adds chunks c0 + w, c0 + w + 16, ... in order, and the 16
+// stripe sums meet in a fixed tree.
+constexpr int MG_SUM_STRIPES = 16;
+__global__ void __launch_bounds__(64 * MG_SUM_STRIPES) k_mg_grp_sum_wide(const int32_t* __restrict__ key_chunk,
+                                                                         const double* __restrict__ part,
+                                                                         double* __restrict__ gbuf) {
+  const int64_t key = blockIdx.x;
+  const int c0 = key_chunk[key], c1 = key_chunk[key + 1];
+  if (c0 == c1) return;   // empty origin: never read (uniform over the workgroup)
+  __shared__ double st[MG_SUM_STRIPES][GB2];
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  for (int e = lane; e < GB2; e += 64) {
+    double acc = 0.0;
+    for (int ch = c0 + w; ch < c1; ch += MG_SUM_STRIPES) acc += part[(int64_t)ch * GB2 + e];
+    st[w][e] = acc;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < GB2; e += 64 * MG_SUM_STRIPES) {
+    double t[MG_SUM_STRIPES];
+#pragma unroll
+    for (int q = 0; q < MG_SUM_STRIPES; ++q) t[q] = st[q][e];
+#pragma unroll
+    for (int m = MG_SUM_STRIPES / 2; m > 0; m >>= 1)
+#pragma unroll
+      for (int q = 0; q < m; ++q) t[q] += t[q + m];
+    gbuf[key * GB2 + e] = t[0];
+  }
+}
+
 }  // namespace mpm
 
 using namespace mpm;
@@ -522,6 +569,8 @@ static int build_chunks(mpm_ctx* c, MgLevel* L) {
   }
   kc[sub->n_okeys] = (int32_t)(ch.size() / 2);
   L->n_chunks = (int64_t)(ch.size() / 2);
+  L->max_key_chunks = 0;
+  for (int64_t k = 0; k < sub->n_okeys; ++k) L->max_key_chunks = std::max(L->max_key_chunks, kc[k + 1] - kc[k]);
   if (L->chunk.ensure(std::max<size_t>(2, ch.size())) != hipSuccess ||
       L->key_chunk.ensure(kc.size()) != hipSuccess ||
       L->part.ensure((size_t)std::max<int64_t>(1, L->n_chunks) * GB2) != hipSuccess ||
@@ -672,7 +721,11 @@ int mg_setup(mpm_ctx* c) {
       k_mg_grp_chunk<<<(unsigned)L->n_chunks, 64, 0, c->stream>>>(L->chunk.p, sub->pdat.p, L->part.p);
       LAUNCH_CHECK(c, "k_mg_grp_chunk");
     }
-    if (sub->n_okeys) {
+    if (sub->n_okeys && L->max_key_chunks >= MG_SUM_STRIPES) {
+      k_mg_grp_sum_wide<<<(unsigned)sub->n_okeys, 64 * MG_SUM_STRIPES, 0, c->stream>>>(L->key_chunk.p, L->part.p,
+                                                                                        sub->gbuf.p);
+      LAUNCH_CHECK(c, "k_mg_grp_sum_wide");
+    } else if (sub->n_okeys) {
       k_mg_grp_sum<<<(unsigned)((sub->n_okeys + 3) / 4), 256, 0, c->stream>>>(sub->n_okeys, L->key_chunk.p,
                                                                              L->part.p, sub->gbuf.p);
       LAUNCH_CHECK(c, "k_mg_grp_sum");
