@@ -141,7 +141,7 @@ struct mpm_ctx {
   bool kfused = true;                          // BiCGStab consumers sum the row-block partials themselves
   int spmv_lanes = 0;                          // lanes per BSR row picked by the autotuner (0: not yet)
   int spmv_pin = 0;                            // lanes per BSR row fixed by the caller (0: autotune)
-  int kprev = 0;                               // BiCGStab iterations of the previous solve (slowest sim)
+  double kdec = 0.0;                           // residual decades per BiCGStab iteration, previous solve
   mpm::DBuf<double> du_base, alpha;            // line search
   // adjoint
   mpm::DBuf<int32_t> tpos;                     // position of the transposed block

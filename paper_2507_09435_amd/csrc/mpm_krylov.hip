@@ -922,12 +922,13 @@ int krylov_solve(mpm_ctx* c, const double* val, double rtol, int max_iter, std::
   int used = 0;           // iterations spent over all (re)starts
   // Iterations are launched in chunks between host checks of the per-sim
   // convergence flags; iterations past a sim's convergence change nothing
-  // but still cost their launches.  The first chunk runs up to one short of
-  // the previous solve's count, later chunks a sixteenth of it (at least
-  // 2): a check costs far less than a preconditioned iteration.
+  // but still cost their launches.  The previous solve's rate (decades of
+  // residual per iteration) predicts this one's count: the first chunk runs
+  // up to one short of it, later chunks a sixteenth of it (at least 2), as
+  // a check costs far less than a preconditioned iteration.
+  const double predicted = c->kdec > 0.0 ? -std::log10(rtol) / c->kdec : 0.0;
   auto next_chunk = [&](int done) {
-    const int ref = c->kprev > 0 ? c->kprev : done;
-    return std::max(2, ref / (c->kprev > 0 ? 16 : 4));
+    return predicted > 0.0 ? std::max(2, (int)(predicted / 16.0)) : std::max(2, done / 4);
   };
   bool good = false;
   double last_worst = INFINITY;
@@ -951,7 +952,7 @@ int krylov_solve(mpm_ctx* c, const double* val, double rtol, int max_iter, std::
     LAUNCH_CHECK(c, "bicgstab init");
     int it = 0;
     bool all_done = false;
-    int chunk = attempt == 0 && c->kprev > 0 ? std::max(1, c->kprev - 1) : 16;
+    int chunk = attempt == 0 && predicted > 0.0 ? std::max(1, (int)predicted - 1) : 16;
     while (!all_done && used + it < bicg_budget) {
       for (int k = 0; k < chunk && used + it < bicg_budget; ++k, ++it) {
         rc = c->nd == 2 ? bicg_iter<2>(c, val, it, K) : bicg_iter<3>(c, val, it, K);
@@ -971,7 +972,7 @@ int krylov_solve(mpm_ctx* c, const double* val, double rtol, int max_iter, std::
       iters_out[s] += its;
       slowest = std::max(slowest, its);
     }
-    if (attempt == 0) c->kprev = slowest;
+    if (attempt == 0 && slowest > 0) c->kdec = -std::log10(rtol) / slowest;
     used += it;
     if ((rc = true_ratios(c, val, K.part_ts, ratio))) break;
     good = true;

@@ -84,7 +84,7 @@ __global__ void k_mg_rec2(int64_t np, const double* __restrict__ xs, const int32
 // One block-Jacobi step on one row (LPR lanes per row):
 // mode 0: x_out = w D^-1 b;  mode 1: x_out = x_in + w D^-1 (b - A x_in);
 // mode 2: x_out = b - A x_in.  The row product does not depend on LPR
-// (4 or 8): block k of the row adds into partial sum k mod 8 in ascending
+// (2, 4 or 8): block k of the row adds into partial sum k mod 8 in ascending
 // k, and the 8 partial sums meet in a fixed butterfly (offsets 4, 2, 1),
 // the levels at offsets >= LPR inside the lane.
 template <int LPR>
@@ -94,7 +94,7 @@ __device__ __forceinline__ void mg_sweep_row(int row, int lane, const int32_t* _
                                              const double* __restrict__ x_in, double* __restrict__ x_out,
                                              double omega, int mode) {
   constexpr int VL = 8, NA = VL / LPR;
-  static_assert(NA == 1 || NA == 2, "LPR must be 4 or 8");
+  static_assert(NA == 1 || NA == 2 || NA == 4, "LPR must be 2, 4 or 8");
   double a0 = 0.0, a1 = 0.0;
   if (mode != 0) {
     double p0[NA], p1[NA];
@@ -114,7 +114,10 @@ __device__ __forceinline__ void mg_sweep_row(int row, int lane, const int32_t* _
         }
       }
     }
-    if (NA == 2) { p0[0] += p0[NA - 1]; p1[0] += p1[NA - 1]; }
+#pragma unroll
+    for (int m = NA / 2; m > 0; m >>= 1)
+#pragma unroll
+      for (int a = 0; a < m; ++a) { p0[a] += p0[a + m]; p1[a] += p1[a + m]; }
     a0 = p0[0];
     a1 = p1[0];
 #pragma unroll
