@@ -37,9 +37,9 @@ def spmv_bytes(n_row, nnzb, bs):
 
 
 def spmv_traffic(lanes):
-    """HBM bytes per SpMV launch from the committed counter passes
-    (profiles/k_spmv_c2_geostatic_pmc.md), or None when the kernel's source
-    or its launch shape has changed since they were taken."""
+    """HBM bytes per SpMV launch with this many lanes per row, from the
+    committed counter passes (profiles/k_spmv_c2_geostatic_pmc.md), or None
+    when the kernel's source has changed since they were taken."""
     import hashlib
     prof = os.path.join(ROOT, "profiles", "k_spmv_c2_geostatic_pmc.md")
     src = os.path.join(ROOT, "paper_2507_09435_amd", "csrc", "mpm_krylov.hip")
@@ -53,9 +53,8 @@ def spmv_traffic(lanes):
     fields = dict(line.split(": ", 1) for line in text.splitlines() if line.startswith(("traffic_", "kernel_")))
     if i < 0 or j < 0 or fields.get("kernel_source_sha1", "").strip() != hashlib.sha1(code[i:j].encode()).hexdigest():
         return None
-    if int(fields.get("kernel_lanes_per_row", "0")) != lanes:
-        return None
-    return int(float(fields["traffic_bytes_per_launch"]))
+    key = f"traffic_bytes_per_launch_lanes{lanes}"
+    return int(float(fields[key])) if key in fields else None
 
 
 def main():
@@ -345,8 +344,11 @@ def pmc_probe(M, W, torch):
     xv = torch.randn(n_row * nd, dtype=torch.float64, device="cuda")
     zv = torch.randn_like(xv)
     yv = torch.empty_like(xv)
-    for _ in range(20):
-        M.mpm_spmv(ctx, val, xv, yv, zv)
+    for lanes in (4, 8, 16):   # every launch shape, 20 dispatches each (same arithmetic)
+        M.mpm_spmv_set_lanes(ctx, lanes)
+        for _ in range(20):
+            M.mpm_spmv(ctx, val, xv, yv, zv)
+    M.mpm_spmv_set_lanes(ctx, 0)
     a = torch.randn(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     for _ in range(3):

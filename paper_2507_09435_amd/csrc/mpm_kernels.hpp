@@ -63,16 +63,15 @@ struct MgTailLevel {
   const int32_t* colind;
   const double* val;        // level operator (BSR, 2x2 blocks)
   const double* dinv;       // inverted diagonal blocks
-  const int64_t* active;    // full-grid node of each row
-  const SimDev* sims;       // per sim: grid and first row
-  const int32_t* node_map;  // full-grid node -> row (-1 inactive)
+  const SimDev* sims;       // per sim: first row
   const uint8_t* cmask;     // constrained unknowns
-  double* y;                // sweep partner
-  double* r;                // residual
-  double* x;                // solution (coarse levels)
-  double* b;                // right-hand side (coarse levels)
+  const int32_t* rtab;      // as the coarse side: per row the 9 finer rows it gathers (-1: none)
+  const int32_t* ptab;      // as the fine side: per row the <= 4 coarser rows it takes (-1: none)
+  const double* pw;         // as the fine side: per row the interpolation weight
   int32_t n_row;
   int32_t nsim;
+  int32_t lds;              // LDS offset (doubles) of this level's vectors y, r, x, b
+  int32_t ldn;              // doubles per LDS vector (2 x the most rows of one sim)
 };
 
 struct MgLevel {
@@ -179,6 +178,10 @@ struct mpm_ctx {
   bool mg_fuse = true;                         // run the coarse tail in one launch
   mpm::DBuf<mpm::MgTailLevel> mg_tail;         // tail levels' device views (first .. coarsest)
   std::vector<mpm::MgTailLevel> mg_tail_h;     // host staging of mg_tail
+  mpm::DBuf<int32_t> mg_tab;                   // tail transfer tables (restriction 9, prolongation 4 per row)
+  mpm::DBuf<double> mg_tabw;                   // tail prolongation weights
+  std::vector<int64_t> mg_tab_off;             // per tail level: rtab, ptab, pw offsets (-1: none)
+  int mg_tail_lds = 0;                         // bytes of LDS the tail kernel uses
 
   int fail(int code, const std::string& msg) { err = msg; return code; }
 };

@@ -370,73 +370,241 @@ __global__ void __launch_bounds__(64) k_mg_dense_apply(const int32_t* __restrict
   mg_dense_lane(blockIdx.x, threadIdx.x, doff, nmax, dense, b, x);
 }
 
+// Transfer tables of the fused tail, in the order the row functions above
+// visit their terms.  rtab: per coarse row the 9 finer rows of the (dj, di)
+// loop (-1 where the term is skipped).  ptab: per fine row the coarser rows
+// of the (J, I) loop in order, -1 after the last; pw: their common weight.
+__global__ void k_mg_rtab(int64_t n_crow, const int64_t* __restrict__ c_active, const int32_t* __restrict__ c_rowsim,
+                          const SimDev* __restrict__ csims, const SimDev* __restrict__ fsims,
+                          const int32_t* __restrict__ f_node_map, int32_t* __restrict__ tab) {
+  const int64_t R = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (R >= n_crow) return;
+  const int s = c_rowsim[R];
+  const SimDev& C = csims[s];
+  const SimDev& F = fsims[s];
+  const int64_t loc = c_active[R] - C.node_base;
+  const int I = (int)(loc % C.nna[0]) - 1, J = (int)(loc / C.nna[0]) - 1;
+  int q = 0;
+  for (int dj = -1; dj <= 1; ++dj)
+    for (int di = -1; di <= 1; ++di, ++q) {
+      const int j = 2 * J + dj, i = 2 * I + di;
+      int32_t fr = -1;
+      if (j >= -1 && j <= F.n[1] + 1 && i >= -1 && i <= F.n[0] + 1)
+        fr = f_node_map[F.node_base + (i + 1) + (int64_t)F.nna[0] * (j + 1)];
+      tab[R * 9 + q] = fr < 0 ? -1 : fr;
+    }
+}
+
+__global__ void k_mg_ptab(int64_t n_frow, const int64_t* __restrict__ f_active, const int32_t* __restrict__ f_rowsim,
+                          const SimDev* __restrict__ fsims, const SimDev* __restrict__ csims,
+                          const int32_t* __restrict__ c_node_map, int32_t* __restrict__ tab, double* __restrict__ w) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_frow) return;
+  const int s = f_rowsim[r];
+  const SimDev& F = fsims[s];
+  const SimDev& C = csims[s];
+  const int64_t loc = f_active[r] - F.node_base;
+  const int i = (int)(loc % F.nna[0]) - 1, j = (int)(loc / F.nna[0]) - 1;
+  const int Ix0 = (i % 2 == 0) ? i / 2 : (i - 1) / 2, Ix1 = (i % 2 == 0) ? i / 2 : (i + 1) / 2;
+  const int Jy0 = (j % 2 == 0) ? j / 2 : (j - 1) / 2, Jy1 = (j % 2 == 0) ? j / 2 : (j + 1) / 2;
+  const double wx = Ix0 == Ix1 ? 1.0 : 0.5, wy = Jy0 == Jy1 ? 1.0 : 0.5;
+  int q = 0;
+  for (int J = Jy0; J <= Jy1; ++J) {
+    if (J < -1 || J > C.n[1] + 1) continue;
+    for (int I = Ix0; I <= Ix1; ++I) {
+      if (I < -1 || I > C.n[0] + 1) continue;
+      const int32_t cr = c_node_map[C.node_base + (I + 1) + (int64_t)C.nna[0] * (J + 1)];
+      if (cr >= 0) tab[r * 4 + q++] = cr;
+    }
+  }
+  for (; q < 4; ++q) tab[r * 4 + q] = -1;
+  w[r] = wx * wy;
+}
+
 // The coarse tail of the V-cycle in one launch: one workgroup per sim runs
-// the levels from the first one with at most MG_TAIL_ROWS rows per sim
-// down to the dense solve and back, with the same row operations in the
-// same order as the level-by-level launches (so the same arithmetic), a
-// workgroup barrier standing in for each launch boundary.  Coarse levels
-// are launch-latency bound: this replaces 7 launches per level.
+// the levels from the first one with at most MG_TAIL_ROWS rows per sim down
+// to the dense solve and back, with the arithmetic of the level-by-level
+// launches (same terms in the same order), a workgroup barrier standing in
+// for each launch boundary.  Coarse levels are bound by launch and memory
+// latency, so the tail keeps its working set close: the vectors of every
+// tail level live in LDS, and each 4-lane group holds its row's blocks and
+// inverted diagonal in registers across the sweeps of a level visit.
 constexpr int MG_TAIL_THREADS = 1024;
-constexpr int MG_TAIL_LPR = 4;   // 256 rows per pass
+constexpr int MG_TAIL_LPR = 4;                          // 256 row groups: one row each
+constexpr int MG_TAIL_KB = (25 + MG_TAIL_LPR - 1) / MG_TAIL_LPR;   // blocks per lane (rows have <= 25)
+constexpr int MG_TAIL_LDS_MAX = 64 * 1024;
+
+struct TailRow {
+  int col[MG_TAIL_KB];          // local column (row within the sim), -1 past the row end
+  double v[MG_TAIL_KB][4];
+  double D[4];
+};
+
+__device__ __forceinline__ void tail_load_row(const MgTailLevel& L, int row, int lane, TailRow& R, int r0) {
+  const int k0 = L.rowptr[row], k1 = L.rowptr[row + 1];
+#pragma unroll
+  for (int j = 0; j < MG_TAIL_KB; ++j) {
+    const int k = k0 + lane + MG_TAIL_LPR * j;
+    const bool ok = k < k1;
+    R.col[j] = ok ? L.colind[k] - r0 : -1;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) R.v[j][e] = ok ? L.val[(int64_t)k * 4 + e] : 0.0;
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) R.D[e] = L.dinv[(int64_t)row * 4 + e];
+}
+
+// mg_sweep_row<4> on a cached row, vectors in LDS (local rows)
+__device__ __forceinline__ void tail_sweep(const TailRow& R, int g, int lane, const double* b, const double* xin,
+                                           double* xout, int mode) {
+  double a0 = 0.0, a1 = 0.0;
+  if (mode != 0) {
+    double p0[2] = {0.0, 0.0}, p1[2] = {0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < MG_TAIL_KB; ++j) {
+      if (R.col[j] >= 0) {
+        const double x0 = xin[R.col[j] * 2], x1 = xin[R.col[j] * 2 + 1];
+        p0[j & 1] += R.v[j][0] * x0 + R.v[j][1] * x1;
+        p1[j & 1] += R.v[j][2] * x0 + R.v[j][3] * x1;
+      }
+    }
+    p0[0] += p0[1];
+    p1[0] += p1[1];
+    a0 = p0[0];
+    a1 = p1[0];
+#pragma unroll
+    for (int off = MG_TAIL_LPR / 2; off > 0; off >>= 1) {
+      a0 += __shfl_xor(a0, off, MG_TAIL_LPR);
+      a1 += __shfl_xor(a1, off, MG_TAIL_LPR);
+    }
+  }
+  if (lane == 0) {
+    const double r0 = b[g * 2] - a0, r1 = b[g * 2 + 1] - a1;
+    if (mode == 2) {
+      xout[g * 2] = r0;
+      xout[g * 2 + 1] = r1;
+    } else {
+      const double base0 = mode == 1 ? xin[g * 2] : 0.0;
+      const double base1 = mode == 1 ? xin[g * 2 + 1] : 0.0;
+      xout[g * 2] = base0 + MG_OMEGA * (R.D[0] * r0 + R.D[1] * r1);
+      xout[g * 2 + 1] = base1 + MG_OMEGA * (R.D[2] * r0 + R.D[3] * r1);
+    }
+  }
+}
+
 __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const MgTailLevel* __restrict__ lv, int nlev,
                                                              const int32_t* __restrict__ simflag,
                                                              const int32_t* __restrict__ doff, int nmax,
                                                              const double* __restrict__ dense,
                                                              const double* __restrict__ b_top,
                                                              double* __restrict__ x_top) {
+  extern __shared__ double lds[];
   const int s = blockIdx.x;
   if (simflag && simflag[2 * s] >= 0) return;   // whole workgroup: the sim's solve is finished
-  constexpr int LPR = MG_TAIL_LPR, NG = MG_TAIL_THREADS / LPR;
-  const int lane = threadIdx.x % LPR, grp = threadIdx.x / LPR;
-  auto rows = [&](const MgTailLevel& L, int& r0, int& r1) {
-    r0 = L.sims[s].row_base;
-    r1 = s + 1 < L.nsim ? L.sims[s + 1].row_base : L.n_row;
-  };
-  auto sweep = [&](const MgTailLevel& L, const double* b, const double* xin, double* xout, int mode) {
-    int r0, r1;
-    rows(L, r0, r1);
-    for (int row = r0 + grp; row < r1; row += NG)
-      mg_sweep_row<LPR>(row, lane, L.rowptr, L.colind, L.val, L.dinv, b, xin, xout, MG_OMEGA, mode);
+  const int tid = threadIdx.x, lane = tid % MG_TAIL_LPR, g = tid / MG_TAIL_LPR;
+  auto first_row = [&](const MgTailLevel& L) { return (int)L.sims[s].row_base; };
+  auto end_row = [&](const MgTailLevel& L) { return s + 1 < L.nsim ? (int)L.sims[s + 1].row_base : L.n_row; };
+  auto vec = [&](const MgTailLevel& L, int q) { return lds + L.lds + q * L.ldn; };   // q: 0 y, 1 r, 2 x, 3 b
+  const bool odd = (MG_NU1 - 1 + MG_NU2) % 2 == 1;
+  const bool pre_in_out = odd == ((MG_NU1 - 1) % 2 == 1);   // where the pre-smoothing iterate ends
+  TailRow R;
+  {
+    const MgTailLevel& L = lv[0];
+    const int r0 = first_row(L), n = end_row(L) - r0;
+    double* b = vec(L, 3);
+    for (int t = tid; t < 2 * n; t += MG_TAIL_THREADS) b[t] = b_top[(int64_t)r0 * 2 + t];
     __syncthreads();
-  };
+  }
   // down: pre-smoothing, residual, restriction
   for (int m = 0; m < nlev; ++m) {
     const MgTailLevel& L = lv[m];
     const MgTailLevel& Cl = lv[m + 1];
-    const double* b = m == 0 ? b_top : L.b;
-    double* out = m == 0 ? x_top : L.x;
-    const bool odd = (MG_NU1 - 1 + MG_NU2) % 2 == 1;
-    double* xa = odd ? L.y : out;
-    double* xb = odd ? out : L.y;
-    sweep(L, b, nullptr, xa, 0);
-    for (int k = 1; k < MG_NU1; ++k) { sweep(L, b, xa, xb, 1); double* t = xa; xa = xb; xb = t; }
-    sweep(L, b, xa, L.r, 2);
-    int c0, c1;
-    rows(Cl, c0, c1);
-    for (int R = c0 + (int)threadIdx.x; R < c1; R += MG_TAIL_THREADS)
-      mg_restrict_row(R, s, Cl.active, Cl.sims, L.sims, L.node_map, L.r, Cl.cmask, Cl.b);
+    const int r0 = first_row(L), n = end_row(L) - r0;
+    const bool mine = g < n;
+    if (mine) tail_load_row(L, r0 + g, lane, R, r0);
+    double *y = vec(L, 0), *r = vec(L, 1), *out = vec(L, 2), *b = vec(L, 3);
+    double* xa = odd ? y : out;
+    double* xb = odd ? out : y;
+    if (mine) tail_sweep(R, g, lane, b, nullptr, xa, 0);
+    __syncthreads();
+    for (int k = 1; k < MG_NU1; ++k) {
+      if (mine) tail_sweep(R, g, lane, b, xa, xb, 1);
+      __syncthreads();
+      double* t = xa; xa = xb; xb = t;
+    }
+    if (mine) tail_sweep(R, g, lane, b, xa, r, 2);
+    __syncthreads();
+    const int c0 = first_row(Cl), nc = end_row(Cl) - c0;
+    double* bc = vec(Cl, 3);
+    for (int t = tid; t < nc; t += MG_TAIL_THREADS) {
+      const int32_t* tab = Cl.rtab + (int64_t)(c0 + t) * 9;
+      double a0 = 0.0, a1 = 0.0;
+      int q = 0;
+      for (int dj = -1; dj <= 1; ++dj) {
+        const double wy = dj == 0 ? 1.0 : 0.5;
+        for (int di = -1; di <= 1; ++di, ++q) {
+          const int32_t fr = tab[q];
+          if (fr < 0) continue;
+          const double wgt = wy * (di == 0 ? 1.0 : 0.5);
+          a0 += wgt * r[(fr - r0) * 2];
+          a1 += wgt * r[(fr - r0) * 2 + 1];
+        }
+      }
+      bc[t * 2] = Cl.cmask[(int64_t)(c0 + t) * 2] ? 0.0 : a0;
+      bc[t * 2 + 1] = Cl.cmask[(int64_t)(c0 + t) * 2 + 1] ? 0.0 : a1;
+    }
     __syncthreads();
   }
-  // coarsest: dense solve
-  if (threadIdx.x < 64) mg_dense_lane(s, threadIdx.x, doff, nmax, dense, lv[nlev].b, lv[nlev].x);
-  __syncthreads();
+  // coarsest: dense solve (mg_dense_lane on the LDS vectors)
+  {
+    const MgTailLevel& C = lv[nlev];
+    const int n = 2 * doff[2 * s + 1];
+    const double* Vt = dense + (int64_t)s * 2 * nmax * nmax + (int64_t)nmax * nmax;
+    const double* bs = vec(C, 3);
+    if (tid < n) {
+      double acc = 0.0;
+      for (int j = 0; j < n; ++j) acc += Vt[(int64_t)j * nmax + tid] * bs[j];
+      vec(C, 2)[tid] = acc;
+    }
+    __syncthreads();
+  }
   // up: prolongation, post-smoothing
   for (int m = nlev - 1; m >= 0; --m) {
     const MgTailLevel& L = lv[m];
     const MgTailLevel& Cl = lv[m + 1];
-    const double* b = m == 0 ? b_top : L.b;
-    double* out = m == 0 ? x_top : L.x;
-    // the pre-smoothing iterate: the sweeps alternate from (odd ? y : out)
-    const bool odd = (MG_NU1 - 1 + MG_NU2) % 2 == 1;
-    const bool pre_in_out = odd == ((MG_NU1 - 1) % 2 == 1);
-    double* xa = pre_in_out ? out : L.y;
-    double* xb = pre_in_out ? L.y : out;
-    int r0, r1;
-    rows(L, r0, r1);
-    for (int r = r0 + (int)threadIdx.x; r < r1; r += MG_TAIL_THREADS)
-      mg_prolong_row(r, s, L.active, L.sims, Cl.sims, Cl.node_map, Cl.x, L.cmask, xa);
+    const int r0 = first_row(L), n = end_row(L) - r0;
+    const int c0 = first_row(Cl);
+    const bool mine = g < n;
+    if (mine) tail_load_row(L, r0 + g, lane, R, r0);
+    double *y = vec(L, 0), *out = vec(L, 2), *b = vec(L, 3);
+    const double* xc = vec(Cl, 2);
+    double* xa = pre_in_out ? out : y;
+    double* xb = pre_in_out ? y : out;
+    for (int t = tid; t < n; t += MG_TAIL_THREADS) {
+      const int32_t* tab = L.ptab + (int64_t)(r0 + t) * 4;
+      const double w = L.pw[r0 + t];
+      double a0 = 0.0, a1 = 0.0;
+      for (int q = 0; q < 4; ++q) {
+        const int32_t cr = tab[q];
+        if (cr < 0) break;
+        a0 += w * xc[(cr - c0) * 2];
+        a1 += w * xc[(cr - c0) * 2 + 1];
+      }
+      if (!L.cmask[(int64_t)(r0 + t) * 2]) xa[t * 2] += a0;
+      if (!L.cmask[(int64_t)(r0 + t) * 2 + 1]) xa[t * 2 + 1] += a1;
+    }
     __syncthreads();
-    for (int k = 0; k < MG_NU2; ++k) { sweep(L, b, xa, xb, 1); double* t = xa; xa = xb; xb = t; }
+    for (int k = 0; k < MG_NU2; ++k) {
+      if (mine) tail_sweep(R, g, lane, b, xa, xb, 1);
+      __syncthreads();
+      double* t = xa; xa = xb; xb = t;
+    }
+  }
+  {
+    const MgTailLevel& L = lv[0];
+    const int r0 = first_row(L), n = end_row(L) - r0;
+    const double* x = vec(L, 2);
+    for (int t = tid; t < 2 * n; t += MG_TAIL_THREADS) x_top[(int64_t)r0 * 2 + t] = x[t];
   }
 }
 
@@ -549,7 +717,7 @@ void mg_release(mpm_ctx* c) {
   for (MgLevel* L : c->mgl) level_release(L);
   c->mgl.clear();
   c->mg_zero.release(); c->mg_inv.release(); c->mg_fine.release(); c->mg_dense.release(); c->mg_doff.release();
-  c->mg_sims.release(); c->mg_tail.release();
+  c->mg_sims.release(); c->mg_tail.release(); c->mg_tab.release(); c->mg_tabw.release();
   c->mg_tail_first = -1;
   mg_drop_graphs(c);
   if (c->cap_stream) { (void)hipStreamDestroy(c->cap_stream); c->cap_stream = nullptr; }
@@ -685,8 +853,52 @@ int mg_build(mpm_ctx* c, const mpm_problem* pb) {
     for (int s = 0; s < nsim; ++s) mx = std::max<int64_t>(mx, L->sim_row_start[s + 1] - L->sim_row_start[s]);
     if (mx <= MG_TAIL_ROWS) c->mg_tail_first = (int)l;
   }
-  if (c->mg_tail_first >= 0 && c->mg_tail.ensure(nl - c->mg_tail_first + 1) != hipSuccess)
-    return c->fail(MPM_E_NOMEM, "multigrid tail allocation failed");
+  if (c->mg_tail_first >= 0) {
+    // LDS layout (four vectors per level, sized for the largest sim) and
+    // the transfer tables of the tail levels
+    const size_t first = (size_t)c->mg_tail_first;
+    std::vector<int64_t> off;
+    int64_t lds = 0, ntab = 0, nw = 0;
+    for (size_t l = first; l <= nl; ++l) {
+      const mpm_ctx* L = l == 0 ? c : c->mgl[l - 1]->sub;
+      int64_t mx = 0;
+      for (int s = 0; s < nsim; ++s) mx = std::max<int64_t>(mx, L->sim_row_start[s + 1] - L->sim_row_start[s]);
+      off.push_back(lds);
+      off.push_back(2 * mx);
+      lds += 4 * 2 * mx;
+      off.push_back(l > first ? ntab : -1);          // rtab (coarse side)
+      if (l > first) ntab += L->n_row * 9;
+      off.push_back(l < nl ? ntab : -1);             // ptab (fine side)
+      off.push_back(l < nl ? nw : -1);               // pw
+      if (l < nl) { ntab += L->n_row * 4; nw += L->n_row; }
+    }
+    if (lds * (int64_t)sizeof(double) > MG_TAIL_LDS_MAX) {
+      c->mg_tail_first = -1;   // too large for one workgroup's LDS: level-by-level launches
+    } else {
+      c->mg_tab_off = off;
+      c->mg_tail_lds = (int)(lds * sizeof(double));
+      if (c->mg_tail.ensure(nl - first + 1) != hipSuccess || c->mg_tab.ensure(std::max<int64_t>(1, ntab)) != hipSuccess ||
+          c->mg_tabw.ensure(std::max<int64_t>(1, nw)) != hipSuccess)
+        return c->fail(MPM_E_NOMEM, "multigrid tail allocation failed");
+      for (size_t l = first; l <= nl; ++l) {
+        const mpm_ctx* L = l == 0 ? c : c->mgl[l - 1]->sub;
+        const int64_t* o = &off[(l - first) * 5];
+        if (l > first && L->n_row) {
+          const mpm_ctx* Fn = l - 1 == 0 ? c : c->mgl[l - 2]->sub;
+          k_mg_rtab<<<nb256(L->n_row), 256, 0, c->stream>>>(L->n_row, L->active_nodes.p, L->row_sim.p, L->sims.p,
+                                                           Fn->sims.p, Fn->node_map.p, c->mg_tab.p + o[2]);
+          LAUNCH_CHECK(c, "k_mg_rtab");
+        }
+        if (l < nl && L->n_row) {
+          const mpm_ctx* Cn = c->mgl[l]->sub;
+          k_mg_ptab<<<nb256(L->n_row), 256, 0, c->stream>>>(L->n_row, L->active_nodes.p, L->row_sim.p, L->sims.p,
+                                                           Cn->sims.p, Cn->node_map.p, c->mg_tab.p + o[3],
+                                                           c->mg_tabw.p + o[4]);
+          LAUNCH_CHECK(c, "k_mg_ptab");
+        }
+      }
+    }
+  }
   // coarsest: dense per sim
   const mpm_ctx* C = nl ? c->mgl.back()->sub : c;
   std::vector<int32_t> doff(2 * nsim);
@@ -752,26 +964,25 @@ int mg_setup(mpm_ctx* c) {
   if (c->mg_tail_first >= 0) {
     // device views of the tail levels (the operators' buffers are final here)
     const size_t nl = c->mgl.size();
+    const size_t first = (size_t)c->mg_tail_first;
     c->mg_tail_h.clear();
-    for (size_t l = (size_t)c->mg_tail_first; l <= nl; ++l) {
+    for (size_t l = first; l <= nl; ++l) {
       const mpm_ctx* L = l == 0 ? c : c->mgl[l - 1]->sub;
-      double* v = l == 0 ? c->mg_fine.p : c->mgl[l - 1]->vec.p;
-      const int64_t nv = L->n_row * 2;
+      const int64_t* o = &c->mg_tab_off[(l - first) * 5];
       MgTailLevel d;
       d.rowptr = L->rowptr.p;
       d.colind = L->colind.p;
       d.val = l == 0 ? c->val.p : L->val.p;
       d.dinv = l == 0 ? c->dinv.p : L->dinv.p;
-      d.active = L->active_nodes.p;
       d.sims = L->sims.p;
-      d.node_map = L->node_map.p;
       d.cmask = L->cmask.p;
-      d.y = v;
-      d.r = v + nv;
-      d.x = l == 0 ? nullptr : v + 2 * nv;   // the finest level's vectors are the caller's
-      d.b = l == 0 ? nullptr : v + 3 * nv;
+      d.rtab = o[2] >= 0 ? c->mg_tab.p + o[2] : nullptr;
+      d.ptab = o[3] >= 0 ? c->mg_tab.p + o[3] : nullptr;
+      d.pw = o[4] >= 0 ? c->mg_tabw.p + o[4] : nullptr;
       d.n_row = (int32_t)L->n_row;
       d.nsim = c->nsim;
+      d.lds = (int32_t)o[0];
+      d.ldn = (int32_t)o[1];
       c->mg_tail_h.push_back(d);
     }
     HIPC(c, hipMemcpyAsync(c->mg_tail.p, c->mg_tail_h.data(), c->mg_tail_h.size() * sizeof(MgTailLevel),
@@ -803,7 +1014,7 @@ static int sweep(mpm_ctx* c, const LevelView& L, const double* b, const double* 
 static int vcycle(mpm_ctx* c, size_t l, const double* b, double* out) {
   const size_t nl = c->mgl.size();
   if (c->mg_fuse && c->mg_tail_first >= 0 && l == (size_t)c->mg_tail_first) {
-    k_mg_tail<<<(unsigned)c->nsim, MG_TAIL_THREADS, 0, c->lstream>>>(
+    k_mg_tail<<<(unsigned)c->nsim, MG_TAIL_THREADS, c->mg_tail_lds, c->lstream>>>(
         c->mg_tail.p, (int)(nl - l), c->simflag.p, c->mg_doff.p, c->mg_nmax, c->mg_dense.p, b, out);
     LAUNCH_CHECK(c, "k_mg_tail");
     return MPM_OK;
