@@ -26,6 +26,12 @@ constexpr int MG_MAX_LEVELS = 12;
 constexpr int MG_DENSE_MAX = 64;        // coarsest unknowns per simulation (inverted in LDS)
 constexpr int MG_TAIL_ROWS = 256;       // levels with at most this many rows per sim run in one launch
 
+// Multiply-adds of the V-cycle are written as explicit fma with a fixed
+// operand order: left to contraction, the compiler may fuse a different
+// product of the same expression in different kernels, and the fused tail,
+// the fused first sweep and the level-by-level launches must round alike.
+__device__ __forceinline__ double dot2(double a0, double x0, double a1, double x1) { return fma(a0, x0, a1 * x1); }
+
 __device__ __forceinline__ int sim_of_node(const SimDev* sims, int nsim, int64_t node) {
   int s = 0;
   while (s + 1 < nsim && node >= sims[s + 1].node_base) ++s;
@@ -83,7 +89,9 @@ __global__ void k_mg_rec2(int64_t np, const double* __restrict__ xs, const int32
 
 // One block-Jacobi step on one row (LPR lanes per row):
 // mode 0: x_out = w D^-1 b;  mode 1: x_out = x_in + w D^-1 (b - A x_in);
-// mode 2: x_out = b - A x_in.  The row product does not depend on LPR
+// mode 2: x_out = b - A x_in;  mode 3: modes 0 and 1 in one pass, the
+// mode-0 iterate of each neighbour formed on the fly from its D^-1 and b
+// with mode 0's own expression (so the same bits as the two passes).  The row product does not depend on LPR
 // (2, 4 or 8): block k of the row adds into partial sum k mod 8 in ascending
 // k, and the 8 partial sums meet in a fixed butterfly (offsets 4, 2, 1),
 // the levels at offsets >= LPR inside the lane.
@@ -108,9 +116,18 @@ __device__ __forceinline__ void mg_sweep_row(int row, int lane, const int32_t* _
         if (k < k1) {
           const double* blk = val + (int64_t)k * 4;
           const int64_t c = colind[k];
-          const double x0 = x_in[c * 2], x1 = x_in[c * 2 + 1];
-          p0[a] += blk[0] * x0 + blk[1] * x1;
-          p1[a] += blk[2] * x0 + blk[3] * x1;
+          double x0, x1;
+          if (mode == 3) {
+            const double* Dc = dinv + c * 4;
+            const double s0 = b[c * 2], s1 = b[c * 2 + 1];
+            x0 = fma(omega, dot2(Dc[0], s0, Dc[1], s1), 0.0);
+            x1 = fma(omega, dot2(Dc[2], s0, Dc[3], s1), 0.0);
+          } else {
+            x0 = x_in[c * 2];
+            x1 = x_in[c * 2 + 1];
+          }
+          p0[a] = p0[a] + dot2(blk[0], x0, blk[1], x1);
+          p1[a] = p1[a] + dot2(blk[2], x0, blk[3], x1);
         }
       }
     }
@@ -133,10 +150,15 @@ __device__ __forceinline__ void mg_sweep_row(int row, int lane, const int32_t* _
       x_out[(int64_t)row * 2 + 1] = r1;
     } else {
       const double* D = dinv + (int64_t)row * 4;
-      const double base0 = mode == 1 ? x_in[(int64_t)row * 2] : 0.0;
-      const double base1 = mode == 1 ? x_in[(int64_t)row * 2 + 1] : 0.0;
-      x_out[(int64_t)row * 2] = base0 + omega * (D[0] * r0 + D[1] * r1);
-      x_out[(int64_t)row * 2 + 1] = base1 + omega * (D[2] * r0 + D[3] * r1);
+      double base0 = mode == 1 ? x_in[(int64_t)row * 2] : 0.0;
+      double base1 = mode == 1 ? x_in[(int64_t)row * 2 + 1] : 0.0;
+      if (mode == 3) {   // this row's mode-0 iterate
+        const double s0 = b[(int64_t)row * 2], s1 = b[(int64_t)row * 2 + 1];
+        base0 = fma(omega, dot2(D[0], s0, D[1], s1), 0.0);
+        base1 = fma(omega, dot2(D[2], s0, D[3], s1), 0.0);
+      }
+      x_out[(int64_t)row * 2] = fma(omega, dot2(D[0], r0, D[1], r1), base0);
+      x_out[(int64_t)row * 2 + 1] = fma(omega, dot2(D[2], r0, D[3], r1), base1);
     }
   }
 }
@@ -178,8 +200,8 @@ __device__ __forceinline__ void mg_restrict_row(int64_t R, int s, const int64_t*
       const int32_t fr = f_node_map[F.node_base + (i + 1) + (int64_t)F.nna[0] * (j + 1)];
       if (fr < 0) continue;
       const double wgt = wy * (di == 0 ? 1.0 : 0.5);
-      a0 += wgt * rf[(int64_t)fr * 2];
-      a1 += wgt * rf[(int64_t)fr * 2 + 1];
+      a0 = fma(wgt, rf[(int64_t)fr * 2], a0);
+      a1 = fma(wgt, rf[(int64_t)fr * 2 + 1], a1);
     }
   }
   bc[R * 2] = c_cmask[R * 2] ? 0.0 : a0;
@@ -219,8 +241,8 @@ __device__ __forceinline__ void mg_prolong_row(int64_t r, int s, const int64_t* 
       if (I < -1 || I > C.n[0] + 1) continue;
       const int32_t cr = c_node_map[C.node_base + (I + 1) + (int64_t)C.nna[0] * (J + 1)];
       if (cr < 0) continue;
-      a0 += wx * wy * xc[(int64_t)cr * 2];
-      a1 += wx * wy * xc[(int64_t)cr * 2 + 1];
+      a0 = fma(wx * wy, xc[(int64_t)cr * 2], a0);
+      a1 = fma(wx * wy, xc[(int64_t)cr * 2 + 1], a1);
     }
   }
   if (!f_cmask[r * 2]) xf[r * 2] += a0;
@@ -360,7 +382,7 @@ __device__ __forceinline__ void mg_dense_lane(int s, int i, const int32_t* __res
   const double* Vt = dense + (int64_t)s * 2 * nmax * nmax + (int64_t)nmax * nmax;
   const double* bs = b + (int64_t)r0 * 2;
   double acc = 0.0;
-  for (int j = 0; j < n; ++j) acc += Vt[(int64_t)j * nmax + i] * bs[j];
+  for (int j = 0; j < n; ++j) acc = fma(Vt[(int64_t)j * nmax + i], bs[j], acc);
   x[(int64_t)r0 * 2 + i] = acc;
 }
 
@@ -464,8 +486,8 @@ __device__ __forceinline__ void tail_sweep(const TailRow& R, int g, int lane, co
     for (int j = 0; j < MG_TAIL_KB; ++j) {
       if (R.col[j] >= 0) {
         const double x0 = xin[R.col[j] * 2], x1 = xin[R.col[j] * 2 + 1];
-        p0[j & 1] += R.v[j][0] * x0 + R.v[j][1] * x1;
-        p1[j & 1] += R.v[j][2] * x0 + R.v[j][3] * x1;
+        p0[j & 1] = p0[j & 1] + dot2(R.v[j][0], x0, R.v[j][1], x1);
+        p1[j & 1] = p1[j & 1] + dot2(R.v[j][2], x0, R.v[j][3], x1);
       }
     }
     p0[0] += p0[1];
@@ -486,8 +508,8 @@ __device__ __forceinline__ void tail_sweep(const TailRow& R, int g, int lane, co
     } else {
       const double base0 = mode == 1 ? xin[g * 2] : 0.0;
       const double base1 = mode == 1 ? xin[g * 2 + 1] : 0.0;
-      xout[g * 2] = base0 + MG_OMEGA * (R.D[0] * r0 + R.D[1] * r1);
-      xout[g * 2 + 1] = base1 + MG_OMEGA * (R.D[2] * r0 + R.D[3] * r1);
+      xout[g * 2] = fma(MG_OMEGA, dot2(R.D[0], r0, R.D[1], r1), base0);
+      xout[g * 2 + 1] = fma(MG_OMEGA, dot2(R.D[2], r0, R.D[3], r1), base1);
     }
   }
 }
@@ -546,8 +568,8 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const MgTailLevel* 
           const int32_t fr = tab[q];
           if (fr < 0) continue;
           const double wgt = wy * (di == 0 ? 1.0 : 0.5);
-          a0 += wgt * r[(fr - r0) * 2];
-          a1 += wgt * r[(fr - r0) * 2 + 1];
+          a0 = fma(wgt, r[(fr - r0) * 2], a0);
+          a1 = fma(wgt, r[(fr - r0) * 2 + 1], a1);
         }
       }
       bc[t * 2] = Cl.cmask[(int64_t)(c0 + t) * 2] ? 0.0 : a0;
@@ -563,7 +585,7 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const MgTailLevel* 
     const double* bs = vec(C, 3);
     if (tid < n) {
       double acc = 0.0;
-      for (int j = 0; j < n; ++j) acc += Vt[(int64_t)j * nmax + tid] * bs[j];
+      for (int j = 0; j < n; ++j) acc = fma(Vt[(int64_t)j * nmax + tid], bs[j], acc);
       vec(C, 2)[tid] = acc;
     }
     __syncthreads();
@@ -587,8 +609,8 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const MgTailLevel* 
       for (int q = 0; q < 4; ++q) {
         const int32_t cr = tab[q];
         if (cr < 0) break;
-        a0 += w * xc[(cr - c0) * 2];
-        a1 += w * xc[(cr - c0) * 2 + 1];
+        a0 = fma(w, xc[(cr - c0) * 2], a0);
+        a1 = fma(w, xc[(cr - c0) * 2 + 1], a1);
       }
       if (!L.cmask[(int64_t)(r0 + t) * 2]) xa[t * 2] += a0;
       if (!L.cmask[(int64_t)(r0 + t) * 2 + 1]) xa[t * 2 + 1] += a1;
@@ -1033,8 +1055,15 @@ static int vcycle(mpm_ctx* c, size_t l, const double* b, double* out) {
   const bool odd = (MG_NU1 - 1 + MG_NU2) % 2 == 1;
   double* xa = odd ? y : out;
   double* xb = odd ? out : y;
-  GUARD(sweep(c, V, b, nullptr, xa, 0));
-  for (int k = 1; k < MG_NU1; ++k) { GUARD(sweep(c, V, b, xa, xb, 1)); std::swap(xa, xb); }
+  int k_first = 1;
+  if (c->mg_fuse && MG_NU1 >= 2) {   // the first two sweeps in one pass
+    GUARD(sweep(c, V, b, nullptr, xb, 3));
+    std::swap(xa, xb);
+    k_first = 2;
+  } else {
+    GUARD(sweep(c, V, b, nullptr, xa, 0));
+  }
+  for (int k = k_first; k < MG_NU1; ++k) { GUARD(sweep(c, V, b, xa, xb, 1)); std::swap(xa, xb); }
   GUARD(sweep(c, V, b, xa, r, 2));
   // coarse correction
   MgLevel* CL = c->mgl[l];
