@@ -405,9 +405,10 @@ __global__ void __launch_bounds__(256) k_jac2_blocks(int64_t n_row, const int64_
 // 2-D residual P2G without atomics.  k_fint2_rec writes one record per
 // particle (sorted order): V0 P (4), for u-p V0 s1 and V0 vv (3), then the
 // stencil's weights and derivatives per axis.  k_fint2_rows gives each row
-// (node a) to one thread, which sums f_a = sum_p V0 P_p grad w_a(x_p) (and the
-// u-p row) over the particles of the (at most nine) stencil groups whose
-// stencil holds a, in group then particle order: deterministic, written once.
+// (node a) 16 lanes: lane q < 9 sums f_a = sum_p V0 P_p grad w_a(x_p) (and the
+// u-p row) over the particles of the q-th stencil group whose stencil may
+// hold a, in particle order, and the 16 lane sums meet in a fixed butterfly:
+// deterministic, written once.
 constexpr int RD2 = 20;   // doubles per residual record: V0 P 0..3, u-p 4..6, wx 8..10, dwx 11..13, wy 14..16, dwy 17..19
 
 __global__ void __launch_bounds__(256) k_fint2_rec(AsmArgs A, const double* __restrict__ du, double* __restrict__ rec) {
@@ -433,37 +434,46 @@ __global__ void __launch_bounds__(256) k_fint2_rec(AsmArgs A, const double* __re
   }
 }
 
+constexpr int RL2 = 16;   // lanes per row of the 2-D row gathers (9 stencil groups used)
+
 __global__ void __launch_bounds__(256) k_fint2_rows(int64_t n_row, int nd, int up,
                                                    const int64_t* __restrict__ active_nodes,
                                                    const int32_t* __restrict__ row_sim,
                                                    const SimDev* __restrict__ sims,
                                                    const int32_t* __restrict__ gstart,
                                                    const double* __restrict__ rec, double* __restrict__ fint) {
-  const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (row >= n_row) return;
+  const int64_t row = ((int64_t)blockIdx.x * 256 + threadIdx.x) / RL2;
+  const int q = (int)(threadIdx.x % RL2);
+  if (row >= n_row) return;   // the row's 16 lanes leave together
   const SimDev& S = sims[row_sim[row]];
   const int64_t nid = active_nodes[row] - S.node_base;
   const int ix = (int)(nid % S.nna[0]) - 1, iy = (int)(nid / S.nna[0]) - 1;
   double f0 = 0.0, f1 = 0.0, f2 = 0.0;
-  for (int oy = max(iy - 2, -1); oy <= min(iy, S.n[1] - 1); ++oy) {
-    const int ay = iy - oy;
-    for (int ox = max(ix - 2, -1); ox <= min(ix, S.n[0] - 1); ++ox) {
-      const int ax = ix - ox;
-      const int64_t key = S.okey_base + (ox + 1) + (int64_t)S.noa[0] * (oy + 1);
-      const int p1 = gstart[key + 1];
-      for (int p = gstart[key]; p < p1; ++p) {
-        const double* R = rec + (int64_t)p * RD2;
-        const double wx = R[8 + ax], dwx = R[11 + ax], wy = R[14 + ay], dwy = R[17 + ay];
-        const double ga0 = dwx * wy, ga1 = wx * dwy;
-        f0 += R[0] * ga0 + R[1] * ga1;
-        f1 += R[2] * ga0 + R[3] * ga1;
-        if (up) f2 += wx * wy * R[4] + ga0 * R[5] + ga1 * R[6];
-      }
+  const int oy = iy - 2 + q / 3, ox = ix - 2 + q % 3;
+  if (q < 9 && oy >= -1 && oy <= S.n[1] - 1 && ox >= -1 && ox <= S.n[0] - 1) {
+    const int ay = iy - oy, ax = ix - ox;
+    const int64_t key = S.okey_base + (ox + 1) + (int64_t)S.noa[0] * (oy + 1);
+    const int p1 = gstart[key + 1];
+    for (int p = gstart[key]; p < p1; ++p) {
+      const double* R = rec + (int64_t)p * RD2;
+      const double wx = R[8 + ax], dwx = R[11 + ax], wy = R[14 + ay], dwy = R[17 + ay];
+      const double ga0 = dwx * wy, ga1 = wx * dwy;
+      f0 += R[0] * ga0 + R[1] * ga1;
+      f1 += R[2] * ga0 + R[3] * ga1;
+      if (up) f2 += wx * wy * R[4] + ga0 * R[5] + ga1 * R[6];
     }
   }
-  fint[row * nd] = f0;
-  fint[row * nd + 1] = f1;
-  if (up) fint[row * nd + 2] = f2;
+#pragma unroll
+  for (int off = RL2 / 2; off > 0; off >>= 1) {
+    f0 += __shfl_xor(f0, off, RL2);
+    f1 += __shfl_xor(f1, off, RL2);
+    f2 += __shfl_xor(f2, off, RL2);
+  }
+  if (q == 0) {
+    fint[row * nd] = f0;
+    fint[row * nd + 1] = f1;
+    if (up) fint[row * nd + 2] = f2;
+  }
 }
 
 // ---------------------------------------------- group-cooperative 3-D ------
@@ -733,7 +743,7 @@ int launch_fint(mpm_ctx* c, const mpm_problem* pb, const double* du) {
       LAUNCH_CHECK(c, "k_fint2_rec");
     }
     if (c->n_row > 0) {
-      k_fint2_rows<<<(unsigned)((c->n_row + 255) / 256), 256, 0, c->stream>>>(
+      k_fint2_rows<<<(unsigned)((c->n_row * RL2 + 255) / 256), 256, 0, c->stream>>>(
           c->n_row, c->nd, c->up, c->active_nodes.p, c->row_sim.p, c->sims.p, c->gstart.p, c->rrec.p, c->fint.p);
       LAUNCH_CHECK(c, "k_fint2_rows");
     }

@@ -367,33 +367,43 @@ __global__ void k_fext2_rows(int64_t n_row, int nd, const int64_t* __restrict__ 
                              const double* __restrict__ vs, const double* __restrict__ fp_user,
                              const int32_t* __restrict__ perm, double rho0, double gx, double gy,
                              double* __restrict__ fext) {
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= n_row) return;
+  // 16 lanes per row: lane q < 9 sums the q-th stencil group that may hold
+  // the row's node, then a fixed butterfly over the 16 lane sums
+  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 16;
+  const int lq = (int)(threadIdx.x % 16);
+  if (row >= n_row) return;   // the row's 16 lanes leave together
   const SimDev& S = sims[row_sim[row]];
   const int64_t nid = active_nodes[row] - S.node_base;
   const int ix = (int)(nid % S.nna[0]) - 1, iy = (int)(nid / S.nna[0]) - 1;
   double f0 = 0.0, f1 = 0.0;
-  for (int oy = max(iy - 2, -1); oy <= min(iy, S.n[1] - 1); ++oy)
-    for (int ox = max(ix - 2, -1); ox <= min(ix, S.n[0] - 1); ++ox) {
-      const int64_t key = S.okey_base + (ox + 1) + (int64_t)S.noa[0] * (oy + 1);
-      const int p1 = gstart[key + 1];
-      for (int p = gstart[key]; p < p1; ++p) {
-        Stencil<2> st;
-        make_stencil<2>(S, xs, np, p, st);
-        const double w = st.w[0][ix - ox] * st.w[1][iy - oy];
-        const double m = rho0 * vs[p];
-        double fx = m * gx, fy = m * gy;
-        if (fp_user) {
-          const int64_t q = perm[p];
-          fx += fp_user[q];
-          fy += fp_user[np + q];
-        }
-        f0 += w * fx;
-        f1 += w * fy;
+  const int oy = iy - 2 + lq / 3, ox = ix - 2 + lq % 3;
+  if (lq < 9 && oy >= -1 && oy <= S.n[1] - 1 && ox >= -1 && ox <= S.n[0] - 1) {
+    const int64_t key = S.okey_base + (ox + 1) + (int64_t)S.noa[0] * (oy + 1);
+    const int p1 = gstart[key + 1];
+    for (int p = gstart[key]; p < p1; ++p) {
+      Stencil<2> st;
+      make_stencil<2>(S, xs, np, p, st);
+      const double w = st.w[0][ix - ox] * st.w[1][iy - oy];
+      const double m = rho0 * vs[p];
+      double fx = m * gx, fy = m * gy;
+      if (fp_user) {
+        const int64_t q = perm[p];
+        fx += fp_user[q];
+        fy += fp_user[np + q];
       }
+      f0 += w * fx;
+      f1 += w * fy;
     }
-  fext[row * nd] = f0;
-  fext[row * nd + 1] = f1;
+  }
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) {
+    f0 += __shfl_xor(f0, off, 16);
+    f1 += __shfl_xor(f1, off, 16);
+  }
+  if (lq == 0) {
+    fext[row * nd] = f0;
+    fext[row * nd + 1] = f1;
+  }
 }
 
 }  // namespace mpm
@@ -567,7 +577,7 @@ int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row_out, int6
       k_node_volume<2><<<nblk(np), TPB, 0, c->stream>>>(np, c->xs.p, c->vol0s.p, c->psim.p, c->sims.p, c->node_map.p,
                                                         c->nvol.p);
       if (!c->mg_level && n_row > 0)   // a multigrid level needs no external force
-        k_fext2_rows<<<nblk(n_row), TPB, 0, c->stream>>>(n_row, nd, c->active_nodes.p, c->row_sim.p, c->sims.p,
+        k_fext2_rows<<<nblk(n_row * 16), TPB, 0, c->stream>>>(n_row, nd, c->active_nodes.p, c->row_sim.p, c->sims.p,
                                                          c->gstart.p, np, c->xs.p, c->vol0s.p, pb->P.fp, c->perm.p,
                                                          pb->mat.rho0, pb->mat.g[0], pb->mat.g[1], c->fext.p);
     } else {
