@@ -315,48 +315,106 @@ __device__ __forceinline__ double sel3(int i, double v0, double v1, double v2) {
 }
 
 
-__global__ void __launch_bounds__(256) k_grp2(int64_t n_okeys, const int32_t* __restrict__ gstart,
-                                             const double* __restrict__ pdat, double* __restrict__ gbuf) {
-  const int64_t key = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
-  if (key >= n_okeys) return;
-  const int p0 = gstart[key], p1 = gstart[key + 1];
-  if (p0 == p1) return;   // empty origin: never read
-  const int lane = threadIdx.x % 64;
-  // blocks j = lane and j = lane + 64 (< 81); j = 9 a + b over local nodes a, b
-  const int j0 = lane, j1 = lane + 64;
-  const int a0 = j0 / 9, b0 = j0 % 9, a1 = (j1 < 81 ? j1 : 80) / 9, b1 = (j1 < 81 ? j1 : 80) % 9;
-  double K0[4] = {0.0, 0.0, 0.0, 0.0}, K1[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int p = p0; p < p1; ++p) {
-    const double* P = pdat + (int64_t)p * PD2;
-    double T[16], w[12];
+// Fused 2-D single-phase Jacobian from the tangent records: a workgroup of
+// JR rows with 16 lanes each.  Lane q < 9 of row a takes the q-th stencil
+// group that may hold node a and accumulates, over its particles in order,
+// the nine 2x2 blocks (a, b) for the group's local nodes b, into LDS.  Then
+// each BSR block (a, b) of the JR rows sums the groups holding both nodes,
+// in group order, and takes Dirichlet rows and columns as the identity's.
+// Every group block is formed once, as by a group-block pass followed by a
+// block gather, without the group blocks' round trip through HBM.
+constexpr int JR = 16;   // rows per workgroup (16 lanes each)
+__global__ void __launch_bounds__(256) k_jac2_rows(int64_t n_row, const int64_t* __restrict__ active_nodes,
+                                                  const int32_t* __restrict__ row_sim,
+                                                  const SimDev* __restrict__ sims,
+                                                  const int32_t* __restrict__ gstart,
+                                                  const double* __restrict__ pdat,
+                                                  const int32_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ colind,
+                                                  const uint8_t* __restrict__ cmask, double* __restrict__ val) {
+  __shared__ double part[JR][9][9 * 4];   // [row][group q][local node b][2x2]
+  const int rl = threadIdx.x / 16, q = threadIdx.x % 16;
+  const int64_t row0 = (int64_t)blockIdx.x * JR;
+  {
+    const int64_t row = row0 + rl;
+    if (row < n_row && q < 9) {
+      const SimDev& S = sims[row_sim[row]];
+      const int64_t nid = active_nodes[row] - S.node_base;
+      const int ix = (int)(nid % S.nna[0]) - 1, iy = (int)(nid / S.nna[0]) - 1;
+      const int oy = iy - 2 + q / 3, ox = ix - 2 + q % 3;
+      double K[9][4];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) T[k] = P[k];
+      for (int lb = 0; lb < 9; ++lb)
 #pragma unroll
-    for (int k = 0; k < 12; ++k) w[k] = P[16 + k];
-    // w: wx 0..2, dwx 3..5, wy 6..8, dwy 9..11; grad w_n = (dwx wy, wx dwy)
+        for (int e = 0; e < 4; ++e) K[lb][e] = 0.0;
+      if (oy >= -1 && oy <= S.n[1] - 1 && ox >= -1 && ox <= S.n[0] - 1) {
+        const int64_t key = S.okey_base + (ox + 1) + (int64_t)S.noa[0] * (oy + 1);
+        const int p1 = gstart[key + 1];
+        const int ax = ix - ox, ay = iy - oy;   // node a's place in the group's 3x3 stencil
+        for (int p = gstart[key]; p < p1; ++p) {
+          const double* P = pdat + (int64_t)p * PD2;
+          double T[16], w[12];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int a = h ? a1 : a0, b = h ? b1 : b0;
-      const int ax = a % 3, ay = a / 3, bx = b % 3, by = b / 3;
-      const double ga0 = sel3(ax, w[3], w[4], w[5]) * sel3(ay, w[6], w[7], w[8]);
-      const double ga1 = sel3(ax, w[0], w[1], w[2]) * sel3(ay, w[9], w[10], w[11]);
-      const double gb0 = sel3(bx, w[3], w[4], w[5]) * sel3(by, w[6], w[7], w[8]);
-      const double gb1 = sel3(bx, w[0], w[1], w[2]) * sel3(by, w[9], w[10], w[11]);
-      double* K = h ? K1 : K0;
+          for (int k = 0; k < 16; ++k) T[k] = P[k];
 #pragma unroll
-      for (int r = 0; r < 2; ++r)
+          for (int k = 0; k < 12; ++k) w[k] = P[16 + k];
+          // w: wx 0..2, dwx 3..5, wy 6..8, dwy 9..11; grad w_n = (dwx wy, wx dwy)
+          const double ga0 = sel3(ax, w[3], w[4], w[5]) * sel3(ay, w[6], w[7], w[8]);
+          const double ga1 = sel3(ax, w[0], w[1], w[2]) * sel3(ay, w[9], w[10], w[11]);
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
-          K[r * 2 + c] += ga0 * (T[(2 * r) * 4 + 2 * c] * gb0 + T[(2 * r) * 4 + 2 * c + 1] * gb1) +
-                          ga1 * (T[(2 * r + 1) * 4 + 2 * c] * gb0 + T[(2 * r + 1) * 4 + 2 * c + 1] * gb1);
+          for (int lb = 0; lb < 9; ++lb) {
+            const int bx = lb % 3, by = lb / 3;
+            const double gb0 = w[3 + bx] * w[6 + by];
+            const double gb1 = w[bx] * w[9 + by];
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+              for (int c = 0; c < 2; ++c)
+                K[lb][r * 2 + c] += ga0 * (T[(2 * r) * 4 + 2 * c] * gb0 + T[(2 * r) * 4 + 2 * c + 1] * gb1) +
+                                    ga1 * (T[(2 * r + 1) * 4 + 2 * c] * gb0 + T[(2 * r + 1) * 4 + 2 * c + 1] * gb1);
+          }
+        }
+      }
+#pragma unroll
+      for (int lb = 0; lb < 9; ++lb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) part[rl][q][lb * 4 + e] = K[lb][e];
     }
   }
-  double* G = gbuf + key * GB2;
+  __syncthreads();
+  // BSR blocks of the JR rows: 32 slots per row (at most 25 used)
+  for (int t = threadIdx.x; t < JR * 32; t += 256) {
+    const int r2 = t / 32;
+    const int64_t row = row0 + r2;
+    if (row >= n_row) continue;
+    const int k = rowptr[row] + t % 32;
+    if (k >= rowptr[row + 1]) continue;
+    const SimDev& S = sims[row_sim[row]];
+    const int64_t na = active_nodes[row] - S.node_base, nb = active_nodes[colind[k]] - S.node_base;
+    const int ix = (int)(na % S.nna[0]) - 1, iy = (int)(na / S.nna[0]) - 1;
+    const int jx = (int)(nb % S.nna[0]) - 1, jy = (int)(nb / S.nna[0]) - 1;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int oy0 = max(max(iy, jy) - 2, -1), oy1 = min(min(iy, jy), S.n[1] - 1);
+    const int ox0 = max(max(ix, jx) - 2, -1), ox1 = min(min(ix, jx), S.n[0] - 1);
+    for (int oy = oy0; oy <= oy1; ++oy)
+      for (int ox = ox0; ox <= ox1; ++ox) {
+        const int qq = (oy - (iy - 2)) * 3 + (ox - (ix - 2));
+        const int lb = (jx - ox) + 3 * (jy - oy);
 #pragma unroll
-  for (int e = 0; e < 4; ++e) G[j0 * 4 + e] = K0[e];
-  if (j1 < 81)
+        for (int e = 0; e < 4; ++e) acc[e] += part[r2][qq][lb * 4 + e];
+      }
+    if (cmask) {
+      const int64_t col = colind[k];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) G[j1 * 4 + e] = K1[e];
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          if (cmask[row * 2 + i] || cmask[col * 2 + j]) acc[i * 2 + j] = (row == col && i == j) ? 1.0 : 0.0;
+    }
+    double* blk = val + (int64_t)k * 4;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) blk[e] = acc[e];
+  }
 }
 
 // 32 lanes per BSR row (two rows per wave); lane k < row length owns slot k.
@@ -781,17 +839,17 @@ int sim_sum_launch(mpm_ctx* c, const double* part, int q, int off) {
   return MPM_OK;
 }
 
-// Group blocks and BSR blocks from the particle records already in c->pdat
-// (2-D single-phase); apply_bc writes constrained rows and columns as the
+// BSR blocks from the particle records already in c->pdat (2-D
+// single-phase); apply_bc writes constrained rows and columns as the
 // identity's.
 int launch_jac2_records(mpm_ctx* c, double* val, bool apply_bc) {
-  if (c->gbuf.ensure(std::max<int64_t>(1, c->n_okeys) * GB2) != hipSuccess)
-    return c->fail(MPM_E_NOMEM, "group block buffer allocation failed");
-  if (c->n_okeys > 0) {
-    k_grp2<<<(unsigned)((c->n_okeys + 3) / 4), 256, 0, c->stream>>>(c->n_okeys, c->gstart.p, c->pdat.p, c->gbuf.p);
-    LAUNCH_CHECK(c, "k_grp2");
+  if (c->n_row > 0) {
+    k_jac2_rows<<<(unsigned)((c->n_row + JR - 1) / JR), 256, 0, c->stream>>>(
+        c->n_row, c->active_nodes.p, c->row_sim.p, c->sims.p, c->gstart.p, c->pdat.p, c->rowptr.p, c->colind.p,
+        apply_bc ? c->cmask.p : nullptr, val);
+    LAUNCH_CHECK(c, "k_jac2_rows");
   }
-  return launch_jac2_blocks(c, val, apply_bc);
+  return MPM_OK;
 }
 
 // BSR blocks from the group blocks already in c->gbuf.
