@@ -181,6 +181,7 @@ struct mpm_ctx {
   mpm::DBuf<int32_t> mg_tab;                   // tail transfer tables (restriction 9, prolongation 4 per row)
   mpm::DBuf<double> mg_tabw;                   // tail prolongation weights
   std::vector<int64_t> mg_tab_off;             // per tail level: rtab, ptab, pw offsets (-1: none)
+  std::vector<int64_t> mg_lvl_off;             // per level: rtab, ptab, pw offsets in mg_tab / mg_tabw (-1: none)
   int mg_tail_lds = 0;                         // bytes of LDS the tail kernel uses
 
   int fail(int code, const std::string& msg) { err = msg; return code; }

@@ -178,6 +178,79 @@ __global__ void __launch_bounds__(ROWS_PER_BLOCK * LPR) k_mg_sweep(
     mg_sweep_row<LPR>(row, lane, rowptr, colind, val, dinv, b, x_in, x_out, omega, mode);
 }
 
+// The first post-smoothing sweep with the prolongation folded in: every
+// value of the iterate it reads is x_in + P x_c (unconstrained unknowns),
+// formed from the per-row prolongation table in the terms and order of the
+// prolongation itself; then mode 1 of mg_sweep_row on those values.
+__device__ __forceinline__ void mg_prolonged(int64_t r, const int32_t* __restrict__ ptab,
+                                             const double* __restrict__ pw, const double* __restrict__ xc,
+                                             const uint8_t* __restrict__ cmask, const double* __restrict__ x_in,
+                                             double& x0, double& x1) {
+  const int32_t* tab = ptab + r * 4;
+  const double w = pw[r];
+  double a0 = 0.0, a1 = 0.0;
+  for (int q = 0; q < 4; ++q) {
+    const int32_t cr = tab[q];
+    if (cr < 0) break;
+    a0 = fma(w, xc[(int64_t)cr * 2], a0);
+    a1 = fma(w, xc[(int64_t)cr * 2 + 1], a1);
+  }
+  x0 = x_in[r * 2];
+  x1 = x_in[r * 2 + 1];
+  if (!cmask[r * 2]) x0 += a0;
+  if (!cmask[r * 2 + 1]) x1 += a1;
+}
+
+template <int LPR>
+__global__ void __launch_bounds__(ROWS_PER_BLOCK * LPR) k_mg_sweep_p(
+    const RowBlock* __restrict__ blocks, const int32_t* __restrict__ simflag, const int32_t* __restrict__ rowptr,
+    const int32_t* __restrict__ colind, const double* __restrict__ val, const double* __restrict__ dinv,
+    const double* __restrict__ b, const double* __restrict__ x_in, double* __restrict__ x_out, double omega,
+    const int32_t* __restrict__ ptab, const double* __restrict__ pw, const double* __restrict__ xc,
+    const uint8_t* __restrict__ cmask) {
+  const RowBlock B = blocks[blockIdx.x];
+  if (simflag && simflag[2 * B.sim] >= 0) return;
+  constexpr int VL = 8, NA = VL / LPR;
+  const int lane = threadIdx.x % LPR, grp = threadIdx.x / LPR;
+  for (int row = B.row0 + grp; row < B.row1; row += ROWS_PER_BLOCK) {
+    double p0[NA], p1[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) p0[a] = p1[a] = 0.0;
+    const int k1 = rowptr[row + 1];
+    for (int k0 = rowptr[row] + lane; k0 < k1; k0 += VL) {
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        const int k = k0 + a * LPR;
+        if (k < k1) {
+          const double* blk = val + (int64_t)k * 4;
+          double x0, x1;
+          mg_prolonged(colind[k], ptab, pw, xc, cmask, x_in, x0, x1);
+          p0[a] = p0[a] + dot2(blk[0], x0, blk[1], x1);
+          p1[a] = p1[a] + dot2(blk[2], x0, blk[3], x1);
+        }
+      }
+    }
+#pragma unroll
+    for (int m = NA / 2; m > 0; m >>= 1)
+#pragma unroll
+      for (int a = 0; a < m; ++a) { p0[a] += p0[a + m]; p1[a] += p1[a + m]; }
+    double a0 = p0[0], a1 = p1[0];
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) {
+      a0 += __shfl_xor(a0, off, LPR);
+      a1 += __shfl_xor(a1, off, LPR);
+    }
+    if (lane == 0) {
+      const double r0 = b[(int64_t)row * 2] - a0, r1 = b[(int64_t)row * 2 + 1] - a1;
+      const double* D = dinv + (int64_t)row * 4;
+      double base0, base1;
+      mg_prolonged(row, ptab, pw, xc, cmask, x_in, base0, base1);
+      x_out[(int64_t)row * 2] = fma(omega, dot2(D[0], r0, D[1], r1), base0);
+      x_out[(int64_t)row * 2 + 1] = fma(omega, dot2(D[2], r0, D[3], r1), base1);
+    }
+  }
+}
+
 // b_c = R r_f on coarse row R of sim s (R = transpose of the linear
 // interpolation); constrained coarse unknowns get 0.
 __device__ __forceinline__ void mg_restrict_row(int64_t R, int s, const int64_t* __restrict__ c_active,
@@ -875,12 +948,41 @@ int mg_build(mpm_ctx* c, const mpm_problem* pb) {
     for (int s = 0; s < nsim; ++s) mx = std::max<int64_t>(mx, L->sim_row_start[s + 1] - L->sim_row_start[s]);
     if (mx <= MG_TAIL_ROWS) c->mg_tail_first = (int)l;
   }
+  // transfer tables of every level (restriction on the coarse side,
+  // prolongation on the fine side): per level rtab, ptab, pw offsets
+  {
+    std::vector<int64_t> toff(3 * (nl + 1), -1);
+    int64_t ntab = 0, nw = 0;
+    for (size_t l = 0; l <= nl; ++l) {
+      const mpm_ctx* L = l == 0 ? c : c->mgl[l - 1]->sub;
+      if (l >= 1) { toff[3 * l] = ntab; ntab += L->n_row * 9; }
+      if (l < nl) { toff[3 * l + 1] = ntab; ntab += L->n_row * 4; toff[3 * l + 2] = nw; nw += L->n_row; }
+    }
+    if (c->mg_tab.ensure(std::max<int64_t>(1, ntab)) != hipSuccess || c->mg_tabw.ensure(std::max<int64_t>(1, nw)) != hipSuccess)
+      return c->fail(MPM_E_NOMEM, "multigrid table allocation failed");
+    for (size_t l = 0; l <= nl; ++l) {
+      const mpm_ctx* L = l == 0 ? c : c->mgl[l - 1]->sub;
+      if (l >= 1 && L->n_row) {
+        const mpm_ctx* Fn = l - 1 == 0 ? c : c->mgl[l - 2]->sub;
+        k_mg_rtab<<<nb256(L->n_row), 256, 0, c->stream>>>(L->n_row, L->active_nodes.p, L->row_sim.p, L->sims.p,
+                                                         Fn->sims.p, Fn->node_map.p, c->mg_tab.p + toff[3 * l]);
+        LAUNCH_CHECK(c, "k_mg_rtab");
+      }
+      if (l < nl && L->n_row) {
+        const mpm_ctx* Cn = c->mgl[l]->sub;
+        k_mg_ptab<<<nb256(L->n_row), 256, 0, c->stream>>>(L->n_row, L->active_nodes.p, L->row_sim.p, L->sims.p,
+                                                         Cn->sims.p, Cn->node_map.p, c->mg_tab.p + toff[3 * l + 1],
+                                                         c->mg_tabw.p + toff[3 * l + 2]);
+        LAUNCH_CHECK(c, "k_mg_ptab");
+      }
+    }
+    c->mg_lvl_off = toff;
+  }
   if (c->mg_tail_first >= 0) {
-    // LDS layout (four vectors per level, sized for the largest sim) and
-    // the transfer tables of the tail levels
+    // LDS layout of the tail: four vectors per level, sized for the largest sim
     const size_t first = (size_t)c->mg_tail_first;
     std::vector<int64_t> off;
-    int64_t lds = 0, ntab = 0, nw = 0;
+    int64_t lds = 0;
     for (size_t l = first; l <= nl; ++l) {
       const mpm_ctx* L = l == 0 ? c : c->mgl[l - 1]->sub;
       int64_t mx = 0;
@@ -888,37 +990,17 @@ int mg_build(mpm_ctx* c, const mpm_problem* pb) {
       off.push_back(lds);
       off.push_back(2 * mx);
       lds += 4 * 2 * mx;
-      off.push_back(l > first ? ntab : -1);          // rtab (coarse side)
-      if (l > first) ntab += L->n_row * 9;
-      off.push_back(l < nl ? ntab : -1);             // ptab (fine side)
-      off.push_back(l < nl ? nw : -1);               // pw
-      if (l < nl) { ntab += L->n_row * 4; nw += L->n_row; }
+      off.push_back(l > first ? c->mg_lvl_off[3 * l] : -1);   // rtab (coarse side, within the tail)
+      off.push_back(c->mg_lvl_off[3 * l + 1]);                 // ptab (fine side)
+      off.push_back(c->mg_lvl_off[3 * l + 2]);                 // pw
     }
     if (lds * (int64_t)sizeof(double) > MG_TAIL_LDS_MAX) {
       c->mg_tail_first = -1;   // too large for one workgroup's LDS: level-by-level launches
     } else {
       c->mg_tab_off = off;
       c->mg_tail_lds = (int)(lds * sizeof(double));
-      if (c->mg_tail.ensure(nl - first + 1) != hipSuccess || c->mg_tab.ensure(std::max<int64_t>(1, ntab)) != hipSuccess ||
-          c->mg_tabw.ensure(std::max<int64_t>(1, nw)) != hipSuccess)
+      if (c->mg_tail.ensure(nl - first + 1) != hipSuccess)
         return c->fail(MPM_E_NOMEM, "multigrid tail allocation failed");
-      for (size_t l = first; l <= nl; ++l) {
-        const mpm_ctx* L = l == 0 ? c : c->mgl[l - 1]->sub;
-        const int64_t* o = &off[(l - first) * 5];
-        if (l > first && L->n_row) {
-          const mpm_ctx* Fn = l - 1 == 0 ? c : c->mgl[l - 2]->sub;
-          k_mg_rtab<<<nb256(L->n_row), 256, 0, c->stream>>>(L->n_row, L->active_nodes.p, L->row_sim.p, L->sims.p,
-                                                           Fn->sims.p, Fn->node_map.p, c->mg_tab.p + o[2]);
-          LAUNCH_CHECK(c, "k_mg_rtab");
-        }
-        if (l < nl && L->n_row) {
-          const mpm_ctx* Cn = c->mgl[l]->sub;
-          k_mg_ptab<<<nb256(L->n_row), 256, 0, c->stream>>>(L->n_row, L->active_nodes.p, L->row_sim.p, L->sims.p,
-                                                           Cn->sims.p, Cn->node_map.p, c->mg_tab.p + o[3],
-                                                           c->mg_tabw.p + o[4]);
-          LAUNCH_CHECK(c, "k_mg_ptab");
-        }
-      }
     }
   }
   // coarsest: dense per sim
@@ -1076,13 +1158,25 @@ static int vcycle(mpm_ctx* c, size_t l, const double* b, double* out) {
     LAUNCH_CHECK(c, "k_mg_restrict");
   }
   GUARD(vcycle(c, l + 1, bc, xc));
-  if (ctx->n_row) {
+  int k_post = 0;
+  if (c->mg_fuse && MG_NU2 >= 1 && l >= 1) {   // prolongation folded into the first post-smoothing sweep
+    // (coarse levels only: on the finest the per-neighbour table reads cost more than the launch)
+    const unsigned nbk = (unsigned)ctx->blocks_h.size();
+    if (nbk) {
+      k_mg_sweep_p<8><<<nbk, ROWS_PER_BLOCK * 8, 0, c->lstream>>>(
+          ctx->blocks.p, c->simflag.p, ctx->rowptr.p, ctx->colind.p, V.val, V.dinv, b, xa, xb, MG_OMEGA,
+          c->mg_tab.p + c->mg_lvl_off[3 * l + 1], c->mg_tabw.p + c->mg_lvl_off[3 * l + 2], xc, ctx->cmask.p);
+      LAUNCH_CHECK(c, "k_mg_sweep_p");
+    }
+    std::swap(xa, xb);
+    k_post = 1;
+  } else if (ctx->n_row) {
     k_mg_prolong<<<nb256(ctx->n_row), 256, 0, c->lstream>>>(ctx->n_row, ctx->active_nodes.p, ctx->row_sim.p,
                                                            ctx->sims.p, C->sims.p, C->node_map.p, xc,
                                                            ctx->cmask.p, xa);
     LAUNCH_CHECK(c, "k_mg_prolong");
   }
-  for (int k = 0; k < MG_NU2; ++k) { GUARD(sweep(c, V, b, xa, xb, 1)); std::swap(xa, xb); }
+  for (int k = k_post; k < MG_NU2; ++k) { GUARD(sweep(c, V, b, xa, xb, 1)); std::swap(xa, xb); }
   if (xa != out) return c->fail(MPM_E_INVALID, "multigrid sweep parity");   // excluded by the choice of xa above
   return MPM_OK;
 }
