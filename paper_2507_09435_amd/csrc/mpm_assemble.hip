@@ -361,6 +361,16 @@ __global__ void __launch_bounds__(256) k_jac2_rows(int64_t n_row, const int64_t*
           // w: wx 0..2, dwx 3..5, wy 6..8, dwy 9..11; grad w_n = (dwx wy, wx dwy)
           const double ga0 = sel3(ax, w[3], w[4], w[5]) * sel3(ay, w[6], w[7], w[8]);
           const double ga1 = sel3(ax, w[0], w[1], w[2]) * sel3(ay, w[9], w[10], w[11]);
+          // K_ab[r][c] = sum_ij ga_i T[(2r+i)4 + 2c+j] gb_j: contract node a's side once,
+          // U[r][c][j] = sum_i ga_i T[(2r+i)4 + 2c+j], then two fma per entry and node b
+          double U[2][2][2];
+#pragma unroll
+          for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+              for (int j = 0; j < 2; ++j)
+                U[r][c][j] = fma(ga1, T[(2 * r + 1) * 4 + 2 * c + j], ga0 * T[(2 * r) * 4 + 2 * c + j]);
 #pragma unroll
           for (int lb = 0; lb < 9; ++lb) {
             const int bx = lb % 3, by = lb / 3;
@@ -370,8 +380,7 @@ __global__ void __launch_bounds__(256) k_jac2_rows(int64_t n_row, const int64_t*
             for (int r = 0; r < 2; ++r)
 #pragma unroll
               for (int c = 0; c < 2; ++c)
-                K[lb][r * 2 + c] += ga0 * (T[(2 * r) * 4 + 2 * c] * gb0 + T[(2 * r) * 4 + 2 * c + 1] * gb1) +
-                                    ga1 * (T[(2 * r + 1) * 4 + 2 * c] * gb0 + T[(2 * r + 1) * 4 + 2 * c + 1] * gb1);
+                K[lb][r * 2 + c] = fma(U[r][c][1], gb1, fma(U[r][c][0], gb0, K[lb][r * 2 + c]));
           }
         }
       }
