@@ -76,6 +76,9 @@ def main():
     ap.add_argument("--c5-fd-steps", type=int, default=10)
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only the SpMV launches and a plain copy of known size, for counter passes")
+    ap.add_argument("--c3-probe", action="store_true",
+                    help="the 128^3 footing cube: one residual, one Jacobian and timed BSR SpMV launches "
+                         "(the HBM-bound regime of the SpMV), one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU layout is a design "
@@ -92,6 +95,9 @@ def main():
         return
     if args.c5_full:
         print(json.dumps(c5_full(M, W, torch, args)))
+        return
+    if args.c3_probe:
+        print(json.dumps(c3_probe(M, W, torch)))
         return
 
     w = W.make_c2(n_steps=1)
@@ -328,6 +334,59 @@ def c5_full(M, W, torch, args):
                                                "fd": float(fd_E[eE.argmax()])},
                                    "worst_phi": {"sim": int(ep.argmax()), "adjoint": float(gphi[ep.argmax()]),
                                                  "fd": float(fd_phi[ep.argmax()])}}}
+
+
+def c3_probe(M, W, torch):
+    """The 3-D footing cube (128^3 cells, 8388608 particles, geostatic
+    load): residual and Jacobian at du = 0 timed with HIP events, then 50
+    back-to-back in-loop SpMV launches (product plus the fused partial dot
+    products) on that Jacobian, timed the same way.  The 10.6 GB matrix
+    streams from HBM on every launch."""
+    w = W.make_c3()
+    P = w.prob
+    stream = torch.cuda.current_stream()
+    ctx = M.mpm_create(0, stream.cuda_stream)
+    dp = M.make_problem([(P, w.particles)], [w.bc(0)])
+    t0 = time.perf_counter()
+    n_row, nnzb, nd = M.mpm_prepare(ctx, dp)
+    torch.cuda.synchronize()
+    t_prep = time.perf_counter() - t0
+    du = torch.zeros(n_row * nd, dtype=torch.float64, device="cuda")
+    r = torch.zeros_like(du)
+    val = torch.zeros(nnzb * nd * nd, dtype=torch.float64, device="cuda")
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    M.mpm_residual(ctx, dp, du, r)        # warm-up of both assemblies
+    M.mpm_jacobian_bsr(ctx, dp, du, val=val)
+    e[0].record(stream)
+    M.mpm_residual(ctx, dp, du, r)
+    e[1].record(stream)
+    M.mpm_jacobian_bsr(ctx, dp, du, val=val)
+    e[2].record(stream)
+    xv = torch.randn(n_row * nd, dtype=torch.float64, device="cuda")
+    zv = torch.randn_like(xv)
+    yv = torch.empty_like(xv)
+    for _ in range(5):
+        M.mpm_spmv(ctx, val, xv, yv, zv)
+    nrep = 50
+    e[3].record(stream)
+    for _ in range(nrep):
+        M.mpm_spmv(ctx, val, xv, yv, zv)
+    e[4].record(stream)
+    e[4].synchronize()
+    spmv_ms = e[3].elapsed_time(e[4]) / nrep
+    lanes = M.mpm_spmv_lanes(ctx)
+    nbytes = spmv_bytes(n_row, nnzb, nd)
+    achieved = nbytes / (spmv_ms * 1e-3) / 1e9
+    M.mpm_destroy(ctx)
+    return {"workload": "3D footing cube 128^3 cells, 8388608 particles, friction U[25,35] deg per particle, "
+                        "geostatic load, du = 0",
+            "particles": w.particles.np, "rows": n_row, "bsr_blocks": nnzb, "block": nd,
+            "prepare_s": round(t_prep, 3),
+            "ms_residual": round(e[0].elapsed_time(e[1]), 3), "ms_jacobian": round(e[1].elapsed_time(e[2]), 3),
+            "spmv": {"kernel": f"k_spmv<3,{lanes}>", "bound": "hbm", "avg_launch_ms": round(spmv_ms, 4),
+                     "timed_launches": nrep, "algorithmic_bytes_per_launch": nbytes,
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4)}}
 
 
 def pmc_probe(M, W, torch):
