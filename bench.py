@@ -147,29 +147,38 @@ def main():
     value = npart / (t_asm_ms * 1e-3) / 1e6
     newton_ms = sum(r["ms_total"] for r in reps) / max(n_jac, 1)
 
-    # dominant kernel: the BSR SpMV of the Krylov loop.  Its average duration
-    # is taken with HIP events on the library's stream around 200 back-to-back
-    # launches of the same kernel doing the same work as inside BiCGStab
-    # (product plus the fused z.y and y.y partial sums) on the converged
-    # Jacobian; a sample of in-loop launches is reported beside it.
+    # roofline kernel: the BSR SpMV of the Krylov loop, the path's HBM-bound
+    # kernel (the multigrid sweeps take more of the time, bound by launch
+    # latency on the coarse levels).  Its average duration is taken with HIP
+    # events on the library's stream around 200 back-to-back launches of the
+    # same kernel doing the same work as inside BiCGStab (product plus the
+    # fused z.y and y.y partial sums) on the converged Jacobian; a sample of
+    # in-loop launches is reported beside it.
     n_row, nnzb, nd = shape
     val = torch.zeros(nnzb * nd * nd, dtype=torch.float64, device="cuda")
     M.mpm_jacobian_bsr(ctx, dp, du, val=val)
     xv = torch.randn(n_row * nd, dtype=torch.float64, device="cuda")
     zv = torch.randn_like(xv)
     yv = torch.empty_like(xv)
-    for _ in range(10):
-        M.mpm_spmv(ctx, val, xv, yv, zv)
-    nrep = 200
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(nrep):
-        M.mpm_spmv(ctx, val, xv, yv, zv)
-    e1.record(stream)
-    e1.synchronize()
-    spmv_us = e0.elapsed_time(e1) * 1e3 / nrep
+    # the autotuner's launch shape for this pattern, then every shape pinned in
+    # turn (the same arithmetic): 200 timed launches each after 10 untimed
     lanes = M.mpm_spmv_lanes(ctx)
+    nrep = 200
+    by_shape = {}
+    for lpr in (4, 8, 16):
+        M.mpm_spmv_set_lanes(ctx, lpr)
+        for _ in range(10):
+            M.mpm_spmv(ctx, val, xv, yv, zv)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(nrep):
+            M.mpm_spmv(ctx, val, xv, yv, zv)
+        e1.record(stream)
+        e1.synchronize()
+        by_shape[lpr] = e0.elapsed_time(e1) * 1e3 / nrep
+    M.mpm_spmv_set_lanes(ctx, 0)
+    spmv_us = by_shape[lanes]
     loop_ms = sum(r["spmv_ms"] for r in reps)
     loop_n = sum(r["spmv_launches"] for r in reps)
     nbytes = spmv_bytes(n_row, nnzb, nd)
@@ -205,6 +214,7 @@ def main():
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": spmv_traffic(lanes),
                      "avg_launch_us": round(spmv_us, 3), "timed_launches": nrep,
+                     "avg_launch_us_by_lanes_per_row": {str(k): round(v, 3) for k, v in by_shape.items()},
                      "in_loop_event_us": round(loop_ms * 1e3 / max(loop_n, 1), 3),
                      "algorithmic_bytes_per_launch": nbytes},
     }

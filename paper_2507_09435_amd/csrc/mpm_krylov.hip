@@ -137,7 +137,13 @@ __global__ void __launch_bounds__(ROWS_PER_BLOCK * LPR) k_spmv(const RowBlock* _
                                               const double* __restrict__ val, const double* __restrict__ x,
                                               double* __restrict__ y, const double* __restrict__ z1,
                                               double* __restrict__ part, int q1, int q2) {
-  const RowBlock b = blocks[blockIdx.x];
+  // Workgroups are dealt to the 8 XCDs in turn (workgroup i to XCD i mod 8),
+  // each with its own L2.  Give XCD x the x-th contiguous eighth of the row
+  // blocks, so the neighbouring rows that share entries of x meet in one L2.
+  const unsigned nwg = gridDim.x, xcd = blockIdx.x % 8, kq = blockIdx.x / 8;
+  const unsigned q8 = nwg / 8, r8 = nwg % 8;
+  const unsigned lbk = xcd * q8 + min(xcd, r8) + kq;   // a bijection of [0, nwg)
+  const RowBlock b = blocks[lbk];
   if (simflag && simflag[2 * b.sim] >= 0) return;
   constexpr int G = ROWS_PER_BLOCK;   // one LPR-lane group per row: the whole block in flight at once
   // The arithmetic does not depend on LPR: block k of a row (counted from
@@ -222,8 +228,8 @@ __global__ void __launch_bounds__(ROWS_PER_BLOCK * LPR) k_spmv(const RowBlock* _
     const double s1 = wave_sum(sh[0][threadIdx.x]);
     const double s2 = wave_sum(sh[1][threadIdx.x]);
     if (threadIdx.x == 0) {
-      if (q1 >= 0) part[blockIdx.x * NQ + q1] = s1;
-      if (q2 >= 0) part[blockIdx.x * NQ + q2] = s2;
+      if (q1 >= 0) part[lbk * NQ + q1] = s1;
+      if (q2 >= 0) part[lbk * NQ + q2] = s2;
     }
   }
 }
