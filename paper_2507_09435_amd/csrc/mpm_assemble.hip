@@ -598,95 +598,135 @@ __global__ void __launch_bounds__(GP3) k_fint3g(AsmArgs A, const double* __restr
   }
 }
 
-// 3-D Jacobian: nine forward passes per particle give its tangent table
-// (V0 dP_ij/d dF_ml) staged in LDS; one task per (group, node b, slab of a)
-// accumulates 9 blocks of 3x3 in registers.
-__global__ void __launch_bounds__(GP3) k_jac3g(AsmArgs A, const double* __restrict__ du,
-                                              const int32_t* __restrict__ rowptr, const int8_t* __restrict__ slot,
-                                              double* __restrict__ val, int32_t* __restrict__ flag) {
-  __shared__ double sT[GP3][81];
-  __shared__ double sW[GP3][3][3], sD[GP3][3][3];
-  __shared__ int32_t sKey[GP3], sRow[GP3][27], sG[GP3 + 1], sWc[GP3 / 64];
-  const int64_t base = (int64_t)blockIdx.x * GP3;
-  const int n = (int)min<int64_t>(GP3, A.np - base);
-  const int t = threadIdx.x;
-  if (t < n) {
-    const int64_t i = base + t;
-    PLoad<3> L;
-    load_particle<3>(A, i, du, L);
-    Mat<dnum> m = make_mat<dnum>(dnum(L.E), A.nu, dnum(L.phi), A.c, A.psi, A.dp, A.match, A.apex_reg);
-    Sym3<double> be = load_be3(A, i);
-    int rerr = 0;
-    for (int q = 0; q < 9; ++q) {
-      dnum F[3][3];
+// 3-D Jacobian without atomics.  k_tan3: one thread per particle writes its
+// tangent table (V0 dP/dF, 81 entries, from 9 forward passes) and its
+// stencil weights and derivatives to a record.  k_jac3c: stencil groups of
+// one colour (origin index mod 3 per axis) hold pairwise disjoint node sets,
+// so one workgroup per group adds its 729 3x3 blocks with plain
+// read-modify-writes; the 27 colours run in a fixed order, every group's
+// particles in order, so the result is deterministic.
+constexpr int PD3 = 100;   // doubles per 3-D record: T 0..80 ((r*3+c)*9 + q), w 81..89 [axis][a], dw 90..98
+constexpr int JC3 = 32;    // records staged in LDS at a time
+
+__global__ void __launch_bounds__(GP3) k_tan3(AsmArgs A, const double* __restrict__ du, double* __restrict__ rec,
+                                              int32_t* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * GP3 + threadIdx.x;
+  if (i >= A.np) return;
+  PLoad<3> L;
+  load_particle<3>(A, i, du, L);
+  Mat<dnum> m = make_mat<dnum>(dnum(L.E), A.nu, dnum(L.phi), A.c, A.psi, A.dp, A.match, A.apex_reg);
+  Sym3<double> be = load_be3(A, i);
+  double* R = rec + i * PD3;
+  int rerr = 0;
+  for (int q = 0; q < 9; ++q) {
+    dnum F[3][3];
 #pragma unroll
-      for (int r = 0; r < 3; ++r)
+    for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) F[r][c] = dnum(L.dF[r][c], q == r * 3 + c ? 1.0 : 0.0);
-      Sym3<dnum> bd;
+      for (int c = 0; c < 3; ++c) F[r][c] = dnum(L.dF[r][c], q == r * 3 + c ? 1.0 : 0.0);
+    Sym3<dnum> bd;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) bd.a[k] = dnum(be.a[k]);
-      Out3<dnum> o;
-      mech3<dnum>(m, F, bd, o, nullptr, &rerr);
+    for (int k = 0; k < 6; ++k) bd.a[k] = dnum(be.a[k]);
+    Out3<dnum> o;
+    mech3<dnum>(m, F, bd, o, nullptr, &rerr);
 #pragma unroll
-      for (int r = 0; r < 3; ++r)
+    for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) sT[t][(r * 3 + c) * 9 + q] = L.v0 * o.P[r][c].d;
-    }
-    if (rerr) atomicOr(flag, 4);
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) { sW[t][k][a] = L.st.w[k][a]; sD[t][k][a] = L.st.dw[k][a]; }
-    for (int a = 0; a < 27; ++a) sRow[t][a] = L.row[a];
-    sKey[t] = origin_key3(A.sims[A.psim[i]], L.st);
+      for (int c = 0; c < 3; ++c) R[(r * 3 + c) * 9 + q] = L.v0 * o.P[r][c].d;
   }
-  __syncthreads();
-  const int G = group_starts(sKey, n, sG, sWc);
-  for (int task = t; task < 81 * G; task += GP3) {
-    const int g = task / 81, rem = task % 81, b = rem / 3, az = rem % 3;
-    const int bx = b % 3, by = (b / 3) % 3, bz = b / 9;
-    double acc[9][3][3];
+  if (rerr) atomicOr(flag, 4);
 #pragma unroll
-    for (int a = 0; a < 9; ++a)
+  for (int k = 0; k < 3; ++k)
 #pragma unroll
-      for (int r = 0; r < 3; ++r)
+    for (int a = 0; a < 3; ++a) {
+      R[81 + k * 3 + a] = L.st.w[k][a];
+      R[90 + k * 3 + a] = L.st.dw[k][a];
+    }
+}
+
+// Origins of colour (cx, cy, cz) along one axis: v = o + 1 in [0, n] with v = c mod 3.
+__device__ __host__ __forceinline__ int colour_count(int n, int c) { return c > n ? 0 : (n - c) / 3 + 1; }
+
+constexpr int JC3T = 256;   // threads: task t < 243 is (column node b, z-layer of a, block row r)
+__global__ void __launch_bounds__(JC3T) k_jac3c(int colour, const int64_t* __restrict__ wstart, int nsim,
+                                                const SimDev* __restrict__ sims, const int32_t* __restrict__ gstart,
+                                                const int32_t* __restrict__ node_map, const double* __restrict__ rec,
+                                                const int32_t* __restrict__ rowptr, const int8_t* __restrict__ slot,
+                                                double* __restrict__ val) {
+  __shared__ double sT[JC3][81];
+  __shared__ double sW[JC3][3][3], sD[JC3][3][3];
+  __shared__ int32_t sRow[27];
+  const int64_t w = blockIdx.x;
+  int s = 0;
+  while (s + 1 < nsim && wstart[s + 1] <= w) ++s;   // workgroup-uniform
+  const SimDev& S = sims[s];
+  const int cx = colour % 3, cy = (colour / 3) % 3, cz = colour / 9;
+  const int nx = colour_count(S.n[0], cx), ny = colour_count(S.n[1], cy);
+  const int64_t loc = w - wstart[s];
+  const int ox = cx + 3 * (int)(loc % nx) - 1, oy = cy + 3 * (int)((loc / nx) % ny) - 1,
+            oz = cz + 3 * (int)(loc / ((int64_t)nx * ny)) - 1;
+  const int64_t key = S.okey_base + (ox + 1) + (int64_t)S.noa[0] * ((oy + 1) + (int64_t)S.noa[1] * (oz + 1));
+  const int p0 = gstart[key], p1 = gstart[key + 1];
+  if (p0 == p1) return;   // empty origin (uniform over the workgroup)
+  const int t = threadIdx.x;
+  if (t < 27) {
+    const int ax = t % 3, ay = (t / 3) % 3, az = t / 9;
+    sRow[t] = node_map[S.node_base + (ox + ax + 1) + (int64_t)S.nna[0] * ((oy + ay + 1) + (int64_t)S.nna[1] * (oz + az + 1))];
+  }
+  const bool task = t < 243;
+  const int r = t % 3, az = (t / 3) % 3, b = t / 9;
+  const int bx = b % 3, by = (b / 3) % 3, bz = b / 9;
+  double acc[9][3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[a][r][c] = 0.0;
-    for (int p = sG[g]; p < sG[g + 1]; ++p) {
-      const double* T = sT[p];
-      const double gb0 = sD[p][0][bx] * sW[p][1][by] * sW[p][2][bz];
-      const double gb1 = sW[p][0][bx] * sD[p][1][by] * sW[p][2][bz];
-      const double gb2 = sW[p][0][bx] * sW[p][1][by] * sD[p][2][bz];
-      double Tb[9][3];
+  for (int a = 0; a < 9; ++a)
 #pragma unroll
-      for (int o = 0; o < 9; ++o)
+    for (int c = 0; c < 3; ++c) acc[a][c] = 0.0;
+  for (int c0 = p0; c0 < p1; c0 += JC3) {
+    const int nc = min(JC3, p1 - c0);
+    __syncthreads();   // the previous chunk is consumed
+    for (int e = t; e < nc * 99; e += JC3T) {
+      const int q = e / 99, k = e % 99;
+      const double v = rec[(int64_t)(c0 + q) * PD3 + k];
+      if (k < 81) sT[q][k] = v;
+      else if (k < 90) sW[q][(k - 81) / 3][(k - 81) % 3] = v;
+      else sD[q][(k - 90) / 3][(k - 90) % 3] = v;
+    }
+    __syncthreads();
+    if (task) {
+      for (int p = 0; p < nc; ++p) {
+        const double* T = sT[p];
+        const double gb0 = sD[p][0][bx] * sW[p][1][by] * sW[p][2][bz];
+        const double gb1 = sW[p][0][bx] * sD[p][1][by] * sW[p][2][bz];
+        const double gb2 = sW[p][0][bx] * sW[p][1][by] * sD[p][2][bz];
+        double Tb[3][3];   // Tb[i][c] = sum_j dP_{r i}/dF_{c j} grad_j w_b
 #pragma unroll
-        for (int mm = 0; mm < 3; ++mm)
-          Tb[o][mm] = T[o * 9 + mm * 3] * gb0 + T[o * 9 + mm * 3 + 1] * gb1 + T[o * 9 + mm * 3 + 2] * gb2;
+        for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int a = 0; a < 9; ++a) {
-        const int ax = a % 3, ay = a / 3;
-        const double ga0 = sD[p][0][ax] * sW[p][1][ay] * sW[p][2][az];
-        const double ga1 = sW[p][0][ax] * sD[p][1][ay] * sW[p][2][az];
-        const double ga2 = sW[p][0][ax] * sW[p][1][ay] * sD[p][2][az];
+          for (int c = 0; c < 3; ++c) {
+            const double* Tq = T + (r * 3 + i) * 9 + c * 3;
+            Tb[i][c] = Tq[0] * gb0 + Tq[1] * gb1 + Tq[2] * gb2;
+          }
 #pragma unroll
-        for (int r = 0; r < 3; ++r)
+        for (int a = 0; a < 9; ++a) {
+          const int ax = a % 3, ay = a / 3;
+          const double ga0 = sD[p][0][ax] * sW[p][1][ay] * sW[p][2][az];
+          const double ga1 = sW[p][0][ax] * sD[p][1][ay] * sW[p][2][az];
+          const double ga2 = sW[p][0][ax] * sW[p][1][ay] * sD[p][2][az];
 #pragma unroll
-          for (int c = 0; c < 3; ++c) acc[a][r][c] += ga0 * Tb[r * 3][c] + ga1 * Tb[r * 3 + 1][c] + ga2 * Tb[r * 3 + 2][c];
+          for (int c = 0; c < 3; ++c) acc[a][c] += ga0 * Tb[0][c] + ga1 * Tb[1][c] + ga2 * Tb[2][c];
+        }
       }
     }
-    const int p0 = sG[g];
+  }
+  if (task) {
 #pragma unroll
     for (int a9 = 0; a9 < 9; ++a9) {
       const int a = a9 + 9 * az;
-      const int32_t ra = sRow[p0][a];
-      const int s = slot[(int64_t)ra * 125 + nb_index<3>(a, b)];
-      double* blk = val + ((int64_t)rowptr[ra] + s) * 9;
+      const int32_t ra = sRow[a];
+      const int sl = slot[(int64_t)ra * 125 + nb_index<3>(a, b)];
+      double* blk = val + ((int64_t)rowptr[ra] + sl) * 9 + r * 3;
 #pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) atomicAdd(&blk[r * 3 + c], acc[a9][r][c]);
+      for (int c = 0; c < 3; ++c) blk[c] += acc[a9][c];   // one writer per entry in this colour
     }
   }
 }
@@ -887,12 +927,38 @@ int launch_jacobian(mpm_ctx* c, const mpm_problem* pb, const double* du, double*
   } else {
     HIPC(c, hipMemsetAsync(val, 0, c->nnzb * nd * nd * sizeof(double), c->stream));
   }
-  if (c->np > 0 && !(c->dim == 2 && !c->up)) {
+  if (c->np > 0 && c->dim == 2 && c->up) {
     const unsigned g8 = (unsigned)((c->np + JT / 8 - 1) / (JT / 8));
-    if (c->dim == 2) k_jac2g<7><<<g8, JT, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val);
-    else k_jac3g<<<(unsigned)((c->np + GP3 - 1) / GP3), GP3, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val,
-                                                                              c->flag.p);
-    LAUNCH_CHECK(c, "k_jac");
+    k_jac2g<7><<<g8, JT, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val);
+    LAUNCH_CHECK(c, "k_jac2g");
+  }
+  if (c->np > 0 && c->dim == 3) {
+    // tangent records, then the 27 colours of stencil groups in order
+    if (c->pdat3.ensure(c->np * PD3) != hipSuccess)
+      return c->fail(MPM_E_NOMEM, "3-D tangent records allocation failed");
+    k_tan3<<<(unsigned)((c->np + GP3 - 1) / GP3), GP3, 0, c->stream>>>(A, du, c->pdat3.p, c->flag.p);
+    LAUNCH_CHECK(c, "k_tan3");
+    const int nsim = c->nsim;
+    c->jc3_ws_h.assign(27 * (size_t)(nsim + 1), 0);
+    for (int col = 0; col < 27; ++col) {
+      int64_t* ws = &c->jc3_ws_h[(size_t)col * (nsim + 1)];
+      for (int s = 0; s < nsim; ++s) {
+        const SimDev& S = c->sims_h[s];
+        ws[s + 1] = ws[s] + (int64_t)colour_count(S.n[0], col % 3) * colour_count(S.n[1], (col / 3) % 3) *
+                                colour_count(S.n[2], col / 9);
+      }
+    }
+    if (c->jc3_ws.ensure(c->jc3_ws_h.size()) != hipSuccess) return c->fail(MPM_E_NOMEM, "colour table allocation failed");
+    HIPC(c, hipMemcpyAsync(c->jc3_ws.p, c->jc3_ws_h.data(), c->jc3_ws_h.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                           c->stream));
+    for (int col = 0; col < 27; ++col) {
+      const int64_t nwg = c->jc3_ws_h[(size_t)col * (nsim + 1) + nsim];
+      if (nwg == 0) continue;
+      k_jac3c<<<(unsigned)nwg, JC3T, 0, c->stream>>>(col, c->jc3_ws.p + (size_t)col * (nsim + 1), nsim, c->sims.p,
+                                                      c->gstart.p, c->node_map.p, c->pdat3.p, c->rowptr.p, c->slot.p,
+                                                      val);
+      LAUNCH_CHECK(c, "k_jac3c");
+    }
   }
   if (apply_bc && c->n_row > 0 && !(c->dim == 2 && !c->up)) {   // the 2-D single-phase writer applies it itself
     k_jac_bc<<<nb256(c->n_row), 256, 0, c->stream>>>(c->n_row, nd, c->rowptr.p, c->colind.p, c->cmask.p, val);

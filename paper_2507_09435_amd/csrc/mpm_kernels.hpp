@@ -126,6 +126,9 @@ struct mpm_ctx {
   mpm::DBuf<double> cval, fext, fint, nvol, work;
   mpm::DBuf<double> val, dinv;
   mpm::DBuf<double> pdat;                      // per-particle tangent records (2-D assembly)
+  mpm::DBuf<double> pdat3;                     // per-particle tangent records (3-D assembly)
+  mpm::DBuf<int64_t> jc3_ws;                   // 3-D colour passes: per colour and sim, first workgroup
+  std::vector<int64_t> jc3_ws_h;               // host staging of jc3_ws
   mpm::DBuf<double> gbuf;                      // per-origin group blocks (2-D assembly)
   mpm::DBuf<double> rrec;                      // per-particle residual records (2-D)
   // Krylov
