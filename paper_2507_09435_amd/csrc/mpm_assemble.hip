@@ -546,58 +546,6 @@ __global__ void __launch_bounds__(256) k_fint2_rows(int64_t n_row, int nd, int u
 // ---------------------------------------------- group-cooperative 3-D ------
 constexpr int GP3 = 64;   // particles (threads) per workgroup in 3-D
 
-__device__ __forceinline__ int32_t origin_key3(const SimDev& S, const Stencil<3>& st) {
-  return (int32_t)(S.okey_base + (st.o[0] + 1) + (int64_t)S.noa[0] * ((st.o[1] + 1) + (int64_t)S.noa[1] * (st.o[2] + 1)));
-}
-
-__global__ void __launch_bounds__(GP3) k_fint3g(AsmArgs A, const double* __restrict__ du, double* __restrict__ fint,
-                                               int32_t* __restrict__ flag) {
-  __shared__ double sP[GP3][9];
-  __shared__ double sW[GP3][3][3], sD[GP3][3][3];
-  __shared__ int32_t sKey[GP3], sRow[GP3][27], sG[GP3 + 1], sWc[GP3 / 64];
-  const int64_t base = (int64_t)blockIdx.x * GP3;
-  const int n = (int)min<int64_t>(GP3, A.np - base);
-  const int t = threadIdx.x;
-  if (t < n) {
-    const int64_t i = base + t;
-    PLoad<3> L;
-    load_particle<3>(A, i, du, L);
-    Mat<double> m = make_mat<double>(L.E, A.nu, L.phi, A.c, A.psi, A.dp, A.match, A.apex_reg);
-    Out3<double> o;
-    int rerr = 0;
-    mech3<double>(m, L.dF, load_be3(A, i), o, nullptr, &rerr);
-    if (rerr) atomicOr(flag, 4);
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) sP[t][r * 3 + c] = L.v0 * o.P[r][c];
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) { sW[t][k][a] = L.st.w[k][a]; sD[t][k][a] = L.st.dw[k][a]; }
-    for (int a = 0; a < 27; ++a) sRow[t][a] = L.row[a];
-    sKey[t] = origin_key3(A.sims[A.psim[i]], L.st);
-  }
-  __syncthreads();
-  const int G = group_starts(sKey, n, sG, sWc);
-  for (int task = t; task < 27 * G; task += GP3) {
-    const int g = task / 27, a = task % 27, ax = a % 3, ay = (a / 3) % 3, az = a / 9;
-    double f0 = 0.0, f1 = 0.0, f2 = 0.0;
-    for (int p = sG[g]; p < sG[g + 1]; ++p) {
-      const double ga0 = sD[p][0][ax] * sW[p][1][ay] * sW[p][2][az];
-      const double ga1 = sW[p][0][ax] * sD[p][1][ay] * sW[p][2][az];
-      const double ga2 = sW[p][0][ax] * sW[p][1][ay] * sD[p][2][az];
-      f0 += sP[p][0] * ga0 + sP[p][1] * ga1 + sP[p][2] * ga2;
-      f1 += sP[p][3] * ga0 + sP[p][4] * ga1 + sP[p][5] * ga2;
-      f2 += sP[p][6] * ga0 + sP[p][7] * ga1 + sP[p][8] * ga2;
-    }
-    double* f = fint + (int64_t)sRow[sG[g]][a] * 3;
-    atomicAdd(&f[0], f0);
-    atomicAdd(&f[1], f1);
-    atomicAdd(&f[2], f2);
-  }
-}
-
 // 3-D Jacobian without atomics.  k_tan3: one thread per particle writes its
 // tangent table (V0 dP/dF, 81 entries, from 9 forward passes) and its
 // stencil weights and derivatives to a record.  k_jac3c: stencil groups of
@@ -731,6 +679,94 @@ __global__ void __launch_bounds__(JC3T) k_jac3c(int colour, const int64_t* __res
   }
 }
 
+// 3-D internal force without atomics: k_fint3_rec writes per particle V0 P
+// and the stencil weights and derivatives; k_p2g3c (shared with the
+// external force) gives one workgroup to each stencil group of a colour and
+// adds the group's sum over its particles, in order, to each of its 27
+// nodes with a plain read-modify-write.
+constexpr int PR3 = 28;    // doubles per 3-D force record: V0 P 0..8 (or the force 0..2), w 9..17 [axis][a], dw 18..26
+
+__global__ void __launch_bounds__(256) k_fint3_rec(AsmArgs A, const double* __restrict__ du, double* __restrict__ rec,
+                                                  int32_t* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= A.np) return;
+  PLoad<3> L;
+  load_particle<3>(A, i, du, L);
+  Mat<double> m = make_mat<double>(L.E, A.nu, L.phi, A.c, A.psi, A.dp, A.match, A.apex_reg);
+  Out3<double> o;
+  int rerr = 0;
+  mech3<double>(m, L.dF, load_be3(A, i), o, nullptr, &rerr);
+  if (rerr) atomicOr(flag, 4);
+  double* R = rec + i * PR3;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) R[r * 3 + c] = L.v0 * o.P[r][c];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      R[9 + k * 3 + a] = L.st.w[k][a];
+      R[18 + k * 3 + a] = L.st.dw[k][a];
+    }
+}
+
+// mode 0: f_a += sum_p V0 P_p grad w_a(x_p) (internal force);
+// mode 1: f_a += sum_p w_a(x_p) f_p (external force).
+constexpr int PG3 = 32;   // records staged in LDS at a time
+__global__ void __launch_bounds__(64) k_p2g3c(int colour, int mode, const int64_t* __restrict__ wstart, int nsim,
+                                             const SimDev* __restrict__ sims, const int32_t* __restrict__ gstart,
+                                             const int32_t* __restrict__ node_map, const double* __restrict__ rec,
+                                             double* __restrict__ out) {
+  __shared__ double sR[PG3][PR3];
+  const int64_t w = blockIdx.x;
+  int s = 0;
+  while (s + 1 < nsim && wstart[s + 1] <= w) ++s;   // workgroup-uniform
+  const SimDev& S = sims[s];
+  const int cx = colour % 3, cy = (colour / 3) % 3, cz = colour / 9;
+  const int nx = colour_count(S.n[0], cx), ny = colour_count(S.n[1], cy);
+  const int64_t loc = w - wstart[s];
+  const int ox = cx + 3 * (int)(loc % nx) - 1, oy = cy + 3 * (int)((loc / nx) % ny) - 1,
+            oz = cz + 3 * (int)(loc / ((int64_t)nx * ny)) - 1;
+  const int64_t key = S.okey_base + (ox + 1) + (int64_t)S.noa[0] * ((oy + 1) + (int64_t)S.noa[1] * (oz + 1));
+  const int p0 = gstart[key], p1 = gstart[key + 1];
+  if (p0 == p1) return;   // empty origin (uniform over the workgroup)
+  const int t = threadIdx.x;
+  const int ax = t % 3, ay = (t / 3) % 3, az = t / 9;
+  double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+  for (int c0 = p0; c0 < p1; c0 += PG3) {
+    const int nc = min(PG3, p1 - c0);
+    __syncthreads();   // the previous chunk is consumed
+    for (int e = t; e < nc * PR3; e += 64) sR[e / PR3][e % PR3] = rec[(int64_t)c0 * PR3 + e];
+    __syncthreads();
+    if (t < 27) {
+      for (int p = 0; p < nc; ++p) {
+        const double* R = sR[p];
+        if (mode == 0) {
+          const double ga0 = R[18 + ax] * R[12 + ay] * R[15 + az];
+          const double ga1 = R[9 + ax] * R[21 + ay] * R[15 + az];
+          const double ga2 = R[9 + ax] * R[12 + ay] * R[24 + az];
+          f0 += R[0] * ga0 + R[1] * ga1 + R[2] * ga2;
+          f1 += R[3] * ga0 + R[4] * ga1 + R[5] * ga2;
+          f2 += R[6] * ga0 + R[7] * ga1 + R[8] * ga2;
+        } else {
+          const double wa = R[9 + ax] * R[12 + ay] * R[15 + az];
+          f0 += wa * R[0];
+          f1 += wa * R[1];
+          f2 += wa * R[2];
+        }
+      }
+    }
+  }
+  if (t < 27) {
+    const int32_t ra = node_map[S.node_base + (ox + ax + 1) + (int64_t)S.nna[0] * ((oy + ay + 1) + (int64_t)S.nna[1] * (oz + az + 1))];
+    double* f = out + (int64_t)ra * 3;
+    f[0] += f0;   // one writer per node in this colour
+    f[1] += f1;
+    f[2] += f2;
+  }
+}
+
 // Dirichlet rows/columns: zero them, 1 on the diagonal (structure unchanged).
 __global__ void k_jac_bc(int64_t n_row, int nd, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
                          const uint8_t* __restrict__ cmask, double* __restrict__ val) {
@@ -839,6 +875,39 @@ static AsmArgs make_args(mpm_ctx* c, const mpm_problem* pb) {
 static unsigned nb256(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + 255) / 256); }
 
 // f_int into c->fint (zeroed first).
+// Per colour of 3-D stencil groups and per sim, the first workgroup of the
+// colour passes (groups of one colour share no node).  Built by prepare.
+int build_colour_table(mpm_ctx* c) {
+  const int nsim = c->nsim;
+  c->jc3_ws_h.assign(27 * (size_t)(nsim + 1), 0);
+  for (int col = 0; col < 27; ++col) {
+    int64_t* ws = &c->jc3_ws_h[(size_t)col * (nsim + 1)];
+    for (int s = 0; s < nsim; ++s) {
+      const SimDev& S = c->sims_h[s];
+      ws[s + 1] = ws[s] + (int64_t)colour_count(S.n[0], col % 3) * colour_count(S.n[1], (col / 3) % 3) *
+                              colour_count(S.n[2], col / 9);
+    }
+  }
+  if (c->jc3_ws.ensure(c->jc3_ws_h.size()) != hipSuccess) return c->fail(MPM_E_NOMEM, "colour table allocation failed");
+  HIPC(c, hipMemcpyAsync(c->jc3_ws.p, c->jc3_ws_h.data(), c->jc3_ws_h.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                         c->stream));
+  return MPM_OK;
+}
+
+// out[row * 3 + k] += the 3-D P2G of the force records rec (mode 0 internal,
+// 1 external), colour by colour.
+int launch_p2g3(mpm_ctx* c, int mode, const double* rec, double* out) {
+  const int nsim = c->nsim;
+  for (int col = 0; col < 27; ++col) {
+    const int64_t nwg = c->jc3_ws_h[(size_t)col * (nsim + 1) + nsim];
+    if (nwg == 0) continue;
+    k_p2g3c<<<(unsigned)nwg, 64, 0, c->stream>>>(col, mode, c->jc3_ws.p + (size_t)col * (nsim + 1), nsim, c->sims.p,
+                                                 c->gstart.p, c->node_map.p, rec, out);
+    LAUNCH_CHECK(c, "k_p2g3c");
+  }
+  return MPM_OK;
+}
+
 int launch_fint(mpm_ctx* c, const mpm_problem* pb, const double* du) {
   AsmArgs A = make_args(c, pb);
   if (c->dim == 2) {
@@ -858,10 +927,11 @@ int launch_fint(mpm_ctx* c, const mpm_problem* pb, const double* du) {
   }
   HIPC(c, hipMemsetAsync(c->fint.p, 0, c->n_row * c->nd * sizeof(double), c->stream));
   if (c->np == 0) return MPM_OK;
-  unsigned g = (unsigned)((c->np + GP3 - 1) / GP3);
-  k_fint3g<<<g, GP3, 0, c->stream>>>(A, du, c->fint.p, c->flag.p);
-  LAUNCH_CHECK(c, "k_fint3g");
-  return MPM_OK;
+  // force records, then the 27 colours of stencil groups in order
+  if (c->rrec.ensure(c->np * PR3) != hipSuccess) return c->fail(MPM_E_NOMEM, "3-D force records allocation failed");
+  k_fint3_rec<<<(unsigned)((c->np + 255) / 256), 256, 0, c->stream>>>(A, du, c->rrec.p, c->flag.p);
+  LAUNCH_CHECK(c, "k_fint3_rec");
+  return launch_p2g3(c, 0, c->rrec.p, c->fint.p);
 }
 
 // Residual with per-sim ||r||^2 -> simsc[s*16+0], reaction -> simsc[s*16+1].
@@ -939,18 +1009,6 @@ int launch_jacobian(mpm_ctx* c, const mpm_problem* pb, const double* du, double*
     k_tan3<<<(unsigned)((c->np + GP3 - 1) / GP3), GP3, 0, c->stream>>>(A, du, c->pdat3.p, c->flag.p);
     LAUNCH_CHECK(c, "k_tan3");
     const int nsim = c->nsim;
-    c->jc3_ws_h.assign(27 * (size_t)(nsim + 1), 0);
-    for (int col = 0; col < 27; ++col) {
-      int64_t* ws = &c->jc3_ws_h[(size_t)col * (nsim + 1)];
-      for (int s = 0; s < nsim; ++s) {
-        const SimDev& S = c->sims_h[s];
-        ws[s + 1] = ws[s] + (int64_t)colour_count(S.n[0], col % 3) * colour_count(S.n[1], (col / 3) % 3) *
-                                colour_count(S.n[2], col / 9);
-      }
-    }
-    if (c->jc3_ws.ensure(c->jc3_ws_h.size()) != hipSuccess) return c->fail(MPM_E_NOMEM, "colour table allocation failed");
-    HIPC(c, hipMemcpyAsync(c->jc3_ws.p, c->jc3_ws_h.data(), c->jc3_ws_h.size() * sizeof(int64_t), hipMemcpyHostToDevice,
-                           c->stream));
     for (int col = 0; col < 27; ++col) {
       const int64_t nwg = c->jc3_ws_h[(size_t)col * (nsim + 1) + nsim];
       if (nwg == 0) continue;

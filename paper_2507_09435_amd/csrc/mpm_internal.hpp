@@ -106,6 +106,8 @@ int launch_bj_inv(mpm_ctx* c, const double* val);
 int launch_spmv(mpm_ctx* c, const double* val, const double* x, double* y, const double* z);
 int krylov_solve(mpm_ctx* c, const double* val, double rtol, int max_iter, std::vector<int>& iters_out);
 int launch_jac2_records(mpm_ctx* c, double* val, bool apply_bc);
+int build_colour_table(mpm_ctx* c);
+int launch_p2g3(mpm_ctx* c, int mode, const double* rec, double* out);
 int launch_jac2_blocks(mpm_ctx* c, double* val, bool apply_bc);
 void ctx_release(mpm_ctx* c);
 // multigrid preconditioner (2-D single-phase)

@@ -333,29 +333,28 @@ __global__ void k_cmask(int64_t n_row, int nd, const int64_t* __restrict__ activ
   }
 }
 
-// External force: f_ext,i = sum_p w_ip (rho0 V0 g + f_p) (Sec. 2.2).
-template <int DIM>
-__global__ void k_fext(int64_t np, int nd, const double* __restrict__ xs, const double* __restrict__ vs,
-                       const double* __restrict__ fp_user, const int32_t* __restrict__ perm,
-                       const int32_t* __restrict__ psim, const SimDev* __restrict__ sims,
-                       const int32_t* __restrict__ node_map, double rho0, double gx, double gy, double gz,
-                       double* __restrict__ fext) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// External force f_ext,i = sum_p w_ip (rho0 V0 g + f_p) (Sec. 2.2).  3-D
+// records for the coloured P2G: the particle's force (slots 0..2) and its
+// stencil weights (slots 9..17).
+__global__ void k_fext3_rec(int64_t np, const double* __restrict__ xs, const double* __restrict__ vs,
+                            const double* __restrict__ fp_user, const int32_t* __restrict__ perm,
+                            const int32_t* __restrict__ psim, const SimDev* __restrict__ sims, double rho0, double gx,
+                            double gy, double gz, double* __restrict__ rec) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= np) return;
   const SimDev& S = sims[psim[i]];
-  Stencil<DIM> st;
-  make_stencil<DIM>(S, xs, np, i, st);
-  double m = rho0 * vs[i];
+  Stencil<3> st;
+  make_stencil<3>(S, xs, np, i, st);
+  const double m = rho0 * vs[i];
   double f[3] = {m * gx, m * gy, m * gz};
   if (fp_user) {
-    int64_t p = perm[i];
-    for (int k = 0; k < DIM; ++k) f[k] += fp_user[k * np + p];
+    const int64_t p = perm[i];
+    for (int k = 0; k < 3; ++k) f[k] += fp_user[k * np + p];
   }
-  for (int a = 0; a < Stencil<DIM>::NN; ++a) {
-    int32_t r = node_map[st.node(S, a)];
-    double w = st.weight(a);
-    for (int k = 0; k < DIM; ++k) atomicAdd(&fext[(int64_t)r * nd + k], w * f[k]);
-  }
+  double* R = rec + i * 28;
+  for (int k = 0; k < 3; ++k) R[k] = f[k];
+  for (int k = 0; k < 3; ++k)
+    for (int a = 0; a < 3; ++a) R[9 + k * 3 + a] = st.w[k][a];
 }
 
 // 2-D external force as a row gather (deterministic, no atomics): f_ext at
@@ -583,9 +582,13 @@ int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row_out, int6
     } else {
       k_node_volume<3><<<nblk(np), TPB, 0, c->stream>>>(np, c->xs.p, c->vol0s.p, c->psim.p, c->sims.p, c->node_map.p,
                                                         c->nvol.p);
-      k_fext<3><<<nblk(np), TPB, 0, c->stream>>>(np, nd, c->xs.p, c->vol0s.p, pb->P.fp, c->perm.p, c->psim.p,
-                                                 c->sims.p, c->node_map.p, pb->mat.rho0, pb->mat.g[0], pb->mat.g[1],
-                                                 pb->mat.g[2], c->fext.p);
+      // force records, then the coloured P2G (deterministic, no atomics)
+      if (c->rrec.ensure(np * 28) != hipSuccess) return c->fail(MPM_E_NOMEM, "external force records allocation failed");
+      k_fext3_rec<<<nblk(np), TPB, 0, c->stream>>>(np, c->xs.p, c->vol0s.p, pb->P.fp, c->perm.p, c->psim.p, c->sims.p,
+                                                   pb->mat.rho0, pb->mat.g[0], pb->mat.g[1], pb->mat.g[2], c->rrec.p);
+      LAUNCH_CHECK(c, "k_fext3_rec");
+      GUARD(build_colour_table(c));
+      GUARD(launch_p2g3(c, 1, c->rrec.p, c->fext.p));
     }
     LAUNCH_CHECK(c, "node volume / fext");
   }

@@ -187,12 +187,14 @@ def test_spmv_does_not_depend_on_its_shape(ctx, name):
         M.mpm_spmv_set_lanes(ctx, 32)
 
 
-@pytest.mark.parametrize("name,method", [("footing_big", 2), ("footing_elastic", 0), ("footing_elastic", 1)])
+@pytest.mark.parametrize("name,method", [("footing_big", 2), ("footing_elastic", 0), ("footing_elastic", 1),
+                                         ("c3small", 0)])
 def test_newton_does_not_depend_on_spmv_shape(ctx, name, method):
-    """Plane-strain single-phase solves (assembled without atomics, so each
-    prepare rebuilds the same matrix bits): the Newton increments and the
-    Newton and Krylov iteration counts are bitwise the same for every SpMV
-    shape, including the Krylov dot products the product fuses."""
+    """Plane-strain single-phase and 3-D solves (assembled without atomics,
+    so each prepare rebuilds the same residual and matrix bits): the Newton
+    increments and the Newton and Krylov iteration counts are bitwise the
+    same for every SpMV shape, including the Krylov dot products the product
+    fuses."""
     from paper_2507_09435_amd import mpm as M
     w = _newton_case(name)
     P = w.prob
