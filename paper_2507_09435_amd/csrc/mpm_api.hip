@@ -86,7 +86,7 @@ void ctx_release(mpm_ctx* c) {
   c->sims.release(); c->sim_start.release(); c->okey.release(); c->gcount.release(); c->gstart.release();
   c->cursor.release(); c->okey_sorted.release(); c->sort_tmp.release(); c->perm.release(); c->psim.release(); c->scan_tmp.release(); c->node_flag.release();
   c->node_map.release(); c->active_nodes.release(); c->row_sim.release(); c->rowcnt.release(); c->rowptr.release();
-  c->colind.release(); c->slot.release(); c->blocks.release(); c->blk_first.release(); c->flag.release();
+  c->colind.release(); c->slot.release(); c->rgrp.release(); c->bcode.release(); c->blocks.release(); c->blk_first.release(); c->flag.release();
   c->xs.release(); c->vol0s.release(); c->Fs.release(); c->bes.release(); c->Es.release(); c->phis.release();
   c->cmask.release(); c->rmask.release(); c->cval.release(); c->fext.release(); c->fint.release(); c->nvol.release();
   c->work.release(); c->val.release(); c->dinv.release(); c->pdat.release(); c->pdat3.release(); c->jc3_ws.release(); c->gbuf.release(); c->rrec.release();

@@ -125,11 +125,53 @@ __global__ void __launch_bounds__(64) k_sim_sum(int nsim, const int32_t* __restr
                                                 const double* __restrict__ part, int q, double* __restrict__ out,
                                                 int out_stride, int out_off) {
   const int s = blockIdx.x;   // one wave per sim, fixed lane assignment and reduction order
+  const int b1 = blk_first[s + 1];
   double acc = 0.0;
-  for (int b = blk_first[s] + (int)threadIdx.x; b < blk_first[s + 1]; b += 64) acc += part[b * NQ + q];
+  // a lane adds its blocks b, b + 64, ... in order; eight loads are issued before their adds
+  for (int b0 = blk_first[s] + (int)threadIdx.x; b0 < b1; b0 += 8 * 64) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = b0 + 64 * u < b1 ? part[(b0 + 64 * u) * NQ + q] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (b0 + 64 * u < b1) acc += v[u];
+  }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if (threadIdx.x == 0) out[s * out_stride + out_off] = acc;
+}
+
+// k_sim_sum for the residual's two partial sums (||r||^2 and the reaction)
+// in one launch, each in the same lanes and order as k_sim_sum.
+__global__ void __launch_bounds__(64) k_sim_sum_res(const int32_t* __restrict__ blk_first,
+                                                    const double* __restrict__ part, double* __restrict__ out) {
+  const int s = blockIdx.x;
+  const int b1 = blk_first[s + 1];
+  double a0 = 0.0, a1 = 0.0;
+  for (int b0 = blk_first[s] + (int)threadIdx.x; b0 < b1; b0 += 8 * 64) {
+    double v0[8], v1[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool in = b0 + 64 * u < b1;
+      v0[u] = in ? part[(b0 + 64 * u) * NQ + 0] : 0.0;
+      v1[u] = in ? part[(b0 + 64 * u) * NQ + 1] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (b0 + 64 * u < b1) {
+        a0 += v0[u];
+        a1 += v1[u];
+      }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a0 += __shfl_xor(a0, off, 64);
+    a1 += __shfl_xor(a1, off, 64);
+  }
+  if (threadIdx.x == 0) {
+    out[s * 16 + 0] = a0;
+    out[s * 16 + 1] = a1;
+  }
 }
 
 // ----------------------------------------------------------- Jacobian ------
@@ -279,13 +321,11 @@ __global__ void __launch_bounds__(JT) k_jac2g(AsmArgs A, const double* __restric
   }
 }
 
-// 2-D single-phase Jacobian without atomics, in three deterministic passes.
+// 2-D single-phase Jacobian without atomics, in two deterministic passes.
 // k_tan2: one record per particle (sorted order): V0 * tangent table (dP/dF,
 // 4x4, output-major) and its stencil's weights and derivatives per axis.
-// k_grp2: one wave per stencil group (origin key) sums the 9x9 local blocks
-// of the group's particles, in particle order, into a per-origin buffer.
-// k_jac2_blocks: every BSR block (a, b) is the sum, in origin order, of the
-// group blocks of the (at most nine) origins whose stencil holds both nodes,
+// k_jac2_rows: every BSR block (a, b) is the sum, in origin order, of the
+// group blocks of the (at most nine) stencil groups holding both nodes,
 // written once (no clearing, no atomics).
 
 __global__ void __launch_bounds__(256) k_tan2(AsmArgs A, const double* __restrict__ du, double* __restrict__ pdat) {
@@ -317,71 +357,82 @@ __device__ __forceinline__ double sel3(int i, double v0, double v1, double v2) {
 
 // Fused 2-D single-phase Jacobian from the tangent records: a workgroup of
 // JR rows with 16 lanes each.  Lane q < 9 of row a takes the q-th stencil
-// group that may hold node a and accumulates, over its particles in order,
-// the nine 2x2 blocks (a, b) for the group's local nodes b, into LDS.  Then
-// each BSR block (a, b) of the JR rows sums the groups holding both nodes,
-// in group order, and takes Dirichlet rows and columns as the identity's.
-// Every group block is formed once, as by a group-block pass followed by a
-// block gather, without the group blocks' round trip through HBM.
+// group that may hold node a (its particle range from the row group table)
+// and accumulates, over its particles in order, the nine 2x2 blocks (a, b)
+// for the group's local nodes b, into LDS.  Then each BSR block (a, b) of the
+// JR rows sums the groups holding both nodes, in group order, and takes
+// Dirichlet rows and columns as the identity's.  Every group block is formed
+// once, as by a group-block pass followed by a block gather, without the
+// group blocks' round trip through HBM.  The second pass needs only the
+// slot and constraint tables of its rows, loaded before the first pass, so
+// no chain of dependent global loads is left on the way.
 constexpr int JR = 16;   // rows per workgroup (16 lanes each)
-__global__ void __launch_bounds__(256) k_jac2_rows(int64_t n_row, const int64_t* __restrict__ active_nodes,
-                                                  const int32_t* __restrict__ row_sim,
-                                                  const SimDev* __restrict__ sims,
-                                                  const int32_t* __restrict__ gstart,
+constexpr int JB = (JR * 25 + 255) / 256;   // stencil offsets per thread in the block pass
+__global__ void __launch_bounds__(256) k_jac2_rows(int64_t n_row, const int32_t* __restrict__ rgrp,
                                                   const double* __restrict__ pdat,
                                                   const int32_t* __restrict__ rowptr,
-                                                  const int32_t* __restrict__ colind,
-                                                  const uint8_t* __restrict__ cmask, double* __restrict__ val) {
+                                                  const int8_t* __restrict__ slot,
+                                                  const uint8_t* __restrict__ bcode, double* __restrict__ val) {
   __shared__ double part[JR][9][9 * 4];   // [row][group q][local node b][2x2]
   const int rl = threadIdx.x / 16, q = threadIdx.x % 16;
   const int64_t row0 = (int64_t)blockIdx.x * JR;
+  // block pass: thread t takes stencil offsets t and t + 256 of the JR rows
+  // (independent loads, in flight during the first pass)
+  int32_t sl[JB], rp[JB];
+  uint32_t code[JB];
+#pragma unroll
+  for (int h = 0; h < JB; ++h) {
+    const int t = threadIdx.x + 256 * h;
+    const int64_t row = row0 + t / 25;
+    sl[h] = -1;
+    rp[h] = 0;
+    code[h] = 0;
+    if (t < JR * 25 && row < n_row) {
+      sl[h] = slot[row * 25 + t % 25];
+      rp[h] = rowptr[row];
+      if (bcode) code[h] = bcode[row * 25 + t % 25];
+    }
+  }
   {
     const int64_t row = row0 + rl;
     if (row < n_row && q < 9) {
-      const SimDev& S = sims[row_sim[row]];
-      const int64_t nid = active_nodes[row] - S.node_base;
-      const int ix = (int)(nid % S.nna[0]) - 1, iy = (int)(nid / S.nna[0]) - 1;
-      const int oy = iy - 2 + q / 3, ox = ix - 2 + q % 3;
+      const int p0 = rgrp[(row * 9 + q) * 2], p1 = rgrp[(row * 9 + q) * 2 + 1];
+      const int ax = 2 - q % 3, ay = 2 - q / 3;   // node a's place in the group's 3x3 stencil
       double K[9][4];
 #pragma unroll
       for (int lb = 0; lb < 9; ++lb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) K[lb][e] = 0.0;
-      if (oy >= -1 && oy <= S.n[1] - 1 && ox >= -1 && ox <= S.n[0] - 1) {
-        const int64_t key = S.okey_base + (ox + 1) + (int64_t)S.noa[0] * (oy + 1);
-        const int p1 = gstart[key + 1];
-        const int ax = ix - ox, ay = iy - oy;   // node a's place in the group's 3x3 stencil
-        for (int p = gstart[key]; p < p1; ++p) {
-          const double* P = pdat + (int64_t)p * PD2;
-          double T[16], w[12];
+      for (int p = p0; p < p1; ++p) {
+        const double* P = pdat + (int64_t)p * PD2;
+        double T[16], w[12];
 #pragma unroll
-          for (int k = 0; k < 16; ++k) T[k] = P[k];
+        for (int k = 0; k < 16; ++k) T[k] = P[k];
 #pragma unroll
-          for (int k = 0; k < 12; ++k) w[k] = P[16 + k];
-          // w: wx 0..2, dwx 3..5, wy 6..8, dwy 9..11; grad w_n = (dwx wy, wx dwy)
-          const double ga0 = sel3(ax, w[3], w[4], w[5]) * sel3(ay, w[6], w[7], w[8]);
-          const double ga1 = sel3(ax, w[0], w[1], w[2]) * sel3(ay, w[9], w[10], w[11]);
-          // K_ab[r][c] = sum_ij ga_i T[(2r+i)4 + 2c+j] gb_j: contract node a's side once,
-          // U[r][c][j] = sum_i ga_i T[(2r+i)4 + 2c+j], then two fma per entry and node b
-          double U[2][2][2];
+        for (int k = 0; k < 12; ++k) w[k] = P[16 + k];
+        // w: wx 0..2, dwx 3..5, wy 6..8, dwy 9..11; grad w_n = (dwx wy, wx dwy)
+        const double ga0 = sel3(ax, w[3], w[4], w[5]) * sel3(ay, w[6], w[7], w[8]);
+        const double ga1 = sel3(ax, w[0], w[1], w[2]) * sel3(ay, w[9], w[10], w[11]);
+        // K_ab[r][c] = sum_ij ga_i T[(2r+i)4 + 2c+j] gb_j: contract node a's side once,
+        // U[r][c][j] = sum_i ga_i T[(2r+i)4 + 2c+j], then two fma per entry and node b
+        double U[2][2][2];
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+              U[r][c][j] = fma(ga1, T[(2 * r + 1) * 4 + 2 * c + j], ga0 * T[(2 * r) * 4 + 2 * c + j]);
+#pragma unroll
+        for (int lb = 0; lb < 9; ++lb) {
+          const int bx = lb % 3, by = lb / 3;
+          const double gb0 = w[3 + bx] * w[6 + by];
+          const double gb1 = w[bx] * w[9 + by];
 #pragma unroll
           for (int r = 0; r < 2; ++r)
 #pragma unroll
             for (int c = 0; c < 2; ++c)
-#pragma unroll
-              for (int j = 0; j < 2; ++j)
-                U[r][c][j] = fma(ga1, T[(2 * r + 1) * 4 + 2 * c + j], ga0 * T[(2 * r) * 4 + 2 * c + j]);
-#pragma unroll
-          for (int lb = 0; lb < 9; ++lb) {
-            const int bx = lb % 3, by = lb / 3;
-            const double gb0 = w[3 + bx] * w[6 + by];
-            const double gb1 = w[bx] * w[9 + by];
-#pragma unroll
-            for (int r = 0; r < 2; ++r)
-#pragma unroll
-              for (int c = 0; c < 2; ++c)
-                K[lb][r * 2 + c] = fma(U[r][c][1], gb1, fma(U[r][c][0], gb0, K[lb][r * 2 + c]));
-          }
+              K[lb][r * 2 + c] = fma(U[r][c][1], gb1, fma(U[r][c][0], gb0, K[lb][r * 2 + c]));
         }
       }
 #pragma unroll
@@ -391,36 +442,32 @@ __global__ void __launch_bounds__(256) k_jac2_rows(int64_t n_row, const int64_t*
     }
   }
   __syncthreads();
-  // BSR blocks of the JR rows: 32 slots per row (at most 25 used)
-  for (int t = threadIdx.x; t < JR * 32; t += 256) {
-    const int r2 = t / 32;
-    const int64_t row = row0 + r2;
-    if (row >= n_row) continue;
-    const int k = rowptr[row] + t % 32;
-    if (k >= rowptr[row + 1]) continue;
-    const SimDev& S = sims[row_sim[row]];
-    const int64_t na = active_nodes[row] - S.node_base, nb = active_nodes[colind[k]] - S.node_base;
-    const int ix = (int)(na % S.nna[0]) - 1, iy = (int)(na / S.nna[0]) - 1;
-    const int jx = (int)(nb % S.nna[0]) - 1, jy = (int)(nb / S.nna[0]) - 1;
+  // BSR block (a, b) at stencil offset (dx, dy) = b - a: groups (qx, qy) with
+  // qx in [max(0, dx), min(2, dx + 2)] (likewise y) hold both nodes; node b
+  // sits at (dx + 2 - qx, dy + 2 - qy) in their stencil.  Groups off the grid
+  // left zeros in LDS, so adding them changes no bit of the sum.
+#pragma unroll
+  for (int h = 0; h < JB; ++h) {
+    if (sl[h] < 0) continue;
+    const int t = threadIdx.x + 256 * h;
+    const int r2 = t / 25, o = t % 25;
+    const int dx = o % 5 - 2, dy = o / 5 - 2;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const int oy0 = max(max(iy, jy) - 2, -1), oy1 = min(min(iy, jy), S.n[1] - 1);
-    const int ox0 = max(max(ix, jx) - 2, -1), ox1 = min(min(ix, jx), S.n[0] - 1);
-    for (int oy = oy0; oy <= oy1; ++oy)
-      for (int ox = ox0; ox <= ox1; ++ox) {
-        const int qq = (oy - (iy - 2)) * 3 + (ox - (ix - 2));
-        const int lb = (jx - ox) + 3 * (jy - oy);
+    for (int qy = max(0, dy); qy <= min(2, dy + 2); ++qy)
+      for (int qx = max(0, dx); qx <= min(2, dx + 2); ++qx) {
+        const int qq = qy * 3 + qx;
+        const int lb = (dx + 2 - qx) + 3 * (dy + 2 - qy);
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[e] += part[r2][qq][lb * 4 + e];
       }
-    if (cmask) {
-      const int64_t col = colind[k];
+    if (code[h]) {
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          if (cmask[row * 2 + i] || cmask[col * 2 + j]) acc[i * 2 + j] = (row == col && i == j) ? 1.0 : 0.0;
+          if (((code[h] >> (2 + i)) | (code[h] >> j)) & 1) acc[i * 2 + j] = (o == 12 && i == j) ? 1.0 : 0.0;
     }
-    double* blk = val + (int64_t)k * 4;
+    double* blk = val + ((int64_t)rp[h] + sl[h]) * 4;
 #pragma unroll
     for (int e = 0; e < 4; ++e) blk[e] = acc[e];
   }
@@ -474,7 +521,7 @@ __global__ void __launch_bounds__(256) k_jac2_blocks(int64_t n_row, const int64_
 // stencil's weights and derivatives per axis.  k_fint2_rows gives each row
 // (node a) 16 lanes: lane q < 9 sums f_a = sum_p V0 P_p grad w_a(x_p) (and the
 // u-p row) over the particles of the q-th stencil group whose stencil may
-// hold a, in particle order, and the 16 lane sums meet in a fixed butterfly:
+// hold a (its range from the row group table), in particle order, and the 16 lane sums meet in a fixed butterfly:
 // deterministic, written once.
 constexpr int RD2 = 20;   // doubles per residual record: V0 P 0..3, u-p 4..6, wx 8..10, dwx 11..13, wy 14..16, dwy 17..19
 
@@ -504,30 +551,37 @@ __global__ void __launch_bounds__(256) k_fint2_rec(AsmArgs A, const double* __re
 constexpr int RL2 = 16;   // lanes per row of the 2-D row gathers (9 stencil groups used)
 
 __global__ void __launch_bounds__(256) k_fint2_rows(int64_t n_row, int nd, int up,
-                                                   const int64_t* __restrict__ active_nodes,
-                                                   const int32_t* __restrict__ row_sim,
-                                                   const SimDev* __restrict__ sims,
-                                                   const int32_t* __restrict__ gstart,
+                                                   const int32_t* __restrict__ rgrp,
                                                    const double* __restrict__ rec, double* __restrict__ fint) {
   const int64_t row = ((int64_t)blockIdx.x * 256 + threadIdx.x) / RL2;
   const int q = (int)(threadIdx.x % RL2);
   if (row >= n_row) return;   // the row's 16 lanes leave together
-  const SimDev& S = sims[row_sim[row]];
-  const int64_t nid = active_nodes[row] - S.node_base;
-  const int ix = (int)(nid % S.nna[0]) - 1, iy = (int)(nid / S.nna[0]) - 1;
   double f0 = 0.0, f1 = 0.0, f2 = 0.0;
-  const int oy = iy - 2 + q / 3, ox = ix - 2 + q % 3;
-  if (q < 9 && oy >= -1 && oy <= S.n[1] - 1 && ox >= -1 && ox <= S.n[0] - 1) {
-    const int ay = iy - oy, ax = ix - ox;
-    const int64_t key = S.okey_base + (ox + 1) + (int64_t)S.noa[0] * (oy + 1);
-    const int p1 = gstart[key + 1];
-    for (int p = gstart[key]; p < p1; ++p) {
-      const double* R = rec + (int64_t)p * RD2;
-      const double wx = R[8 + ax], dwx = R[11 + ax], wy = R[14 + ay], dwy = R[17 + ay];
-      const double ga0 = dwx * wy, ga1 = wx * dwy;
-      f0 += R[0] * ga0 + R[1] * ga1;
-      f1 += R[2] * ga0 + R[3] * ga1;
-      if (up) f2 += wx * wy * R[4] + ga0 * R[5] + ga1 * R[6];
+  if (q < 9) {
+    const int p0 = rgrp[(row * 9 + q) * 2], p1 = rgrp[(row * 9 + q) * 2 + 1];
+    const int ax = 2 - q % 3, ay = 2 - q / 3;   // node a's place in the group's 3x3 stencil
+    // the loads of up to four particles are issued before their sums, which
+    // take the particles in order
+    for (int pb = p0; pb < p1; pb += 4) {
+      double v[4][8];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double* R = rec + (int64_t)min(pb + u, p1 - 1) * RD2;
+        v[u][0] = R[0]; v[u][1] = R[1]; v[u][2] = R[2]; v[u][3] = R[3];
+        v[u][4] = R[8 + ax]; v[u][5] = R[11 + ax]; v[u][6] = R[14 + ay]; v[u][7] = R[17 + ay];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (pb + u >= p1) break;
+        const double wx = v[u][4], dwx = v[u][5], wy = v[u][6], dwy = v[u][7];
+        const double ga0 = dwx * wy, ga1 = wx * dwy;
+        f0 += fma(v[u][0], ga0, v[u][1] * ga1);
+        f1 += fma(v[u][2], ga0, v[u][3] * ga1);
+        if (up) {
+          const double* R = rec + (int64_t)(pb + u) * RD2;
+          f2 += fma(wx * wy, R[4], fma(ga0, R[5], ga1 * R[6]));
+        }
+      }
     }
   }
 #pragma unroll
@@ -920,7 +974,7 @@ int launch_fint(mpm_ctx* c, const mpm_problem* pb, const double* du) {
     }
     if (c->n_row > 0) {
       k_fint2_rows<<<(unsigned)((c->n_row * RL2 + 255) / 256), 256, 0, c->stream>>>(
-          c->n_row, c->nd, c->up, c->active_nodes.p, c->row_sim.p, c->sims.p, c->gstart.p, c->rrec.p, c->fint.p);
+          c->n_row, c->nd, c->up, c->rgrp.p, c->rrec.p, c->fint.p);
       LAUNCH_CHECK(c, "k_fint2_rows");
     }
     return MPM_OK;
@@ -946,9 +1000,8 @@ int launch_residual(mpm_ctx* c, const mpm_problem* pb, const double* du, double*
   } else {
     HIPC(c, hipMemsetAsync(c->part.p, 0, NQ * sizeof(double), c->stream));
   }
-  k_sim_sum<<<c->nsim, 64, 0, c->stream>>>(c->nsim, c->blk_first.p, c->part.p, 0, c->simsc.p, 16, 0);
-  k_sim_sum<<<c->nsim, 64, 0, c->stream>>>(c->nsim, c->blk_first.p, c->part.p, 1, c->simsc.p, 16, 1);
-  LAUNCH_CHECK(c, "k_sim_sum");
+  k_sim_sum_res<<<c->nsim, 64, 0, c->stream>>>(c->blk_first.p, c->part.p, c->simsc.p);
+  LAUNCH_CHECK(c, "k_sim_sum_res");
   return MPM_OK;
 }
 
@@ -964,8 +1017,7 @@ int sim_sum_launch(mpm_ctx* c, const double* part, int q, int off) {
 int launch_jac2_records(mpm_ctx* c, double* val, bool apply_bc) {
   if (c->n_row > 0) {
     k_jac2_rows<<<(unsigned)((c->n_row + JR - 1) / JR), 256, 0, c->stream>>>(
-        c->n_row, c->active_nodes.p, c->row_sim.p, c->sims.p, c->gstart.p, c->pdat.p, c->rowptr.p, c->colind.p,
-        apply_bc ? c->cmask.p : nullptr, val);
+        c->n_row, c->rgrp.p, c->pdat.p, c->rowptr.p, c->slot.p, apply_bc ? c->bcode.p : nullptr, val);
     LAUNCH_CHECK(c, "k_jac2_rows");
   }
   return MPM_OK;

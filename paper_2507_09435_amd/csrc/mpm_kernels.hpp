@@ -114,6 +114,8 @@ struct mpm_ctx {
   mpm::DBuf<int64_t> active_nodes;
   mpm::DBuf<int32_t> row_sim, rowcnt, rowptr, colind;
   mpm::DBuf<int8_t> slot;                      // [n_row][5^d] position in row or -1
+  mpm::DBuf<int32_t> rgrp;                     // 2-D: [n_row][9][2] particle range of each stencil group
+  mpm::DBuf<uint8_t> bcode;                    // 2-D, 2 unknowns: [n_row][25] constrained row (bits 2,3) / column (0,1) unknowns
   mpm::DBuf<mpm::RowBlock> blocks;
   mpm::DBuf<int32_t> blk_first;                // [nsim+1]
   mpm::DBuf<int32_t> flag;                     // device error flags

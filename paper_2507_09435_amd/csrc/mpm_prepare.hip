@@ -289,6 +289,51 @@ __global__ void k_rows(int mode, int64_t n_row, int dim, const int64_t* __restri
   if (mode == 0) rowcnt[r] = c;
 }
 
+// 2-D: per row (node a) and stencil group q, the group whose origin is
+// a - 2 + (q mod 3, q div 3) (in q's order, the groups whose 3x3 stencil may
+// hold a), its particle range [p0, p1) in sorted order; empty where that
+// origin lies outside the grid.  Node a sits at (2 - q mod 3, 2 - q div 3)
+// in the group's stencil, so the row gathers need nothing else of the node.
+__global__ void k_row_groups(int64_t n_row, const int64_t* __restrict__ active, const int32_t* __restrict__ row_sim,
+                             const SimDev* __restrict__ sims, const int32_t* __restrict__ gstart,
+                             int32_t* __restrict__ rgrp) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_row * 9) return;
+  const int64_t row = t / 9;
+  const int q = (int)(t % 9);
+  const SimDev& S = sims[row_sim[row]];
+  const int64_t nid = active[row] - S.node_base;
+  const int ix = (int)(nid % S.nna[0]) - 1, iy = (int)(nid / S.nna[0]) - 1;
+  const int oy = iy - 2 + q / 3, ox = ix - 2 + q % 3;
+  int32_t p0 = 0, p1 = 0;
+  if (oy >= -1 && oy <= S.n[1] - 1 && ox >= -1 && ox <= S.n[0] - 1) {
+    const int64_t key = S.okey_base + (ox + 1) + (int64_t)S.noa[0] * (oy + 1);
+    p0 = gstart[key];
+    p1 = gstart[key + 1];
+  }
+  rgrp[2 * t] = p0;
+  rgrp[2 * t + 1] = p1;
+}
+
+// 2-D with two unknowns per node: per row and stencil offset o (the slot
+// table's order), bits 0 and 1 mark the column node's constrained unknowns,
+// bits 2 and 3 the row's; 0 where the row has no block at o.
+__global__ void k_row_bc(int64_t n_row, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+                         const int8_t* __restrict__ slot, const uint8_t* __restrict__ cmask,
+                         uint8_t* __restrict__ bcode) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_row * 25) return;
+  const int64_t row = t / 25;
+  const int s = slot[t];
+  uint8_t code = 0;
+  if (s >= 0) {
+    const int64_t col = colind[rowptr[row] + s];
+    code = (uint8_t)((cmask[col * 2] ? 1 : 0) | (cmask[col * 2 + 1] ? 2 : 0) | (cmask[row * 2] ? 4 : 0) |
+                     (cmask[row * 2 + 1] ? 8 : 0));
+  }
+  bcode[t] = code;
+}
+
 // Sum of w * V0 per row (a row whose sum is zero carries no material).
 template <int DIM>
 __global__ void k_node_volume(int64_t np, const double* __restrict__ xs, const double* __restrict__ vs,
@@ -562,6 +607,15 @@ int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row_out, int6
                                                c->node_map.p, nullptr, c->rowptr.p, c->colind.p, c->slot.p);
     LAUNCH_CHECK(c, "k_rows fill");
   }
+  if (dim == 2) {
+    if (c->rgrp.ensure(std::max<int64_t>(1, n_row) * 18) != hipSuccess)
+      return c->fail(MPM_E_NOMEM, "row group table allocation failed");
+    if (n_row > 0) {
+      k_row_groups<<<nblk(n_row * 9), TPB, 0, c->stream>>>(n_row, c->active_nodes.p, c->row_sim.p, c->sims.p,
+                                                           c->gstart.p, c->rgrp.p);
+      LAUNCH_CHECK(c, "k_row_groups");
+    }
+  }
 
   // grid vectors
   const int64_t nv = n_row * nd;
@@ -596,6 +650,15 @@ int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row_out, int6
     k_cmask<<<nblk(n_row), TPB, 0, c->stream>>>(n_row, nd, c->active_nodes.p, pb->bc_mask, pb->bc_value,
                                                 pb->react_mask, c->nvol.p, c->cmask.p, c->cval.p, c->rmask.p);
     LAUNCH_CHECK(c, "k_cmask");
+  }
+  if (dim == 2 && nd == 2) {
+    if (c->bcode.ensure(std::max<int64_t>(1, n_row) * 25) != hipSuccess)
+      return c->fail(MPM_E_NOMEM, "row constraint table allocation failed");
+    if (n_row > 0) {
+      k_row_bc<<<nblk(n_row * 25), TPB, 0, c->stream>>>(n_row, c->rowptr.p, c->colind.p, c->slot.p, c->cmask.p,
+                                                        c->bcode.p);
+      LAUNCH_CHECK(c, "k_row_bc");
+    }
   }
 
   // row blocks (never spanning two sims)
