@@ -550,7 +550,7 @@ __global__ void __launch_bounds__(256) k_fint2_rec(AsmArgs A, const double* __re
 
 constexpr int RL2 = 16;   // lanes per row of the 2-D row gathers (9 stencil groups used)
 
-__global__ void __launch_bounds__(256) k_fint2_rows(int64_t n_row, int nd, int up,
+__global__ void __launch_bounds__(256, 8) k_fint2_rows(int64_t n_row, int nd, int up,
                                                    const int32_t* __restrict__ rgrp,
                                                    const double* __restrict__ rec, double* __restrict__ fint) {
   const int64_t row = ((int64_t)blockIdx.x * 256 + threadIdx.x) / RL2;
@@ -560,18 +560,18 @@ __global__ void __launch_bounds__(256) k_fint2_rows(int64_t n_row, int nd, int u
   if (q < 9) {
     const int p0 = rgrp[(row * 9 + q) * 2], p1 = rgrp[(row * 9 + q) * 2 + 1];
     const int ax = 2 - q % 3, ay = 2 - q / 3;   // node a's place in the group's 3x3 stencil
-    // the loads of up to four particles are issued before their sums, which
-    // take the particles in order
-    for (int pb = p0; pb < p1; pb += 4) {
-      double v[4][8];
+    // the loads of two particles are issued before their sums, which take
+    // the particles in order
+    for (int pb = p0; pb < p1; pb += 2) {
+      double v[2][8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 2; ++u) {
         const double* R = rec + (int64_t)min(pb + u, p1 - 1) * RD2;
         v[u][0] = R[0]; v[u][1] = R[1]; v[u][2] = R[2]; v[u][3] = R[3];
         v[u][4] = R[8 + ax]; v[u][5] = R[11 + ax]; v[u][6] = R[14 + ay]; v[u][7] = R[17 + ay];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 2; ++u) {
         if (pb + u >= p1) break;
         const double wx = v[u][4], dwx = v[u][5], wy = v[u][6], dwy = v[u][7];
         const double ga0 = dwx * wy, ga1 = wx * dwy;
