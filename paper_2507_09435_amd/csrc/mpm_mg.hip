@@ -251,86 +251,44 @@ __global__ void __launch_bounds__(ROWS_PER_BLOCK * LPR) k_mg_sweep_p(
   }
 }
 
-// b_c = R r_f on coarse row R of sim s (R = transpose of the linear
-// interpolation); constrained coarse unknowns get 0.
-__device__ __forceinline__ void mg_restrict_row(int64_t R, int s, const int64_t* __restrict__ c_active,
-                                                const SimDev* __restrict__ csims, const SimDev* __restrict__ fsims,
-                                                const int32_t* __restrict__ f_node_map,
-                                                const double* __restrict__ rf, const uint8_t* __restrict__ c_cmask,
-                                                double* __restrict__ bc) {
-  const SimDev& C = csims[s];
-  const SimDev& F = fsims[s];
-  const int64_t loc = c_active[R] - C.node_base;
-  const int I = (int)(loc % C.nna[0]) - 1, J = (int)(loc / C.nna[0]) - 1;
+// b_c = R r_f on one coarse row per thread (R = transpose of the linear
+// interpolation): fine node (2I + di, 2J + dj), di, dj in {-1, 0, 1}, weighs
+// (1 or 1/2 per axis); the restriction table lists its row in (dj, di) order,
+// -1 where it is off the grid or inactive.  Constrained coarse unknowns get 0.
+// The nine row loads are issued together, then the products are added in
+// table order.
+__global__ void k_mg_restrict(int64_t n_crow, const int32_t* __restrict__ rtab, const double* __restrict__ rf,
+                              const uint8_t* __restrict__ c_cmask, double* __restrict__ bc) {
+  const int64_t R = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (R >= n_crow) return;
+  int32_t fr[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) fr[q] = rtab[R * 9 + q];
   double a0 = 0.0, a1 = 0.0;
-  for (int dj = -1; dj <= 1; ++dj) {
-    const int j = 2 * J + dj;
-    if (j < -1 || j > F.n[1] + 1) continue;
-    const double wy = dj == 0 ? 1.0 : 0.5;
-    for (int di = -1; di <= 1; ++di) {
-      const int i = 2 * I + di;
-      if (i < -1 || i > F.n[0] + 1) continue;
-      const int32_t fr = f_node_map[F.node_base + (i + 1) + (int64_t)F.nna[0] * (j + 1)];
-      if (fr < 0) continue;
-      const double wgt = wy * (di == 0 ? 1.0 : 0.5);
-      a0 = fma(wgt, rf[(int64_t)fr * 2], a0);
-      a1 = fma(wgt, rf[(int64_t)fr * 2 + 1], a1);
-    }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    if (fr[q] < 0) continue;
+    const double wy = q / 3 == 1 ? 1.0 : 0.5;
+    const double wgt = wy * (q % 3 == 1 ? 1.0 : 0.5);
+    a0 = fma(wgt, rf[(int64_t)fr[q] * 2], a0);
+    a1 = fma(wgt, rf[(int64_t)fr[q] * 2 + 1], a1);
   }
   bc[R * 2] = c_cmask[R * 2] ? 0.0 : a0;
   bc[R * 2 + 1] = c_cmask[R * 2 + 1] ? 0.0 : a1;
 }
 
-// The restriction on one coarse row per thread.
-__global__ void k_mg_restrict(int64_t n_crow, const int64_t* __restrict__ c_active,
-                              const int32_t* __restrict__ c_rowsim, const SimDev* __restrict__ csims,
-                              const SimDev* __restrict__ fsims, const int32_t* __restrict__ f_node_map,
-                              const double* __restrict__ rf, const uint8_t* __restrict__ c_cmask,
-                              double* __restrict__ bc) {
-  const int64_t R = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (R >= n_crow) return;
-  mg_restrict_row(R, c_rowsim[R], c_active, csims, fsims, f_node_map, rf, c_cmask, bc);
-}
-
-// x_f += P x_c on fine row r of sim s; constrained fine unknowns keep
-// their value.
-__device__ __forceinline__ void mg_prolong_row(int64_t r, int s, const int64_t* __restrict__ f_active,
-                                               const SimDev* __restrict__ fsims, const SimDev* __restrict__ csims,
-                                               const int32_t* __restrict__ c_node_map,
-                                               const double* __restrict__ xc, const uint8_t* __restrict__ f_cmask,
-                                               double* __restrict__ xf) {
-  const SimDev& F = fsims[s];
-  const SimDev& C = csims[s];
-  const int64_t loc = f_active[r] - F.node_base;
-  const int i = (int)(loc % F.nna[0]) - 1, j = (int)(loc / F.nna[0]) - 1;
-  // coarse neighbours per axis: an even index maps to one node, an odd one to two
-  const int Ix0 = (i % 2 == 0) ? i / 2 : (i - 1) / 2, Ix1 = (i % 2 == 0) ? i / 2 : (i + 1) / 2;
-  const int Jy0 = (j % 2 == 0) ? j / 2 : (j - 1) / 2, Jy1 = (j % 2 == 0) ? j / 2 : (j + 1) / 2;
-  const double wx = Ix0 == Ix1 ? 1.0 : 0.5, wy = Jy0 == Jy1 ? 1.0 : 0.5;
-  double a0 = 0.0, a1 = 0.0;
-  for (int J = Jy0; J <= Jy1; ++J) {
-    if (J < -1 || J > C.n[1] + 1) continue;
-    for (int I = Ix0; I <= Ix1; ++I) {
-      if (I < -1 || I > C.n[0] + 1) continue;
-      const int32_t cr = c_node_map[C.node_base + (I + 1) + (int64_t)C.nna[0] * (J + 1)];
-      if (cr < 0) continue;
-      a0 = fma(wx * wy, xc[(int64_t)cr * 2], a0);
-      a1 = fma(wx * wy, xc[(int64_t)cr * 2 + 1], a1);
-    }
-  }
-  if (!f_cmask[r * 2]) xf[r * 2] += a0;
-  if (!f_cmask[r * 2 + 1]) xf[r * 2 + 1] += a1;
-}
-
-// The prolongation on one fine row per thread.
-__global__ void k_mg_prolong(int64_t n_frow, const int64_t* __restrict__ f_active,
-                             const int32_t* __restrict__ f_rowsim, const SimDev* __restrict__ fsims,
-                             const SimDev* __restrict__ csims, const int32_t* __restrict__ c_node_map,
+// x_f += P x_c on one fine row per thread, from the prolongation table (the
+// terms and order of mg_prolonged); constrained fine unknowns keep their
+// value.
+__global__ void k_mg_prolong(int64_t n_frow, const int32_t* __restrict__ ptab, const double* __restrict__ pw,
                              const double* __restrict__ xc, const uint8_t* __restrict__ f_cmask,
                              double* __restrict__ xf) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n_frow) return;
-  mg_prolong_row(r, f_rowsim[r], f_active, fsims, csims, c_node_map, xc, f_cmask, xf);
+  double x0, x1;
+  mg_prolonged(r, ptab, pw, xc, f_cmask, xf, x0, x1);
+  xf[r * 2] = x0;
+  xf[r * 2 + 1] = x1;
 }
 
 // Coarsest level: dense matrix of each sim (n_s = 2 * rows, stride nmax),
@@ -1153,8 +1111,8 @@ static int vcycle(mpm_ctx* c, size_t l, const double* b, double* out) {
   double* xc = CL->vec.p + 2 * C->n_row * 2;
   double* bc = CL->vec.p + 3 * C->n_row * 2;
   if (C->n_row) {
-    k_mg_restrict<<<nb256(C->n_row), 256, 0, c->lstream>>>(C->n_row, C->active_nodes.p, C->row_sim.p, C->sims.p,
-                                                          ctx->sims.p, ctx->node_map.p, r, C->cmask.p, bc);
+    k_mg_restrict<<<nb256(C->n_row), 256, 0, c->lstream>>>(C->n_row, c->mg_tab.p + c->mg_lvl_off[3 * (l + 1)], r,
+                                                          C->cmask.p, bc);
     LAUNCH_CHECK(c, "k_mg_restrict");
   }
   GUARD(vcycle(c, l + 1, bc, xc));
@@ -1171,9 +1129,9 @@ static int vcycle(mpm_ctx* c, size_t l, const double* b, double* out) {
     std::swap(xa, xb);
     k_post = 1;
   } else if (ctx->n_row) {
-    k_mg_prolong<<<nb256(ctx->n_row), 256, 0, c->lstream>>>(ctx->n_row, ctx->active_nodes.p, ctx->row_sim.p,
-                                                           ctx->sims.p, C->sims.p, C->node_map.p, xc,
-                                                           ctx->cmask.p, xa);
+    k_mg_prolong<<<nb256(ctx->n_row), 256, 0, c->lstream>>>(ctx->n_row, c->mg_tab.p + c->mg_lvl_off[3 * l + 1],
+                                                           c->mg_tabw.p + c->mg_lvl_off[3 * l + 2], xc, ctx->cmask.p,
+                                                           xa);
     LAUNCH_CHECK(c, "k_mg_prolong");
   }
   for (int k = k_post; k < MG_NU2; ++k) { GUARD(sweep(c, V, b, xa, xb, 1)); std::swap(xa, xb); }
