@@ -95,12 +95,12 @@ __global__ void k_mg_rec2(int64_t np, const double* __restrict__ xs, const int32
 // (2, 4 or 8): block k of the row adds into partial sum k mod 8 in ascending
 // k, and the 8 partial sums meet in a fixed butterfly (offsets 4, 2, 1),
 // the levels at offsets >= LPR inside the lane.
-template <int LPR>
-__device__ __forceinline__ void mg_sweep_row(int row, int lane, const int32_t* __restrict__ rowptr,
+template <int LPR, int mode>
+__device__ __forceinline__ void mg_sweep_row(int row, int lane, int k0r, int k1,
                                              const int32_t* __restrict__ colind, const double* __restrict__ val,
                                              const double* __restrict__ dinv, const double* __restrict__ b,
                                              const double* __restrict__ x_in, double* __restrict__ x_out,
-                                             double omega, int mode) {
+                                             double omega, bool live) {
   constexpr int VL = 8, NA = VL / LPR;
   static_assert(NA == 1 || NA == 2 || NA == 4, "LPR must be 2, 4 or 8");
   double a0 = 0.0, a1 = 0.0;
@@ -108,28 +108,51 @@ __device__ __forceinline__ void mg_sweep_row(int row, int lane, const int32_t* _
     double p0[NA], p1[NA];
 #pragma unroll
     for (int a = 0; a < NA; ++a) p0[a] = p1[a] = 0.0;
-    const int k1 = rowptr[row + 1];
-    for (int k0 = rowptr[row] + lane; k0 < k1; k0 += VL) {
+    // four steps of VL blocks at a time: every index, block and x entry of
+    // the batch is loaded before the first sum (indices past the row's end
+    // read its last block and are not added), then the sums take the blocks
+    // in the order of the one-step loop
+    constexpr int NS = 4;
+    for (int kb = k0r + lane; kb < k1; kb += NS * VL) {
+      int64_t cc[NS][NA];
+      double bl[NS][NA][4], xv[NS][NA][2];
 #pragma unroll
-      for (int a = 0; a < NA; ++a) {
-        const int k = k0 + a * LPR;
-        if (k < k1) {
-          const double* blk = val + (int64_t)k * 4;
-          const int64_t c = colind[k];
-          double x0, x1;
-          if (mode == 3) {
+      for (int j = 0; j < NS; ++j)
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          const int k = min(kb + j * VL + a * LPR, k1 - 1);
+          cc[j][a] = colind[k];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) bl[j][a][e] = val[(int64_t)k * 4 + e];
+        }
+      if (mode == 3) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j)
+#pragma unroll
+          for (int a = 0; a < NA; ++a) {
+            const int64_t c = cc[j][a];
             const double* Dc = dinv + c * 4;
             const double s0 = b[c * 2], s1 = b[c * 2 + 1];
-            x0 = fma(omega, dot2(Dc[0], s0, Dc[1], s1), 0.0);
-            x1 = fma(omega, dot2(Dc[2], s0, Dc[3], s1), 0.0);
-          } else {
-            x0 = x_in[c * 2];
-            x1 = x_in[c * 2 + 1];
+            xv[j][a][0] = fma(omega, dot2(Dc[0], s0, Dc[1], s1), 0.0);
+            xv[j][a][1] = fma(omega, dot2(Dc[2], s0, Dc[3], s1), 0.0);
           }
-          p0[a] = p0[a] + dot2(blk[0], x0, blk[1], x1);
-          p1[a] = p1[a] + dot2(blk[2], x0, blk[3], x1);
-        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < NS; ++j)
+#pragma unroll
+          for (int a = 0; a < NA; ++a) {
+            xv[j][a][0] = x_in[cc[j][a] * 2];
+            xv[j][a][1] = x_in[cc[j][a] * 2 + 1];
+          }
       }
+#pragma unroll
+      for (int j = 0; j < NS; ++j)
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
+          if (kb + j * VL + a * LPR < k1) {
+            p0[a] = p0[a] + dot2(bl[j][a][0], xv[j][a][0], bl[j][a][1], xv[j][a][1]);
+            p1[a] = p1[a] + dot2(bl[j][a][2], xv[j][a][0], bl[j][a][3], xv[j][a][1]);
+          }
     }
 #pragma unroll
     for (int m = NA / 2; m > 0; m >>= 1)
@@ -143,7 +166,7 @@ __device__ __forceinline__ void mg_sweep_row(int row, int lane, const int32_t* _
       a1 += __shfl_xor(a1, off, LPR);
     }
   }
-  if (lane == 0) {
+  if (lane == 0 && live) {
     const double r0 = b[(int64_t)row * 2] - a0, r1 = b[(int64_t)row * 2 + 1] - a1;
     if (mode == 2) {
       x_out[(int64_t)row * 2] = r0;
@@ -163,19 +186,24 @@ __device__ __forceinline__ void mg_sweep_row(int row, int lane, const int32_t* _
   }
 }
 
-// One sweep over the row blocks of a level; skips sims whose Krylov solve
-// is finished.
-template <int LPR>
+// One sweep over the rows of a level, 64 rows per workgroup in row order
+// (a sweep has no per-block sums, so rows need not follow the row blocks);
+// rows of sims whose Krylov solve is finished (flag set) write nothing.  The
+// row's sim and its flag are read beside the row pointers and the blocks,
+// and the flag is tested only at the write.
+template <int LPR, int mode>
 __global__ void __launch_bounds__(ROWS_PER_BLOCK * LPR) k_mg_sweep(
-    const RowBlock* __restrict__ blocks, const int32_t* __restrict__ simflag, const int32_t* __restrict__ rowptr,
-    const int32_t* __restrict__ colind, const double* __restrict__ val, const double* __restrict__ dinv,
-    const double* __restrict__ b, const double* __restrict__ x_in, double* __restrict__ x_out, double omega,
-    int mode) {
-  const RowBlock B = blocks[blockIdx.x];
-  if (simflag && simflag[2 * B.sim] >= 0) return;
+    int64_t n_row, const int32_t* __restrict__ row_sim, const int32_t* __restrict__ simflag,
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind, const double* __restrict__ val,
+    const double* __restrict__ dinv, const double* __restrict__ b, const double* __restrict__ x_in,
+    double* __restrict__ x_out, double omega) {
   const int lane = threadIdx.x % LPR, grp = threadIdx.x / LPR;
-  for (int row = B.row0 + grp; row < B.row1; row += ROWS_PER_BLOCK)
-    mg_sweep_row<LPR>(row, lane, rowptr, colind, val, dinv, b, x_in, x_out, omega, mode);
+  const int64_t row = (int64_t)blockIdx.x * ROWS_PER_BLOCK + grp;
+  if (row >= n_row) return;   // the row's LPR lanes leave together
+  const int k0r = rowptr[row], k1r = rowptr[row + 1];
+  const int s = row_sim[row];
+  const bool live = simflag[2 * s] < 0;
+  mg_sweep_row<LPR, mode>((int)row, lane, k0r, k1r, colind, val, dinv, b, x_in, x_out, omega, live);
 }
 
 // The first post-smoothing sweep with the prolongation folded in: every
@@ -1063,11 +1091,18 @@ struct LevelView {
 }
 
 static int sweep(mpm_ctx* c, const LevelView& L, const double* b, const double* xin, double* xout, int mode) {
-  const unsigned nbk = (unsigned)L.ctx->blocks_h.size();
-  if (!nbk) return MPM_OK;
-  k_mg_sweep<8><<<nbk, ROWS_PER_BLOCK * 8, 0, c->lstream>>>(L.ctx->blocks.p, c->simflag.p, L.ctx->rowptr.p,
-                                                          L.ctx->colind.p, L.val, L.dinv, b, xin, xout, MG_OMEGA,
-                                                          mode);
+  const int64_t n_row = L.ctx->n_row;
+  if (!n_row) return MPM_OK;
+  const unsigned g = (unsigned)((n_row + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK);
+  const unsigned t = ROWS_PER_BLOCK * 8;
+  const int32_t *rs = L.ctx->row_sim.p, *rp = L.ctx->rowptr.p, *ci = L.ctx->colind.p;
+  switch (mode) {
+    case 0: k_mg_sweep<8, 0><<<g, t, 0, c->lstream>>>(n_row, rs, c->simflag.p, rp, ci, L.val, L.dinv, b, xin, xout, MG_OMEGA); break;
+    case 1: k_mg_sweep<8, 1><<<g, t, 0, c->lstream>>>(n_row, rs, c->simflag.p, rp, ci, L.val, L.dinv, b, xin, xout, MG_OMEGA); break;
+    case 2: k_mg_sweep<8, 2><<<g, t, 0, c->lstream>>>(n_row, rs, c->simflag.p, rp, ci, L.val, L.dinv, b, xin, xout, MG_OMEGA); break;
+    case 3: k_mg_sweep<8, 3><<<g, t, 0, c->lstream>>>(n_row, rs, c->simflag.p, rp, ci, L.val, L.dinv, b, xin, xout, MG_OMEGA); break;
+    default: return c->fail(MPM_E_INVALID, "multigrid sweep mode");
+  }
   LAUNCH_CHECK(c, "k_mg_sweep");
   return MPM_OK;
 }
