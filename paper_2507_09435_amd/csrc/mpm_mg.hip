@@ -214,15 +214,27 @@ __device__ __forceinline__ void mg_prolonged(int64_t r, const int32_t* __restric
                                              const double* __restrict__ pw, const double* __restrict__ xc,
                                              const uint8_t* __restrict__ cmask, const double* __restrict__ x_in,
                                              double& x0, double& x1) {
-  const int32_t* tab = ptab + r * 4;
+  // the table lists its coarse rows first, then -1: every entry is loaded
+  // at once (a -1 entry reads this row's own x_in, always in bounds, and is
+  // not added) and the terms are added in table order
+  int32_t cr[4];
+  double v[4][2];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) cr[q] = ptab[r * 4 + q];
   const double w = pw[r];
-  double a0 = 0.0, a1 = 0.0;
+#pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int32_t cr = tab[q];
-    if (cr < 0) break;
-    a0 = fma(w, xc[(int64_t)cr * 2], a0);
-    a1 = fma(w, xc[(int64_t)cr * 2 + 1], a1);
+    const double* src = cr[q] >= 0 ? xc + (int64_t)cr[q] * 2 : x_in + r * 2;
+    v[q][0] = src[0];
+    v[q][1] = src[1];
   }
+  double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (cr[q] >= 0) {
+      a0 = fma(w, v[q][0], a0);
+      a1 = fma(w, v[q][1], a1);
+    }
   x0 = x_in[r * 2];
   x1 = x_in[r * 2 + 1];
   if (!cmask[r * 2]) x0 += a0;
@@ -231,51 +243,65 @@ __device__ __forceinline__ void mg_prolonged(int64_t r, const int32_t* __restric
 
 template <int LPR>
 __global__ void __launch_bounds__(ROWS_PER_BLOCK * LPR) k_mg_sweep_p(
-    const RowBlock* __restrict__ blocks, const int32_t* __restrict__ simflag, const int32_t* __restrict__ rowptr,
-    const int32_t* __restrict__ colind, const double* __restrict__ val, const double* __restrict__ dinv,
-    const double* __restrict__ b, const double* __restrict__ x_in, double* __restrict__ x_out, double omega,
-    const int32_t* __restrict__ ptab, const double* __restrict__ pw, const double* __restrict__ xc,
-    const uint8_t* __restrict__ cmask) {
-  const RowBlock B = blocks[blockIdx.x];
-  if (simflag && simflag[2 * B.sim] >= 0) return;
-  constexpr int VL = 8, NA = VL / LPR;
+    int64_t n_row, const int32_t* __restrict__ row_sim, const int32_t* __restrict__ simflag,
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind, const double* __restrict__ val,
+    const double* __restrict__ dinv, const double* __restrict__ b, const double* __restrict__ x_in,
+    double* __restrict__ x_out, double omega, const int32_t* __restrict__ ptab, const double* __restrict__ pw,
+    const double* __restrict__ xc, const uint8_t* __restrict__ cmask) {
+  constexpr int VL = 8, NA = VL / LPR, NS = 4;
   const int lane = threadIdx.x % LPR, grp = threadIdx.x / LPR;
-  for (int row = B.row0 + grp; row < B.row1; row += ROWS_PER_BLOCK) {
-    double p0[NA], p1[NA];
+  const int64_t row = (int64_t)blockIdx.x * ROWS_PER_BLOCK + grp;
+  if (row >= n_row) return;   // the row's LPR lanes leave together
+  // rows in row order, the sim's flag tested at the write (as k_mg_sweep)
+  const int k0r = rowptr[row], k1 = rowptr[row + 1];
+  const int s = row_sim[row];
+  const bool live = simflag[2 * s] < 0;
+  double p0[NA], p1[NA];
 #pragma unroll
-    for (int a = 0; a < NA; ++a) p0[a] = p1[a] = 0.0;
-    const int k1 = rowptr[row + 1];
-    for (int k0 = rowptr[row] + lane; k0 < k1; k0 += VL) {
+  for (int a = 0; a < NA; ++a) p0[a] = p1[a] = 0.0;
+  // batches of four steps, loaded before their sums (as mg_sweep_row)
+  for (int kb = k0r + lane; kb < k1; kb += NS * VL) {
+    int64_t cc[NS][NA];
+    double bl[NS][NA][4], xv[NS][NA][2];
+#pragma unroll
+    for (int j = 0; j < NS; ++j)
 #pragma unroll
       for (int a = 0; a < NA; ++a) {
-        const int k = k0 + a * LPR;
-        if (k < k1) {
-          const double* blk = val + (int64_t)k * 4;
-          double x0, x1;
-          mg_prolonged(colind[k], ptab, pw, xc, cmask, x_in, x0, x1);
-          p0[a] = p0[a] + dot2(blk[0], x0, blk[1], x1);
-          p1[a] = p1[a] + dot2(blk[2], x0, blk[3], x1);
-        }
+        const int k = min(kb + j * VL + a * LPR, k1 - 1);
+        cc[j][a] = colind[k];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bl[j][a][e] = val[(int64_t)k * 4 + e];
       }
-    }
 #pragma unroll
-    for (int m = NA / 2; m > 0; m >>= 1)
+    for (int j = 0; j < NS; ++j)
 #pragma unroll
-      for (int a = 0; a < m; ++a) { p0[a] += p0[a + m]; p1[a] += p1[a + m]; }
-    double a0 = p0[0], a1 = p1[0];
+      for (int a = 0; a < NA; ++a) mg_prolonged(cc[j][a], ptab, pw, xc, cmask, x_in, xv[j][a][0], xv[j][a][1]);
 #pragma unroll
-    for (int off = LPR / 2; off > 0; off >>= 1) {
-      a0 += __shfl_xor(a0, off, LPR);
-      a1 += __shfl_xor(a1, off, LPR);
-    }
-    if (lane == 0) {
-      const double r0 = b[(int64_t)row * 2] - a0, r1 = b[(int64_t)row * 2 + 1] - a1;
-      const double* D = dinv + (int64_t)row * 4;
-      double base0, base1;
-      mg_prolonged(row, ptab, pw, xc, cmask, x_in, base0, base1);
-      x_out[(int64_t)row * 2] = fma(omega, dot2(D[0], r0, D[1], r1), base0);
-      x_out[(int64_t)row * 2 + 1] = fma(omega, dot2(D[2], r0, D[3], r1), base1);
-    }
+    for (int j = 0; j < NS; ++j)
+#pragma unroll
+      for (int a = 0; a < NA; ++a)
+        if (kb + j * VL + a * LPR < k1) {
+          p0[a] = p0[a] + dot2(bl[j][a][0], xv[j][a][0], bl[j][a][1], xv[j][a][1]);
+          p1[a] = p1[a] + dot2(bl[j][a][2], xv[j][a][0], bl[j][a][3], xv[j][a][1]);
+        }
+  }
+#pragma unroll
+  for (int m = NA / 2; m > 0; m >>= 1)
+#pragma unroll
+    for (int a = 0; a < m; ++a) { p0[a] += p0[a + m]; p1[a] += p1[a + m]; }
+  double a0 = p0[0], a1 = p1[0];
+#pragma unroll
+  for (int off = LPR / 2; off > 0; off >>= 1) {
+    a0 += __shfl_xor(a0, off, LPR);
+    a1 += __shfl_xor(a1, off, LPR);
+  }
+  if (lane == 0 && live) {
+    const double r0 = b[row * 2] - a0, r1 = b[row * 2 + 1] - a1;
+    const double* D = dinv + row * 4;
+    double base0, base1;
+    mg_prolonged(row, ptab, pw, xc, cmask, x_in, base0, base1);
+    x_out[row * 2] = fma(omega, dot2(D[0], r0, D[1], r1), base0);
+    x_out[row * 2 + 1] = fma(omega, dot2(D[2], r0, D[3], r1), base1);
   }
 }
 
@@ -1154,11 +1180,12 @@ static int vcycle(mpm_ctx* c, size_t l, const double* b, double* out) {
   int k_post = 0;
   if (c->mg_fuse && MG_NU2 >= 1 && l >= 1) {   // prolongation folded into the first post-smoothing sweep
     // (coarse levels only: on the finest the per-neighbour table reads cost more than the launch)
-    const unsigned nbk = (unsigned)ctx->blocks_h.size();
-    if (nbk) {
-      k_mg_sweep_p<8><<<nbk, ROWS_PER_BLOCK * 8, 0, c->lstream>>>(
-          ctx->blocks.p, c->simflag.p, ctx->rowptr.p, ctx->colind.p, V.val, V.dinv, b, xa, xb, MG_OMEGA,
-          c->mg_tab.p + c->mg_lvl_off[3 * l + 1], c->mg_tabw.p + c->mg_lvl_off[3 * l + 2], xc, ctx->cmask.p);
+    if (ctx->n_row) {
+      k_mg_sweep_p<8><<<(unsigned)((ctx->n_row + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK), ROWS_PER_BLOCK * 8, 0,
+                        c->lstream>>>(
+          ctx->n_row, ctx->row_sim.p, c->simflag.p, ctx->rowptr.p, ctx->colind.p, V.val, V.dinv, b, xa, xb,
+          MG_OMEGA, c->mg_tab.p + c->mg_lvl_off[3 * l + 1], c->mg_tabw.p + c->mg_lvl_off[3 * l + 2], xc,
+          ctx->cmask.p);
       LAUNCH_CHECK(c, "k_mg_sweep_p");
     }
     std::swap(xa, xb);
