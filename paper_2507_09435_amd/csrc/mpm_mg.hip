@@ -549,13 +549,24 @@ struct TailRow {
 
 __device__ __forceinline__ void tail_load_row(const MgTailLevel& L, int row, int lane, TailRow& R, int r0) {
   const int k0 = L.rowptr[row], k1 = L.rowptr[row + 1];
+  // every load is issued unconditionally (slots past the row end read its
+  // first block and are then marked empty), so they are all in flight at once
+  int ci[MG_TAIL_KB];
+  double vv[MG_TAIL_KB][4];
 #pragma unroll
   for (int j = 0; j < MG_TAIL_KB; ++j) {
     const int k = k0 + lane + MG_TAIL_LPR * j;
-    const bool ok = k < k1;
-    R.col[j] = ok ? L.colind[k] - r0 : -1;
+    const int kc = k < k1 ? k : k0;   // a row holds at least its diagonal block
+    ci[j] = L.colind[kc];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) R.v[j][e] = ok ? L.val[(int64_t)k * 4 + e] : 0.0;
+    for (int e = 0; e < 4; ++e) vv[j][e] = L.val[(int64_t)kc * 4 + e];
+  }
+#pragma unroll
+  for (int j = 0; j < MG_TAIL_KB; ++j) {
+    const bool ok = k0 + lane + MG_TAIL_LPR * j < k1;
+    R.col[j] = ok ? ci[j] - r0 : -1;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) R.v[j][e] = ok ? vv[j][e] : 0.0;
   }
 #pragma unroll
   for (int e = 0; e < 4; ++e) R.D[e] = L.dinv[(int64_t)row * 4 + e];
@@ -645,20 +656,21 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const MgTailLevel* 
     double* bc = vec(Cl, 3);
     for (int t = tid; t < nc; t += MG_TAIL_THREADS) {
       const int32_t* tab = Cl.rtab + (int64_t)(c0 + t) * 9;
+      int32_t fr[9];   // the table and mask loads are issued together
+#pragma unroll
+      for (int q = 0; q < 9; ++q) fr[q] = tab[q];
+      const uint8_t m0 = Cl.cmask[(int64_t)(c0 + t) * 2], m1 = Cl.cmask[(int64_t)(c0 + t) * 2 + 1];
       double a0 = 0.0, a1 = 0.0;
-      int q = 0;
-      for (int dj = -1; dj <= 1; ++dj) {
-        const double wy = dj == 0 ? 1.0 : 0.5;
-        for (int di = -1; di <= 1; ++di, ++q) {
-          const int32_t fr = tab[q];
-          if (fr < 0) continue;
-          const double wgt = wy * (di == 0 ? 1.0 : 0.5);
-          a0 = fma(wgt, r[(fr - r0) * 2], a0);
-          a1 = fma(wgt, r[(fr - r0) * 2 + 1], a1);
-        }
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        if (fr[q] < 0) continue;
+        const double wy = q / 3 == 1 ? 1.0 : 0.5;
+        const double wgt = wy * (q % 3 == 1 ? 1.0 : 0.5);
+        a0 = fma(wgt, r[(fr[q] - r0) * 2], a0);
+        a1 = fma(wgt, r[(fr[q] - r0) * 2 + 1], a1);
       }
-      bc[t * 2] = Cl.cmask[(int64_t)(c0 + t) * 2] ? 0.0 : a0;
-      bc[t * 2 + 1] = Cl.cmask[(int64_t)(c0 + t) * 2 + 1] ? 0.0 : a1;
+      bc[t * 2] = m0 ? 0.0 : a0;
+      bc[t * 2 + 1] = m1 ? 0.0 : a1;
     }
     __syncthreads();
   }
@@ -689,16 +701,20 @@ __global__ void __launch_bounds__(MG_TAIL_THREADS) k_mg_tail(const MgTailLevel* 
     double* xb = pre_in_out ? y : out;
     for (int t = tid; t < n; t += MG_TAIL_THREADS) {
       const int32_t* tab = L.ptab + (int64_t)(r0 + t) * 4;
+      int32_t cr[4];   // coarse rows first, then -1; all loads issued together
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cr[q] = tab[q];
       const double w = L.pw[r0 + t];
+      const uint8_t m0 = L.cmask[(int64_t)(r0 + t) * 2], m1 = L.cmask[(int64_t)(r0 + t) * 2 + 1];
       double a0 = 0.0, a1 = 0.0;
-      for (int q = 0; q < 4; ++q) {
-        const int32_t cr = tab[q];
-        if (cr < 0) break;
-        a0 = fma(w, xc[(cr - c0) * 2], a0);
-        a1 = fma(w, xc[(cr - c0) * 2 + 1], a1);
-      }
-      if (!L.cmask[(int64_t)(r0 + t) * 2]) xa[t * 2] += a0;
-      if (!L.cmask[(int64_t)(r0 + t) * 2 + 1]) xa[t * 2 + 1] += a1;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (cr[q] >= 0) {
+          a0 = fma(w, xc[(cr[q] - c0) * 2], a0);
+          a1 = fma(w, xc[(cr[q] - c0) * 2 + 1], a1);
+        }
+      if (!m0) xa[t * 2] += a0;
+      if (!m1) xa[t * 2 + 1] += a1;
     }
     __syncthreads();
     for (int k = 0; k < MG_NU2; ++k) {
