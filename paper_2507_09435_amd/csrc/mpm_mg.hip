@@ -318,17 +318,27 @@ __global__ void k_mg_restrict(int64_t n_crow, const int32_t* __restrict__ rtab, 
   int32_t fr[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) fr[q] = rtab[R * 9 + q];
+  const uint8_t m0 = c_cmask[R * 2], m1 = c_cmask[R * 2 + 1];
+  // every fine value is loaded at once (a -1 entry reads fine row 0, which
+  // exists whenever this level has rows, and is not added)
+  double v[9][2];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const double* src = rf + (int64_t)(fr[q] < 0 ? 0 : fr[q]) * 2;
+    v[q][0] = src[0];
+    v[q][1] = src[1];
+  }
   double a0 = 0.0, a1 = 0.0;
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
     if (fr[q] < 0) continue;
     const double wy = q / 3 == 1 ? 1.0 : 0.5;
     const double wgt = wy * (q % 3 == 1 ? 1.0 : 0.5);
-    a0 = fma(wgt, rf[(int64_t)fr[q] * 2], a0);
-    a1 = fma(wgt, rf[(int64_t)fr[q] * 2 + 1], a1);
+    a0 = fma(wgt, v[q][0], a0);
+    a1 = fma(wgt, v[q][1], a1);
   }
-  bc[R * 2] = c_cmask[R * 2] ? 0.0 : a0;
-  bc[R * 2 + 1] = c_cmask[R * 2 + 1] ? 0.0 : a1;
+  bc[R * 2] = m0 ? 0.0 : a0;
+  bc[R * 2 + 1] = m1 ? 0.0 : a1;
 }
 
 // x_f += P x_c on one fine row per thread, from the prolongation table (the
