@@ -50,23 +50,59 @@ __device__ __forceinline__ void load_particle(const AsmArgs& A, int64_t i, const
 #pragma unroll
   for (int k = 0; k < DIM; ++k) L.gp[k] = 0.0;
   const int nd = A.nd;
-  for (int a = 0; a < Stencil<DIM>::NN; ++a) {
-    int32_t r = A.node_map[L.st.node(S, a)];
-    L.row[a] = r;
-    double g[DIM];
-    L.st.grad(a, g);
-    const double* u = du + (int64_t)r * nd;
+  if constexpr (DIM == 2) {
+    // every node-map load, then every increment load, is issued before the
+    // first sum (the u-p choice is made once, outside the node loop); the
+    // sums then take the nodes in order, as in the loop below
+    constexpr int NN = Stencil<2>::NN;
+    int32_t rr[NN];
 #pragma unroll
-    for (int q = 0; q < DIM; ++q) {
-      double uq = u[q];
+    for (int a = 0; a < NN; ++a) rr[a] = A.node_map[L.st.node(S, a)];
+    double uu[NN][3];
+    if (A.up) {
 #pragma unroll
-      for (int k = 0; k < DIM; ++k) L.dF[q][k] += uq * g[k];
+      for (int a = 0; a < NN; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) uu[a][c] = du[(int64_t)rr[a] * 3 + c];
+    } else {
+#pragma unroll
+      for (int a = 0; a < NN; ++a) {
+        uu[a][0] = du[(int64_t)rr[a] * 2];
+        uu[a][1] = du[(int64_t)rr[a] * 2 + 1];
+        uu[a][2] = 0.0;
+      }
     }
-    if (DIM == 2 && A.up) {
-      double pa = u[2];
-      L.pp += L.st.weight(a) * pa;
 #pragma unroll
-      for (int k = 0; k < DIM; ++k) L.gp[k] += pa * g[k];
+    for (int a = 0; a < NN; ++a) {
+      L.row[a] = rr[a];
+      double g[2];
+      L.st.grad(a, g);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const double uq = uu[a][q];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) L.dF[q][k] += uq * g[k];
+      }
+      if (A.up) {
+        const double pa = uu[a][2];
+        L.pp += L.st.weight(a) * pa;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) L.gp[k] += pa * g[k];
+      }
+    }
+  } else {
+    for (int a = 0; a < Stencil<DIM>::NN; ++a) {
+      int32_t r = A.node_map[L.st.node(S, a)];
+      L.row[a] = r;
+      double g[DIM];
+      L.st.grad(a, g);
+      const double* u = du + (int64_t)r * nd;
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) {
+        double uq = u[q];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) L.dF[q][k] += uq * g[k];
+      }
     }
   }
   L.v0 = A.vs[i];
