@@ -100,7 +100,7 @@ __device__ __forceinline__ void mg_sweep_row(int row, int lane, int k0r, int k1,
                                              const int32_t* __restrict__ colind, const double* __restrict__ val,
                                              const double* __restrict__ dinv, const double* __restrict__ b,
                                              const double* __restrict__ x_in, double* __restrict__ x_out,
-                                             double omega, bool live) {
+                                             double omega) {
   constexpr int VL = 8, NA = VL / LPR;
   static_assert(NA == 1 || NA == 2 || NA == 4, "LPR must be 2, 4 or 8");
   double a0 = 0.0, a1 = 0.0;
@@ -166,7 +166,7 @@ __device__ __forceinline__ void mg_sweep_row(int row, int lane, int k0r, int k1,
       a1 += __shfl_xor(a1, off, LPR);
     }
   }
-  if (lane == 0 && live) {
+  if (lane == 0) {
     const double r0 = b[(int64_t)row * 2] - a0, r1 = b[(int64_t)row * 2 + 1] - a1;
     if (mode == 2) {
       x_out[(int64_t)row * 2] = r0;
@@ -187,10 +187,10 @@ __device__ __forceinline__ void mg_sweep_row(int row, int lane, int k0r, int k1,
 }
 
 // One sweep over the rows of a level, 64 rows per workgroup in row order
-// (a sweep has no per-block sums, so rows need not follow the row blocks);
-// rows of sims whose Krylov solve is finished (flag set) write nothing.  The
-// row's sim and its flag are read beside the row pointers and the blocks,
-// and the flag is tested only at the write.
+// (a sweep has no per-block sums, so rows need not follow the row blocks).
+// A row reads its sim beside its row pointers; rows of sims whose Krylov
+// solve is finished (flag set) leave before their block loads, so a batch
+// does no work for its finished sims.
 template <int LPR, int mode>
 __global__ void __launch_bounds__(ROWS_PER_BLOCK * LPR) k_mg_sweep(
     int64_t n_row, const int32_t* __restrict__ row_sim, const int32_t* __restrict__ simflag,
@@ -201,9 +201,8 @@ __global__ void __launch_bounds__(ROWS_PER_BLOCK * LPR) k_mg_sweep(
   const int64_t row = (int64_t)blockIdx.x * ROWS_PER_BLOCK + grp;
   if (row >= n_row) return;   // the row's LPR lanes leave together
   const int k0r = rowptr[row], k1r = rowptr[row + 1];
-  const int s = row_sim[row];
-  const bool live = simflag[2 * s] < 0;
-  mg_sweep_row<LPR, mode>((int)row, lane, k0r, k1r, colind, val, dinv, b, x_in, x_out, omega, live);
+  if (simflag[2 * row_sim[row]] >= 0) return;   // the row's LPR lanes leave together
+  mg_sweep_row<LPR, mode>((int)row, lane, k0r, k1r, colind, val, dinv, b, x_in, x_out, omega);
 }
 
 // The first post-smoothing sweep with the prolongation folded in: every
@@ -252,10 +251,9 @@ __global__ void __launch_bounds__(ROWS_PER_BLOCK * LPR) k_mg_sweep_p(
   const int lane = threadIdx.x % LPR, grp = threadIdx.x / LPR;
   const int64_t row = (int64_t)blockIdx.x * ROWS_PER_BLOCK + grp;
   if (row >= n_row) return;   // the row's LPR lanes leave together
-  // rows in row order, the sim's flag tested at the write (as k_mg_sweep)
+  // rows in row order; rows of finished sims leave before their block loads (as k_mg_sweep)
   const int k0r = rowptr[row], k1 = rowptr[row + 1];
-  const int s = row_sim[row];
-  const bool live = simflag[2 * s] < 0;
+  if (simflag[2 * row_sim[row]] >= 0) return;   // the row's LPR lanes leave together
   double p0[NA], p1[NA];
 #pragma unroll
   for (int a = 0; a < NA; ++a) p0[a] = p1[a] = 0.0;
@@ -295,7 +293,7 @@ __global__ void __launch_bounds__(ROWS_PER_BLOCK * LPR) k_mg_sweep_p(
     a0 += __shfl_xor(a0, off, LPR);
     a1 += __shfl_xor(a1, off, LPR);
   }
-  if (lane == 0 && live) {
+  if (lane == 0) {
     const double r0 = b[row * 2] - a0, r1 = b[row * 2 + 1] - a1;
     const double* D = dinv + row * 4;
     double base0, base1;
