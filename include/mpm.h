@@ -191,21 +191,34 @@ typedef struct {
   int32_t *sim_iters;                   /* host [nsim] or NULL */
   int32_t *sim_converged;               /* host [nsim] or NULL */
   double *sim_reaction;                 /* host [nsim] or NULL: reaction at convergence */
+  double *sim_rel;                      /* host [nsim] or NULL: ||r_k|| / ||r_0|| at the last iterate
+                                           (the stopping tolerance each sim actually reached) */
+  int32_t precond_flags;                /* preconditioner faults seen during the step: 8 = a singular
+                                           or missing diagonal block was replaced by the identity in
+                                           block-Jacobi, 16 = a zero pivot in the coarsest multigrid
+                                           solve left a column unreduced (0: none) */
+  int32_t reserved;
 } mpm_newton_report;
 
 /* One load step of Newton's method (Sec. 2.2).  du: compact unknowns,
  * in = initial guess (constrained entries are overwritten by bc_value),
  * out = converged solution (NULL allowed when n_row is 0).  Requires
- * mpm_prepare for this problem.
+ * mpm_prepare for this problem.  With commit = 1 a successful step writes
+ * the end-of-step state into the problem's particle arrays, which ends the
+ * prepared state: the next residual, Jacobian, Newton or adjoint call needs
+ * a new mpm_prepare (else INVALID).
  * Errors: NOT_CONVERGED (du holds the last iterate, nothing committed),
- * KRYLOV, NONFINITE, INVALID, HIP.  Synchronises the stream. */
+ * KRYLOV (its message names a preconditioner fault when one was seen, see
+ * precond_flags), NONFINITE, INVALID, HIP.  Synchronises the stream. */
 int mpm_newton_step(mpm_ctx *ctx, const mpm_problem *prob, const mpm_newton_opts *opts, double *du,
                     mpm_newton_report *rep);
 
-/* End-of-step particle update at compact du (x += sum w du, F = dF F,
- * b^e = exp(2 eps^e)), written to x_out, F_out, be_out (may alias the
- * problem's arrays).  du may be NULL when n_row is 0.  Errors: INVALID,
- * RANGE, HIP. */
+/* End-of-step particle update (Sec. 2.2: the last stage of a step, after
+ * the grid solve, carries the converged increment back to the particles) at
+ * compact du: x += sum w du, F = dF F, b^e = exp(2 eps^e), written to x_out,
+ * F_out, be_out (may alias the problem's arrays; when one does, the prepared
+ * state ends as after a committed Newton step).  du may be NULL when n_row
+ * is 0.  Errors: INVALID, RANGE, HIP. */
 int mpm_update(mpm_ctx *ctx, const mpm_problem *prob, const double *du, double *x_out, double *F_out,
                double *be_out);
 
@@ -219,15 +232,21 @@ int mpm_update(mpm_ctx *ctx, const mpm_problem *prob, const double *du, double *
  * dL/ds_{n+1}, or NULL for zero.  Outputs: sbar_n (device [10][np], may be
  * NULL) = dL/ds_n; theta_bar (device [nsim][2]) = this step's contribution
  * to dL/dE and dL/dphi of each sim (E, phi per particle, summed per sim).
- * The transposed system uses the step's Dirichlet-modified Jacobian; its
- * solve runs to krylov_rtol (0: 1e-12); krylov_iters (host [nsim] or NULL).
+ * The transposed system uses the step's Dirichlet-modified Jacobian and is
+ * solved by block-Jacobi BiCGStab (GMRES(100) fallback, at most 20000
+ * iterations) to a true relative residual of krylov_rtol (0: 1e-12);
+ * krylov_iters (host [nsim] or NULL) and krylov_rel (host [nsim] or NULL:
+ * the true relative residual each sim reached) describe it.  A solve that
+ * stops above 10 x krylov_rtol returns KRYLOV: the gradient would carry its
+ * error (pass a looser krylov_rtol to accept that).
  * Errors: INVALID (not prepared, 3-D or u-p), NOMEM, KRYLOV, HIP. */
 int mpm_adjoint_step(mpm_ctx *ctx, const mpm_problem *prob, const double *du, const double *react_bar,
                      const double *sbar_next, double *sbar_n, double *theta_bar, double krylov_rtol,
-                     int32_t *krylov_iters);
+                     int32_t *krylov_iters, double *krylov_rel);
 
-/* y = J x with the BSR values val of this load step's pattern (the
- * matrix-vector product that drives the Krylov solve).  val [nnzb][ndof][ndof]
+/* y = J x with the BSR values val of this load step's pattern: the
+ * matrix-vector product that drives the preconditioned iterative solve of
+ * each Newton correction (Remark 2 of Sec. 2.2).  val [nnzb][ndof][ndof]
  * as returned by mpm_jacobian_bsr; x, y compact [n_row*ndof], must not
  * alias.  z (may be NULL): the product also forms the per-row-block partial
  * sums of z.y and y.y that the Krylov iteration fuses into it (kept in

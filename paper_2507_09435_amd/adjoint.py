@@ -35,6 +35,7 @@ class Run:
     increments: list               # per step: converged compact du (device)
     newton_iters: list
     krylov_iters: list
+    newton_rel: list               # per step: largest ||r||/||r_0|| over sims at the accepted iterate
 
 
 def make_batch(sims, E, phi):
@@ -55,26 +56,30 @@ def set_params(dp, sims, E, phi):
 
 
 def forward(ctx, dp, sims, steps, tol=1e-10, krylov_rtol=1e-12, max_iter=25, line_search=0, krylov_method=0,
-            progress=None):
+            stall_factor=1e3, progress=None):
     """Run the load steps of a batch, keeping checkpoints; progress(step,
-    report) is called after each step when given."""
+    report) is called after each step when given.  stall_factor = 0 makes
+    every step reach ||r|| <= tol ||r_0|| (no early stop at the round-off
+    floor), which the adjoint's r = 0 assumption and finite differences of
+    the reactions want; each step's reached ratio is kept in newton_rel."""
     import torch
     T = dp.tensors
-    R, cps, dus, nit, kit = [], [], [], [], []
+    R, cps, dus, nit, kit, rel = [], [], [], [], [], []
     for step in steps:
         M.set_bc(dp, [w.bc(step) for w in sims])
         cps.append((T["x"].clone(), T["F"].clone(), T["be"].clone()))
         n_row, nnzb, nd = M.mpm_prepare(ctx, dp)
         du = torch.zeros(n_row * nd, dtype=torch.float64, device=T["x"].device)
         rep = M.mpm_newton_step(ctx, dp, du, tol=tol, max_iter=max_iter, commit=True, krylov_rtol=krylov_rtol,
-                                line_search=line_search, krylov_method=krylov_method)
+                                line_search=line_search, krylov_method=krylov_method, stall_factor=stall_factor)
         R.append(rep["sim_reaction"])
+        rel.append(max(rep["sim_rel"]) if rep["sim_rel"] else 0.0)
         dus.append(du)
         nit.append(rep["iters"])
         if progress is not None:
             progress(step, rep)
         kit.append(rep["krylov_iters"])
-    return Run(dp, sims, list(steps), np.array(R), cps, dus, nit, kit)
+    return Run(dp, sims, list(steps), np.array(R), cps, dus, nit, kit, rel)
 
 
 def backward(ctx, run: Run, react_bar, krylov_rtol=1e-12, progress=None):

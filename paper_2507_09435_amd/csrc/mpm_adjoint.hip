@@ -233,7 +233,7 @@ int launch_tpos(mpm_ctx* c) {
 
 extern "C" int mpm_adjoint_step(mpm_ctx* c, const mpm_problem* pb, const double* du, const double* react_bar,
                                 const double* sbar_next, double* sbar_n, double* theta_bar, double krylov_rtol,
-                                int32_t* krylov_iters) {
+                                int32_t* krylov_iters, double* krylov_rel) {
   if (!c) return MPM_E_INVALID;
   c->err.clear();
   int rc = check_prepared(c, pb);
@@ -288,11 +288,23 @@ extern "C" int mpm_adjoint_step(mpm_ctx* c, const mpm_problem* pb, const double*
   std::vector<int> kit;
   c->ktrans = true;
   c->kmethod = 0;
-  rc = krylov_solve(c, c->val.p, krylov_rtol > 0 ? krylov_rtol : 1e-12, 20000, kit);
+  const double artol = krylov_rtol > 0 ? krylov_rtol : 1e-12;
+  rc = krylov_solve(c, c->val.p, artol, 20000, kit);
   c->ktrans = false;
   if (rc) return rc;
   if (krylov_iters)
     for (int s = 0; s < nsim; ++s) krylov_iters[s] = kit[s];
+  if (krylov_rel)
+    for (int s = 0; s < nsim; ++s) krylov_rel[s] = s < (int)c->kratio.size() ? c->kratio[s] : 0.0;
+  if (c->krylov_soft) {
+    // the Newton driver may continue from a stalled solve; a gradient may not
+    double worst = 0.0;
+    int ws = 0;
+    for (int s = 0; s < (int)c->kratio.size(); ++s)
+      if (c->kratio[s] > worst) { worst = c->kratio[s]; ws = s; }
+    return c->fail(MPM_E_KRYLOV, "transposed solve stalled at true relative residual " + std::to_string(worst) +
+                                     " (sim " + std::to_string(ws) + ") above krylov_rtol " + std::to_string(artol));
+  }
   k_nu<<<gv, 256, 0, c->stream>>>(nv, c->adj_mu.p, c->kx.p, c->adj_nu.p);
   LAUNCH_CHECK(c, "k_nu");
   // pass 2: state and parameter adjoints

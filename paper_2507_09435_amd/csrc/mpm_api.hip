@@ -176,6 +176,8 @@ int mpm_update(mpm_ctx* c, const mpm_problem* pb, const double* du, double* x_ou
   HIPC(c, hipSetDevice(c->device));
   HIPC(c, hipMemsetAsync(c->flag.p, 0, sizeof(int32_t), c->stream));
   GUARD(launch_update(c, pb, du, x_out, F_out, be_out));
+  if ((x_out && x_out == pb->P.x) || (F_out && F_out == pb->P.F) || (be_out && be_out == pb->P.be))
+    c->prepared = false;   // the problem's state has moved past the one prepare sorted
   int32_t hf = 0;
   HIPC(c, hipMemcpyAsync(&hf, c->flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   HIPC(c, hipStreamSynchronize(c->stream));
@@ -287,28 +289,31 @@ int mpm_newton_step(mpm_ctx* c, const mpm_problem* pb, const mpm_newton_opts* op
       std::vector<int> done(nsim, 0);
       for (int s = 0; s < nsim; ++s) if (!act[s]) { alpha[s] = 0.0; done[s] = 1; }
       const unsigned nbk = (unsigned)c->blocks_h.size();
-      for (int trial = 0; trial <= opts->line_search; ++trial) {
+      // step lengths 1, 1/2, ..., 2^-(L-1); a sim that finds no decrease in
+      // those L trials takes the full step
+      bool fallback = false;
+      for (int trial = 0; trial < opts->line_search; ++trial) {
         HIPC(c, hipMemcpyAsync(c->alpha.p, alpha.data(), nsim * sizeof(double), hipMemcpyHostToDevice, c->stream));
         k_trial<<<nbk, 64, 0, c->stream>>>(c->blocks.p, nd, c->alpha.p, c->du_base.p, c->kx.p, du);
         LAUNCH_CHECK(c, "k_trial");
         GUARD(launch_residual(c, pb, du, c->work.p, nullptr));
         HIPC(c, hipMemcpyAsync(sc.data(), c->simsc.p, 16 * nsim * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPC(c, hipStreamSynchronize(c->stream));
-        bool all_ok = true;
+        bool pending = false;
         for (int s = 0; s < nsim; ++s) {
           if (done[s]) continue;
           double nt = std::sqrt(sc[s * 16 + 0]);
           if (std::isfinite(nt) && nt < (1.0 - 1e-4 * alpha[s]) * prev[s]) { done[s] = 1; continue; }
-          if (trial == opts->line_search) { alpha[s] = 1.0; continue; }   // no decrease found: full step
+          if (trial + 1 == opts->line_search) { alpha[s] = 1.0; done[s] = 1; fallback = true; continue; }
           alpha[s] *= 0.5;
-          all_ok = false;
+          pending = true;
         }
-        if (all_ok) break;
-        if (trial == opts->line_search) {
-          HIPC(c, hipMemcpyAsync(c->alpha.p, alpha.data(), nsim * sizeof(double), hipMemcpyHostToDevice, c->stream));
-          k_trial<<<nbk, 64, 0, c->stream>>>(c->blocks.p, nd, c->alpha.p, c->du_base.p, c->kx.p, du);
-          LAUNCH_CHECK(c, "k_trial");
-        }
+        if (!pending) break;
+      }
+      if (fallback) {   // du still holds the last trial: rebuild it with the final step lengths
+        HIPC(c, hipMemcpyAsync(c->alpha.p, alpha.data(), nsim * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        k_trial<<<nbk, 64, 0, c->stream>>>(c->blocks.p, nd, c->alpha.p, c->du_base.p, c->kx.p, du);
+        LAUNCH_CHECK(c, "k_trial");
       }
     } else {
       k_axpy<<<g, 256, 0, c->stream>>>(nv, 1.0, c->kx.p, du);
@@ -324,8 +329,17 @@ int mpm_newton_step(mpm_ctx* c, const mpm_problem* pb, const mpm_newton_opts* op
   int32_t hf = 0;
   HIPC(c, hipMemcpyAsync(&hf, c->flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   HIPC(c, hipStreamSynchronize(c->stream));
+  if (status == MPM_E_KRYLOV && (hf & 24)) {
+    std::string why;
+    if (hf & 8) why += " a singular or missing diagonal block was replaced by the identity in block-Jacobi;";
+    if (hf & 16) why += " a zero pivot in the coarsest multigrid solve left a column unreduced;";
+    c->err += " (preconditioner faults:" + why + ")";
+  }
   if (status == MPM_OK && (hf & 4)) status = c->fail(MPM_E_RANGE, "elastic strain outside the log series range");
-  if (status == MPM_OK && opts->commit) GUARD(launch_update(c, pb, du, pb->P.x, pb->P.F, pb->P.be));
+  if (status == MPM_OK && opts->commit) {
+    GUARD(launch_update(c, pb, du, pb->P.x, pb->P.F, pb->P.be));
+    c->prepared = false;   // the sorted copies hold the step-start state, the caller's arrays the new one
+  }
   HIPC(c, hipEventRecord(ev[7], c->stream));
   HIPC(c, hipEventSynchronize(ev[7]));
   float tt = 0;
@@ -343,10 +357,12 @@ int mpm_newton_step(mpm_ctx* c, const mpm_problem* pb, const mpm_newton_opts* op
     rep->krylov_iters = kr_total;
     rep->ms_residual = ms_res; rep->ms_jacobian = ms_jac; rep->ms_krylov = ms_kry; rep->ms_total = tt;
     rep->spmv_ms = c->spmv_ms; rep->spmv_launches = c->spmv_n;
+    rep->precond_flags = hf & 24;
     for (int s = 0; s < nsim; ++s) {
       if (rep->sim_iters) rep->sim_iters[s] = iters[s];
       if (rep->sim_converged) rep->sim_converged[s] = conv[s];
       if (rep->sim_reaction) rep->sim_reaction[s] = react[s];
+      if (rep->sim_rel) rep->sim_rel[s] = norm0[s] > 0 ? prev[s] / norm0[s] : 0.0;
     }
   }
   c->time_spmv = 0;

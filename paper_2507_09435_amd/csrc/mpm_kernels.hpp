@@ -153,6 +153,7 @@ struct mpm_ctx {
   bool ktrans = false;                         // Krylov on J^T
   mpm::DBuf<double> dinvT, adj_mu, adj_nu, adj_theta, adj_rbar;
   bool krylov_soft = false;                    // last solve stopped at its floor above rtol
+  std::vector<double> kratio;                  // last solve: true relative residual per sim
   int time_spmv = 0;                           // sample period of SpMV timing (0: off)
   std::vector<hipEvent_t> spmv_events;
   double spmv_ms = 0.0;

@@ -1022,6 +1022,7 @@ int krylov_solve(mpm_ctx* c, const double* val, double rtol, int max_iter, std::
   // system is still a usable Newton direction when its true residual is at
   // most 1e-6 ||b||; the Newton test on the nonlinear residual decides.
   c->krylov_soft = !good && last_worst <= 1e-6;
+  c->kratio = ratio;
   const int status = (good || c->krylov_soft) ? MPM_OK : MPM_E_KRYLOV;
   if (!c->spmv_events.empty()) {
     HIPC(c, hipStreamSynchronize(c->stream));

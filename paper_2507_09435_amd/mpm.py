@@ -64,7 +64,8 @@ class mpm_newton_report(C.Structure):
                 ("ms_residual", C.c_double), ("ms_jacobian", C.c_double), ("ms_krylov", C.c_double),
                 ("ms_total", C.c_double), ("spmv_ms", C.c_double), ("spmv_launches", C.c_int64),
                 ("sim_iters", C.POINTER(C.c_int32)),
-                ("sim_converged", C.POINTER(C.c_int32)), ("sim_reaction", C.POINTER(C.c_double))]
+                ("sim_converged", C.POINTER(C.c_int32)), ("sim_reaction", C.POINTER(C.c_double)),
+                ("sim_rel", C.POINTER(C.c_double)), ("precond_flags", C.c_int32), ("reserved", C.c_int32)]
 
 
 EXPORTS = ["mpm_create", "mpm_destroy", "mpm_last_error", "mpm_prepare", "mpm_residual", "mpm_jacobian_bsr",
@@ -98,7 +99,7 @@ def load():
         "mpm_spmv_lanes": ([P], C.c_int),
         "mpm_spmv_set_lanes": ([P, C.c_int32], C.c_int),
         "mpm_adjoint_step": ([P, C.POINTER(mpm_problem), P, C.POINTER(C.c_double), P, P, P, C.c_double,
-                              C.POINTER(C.c_int32)], C.c_int),
+                              C.POINTER(C.c_int32), C.POINTER(C.c_double)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -257,14 +258,16 @@ def mpm_newton_step(ctx, dp: DeviceProblem, du, tol=1e-10, max_iter=25, commit=T
     it = (C.c_int32 * dp.nsim)()
     cv = (C.c_int32 * dp.nsim)()
     re = (C.c_double * dp.nsim)()
-    rep.sim_iters, rep.sim_converged, rep.sim_reaction = it, cv, re
+    rl = (C.c_double * dp.nsim)()
+    rep.sim_iters, rep.sim_converged, rep.sim_reaction, rep.sim_rel = it, cv, re, rl
     rc = load().mpm_newton_step(ctx, C.byref(dp.struct), C.byref(o), _ptr(du), C.byref(rep))
     out = {"status": rc, "iters": rep.iters, "converged": bool(rep.converged), "krylov_iters": rep.krylov_iters,
            "norms": list(rep.norms[:max(1, min(rep.iters + 1, MPM_MAX_REPORT))]),
            "krylov": list(rep.krylov[:max(0, min(rep.iters, MPM_MAX_REPORT))]),
            "ms_residual": rep.ms_residual, "ms_jacobian": rep.ms_jacobian, "ms_krylov": rep.ms_krylov,
            "ms_total": rep.ms_total, "spmv_ms": rep.spmv_ms, "spmv_launches": rep.spmv_launches,
-           "sim_iters": list(it), "sim_converged": list(cv), "sim_reaction": list(re)}
+           "sim_iters": list(it), "sim_converged": list(cv), "sim_reaction": list(re), "sim_rel": list(rl),
+           "precond_flags": rep.precond_flags}
     if rc != MPM_OK and raise_on_fail:
         _check(ctx, rc)
     return out
@@ -289,11 +292,14 @@ def mpm_spmv_set_lanes(ctx, lanes):
     _check(ctx, load().mpm_spmv_set_lanes(ctx, int(lanes)))
 
 
-def mpm_adjoint_step(ctx, dp: DeviceProblem, du, react_bar, sbar_next, sbar_n, theta_bar, krylov_rtol=1e-12):
+def mpm_adjoint_step(ctx, dp: DeviceProblem, du, react_bar, sbar_next, sbar_n, theta_bar, krylov_rtol=1e-12,
+                     with_rel=False):
     """One step's adjoint; react_bar is a host sequence [nsim].  Returns the
-    Krylov iterations of the transposed solve per sim."""
+    Krylov iterations of the transposed solve per sim (and, with with_rel,
+    the true relative residual each sim's solve reached)."""
     rb = (C.c_double * dp.nsim)(*[float(v) for v in react_bar])
     it = (C.c_int32 * dp.nsim)()
+    rl = (C.c_double * dp.nsim)()
     _check(ctx, load().mpm_adjoint_step(ctx, C.byref(dp.struct), _ptr(du), rb, _ptr(sbar_next), _ptr(sbar_n),
-                                        _ptr(theta_bar), float(krylov_rtol), it))
-    return list(it)
+                                        _ptr(theta_bar), float(krylov_rtol), it, rl))
+    return (list(it), list(rl)) if with_rel else list(it)

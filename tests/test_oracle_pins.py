@@ -291,6 +291,72 @@ def test_dp_matches_mohr_coulomb_on_meridian(match, meridian):
     assert abs(w[0] / w[2] - ratio) < 1e-12 * ratio
 
 
+def _plane_strain_mc_state(phi, sig_minor=-1.0e5):
+    """A plane-strain failure state of Mohr-Coulomb (c = 0) with its cone
+    slope, derived without the oracle: in-plane principal stresses in the
+    Mohr-Coulomb ratio (1 + sin phi) / (1 - sin phi); the out-of-plane stress
+    and the Drucker-Prager slope eta follow from two conditions on the cone
+    sqrt(J2) + eta p = 0: the state lies on it, and the associated flow
+    (normal s / (2 sqrt J2) + eta/3 1) has no out-of-plane component, as
+    plane strain requires of the plastic strain increment.  eta is the root
+    of a scalar equation (brentq), not a retyped formula."""
+    from scipy.optimize import brentq
+    sx = sig_minor
+    sy = sig_minor * (1 + math.sin(phi)) / (1 - math.sin(phi))
+
+    def state(eta):
+        p = (sx + sy) / (2.0 - 2.0 * eta * eta / 3.0)     # from s_zz = (2 eta^2 / 3) p and p = tr / 3
+        sz = p * (1.0 + 2.0 * eta * eta / 3.0)
+        return np.diag([sx, sy, sz])
+
+    def on_cone(eta):
+        p, _, q = _dp_invariants(state(eta))
+        return q + eta * p
+
+    eta = brentq(on_cone, 1e-6, 1.2, xtol=1e-15, rtol=1e-15)
+    return eta, state(eta)
+
+
+@pytest.mark.parametrize("phi_deg", [20.0, 30.0, 40.0])
+@pytest.mark.parametrize("c", [0.0, 5.0e3])
+@pytest.mark.parametrize("theta", [0.0, 0.3])
+def test_dp_plane_strain_match_reproduces_mohr_coulomb(phi_deg, c, theta):
+    """Plane-strain matched cone (dp_match 1) with associated flow: a trial
+    strain built from a Mohr-Coulomb plane-strain failure state (shifted by
+    c cot(phi) for cohesion, rotated in plane by theta) returns exactly to
+    that state with no out-of-plane plastic flow.  The outer cone does not
+    (so the check separates the two matches), and dp_match 1 with psi = phi
+    equals associated flow (the dilatancy slope uses the same match)."""
+    E, nu, phi = 1e7, 0.3, math.radians(phi_deg)
+    G, K = E / (2 * (1 + nu)), E / (3 * (1 - 2 * nu))
+    eta, tau0 = _plane_strain_mc_state(phi)
+    tau0 = tau0 + c / math.tan(phi) * np.eye(3)                # Mohr-Coulomb with cohesion: shifted apex
+    R = np.array([[math.cos(theta), -math.sin(theta), 0.0], [math.sin(theta), math.cos(theta), 0.0], [0, 0, 1.0]])
+    tau_star = R @ tau0 @ R.T
+    p, s, q = _dp_invariants(tau_star)
+    n = s / (2 * q) + eta / 3 * np.eye(3)
+    assert abs(n[2, 2]) <= 1e-14
+    ee_star = s / (2 * G) + p / (3 * K) * np.eye(3)           # Hencky: tau = K tr(eps) 1 + 2 G dev(eps)
+    dgam = 2e-3
+    eps_tr = ee_star + dgam * n
+    tau, ee, reg = ret(_cfg(dp=1, nu=nu, dp_match=5, c=c, phi=phi), E, phi, eps_tr)
+    assert reg == 1
+    scale = np.abs(tau_star).max()
+    assert np.abs(tau - tau_star).max() <= 1e-10 * scale, (tau, tau_star)
+    dep = eps_tr - ee
+    assert abs(dep[2, 2]) <= 1e-12 * np.abs(dep).max()
+    w = np.sort(np.linalg.eigvalsh(tau - c / math.tan(phi) * np.eye(3)))
+    inplane = sorted([w[0], w[2]] if abs(w[1] - tau0[2, 2] + c / math.tan(phi)) < 1e-6 * scale else [w[0], w[1]])
+    ratio = (1 + math.sin(phi)) / (1 - math.sin(phi))
+    assert abs(inplane[0] / inplane[1] - ratio) <= 1e-9 * ratio
+    # the outer cone (triaxial-compression match) returns elsewhere
+    tau_o, _, _ = ret(_cfg(dp=1, nu=nu, dp_match=4, c=c, phi=phi), E, phi, eps_tr)
+    assert np.abs(tau_o - tau_star).max() >= 1e-3 * scale
+    # non-associated with psi = phi is associated flow under the same match
+    tau_n, _, reg_n = ret(_cfg(dp=1, nu=nu, dp_match=1, c=c, phi=phi, psi=phi), E, phi, eps_tr)
+    assert reg_n == 1 and np.abs(tau_n - tau).max() <= 1e-12 * scale
+
+
 def test_dp_tangent_matches_fd():
     rng = np.random.default_rng(12)
     E, nu, phi = 1e7, 0.3, math.radians(30)
@@ -581,6 +647,34 @@ def terzaghi(z, t, cv, H, nterm=400):
         M = math.pi * (2 * m + 1) / 2
         s += 2 / M * np.sin(M * z / H) * math.exp(-M * M * T)
     return s
+
+
+def test_up_hydrostatic_column_has_no_fluid_flux():
+    """Gravity in the Darcy flux: a saturated column at rest with a
+    hydrostatic pore pressure p = rho_f |g| (H - y) (linear, so the B-spline
+    interpolation reproduces it and its gradient exactly) drives no flow,
+    grad p - rho_f g = 0, so every fluid row of the residual vanishes at
+    du = 0 (ln det dF = 0).  Dropping the gravity term leaves the flux of
+    grad p alone, and a sign error doubles it; both are far from zero."""
+    import dataclasses
+    w = W.make_c4(n=16, n_steps=1, width_cells=3, load=0.0, dt=50.0)
+    g = 9.81
+    P = dataclasses.replace(w.prob, g=(0.0, -g, 0.0))
+    st = w.particles
+    pat = O.pattern(P, st)
+    idx = P.node_grid_index()
+    y = P.x0[1] + idx[1] * P.h
+    dof = np.zeros((P.n_nodes, 3))
+    dof[:, 2] = P.rho_f * g * (1.0 - y)
+    fint, _ = O.forces(P, st, dof)
+    fluid = fint[pat.active, 2]
+    P0 = dataclasses.replace(P, g=(0.0, 0.0, 0.0))
+    fint0, _ = O.forces(P0, st, dof)
+    fluid0 = fint0[pat.active, 2]
+    assert np.linalg.norm(fluid0) > 0.0
+    assert np.abs(fluid).max() <= 1e-12 * np.abs(fluid0).max(), (np.abs(fluid).max(), np.abs(fluid0).max())
+    # the flux of grad p alone points upward (out of the top): the row sums of a closed column cancel
+    assert abs(fluid0.sum()) <= 1e-9 * np.abs(fluid0).sum()
 
 
 def test_up_consolidation_terzaghi():
