@@ -206,9 +206,15 @@ def test_problem_without_particles(ctx, method):
     M.mpm_jacobian_bsr(ctx, dp, None, rowptr=rowptr)
     torch.cuda.synchronize()
     assert int(rowptr.item()) == 0
-    rep = M.mpm_newton_step(ctx, dp, None, krylov_method=method)
+    rep = M.mpm_newton_step(ctx, dp, None, commit=False, krylov_method=method)
     assert rep["converged"] and rep["iters"] == 0 and rep["krylov_iters"] == 0
     M.mpm_update(ctx, dp, None, None, None, None)
+    # a committed step advances the problem's state: the context needs a new prepare
+    rep = M.mpm_newton_step(ctx, dp, None, commit=True, krylov_method=method)
+    assert rep["converged"]
+    with pytest.raises(M.MPMError) as ei:
+        M.mpm_update(ctx, dp, None, None, None, None)
+    assert ei.value.code == M.MPM_E_INVALID
 
 
 # ------------------------------------------------------- rejected inputs ---
