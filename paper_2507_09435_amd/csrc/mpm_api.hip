@@ -84,7 +84,7 @@ int check_prepared(mpm_ctx* c, const mpm_problem* pb) {
 void ctx_release(mpm_ctx* c) {
   mg_release(c);
   c->sims.release(); c->sim_start.release(); c->okey.release(); c->gcount.release(); c->gstart.release();
-  c->cursor.release(); c->okey_sorted.release(); c->sort_tmp.release(); c->perm.release(); c->psim.release(); c->scan_tmp.release(); c->node_flag.release();
+  c->cursor.release(); c->okey_sorted.release(); c->sort_hist.release(); c->sort_off.release(); c->perm.release(); c->psim.release(); c->scan_tmp.release(); c->node_flag.release();
   c->node_map.release(); c->active_nodes.release(); c->row_sim.release(); c->rowcnt.release(); c->rowptr.release();
   c->colind.release(); c->slot.release(); c->rgrp.release(); c->bcode.release(); c->blocks.release(); c->blk_first.release(); c->flag.release();
   c->xs.release(); c->vol0s.release(); c->Fs.release(); c->bes.release(); c->Es.release(); c->phis.release();

@@ -106,9 +106,9 @@ struct mpm_ctx {
   // sorting / pattern
   mpm::DBuf<mpm::SimDev> sims;
   mpm::DBuf<int64_t> sim_start;
-  mpm::DBuf<int32_t> okey, gcount, gstart, cursor, perm, psim;   // cursor: 0..np-1 for the key sort
+  mpm::DBuf<int32_t> okey, gcount, gstart, cursor, perm, psim;   // cursor: input indices between sort passes
   mpm::DBuf<int32_t> okey_sorted;
-  mpm::DBuf<uint8_t> sort_tmp;
+  mpm::DBuf<int32_t> sort_hist, sort_off;      // key sort: per (digit, tile) counts and their scan
   mpm::DBuf<int32_t> scan_tmp;
   mpm::DBuf<int32_t> node_flag, node_map;      // node_map: full node -> row or -1
   mpm::DBuf<int64_t> active_nodes;

@@ -1,8 +1,6 @@
 // Particle binning by B-spline stencil origin and the block-sparse Jacobian
 // pattern of one load step (Sec. 3.2: every particle couples the 3^d nodes
 // of its stencil, so a node row couples at most 5^d nodes, Table 1).
-#include <hipcub/hipcub.hpp>
-
 #include "mpm_kernels.hpp"
 #include "mpm_internal.hpp"
 
@@ -140,9 +138,75 @@ __global__ void k_hist(const int32_t* __restrict__ okey, int64_t np, int32_t* __
   }
 }
 
-__global__ void k_iota(int64_t np, int32_t* __restrict__ v) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < np) v[i] = (int32_t)i;
+// ------------------------------------------------- stable key sort ------
+// Least-significant-digit radix sort of (origin key, input index) with 8-bit
+// digits.  Every pass is a stable counting sort: per tile of RS_TILE input
+// positions a digit histogram, one exclusive scan over (digit, tile) in
+// digit-major order, then a scatter in which an element's place is its
+// digit's offset for its tile plus the number of equal digits before it in
+// the tile.  Equal keys therefore keep ascending input index, so a stencil
+// group's particles are in input order and the result is deterministic.
+constexpr int RS_TPB = 256, RS_ROUNDS = 8, RS_TILE = RS_TPB * RS_ROUNDS, RS_RADIX = 256;
+
+__global__ void __launch_bounds__(RS_TPB) k_rs_count(const int32_t* __restrict__ key, int64_t n, int shift,
+                                                      int64_t ntiles, int32_t* __restrict__ hist) {
+  __shared__ int32_t cnt[RS_RADIX];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  for (int j = 0; j < RS_ROUNDS; ++j) {
+    const int64_t i = base + (int64_t)j * RS_TPB + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[((uint32_t)key[i] >> shift) & (RS_RADIX - 1)], 1);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// off: exclusive scan of hist.  vin == nullptr means the identity (pass 0).
+// kout may be null (last pass: only the permutation is needed).
+__global__ void __launch_bounds__(RS_TPB) k_rs_scatter(const int32_t* __restrict__ kin, const int32_t* __restrict__ vin,
+                                                        int64_t n, int shift, int64_t ntiles,
+                                                        const int32_t* __restrict__ off, int32_t* __restrict__ kout,
+                                                        int32_t* __restrict__ vout) {
+  constexpr int NW = RS_TPB / 64;
+  __shared__ int32_t run[RS_RADIX];        // next free place of each digit for this tile
+  __shared__ int32_t wcnt[NW][RS_RADIX];   // this round: elements of each digit per wave
+  const int t = threadIdx.x, lane = t % 64, wv = t / 64;
+  run[t] = off[(int64_t)t * ntiles + blockIdx.x];
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  for (int j = 0; j < RS_ROUNDS; ++j) {
+#pragma unroll
+    for (int w = 0; w < NW; ++w) wcnt[w][t] = 0;
+    __syncthreads();
+    const int64_t i = base + (int64_t)j * RS_TPB + t;
+    const bool valid = i < n;
+    const int32_t k = valid ? kin[i] : 0;
+    const uint32_t d = ((uint32_t)k >> shift) & (RS_RADIX - 1);
+    // lanes of this wave holding the same digit, from one ballot per digit bit
+    uint64_t same = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t m = __ballot((d >> b) & 1u);
+      same &= ((d >> b) & 1u) ? m : ~m;
+    }
+    const int rank = __popcll(same & below);
+    if (valid && rank == 0) wcnt[wv][d] = __popcll(same);
+    __syncthreads();
+    int32_t pre = run[d];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) pre += (w < wv) ? wcnt[w][d] : 0;
+    if (valid) {
+      const int64_t pos = pre + rank;
+      if (kout) kout[pos] = k;
+      vout[pos] = vin ? vin[i] : (int32_t)i;
+    }
+    __syncthreads();   // every thread has read run[] for this round
+    int32_t tot = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) tot += wcnt[w][t];
+    run[t] += tot;
+  }
 }
 
 // Sorted SoA copies of the particle state.
@@ -544,17 +608,29 @@ int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row_out, int6
   if (np > 0) {
     // stable radix sort of (origin key, input index): each stencil group is
     // contiguous, ascending input index inside it (deterministic order)
-    k_iota<<<nblk(np), TPB, 0, c->stream>>>(np, c->cursor.p);
-    LAUNCH_CHECK(c, "k_iota");
     int bits = 1;
     while (bits < 31 && (int64_t(1) << bits) < ob) ++bits;
-    size_t tmp_bytes = 0;
-    HIPC(c, hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, c->okey.p, c->okey_sorted.p, c->cursor.p,
-                                               c->perm.p, (int)np, 0, bits, c->stream));
-    if (c->sort_tmp.ensure(std::max<size_t>(1, tmp_bytes)) != hipSuccess)
+    const int passes = (bits + 7) / 8;
+    const int64_t ntiles = (np + RS_TILE - 1) / RS_TILE;
+    if (c->sort_hist.ensure(RS_RADIX * ntiles + 1) != hipSuccess ||
+        c->sort_off.ensure(RS_RADIX * ntiles + 1) != hipSuccess)
       return c->fail(MPM_E_NOMEM, "sort scratch allocation failed");
-    HIPC(c, hipcub::DeviceRadixSort::SortPairs(c->sort_tmp.p, tmp_bytes, c->okey.p, c->okey_sorted.p, c->cursor.p,
-                                               c->perm.p, (int)np, 0, bits, c->stream));
+    const int32_t* kin = c->okey.p;
+    const int32_t* vin = nullptr;
+    for (int ps = 0; ps < passes; ++ps) {
+      const bool last = ps == passes - 1;
+      int32_t* kout = last ? nullptr : ((ps % 2 == 0) ? c->okey_sorted.p : c->okey.p);
+      int32_t* vout = ((passes - 1 - ps) % 2 == 0) ? c->perm.p : c->cursor.p;
+      k_rs_count<<<(unsigned)ntiles, RS_TPB, 0, c->stream>>>(kin, np, 8 * ps, ntiles, c->sort_hist.p);
+      LAUNCH_CHECK(c, "k_rs_count");
+      rc = scan_excl(c, c->sort_hist.p, RS_RADIX * ntiles, c->sort_off.p, nullptr);
+      if (rc) return rc;
+      k_rs_scatter<<<(unsigned)ntiles, RS_TPB, 0, c->stream>>>(kin, vin, np, 8 * ps, ntiles, c->sort_off.p, kout,
+                                                               vout);
+      LAUNCH_CHECK(c, "k_rs_scatter");
+      kin = kout;
+      vin = vout;
+    }
     k_gather<<<nblk(np), TPB, 0, c->stream>>>(np, dim, c->perm.p, psim_in, pb->P.x, pb->P.vol0, pb->P.F, pb->P.be,
                                               pb->P.E, pb->P.phi, c->xs.p, c->vol0s.p, c->Fs.p, c->bes.p, c->Es.p,
                                               c->phis.p, c->psim.p);
