@@ -204,6 +204,9 @@ struct Cfg {
   double rho0, g[3];
   double perm, mu_f, biot, rho_f, dt;
   double apex_reg;   // tangent of an apex return = apex_reg * trial elastic tangent
+  int32_t shape;     // 0 quadratic B-spline, 1 cpGIMP (convected particle domain)
+  int32_t pad_;
+  double lp0[3];     // cpGIMP: initial half-width of the particle domain per axis
 };
 
 struct Particles {
@@ -279,6 +282,41 @@ void bspline_axis(const T& u, int64_t o, T w[3], T dwdu[3]) {
 
 inline int64_t origin_axis(double x, double x0, double h) { return (int64_t)std::floor((x - x0) / h - 0.5); }
 
+// cpGIMP (Sec. 2.2 names the convected-particle-domain GIMP functions): the
+// weight of a node is the average of its linear hat function over the
+// particle's domain, a segment of half-width l (in cells) around the particle
+// along each axis.  With r = particle minus node position (cells):
+//   |r| < l          : 1 - (r^2 + l^2) / (2 l)
+//   l <= |r| < 1 - l : 1 - |r|
+//   1-l <= |r| < 1+l : (1 + l - |r|)^2 / (4 l)
+//   otherwise        : 0
+// For l <= 1/2 the nodes with a nonzero weight are o..o+2 of the B-spline
+// origin o, so the stencil and the block pattern are the B-spline ones.
+// dwdu is the derivative with respect to u = (x - x0)/h.
+template <class T>
+void gimp_axis(const T& u, int64_t o, const T& l, T w[3], T dwdu[3]) {
+  for (int a = 0; a < 3; ++a) {
+    T r = u - (double)(o + a);
+    double rv = val(r), lv = val(l);
+    double sg = rv < 0.0 ? -1.0 : 1.0;
+    T ar = r * sg;
+    if (std::fabs(rv) < lv) {
+      w[a] = 1.0 - (r * r + l * l) / (2.0 * l);
+      dwdu[a] = (-1.0) * r / l;
+    } else if (std::fabs(rv) < 1.0 - lv) {
+      w[a] = 1.0 - ar;
+      dwdu[a] = T(-sg);
+    } else if (std::fabs(rv) < 1.0 + lv) {
+      T e = 1.0 + l - ar;
+      w[a] = e * e / (4.0 * l);
+      dwdu[a] = (-sg) * e / (2.0 * l);
+    } else {
+      w[a] = T(0.0);
+      dwdu[a] = T(0.0);
+    }
+  }
+}
+
 template <class T>
 struct Stencil {
   int nn;              // 3^d
@@ -297,7 +335,13 @@ Stencil<T> make_stencil(const Cfg& c, const PState<T>& s) {
   for (int k = 0; k < d; ++k) {
     o[k] = origin_axis(val(s.x[k]), c.x0[k], c.h);
     T u = (s.x[k] - c.x0[k]) / c.h;
-    bspline_axis(u, o[k], w1[k], dw1[k]);
+    if (c.shape == 1) {
+      // the domain is convected with the stretch of its axis: l = lp0 F_kk
+      T l = s.F.a[k][k] * (c.lp0[k] / c.h);
+      gimp_axis(u, o[k], l, w1[k], dw1[k]);
+    } else {
+      bspline_axis(u, o[k], w1[k], dw1[k]);
+    }
     for (int a = 0; a < 3; ++a) dw1[k][a] = dw1[k][a] / c.h;
   }
   st.nn = (d == 2) ? 9 : 27;
@@ -336,6 +380,14 @@ Moduli<T> moduli(const T& E, double nu) {
 template <class T>
 void dp_coeffs(int match, const T& phi, double psi, T& eta, T& xi, T& etabar) {
   const double r3 = std::sqrt(3.0);
+  if (match == 3) {
+    // J2 (von Mises) as the pressure-independent cone: sqrt(2 J2) <= c, i.e.
+    // f = sqrt(J2) - c / sqrt(2) (Sec. 4.2, the elastoplastic bar); radial
+    // return without volume change
+    eta = T(0.0); xi = T(1.0 / std::sqrt(2.0)); etabar = T(0.0);
+    (void)phi; (void)psi;
+    return;
+  }
   if (match == 1) {
     T t = tan(phi);
     T den = sqrt(9.0 + 12.0 * t * t);
@@ -840,6 +892,11 @@ int orc_return_map_dir(const Cfg* c, double E, double phi, const double* eps_tr,
   int reg = hencky_dp(*c, Dual<1>(E), Dual<1>(phi), e, t, ee);
   for (int i = 0; i < 9; ++i) { tau[i] = t.a[i / 3][i % 3].v; dtau[i] = t.a[i / 3][i % 3].d[0]; }
   return reg; }
+int orc_gimp(double u, int64_t o, double l, double* w, double* dw) {
+  gimp_axis<double>(u, o, l, w, dw);
+  return 0;
+}
+
 int orc_bspline(double u, int64_t o, double* w, double* dw) {
   bspline_axis(u, o, w, dw); return 0; }
 

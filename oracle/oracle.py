@@ -51,7 +51,8 @@ class _Cfg(C.Structure):
                 ("E", C.c_double), ("nu", C.c_double), ("phi", C.c_double), ("c", C.c_double),
                 ("psi", C.c_double), ("rho0", C.c_double), ("g", C.c_double * 3),
                 ("perm", C.c_double), ("mu_f", C.c_double), ("biot", C.c_double),
-                ("rho_f", C.c_double), ("dt", C.c_double), ("apex_reg", C.c_double)]
+                ("rho_f", C.c_double), ("dt", C.c_double), ("apex_reg", C.c_double),
+                ("shape", C.c_int32), ("pad_", C.c_int32), ("lp0", C.c_double * 3)]
 
 
 class _Particles(C.Structure):
@@ -83,6 +84,7 @@ def lib():
             ("orc_return_map", [P, C.c_double, C.c_double, P, P, P]),
             ("orc_return_map_dir", [P, C.c_double, C.c_double, P, P, P, P]),
             ("orc_bspline", [C.c_double, C.c_int64, P, P]),
+            ("orc_gimp", [C.c_double, C.c_int64, C.c_double, P, P]),
             ("orc_forces_tan", [P, P, P, P, P, P, P, P, P]),
             ("orc_update_tan", [P, P, P, P, P, P, P, P, P, P, P]),
         ]:
@@ -112,6 +114,10 @@ def cfg(prob) -> _Cfg:
     c.rho0, c.perm, c.mu_f, c.biot, c.rho_f, c.dt = (float(v) for v in (
         prob.rho0, prob.perm, prob.mu_f, prob.biot, prob.rho_f, prob.dt))
     c.apex_reg = float(getattr(prob, "apex_reg", 0.0))
+    c.shape = int(getattr(prob, "shape", 0))
+    lp0 = getattr(prob, "lp0", (0.0, 0.0, 0.0))
+    for k in range(3):
+        c.lp0[k] = float(lp0[k]) if k < len(lp0) else 0.0
     return c
 
 

@@ -58,6 +58,8 @@ class Problem:
     rho_f: float = 1000.0
     dt: float = 1.0
     apex_reg: float = 1e-6          # tangent scale of apex returns (values are exact)
+    shape: int = 0                # 0 quadratic B-splines, 1 cpGIMP
+    lp0: tuple = (0.0, 0.0, 0.0)  # cpGIMP: initial half-width of the particle domain per axis
     name: str = ""
 
     @property
@@ -175,12 +177,13 @@ class Workload:
 
 
 # ---------------------------------------------------------------- builders --
-def gauss_particles(dim: int, h: float, x0, cell_lo, cell_hi):
-    """2 Gauss points per axis in every cell of the box [cell_lo, cell_hi).
-    Order: cells x fastest, then Gauss points x fastest."""
+def gauss_particles(dim: int, h: float, x0, cell_lo, cell_hi, points=GAUSS_1D):
+    """2 points per axis in every cell of the box [cell_lo, cell_hi), at the
+    given cell fractions (default: the 2-point Gauss rule).  Order: cells x
+    fastest, then points x fastest."""
     cells = [np.arange(cell_lo[k], cell_hi[k]) for k in range(dim)]
     cmesh = [m.reshape(-1) for m in np.meshgrid(*cells[::-1], indexing="ij")[::-1]]
-    gp = [np.array(GAUSS_1D)] * dim
+    gp = [np.array(points)] * dim
     gmesh = [m.reshape(-1) for m in np.meshgrid(*gp[::-1], indexing="ij")[::-1]]
     nc, ng = cmesh[0].shape[0], gmesh[0].shape[0]
     x = np.empty((dim, nc * ng))
@@ -334,13 +337,23 @@ def small_footing(n_y: int = 8, n_steps: int = 3, E=1e7, phi_deg=30.0) -> Worklo
 
 
 def bar_column(n_cells: int = 64, l0: float = 50.0, rho0: float = 80.0, E: float = 1e4, nu: float = 0.0,
-               n_steps: int = 40) -> Workload:
+               n_steps: int = 40, j2_yield: float | None = None, cpgimp: bool = False) -> Workload:
     """Bar compaction under self-weight (paper Sec. 4.2 geometry): a one-cell
     wide plane-strain column of height l0 with 2x2 particles per cell,
-    rollers on both sides, fixed base; gravity is ramped over n_steps."""
+    rollers on both sides, fixed base; gravity is ramped over n_steps.
+    j2_yield: the elastoplastic case, J2 plasticity with sqrt(2 J2) <= j2_yield
+    (5 kPa in the paper); cpgimp: the paper's shape functions (particle domain
+    half-width h/4 per axis, 2 particles per cell and axis)."""
     h = l0 / n_cells
     P = Problem(dim=2, n=(1, n_cells, 0), h=h, E=E, nu=nu, rho0=rho0, g=(0.0, -9.81, 0.0), name="bar")
-    x = gauss_particles(2, h, (0.0, 0.0), (0, 0), (1, n_cells))
+    if j2_yield is not None:
+        P.dp, P.dp_match, P.c = 1, 3, float(j2_yield)
+    if cpgimp:
+        # particle domains of half-width h/4 around the cell quarter points tile the bar
+        P.shape, P.lp0 = 1, (h / 4.0, h / 4.0, 0.0)
+        x = gauss_particles(2, h, (0.0, 0.0), (0, 0), (1, n_cells), points=(0.25, 0.75))
+    else:
+        x = gauss_particles(2, h, (0.0, 0.0), (0, 0), (1, n_cells))
     parts = identity_state(2, x, h, 4)
     walls = [(0, "lo", 2, (0,)), (1, "lo", 0, (0, 1))]   # every x-node is a roller
     return Workload(P, parts, n_steps=n_steps, walls=walls)
