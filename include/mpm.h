@@ -117,7 +117,10 @@ typedef struct {
 typedef struct mpm_ctx mpm_ctx;
 
 /* Create a context bound to a device and a stream (hipStream_t as void*, NULL
- * = the null stream).  *ctx receives the handle.  Errors: INVALID, HIP. */
+ * = the null stream).  *ctx receives the handle.  The first context on a
+ * device also looks up that device's address of the fixed scratch array of
+ * mpm_residual_noalloc.  Errors: INVALID (device out of range, or at or
+ * above MPM_MAX_DEVICES), HIP. */
 int mpm_create(mpm_ctx **ctx, int device, void *stream);
 /* Release the context and all library scratch.  Accepts NULL. */
 int mpm_destroy(mpm_ctx *ctx);
@@ -145,6 +148,24 @@ int mpm_prepare(mpm_ctx *ctx, const mpm_problem *prob, int64_t *n_row, int64_t *
  * Errors: INVALID (no prepare / different problem), HIP. */
 int mpm_residual(mpm_ctx *ctx, const mpm_problem *prob, const double *du, double *r, double *r_raw,
                  double *reaction);
+
+/* mpm_residual without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, results and errors as mpm_residual (the
+ * same kernels, so the same bits); the context must be prepared
+ * (mpm_prepare allocates the pattern and the vectors).  The per-particle
+ * force records the residual needs (np * 160 bytes in plane strain,
+ * np * 224 bytes in 3-D) go to a fixed library-owned device array of
+ * MPM_NOALLOC_SCRATCH_BYTES per device instead of context memory; a larger
+ * problem is rejected with INVALID.  The array is shared by every call on
+ * that device and keeps the last call's contents (nothing in it needs to
+ * start at zero): calls that overlap on one device, from any contexts or
+ * streams, race and must be serialised by the caller.  reaction (host) makes
+ * the call synchronise the stream; without it the call is asynchronous. */
+#define MPM_NOALLOC_SCRATCH_BYTES (32u << 20)
+#define MPM_MAX_DEVICES 64
+int mpm_residual_noalloc(mpm_ctx *ctx, const mpm_problem *prob, const double *du, double *r, double *r_raw,
+                         double *reaction);
 
 /* Jacobian J = dr/d(du) at du in BSR form (Sec. 3.2): rowptr [n_row+1],
  * colind [nnzb] (ascending per row), val [nnzb][ndof][ndof] row-major

@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "mpm_internal.hpp"
@@ -37,6 +38,31 @@ __global__ void k_trial(const RowBlock* __restrict__ blocks, int nd, const doubl
   for (int c = 0; c < nd; ++c) du[row * nd + c] = base[row * nd + c] + a * x[row * nd + c];
 }
 }  // namespace mpm
+
+// Scratch of mpm_residual_noalloc: the residual's per-particle force records
+// in a fixed device array, so that call allocates nothing.  Each device the
+// library runs on holds its own copy for the life of the process; host code
+// reaches it only through the address hipGetSymbolAddress returns on that
+// device (noalloc_scratch_ptr), never through the symbol itself.
+static __device__ __align__(256) double scratch[MPM_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[MPM_MAX_DEVICES] = {};
+
+// Called with `device` current (mpm_create).
+static int noalloc_scratch_setup(int device) {
+  if (device < 0 || device >= MPM_MAX_DEVICES) return MPM_E_INVALID;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return MPM_OK;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return MPM_E_HIP;
+  g_scratch_ptr[device] = ptr;
+  return MPM_OK;
+}
+
+static double* noalloc_scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (device >= 0 && device < MPM_MAX_DEVICES) ? (double*)g_scratch_ptr[device] : nullptr;
+}
 
 int validate_problem(mpm_ctx* c, const mpm_problem* pb) {
   if (!pb) return c->fail(MPM_E_INVALID, "problem is NULL");
@@ -106,6 +132,9 @@ int mpm_create(mpm_ctx** out, int device, void* stream) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return MPM_E_INVALID;
   if (hipSetDevice(device) != hipSuccess) return MPM_E_HIP;
+  if (device >= MPM_MAX_DEVICES) return MPM_E_INVALID;
+  const int src = noalloc_scratch_setup(device);
+  if (src) return src;
   mpm_ctx* c = new (std::nothrow) mpm_ctx();
   if (!c) return MPM_E_NOMEM;
   c->device = device;
@@ -144,6 +173,31 @@ int mpm_residual(mpm_ctx* c, const mpm_problem* pb, const double* du, double* r,
     HIPC(c, hipMemcpyAsync(sc.data(), c->simsc.p, sc.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPC(c, hipStreamSynchronize(c->stream));
     for (int s = 0; s < c->nsim; ++s) reaction[s] = -sc[s * 16 + 1];
+  }
+  return MPM_OK;
+}
+
+int mpm_residual_noalloc(mpm_ctx* c, const mpm_problem* pb, const double* du, double* r, double* r_raw,
+                         double* reaction) {
+  if (!c) return MPM_E_INVALID;
+  c->err.clear();
+  GUARD(check_prepared(c, pb));
+  if (!du && c->n_row) return c->fail(MPM_E_INVALID, "du is NULL");
+  const int64_t need = c->np * fint_record_doubles(c->dim) * (int64_t)sizeof(double);
+  if (need > (int64_t)MPM_NOALLOC_SCRATCH_BYTES)
+    return c->fail(MPM_E_INVALID, "mpm_residual_noalloc: " + std::to_string(c->np) + " particles need " +
+                                      std::to_string(need) + " bytes of scratch, more than its fixed " +
+                                      std::to_string((long long)MPM_NOALLOC_SCRATCH_BYTES));
+  HIPC(c, hipSetDevice(c->device));
+  double* rec = noalloc_scratch_ptr(c->device);
+  if (!rec) return c->fail(MPM_E_HIP, "scratch address of this device is not set up");
+  GUARD(launch_residual(c, pb, du, r, r_raw, rec));
+  if (reaction) {
+    // column 1 of the per-sim scalars [nsim][16], straight into the caller's array
+    HIPC(c, hipMemcpy2DAsync(reaction, sizeof(double), c->simsc.p + 1, 16 * sizeof(double), sizeof(double),
+                             c->nsim, hipMemcpyDeviceToHost, c->stream));
+    HIPC(c, hipStreamSynchronize(c->stream));
+    for (int s = 0; s < c->nsim; ++s) reaction[s] = -reaction[s];
   }
   return MPM_OK;
 }

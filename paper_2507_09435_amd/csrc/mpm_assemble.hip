@@ -998,19 +998,27 @@ int launch_p2g3(mpm_ctx* c, int mode, const double* rec, double* out) {
   return MPM_OK;
 }
 
-int launch_fint(mpm_ctx* c, const mpm_problem* pb, const double* du) {
+// Doubles per particle of the residual's force records.
+int64_t fint_record_doubles(int dim) { return dim == 2 ? RD2 : PR3; }
+
+// f_int into c->fint.  rec: the force records (np * fint_record_doubles
+// doubles); null uses the context's own buffer (allocated on first use).
+int launch_fint(mpm_ctx* c, const mpm_problem* pb, const double* du, double* rec) {
   AsmArgs A = make_args(c, pb);
+  if (!rec) {
+    if (c->rrec.ensure(std::max<int64_t>(1, c->np) * fint_record_doubles(c->dim)) != hipSuccess)
+      return c->fail(MPM_E_NOMEM, "residual records allocation failed");
+    rec = c->rrec.p;
+  }
   if (c->dim == 2) {
     // particle records, then one writer per row (deterministic, no clearing)
-    if (c->rrec.ensure(std::max<int64_t>(1, c->np) * RD2) != hipSuccess)
-      return c->fail(MPM_E_NOMEM, "residual records allocation failed");
     if (c->np > 0) {
-      k_fint2_rec<<<(unsigned)((c->np + 255) / 256), 256, 0, c->stream>>>(A, du, c->rrec.p);
+      k_fint2_rec<<<(unsigned)((c->np + 255) / 256), 256, 0, c->stream>>>(A, du, rec);
       LAUNCH_CHECK(c, "k_fint2_rec");
     }
     if (c->n_row > 0) {
       k_fint2_rows<<<(unsigned)((c->n_row * RL2 + 255) / 256), 256, 0, c->stream>>>(
-          c->n_row, c->nd, c->up, c->rgrp.p, c->rrec.p, c->fint.p);
+          c->n_row, c->nd, c->up, c->rgrp.p, rec, c->fint.p);
       LAUNCH_CHECK(c, "k_fint2_rows");
     }
     return MPM_OK;
@@ -1018,15 +1026,14 @@ int launch_fint(mpm_ctx* c, const mpm_problem* pb, const double* du) {
   HIPC(c, hipMemsetAsync(c->fint.p, 0, c->n_row * c->nd * sizeof(double), c->stream));
   if (c->np == 0) return MPM_OK;
   // force records, then the 27 colours of stencil groups in order
-  if (c->rrec.ensure(c->np * PR3) != hipSuccess) return c->fail(MPM_E_NOMEM, "3-D force records allocation failed");
-  k_fint3_rec<<<(unsigned)((c->np + 255) / 256), 256, 0, c->stream>>>(A, du, c->rrec.p, c->flag.p);
+  k_fint3_rec<<<(unsigned)((c->np + 255) / 256), 256, 0, c->stream>>>(A, du, rec, c->flag.p);
   LAUNCH_CHECK(c, "k_fint3_rec");
-  return launch_p2g3(c, 0, c->rrec.p, c->fint.p);
+  return launch_p2g3(c, 0, rec, c->fint.p);
 }
 
 // Residual with per-sim ||r||^2 -> simsc[s*16+0], reaction -> simsc[s*16+1].
-int launch_residual(mpm_ctx* c, const mpm_problem* pb, const double* du, double* r, double* r_raw) {
-  int rc = launch_fint(c, pb, du);
+int launch_residual(mpm_ctx* c, const mpm_problem* pb, const double* du, double* r, double* r_raw, double* rec) {
+  int rc = launch_fint(c, pb, du, rec);
   if (rc) return rc;
   unsigned nbk = (unsigned)c->blocks_h.size();
   if (nbk) {

@@ -98,8 +98,10 @@ namespace mpm {
 int scan_excl(mpm_ctx* c, const int32_t* in, int64_t n, int32_t* out, int32_t* total);
 }
 int sim_sum_launch(mpm_ctx* c, const double* part, int q, int off);
-int launch_fint(mpm_ctx* c, const mpm_problem* pb, const double* du);
-int launch_residual(mpm_ctx* c, const mpm_problem* pb, const double* du, double* r, double* r_raw);
+int64_t fint_record_doubles(int dim);
+int launch_fint(mpm_ctx* c, const mpm_problem* pb, const double* du, double* rec = nullptr);
+int launch_residual(mpm_ctx* c, const mpm_problem* pb, const double* du, double* r, double* r_raw,
+                    double* rec = nullptr);
 int launch_jacobian(mpm_ctx* c, const mpm_problem* pb, const double* du, double* val, bool apply_bc);
 int launch_update(mpm_ctx* c, const mpm_problem* pb, const double* du, double* x, double* F, double* be);
 int launch_bj_inv(mpm_ctx* c, const double* val);

@@ -70,7 +70,8 @@ class mpm_newton_report(C.Structure):
 
 EXPORTS = ["mpm_create", "mpm_destroy", "mpm_last_error", "mpm_prepare", "mpm_residual", "mpm_jacobian_bsr",
            "mpm_newton_step", "mpm_update", "mpm_spmv", "mpm_spmv_lanes", "mpm_spmv_set_lanes",
-           "mpm_adjoint_step"]
+           "mpm_adjoint_step", "mpm_residual_noalloc"]
+MPM_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 _lib = None
 
@@ -91,6 +92,7 @@ def load():
         "mpm_prepare": ([P, C.POINTER(mpm_problem), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                          C.POINTER(C.c_int32)], C.c_int),
         "mpm_residual": ([P, C.POINTER(mpm_problem), P, P, P, C.POINTER(C.c_double)], C.c_int),
+        "mpm_residual_noalloc": ([P, C.POINTER(mpm_problem), P, P, P, C.POINTER(C.c_double)], C.c_int),
         "mpm_jacobian_bsr": ([P, C.POINTER(mpm_problem), P, P, P, P, P, C.c_int32], C.c_int),
         "mpm_newton_step": ([P, C.POINTER(mpm_problem), C.POINTER(mpm_newton_opts), P,
                              C.POINTER(mpm_newton_report)], C.c_int),
@@ -241,6 +243,13 @@ def mpm_residual(ctx, dp: DeviceProblem, du, r, r_raw=None, want_reaction=False)
     react = (C.c_double * dp.nsim)() if want_reaction else None
     _check(ctx, load().mpm_residual(ctx, C.byref(dp.struct), _ptr(du), _ptr(r), _ptr(r_raw),
                                     react if react is not None else None))
+    return None if react is None else np.array(react[:])
+
+
+def mpm_residual_noalloc(ctx, dp: DeviceProblem, du, r, r_raw=None, want_reaction=False):
+    react = (C.c_double * dp.nsim)() if want_reaction else None
+    _check(ctx, load().mpm_residual_noalloc(ctx, C.byref(dp.struct), _ptr(du), _ptr(r), _ptr(r_raw),
+                                            react if react is not None else None))
     return None if react is None else np.array(react[:])
 
 
