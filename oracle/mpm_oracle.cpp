@@ -39,6 +39,9 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <vector>
 
 namespace orc {
@@ -207,6 +210,8 @@ struct Cfg {
   int32_t shape;     // 0 quadratic B-spline, 1 cpGIMP (convected particle domain)
   int32_t pad_;
   double lp0[3];     // cpGIMP: initial half-width of the particle domain per axis
+  int32_t elastic;   // 0 Hencky, 1 compressible Neo-Hookean (dp = 0 only)
+  int32_t pad2_;
 };
 
 struct Particles {
@@ -465,6 +470,24 @@ int hencky_dp(const Cfg& c, const T& E, const T& phi, const M3<T>& eps_tr, M3<T>
   return regime;
 }
 
+// Kirchhoff stress from the trial left Cauchy-Green tensor b_tr.  Hencky
+// (with the optional return map): eps_e receives the elastic log strain.
+// Compressible Neo-Hookean (Sec. 4.5): tau = mu (b - 1) + lambda ln J 1 with
+// J = sqrt(det b), b being the whole left Cauchy-Green tensor (no plasticity).
+template <class T>
+int stress_update(const Cfg& c, const T& E, const T& phi, const M3<T>& be_tr, M3<T>& tau, M3<T>& eps_e) {
+  if (c.elastic == 1) {
+    Moduli<T> m = moduli(E, c.nu);
+    T lnJ = 0.5 * log(det(be_tr));
+    tau = scale(sub(be_tr, M3<T>::eye()), m.G);
+    for (int i = 0; i < 3; ++i) tau.a[i][i] += m.lam * lnJ;
+    eps_e = M3<T>::zero();
+    return 0;
+  }
+  M3<T> eps_tr = scale(logm_spd(be_tr), 0.5);
+  return hencky_dp(c, E, phi, eps_tr, tau, eps_e);
+}
+
 // --------------------------------------------------- particle evaluation ---
 // du_loc: local unknowns, node-interleaved [nn][ndof] (ndof = dim or dim+1).
 // Outputs (each optional): fint_loc/fext_loc [nn][ndof]; new state.
@@ -476,11 +499,10 @@ int eval_particle(const Cfg& c, const PState<T>& s, const Stencil<T>& st, const 
   M3<T> dF = M3<T>::eye();
   for (int a = 0; a < nn; ++a)
     for (int i = 0; i < d; ++i) for (int j = 0; j < d; ++j) dF.a[i][j] += du_loc[a * nd + i] * st.grad[a][j];
-  // Hencky trial state and return map
+  // trial state b_tr = dF b^e_n dF^T, then the stress
   M3<T> be_tr = mul(mul(dF, s.be), transpose(dF));
-  M3<T> eps_tr = scale(logm_spd(be_tr), 0.5);
   M3<T> tau, eps_e;
-  int regime = hencky_dp(c, s.E, s.phi, eps_tr, tau, eps_e);
+  int regime = stress_update(c, s.E, s.phi, be_tr, tau, eps_e);
   M3<T> dFinvT = transpose(inverse(dF));
   T ddet = det(dF);
   T Jn = det(s.F);
@@ -536,7 +558,7 @@ int eval_particle(const Cfg& c, const PState<T>& s, const Stencil<T>& st, const 
       snew->x[i] = s.x[i] + dx;
     }
     snew->F = mul(dF, s.F);
-    snew->be = expm_sym(scale(eps_e, 2.0));
+    snew->be = c.elastic == 1 ? be_tr : expm_sym(scale(eps_e, 2.0));
   }
   return regime;
 }
@@ -630,20 +652,46 @@ extern "C" {
 int orc_forces(const Cfg* c, const Particles* P, const double* dof_full, double* fint, double* fext, int32_t* regime) {
   const int nd = ndof_of(*c);
   const int64_t nn_full = n_nodes(*c);
-  std::memset(fint, 0, sizeof(double) * nn_full * nd);
-  if (fext) std::memset(fext, 0, sizeof(double) * nn_full * nd);
-  for (int64_t p = 0; p < P->np; ++p) {
-    PState<double> s = load_particle<double>(*c, *P, p);
-    Stencil<double> st = make_stencil(*c, s);
-    double du[27 * 4], fi[27 * 4], fe[27 * 4];
-    gather_local(*c, st, dof_full, du);
-    int reg = eval_particle(*c, s, st, du, fi, fe, (PState<double>*)nullptr);
-    if (regime) regime[p] = reg;
-    for (int a = 0; a < st.nn; ++a)
-      for (int k = 0; k < nd; ++k) {
-        fint[st.node[a] * nd + k] += fi[a * nd + k];
-        if (fext) fext[st.node[a] * nd + k] += fe[a * nd + k];
-      }
+  const int64_t nv = nn_full * nd;
+  std::memset(fint, 0, sizeof(double) * nv);
+  if (fext) std::memset(fext, 0, sizeof(double) * nv);
+  // particles split into one contiguous range per thread, each thread
+  // scattering into its own full-grid copy; the copies are then summed in
+  // thread order (the result depends on the thread count only through the
+  // order of the sums)
+  int nth = 1;
+#ifdef _OPENMP
+  nth = P->np >= 4096 ? omp_get_max_threads() : 1;
+#endif
+  std::vector<std::vector<double>> acc_i(nth), acc_e(nth);
+#pragma omp parallel num_threads(nth)
+  {
+    int t = 0;
+#ifdef _OPENMP
+    t = omp_get_thread_num();
+#endif
+    std::vector<double>& ai = acc_i[t];
+    std::vector<double>& ae = acc_e[t];
+    ai.assign(nv, 0.0);
+    if (fext) ae.assign(nv, 0.0);
+    const int64_t p0 = P->np * t / nth, p1 = P->np * (t + 1) / nth;
+    for (int64_t p = p0; p < p1; ++p) {
+      PState<double> s = load_particle<double>(*c, *P, p);
+      Stencil<double> st = make_stencil(*c, s);
+      double du[27 * 4], fi[27 * 4], fe[27 * 4];
+      gather_local(*c, st, dof_full, du);
+      int reg = eval_particle(*c, s, st, du, fi, fe, (PState<double>*)nullptr);
+      if (regime) regime[p] = reg;
+      for (int a = 0; a < st.nn; ++a)
+        for (int k = 0; k < nd; ++k) {
+          ai[st.node[a] * nd + k] += fi[a * nd + k];
+          if (fext) ae[st.node[a] * nd + k] += fe[a * nd + k];
+        }
+    }
+  }
+  for (int t = 0; t < nth; ++t) {
+    for (int64_t i = 0; i < nv; ++i) fint[i] += acc_i[t][i];
+    if (fext) for (int64_t i = 0; i < nv; ++i) fext[i] += acc_e[t][i];
   }
   return 0;
 }
@@ -777,8 +825,8 @@ int orc_stress(const Cfg* c, const Particles* P, const double* dof_full, double*
     for (int a = 0; a < st.nn; ++a)
       for (int i = 0; i < c->dim; ++i) for (int j = 0; j < c->dim; ++j) dF.a[i][j] += du[a * nd + i] * st.grad[a][j];
     M3<double> be_tr = mul(mul(dF, s.be), transpose(dF));
-    M3<double> eps = scale(logm_spd(be_tr), 0.5), tau, ee;
-    int reg = hencky_dp(*c, s.E, s.phi, eps, tau, ee);
+    M3<double> tau, ee;
+    int reg = stress_update(*c, s.E, s.phi, be_tr, tau, ee);
     for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) tau_out[(i * 3 + j) * P->np + p] = tau.a[i][j];
     if (regime) regime[p] = reg;
   }

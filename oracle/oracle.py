@@ -52,7 +52,8 @@ class _Cfg(C.Structure):
                 ("psi", C.c_double), ("rho0", C.c_double), ("g", C.c_double * 3),
                 ("perm", C.c_double), ("mu_f", C.c_double), ("biot", C.c_double),
                 ("rho_f", C.c_double), ("dt", C.c_double), ("apex_reg", C.c_double),
-                ("shape", C.c_int32), ("pad_", C.c_int32), ("lp0", C.c_double * 3)]
+                ("shape", C.c_int32), ("pad_", C.c_int32), ("lp0", C.c_double * 3),
+                ("elastic", C.c_int32), ("pad2_", C.c_int32)]
 
 
 class _Particles(C.Structure):
@@ -115,6 +116,7 @@ def cfg(prob) -> _Cfg:
         prob.rho0, prob.perm, prob.mu_f, prob.biot, prob.rho_f, prob.dt))
     c.apex_reg = float(getattr(prob, "apex_reg", 0.0))
     c.shape = int(getattr(prob, "shape", 0))
+    c.elastic = int(getattr(prob, "elastic", 0))
     lp0 = getattr(prob, "lp0", (0.0, 0.0, 0.0))
     for k in range(3):
         c.lp0[k] = float(lp0[k]) if k < len(lp0) else 0.0
