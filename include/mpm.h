@@ -74,9 +74,13 @@ typedef struct {
   int32_t up;         /* 1: u-p poromechanics (Sec. 2.2, Remark 1) */
   int32_t dp;         /* 1: Drucker-Prager return map on top of Hencky elasticity */
   int32_t dp_match;   /* 0: cone through the triaxial-compression meridian of Mohr-Coulomb,
-                         1: plane-strain match, 2: triaxial-extension meridian;
+                         1: plane-strain match, 2: triaxial-extension meridian,
+                         3: J2 (von Mises, Sec. 4.2): sqrt(2 J2) <= c, phi and psi unused;
                          + 4: associated flow (dilation slope = friction slope, psi unused) */
-  int32_t reserved;
+  int32_t shape;      /* 0: quadratic B-splines; 1: cpGIMP (Sec. 2.2): node weights are the
+                         averages of the linear hat functions over the particle domain, a box
+                         of half-widths lp0[k] F_kk (convected with the stretch of each axis)
+                         that must stay <= h/2; same 3^d stencil and pattern */
   double E, nu;       /* Young's modulus [Pa], Poisson ratio */
   double phi, c, psi; /* friction angle [rad], cohesion [Pa], dilation angle [rad] */
   double rho0;        /* reference density [kg/m^3] */
@@ -86,6 +90,11 @@ typedef struct {
   double dt;          /* time step [s] (u-p) */
   double apex_reg;    /* tangent of an apex return = apex_reg x trial elastic tangent (the
                          exact one is zero for c = 0); stresses and residuals are exact */
+  double lp0[3];      /* cpGIMP: initial half-width of the particle domain per axis [m] */
+  int32_t elastic;    /* elastic law (dp = 0 only): 0 Hencky, tau = lambda tr(eps) 1 + 2 mu eps with
+                         eps = 1/2 ln b^e (Sec. 4.2); 1 compressible Neo-Hookean,
+                         tau = mu (b - 1) + lambda ln J 1 (Sec. 4.5) */
+  int32_t reserved;
 } mpm_material;
 
 /* Particle state at the start of the load step (device, SoA). */
@@ -154,10 +163,11 @@ int mpm_residual(mpm_ctx *ctx, const mpm_problem *prob, const double *du, double
  * forbid hipMalloc.  Same arguments, results and errors as mpm_residual (the
  * same kernels, so the same bits); the context must be prepared
  * (mpm_prepare allocates the pattern and the vectors).  The per-particle
- * force records the residual needs (np * 160 bytes in plane strain,
- * np * 224 bytes in 3-D) go to a fixed library-owned device array of
- * MPM_NOALLOC_SCRATCH_BYTES per device instead of context memory; a larger
- * problem is rejected with INVALID.  The array is shared by every call on
+ * force records the plane-strain residual needs (np * 160 bytes) go to a
+ * fixed library-owned device array of MPM_NOALLOC_SCRATCH_BYTES per device
+ * instead of context memory; a larger problem is rejected with INVALID.  The
+ * 3-D residual evaluates its stresses inside its scatter and keeps no
+ * records, so it has no such limit.  The array is shared by every call on
  * that device and keeps the last call's contents (nothing in it needs to
  * start at zero): calls that overlap on one device, from any contexts or
  * streams, race and must be serialised by the caller.  reaction (host) makes
@@ -194,9 +204,11 @@ typedef struct {
                              preconditioner for the sims still above tolerance; 1: GMRES only;
                              2: as 0, with a geometric multigrid V-cycle (coarse levels
                              rediscretized from the particles on grids of 2^l h) preconditioning
-                             BiCGStab, replayed from a captured HIP graph; 3: as 2 with the
-                             V-cycle launched kernel by kernel (same arithmetic); 2 and 3 are
-                             2-D single-phase only (else INVALID) */
+                             BiCGStab: plane-strain single-phase levels smoothed by damped
+                             block-Jacobi and replayed from a captured HIP graph; 3-D and u-p
+                             levels (3x3 blocks) smoothed by Chebyshev polynomials and launched
+                             eagerly; 3: as 2 with the plane-strain V-cycle launched kernel by
+                             kernel (same arithmetic) */
 } mpm_newton_opts;
 
 #define MPM_MAX_REPORT 32
@@ -273,6 +285,23 @@ int mpm_adjoint_step(mpm_ctx *ctx, const mpm_problem *prob, const double *du, co
  * sums of z.y and y.y that the Krylov iteration fuses into it (kept in
  * library scratch).  Errors: INVALID, HIP. */
 int mpm_spmv(mpm_ctx *ctx, const double *val, const double *x, double *y, const double *z);
+
+/* y = J x without forming the matrix: the matrix-free Newton-Krylov variant
+ * the paper names for large problems (Sec. 2.2, Remark 2).  Each particle's
+ * tangent table V0 dP/dF at du (d^2 x d^2 doubles, the same forward passes as
+ * mpm_jacobian_bsr) is stored, and the product is applied on the fly: per
+ * particle dF = sum_b x_b (x) grad w_b, dP = T : dF, then the scatter of
+ * dP grad w_a like the internal force.  Equal to the BSR product of
+ * mpm_jacobian_bsr at the same du up to summation order.  flags &
+ * MPM_JAC_RAW: the raw derivative of f_int; otherwise the Dirichlet-modified
+ * matrix (constrained columns read as zero, constrained rows return x).
+ * flags & MPM_JV_REUSE: reuse the tangent tables of the previous mpm_jv,
+ * mpm_jacobian_bsr or Newton assembly of this prepare (du ignored, may be
+ * NULL), so a Krylov loop pays one tangent pass per Newton iteration.  x, y
+ * compact [n_row*ndof], must not alias.  Single-phase only.
+ * Errors: INVALID (u-p, no tables to reuse, aliasing), NOMEM, HIP. */
+#define MPM_JV_REUSE 2
+int mpm_jv(mpm_ctx *ctx, const mpm_problem *prob, const double *du, const double *x, double *y, int32_t flags);
 
 /* Lanes per BSR row of the SpMV launch shape in use: the pinned one (see
  * mpm_spmv_set_lanes), else the one the autotuner picked for the current

@@ -130,6 +130,7 @@ class ReactionCurves:
                 fopts = {k: v for k, v in outer.opts.items() if k != "adjoint_progress"}
                 run = forward(outer.ctx, dp, outer.sims, outer.steps, **fopts)
                 fctx.run = run
+                outer.last_run = run
                 return torch.from_numpy(run.reactions.copy()).to(E.device)
 
             @staticmethod

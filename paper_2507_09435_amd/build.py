@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmpm_hip.so")
-SOURCES = ["mpm_prepare.hip", "mpm_assemble.hip", "mpm_krylov.hip", "mpm_mg.hip", "mpm_adjoint.hip",
+SOURCES = ["mpm_prepare.hip", "mpm_assemble.hip", "mpm_krylov.hip", "mpm_mg.hip", "mpm_mg3.hip", "mpm_adjoint.hip",
            "mpm_api.hip"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

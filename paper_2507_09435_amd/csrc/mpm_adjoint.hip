@@ -74,9 +74,9 @@ __device__ double adj_dir2(const AdjArgs& A, int64_t i, const double* __restrict
   Mat<dnum> m = make_mat<dnum>(E, A.nu, phi, A.c, A.psi, A.dp, A.match, A.apex_reg);
   UpPar u0{0.0, 0.0, 0.0, 0.0, {0.0, 0.0, 0.0}};
   Out2<dnum> out;
-  Sym2<dnum> ee;
+  Sym2<dnum> b;
   dnum zero(0.0), gp0[2] = {dnum(0.0), dnum(0.0)};
-  mech2<dnum>(m, dF, be, dnum(1.0), 0, u0, zero, gp0, out, &ee);
+  mech2<dnum>(m, dF, be, dnum(1.0), 0, u0, zero, gp0, out, &b);
   const double v0 = A.vs[i];
   const int64_t p = A.perm[i];
   double fpx = 0.0, fpy = 0.0;
@@ -102,7 +102,6 @@ __device__ double adj_dir2(const AdjArgs& A, int64_t i, const double* __restrict
         dnum f = dF[r][0] * Fn[0][c] + dF[r][1] * Fn[1][c];
         acc += sbar[2 + r * 2 + c] * f.d;
       }
-    Sym2<dnum> b = exp2eps2(ee);
     acc += sbar[6] * b.xx.d + sbar[7] * b.yy.d + sbar[8] * b.xy.d + sbar[9] * b.zz.d;
   }
   return acc;
@@ -239,6 +238,8 @@ extern "C" int mpm_adjoint_step(mpm_ctx* c, const mpm_problem* pb, const double*
   int rc = check_prepared(c, pb);
   if (rc) return rc;
   if (c->dim != 2 || c->up) return c->fail(MPM_E_INVALID, "the adjoint step covers plane-strain single-phase problems");
+  if (pb->mat.shape != 0 || (pb->mat.dp && (pb->mat.dp_match & 3) == 3))
+    return c->fail(MPM_E_INVALID, "the adjoint step covers B-spline Hencky, Drucker-Prager and Neo-Hookean problems");
   if (!du || !react_bar || !theta_bar) return c->fail(MPM_E_INVALID, "du, react_bar and theta_bar are required");
   HIPC(c, hipSetDevice(c->device));
   const int nd = c->nd, nsim = c->nsim;

@@ -92,8 +92,17 @@ int validate_problem(mpm_ctx* c, const mpm_problem* pb) {
   }
   if (!(pb->mat.E > 0.0) && !pb->P.E) return c->fail(MPM_E_INVALID, "Young's modulus must be positive");
   if (!(pb->mat.nu > -1.0 && pb->mat.nu < 0.5)) return c->fail(MPM_E_INVALID, "Poisson ratio out of range");
-  if ((pb->mat.dp_match & 3) > 2 || (pb->mat.dp_match & ~7) != 0)
-    return c->fail(MPM_E_INVALID, "dp_match must be 0, 1 or 2, plus 4 for associated flow");
+  if ((pb->mat.dp_match & ~7) != 0)
+    return c->fail(MPM_E_INVALID, "dp_match must be 0, 1, 2 or 3, plus 4 for associated flow");
+  if ((pb->mat.dp_match & 3) == 3 && pb->mat.dp && !(pb->mat.c > 0.0))
+    return c->fail(MPM_E_INVALID, "J2 plasticity (dp_match 3) needs a positive yield strength c");
+  if (pb->mat.shape != 0 && pb->mat.shape != 1) return c->fail(MPM_E_INVALID, "shape must be 0 or 1");
+  if (pb->mat.elastic != 0 && pb->mat.elastic != 1) return c->fail(MPM_E_INVALID, "elastic must be 0 or 1");
+  if (pb->mat.elastic == 1 && pb->mat.dp)
+    return c->fail(MPM_E_INVALID, "the Neo-Hookean law is elastic (dp must be 0)");
+  if (pb->mat.shape == 1)
+    for (int k = 0; k < dim; ++k)
+      if (!(pb->mat.lp0[k] > 0.0)) return c->fail(MPM_E_INVALID, "cpGIMP needs lp0 > 0 on every axis");
   return MPM_OK;
 }
 
@@ -115,7 +124,7 @@ void ctx_release(mpm_ctx* c) {
   c->colind.release(); c->slot.release(); c->rgrp.release(); c->bcode.release(); c->blocks.release(); c->blk_first.release(); c->flag.release();
   c->xs.release(); c->vol0s.release(); c->Fs.release(); c->bes.release(); c->Es.release(); c->phis.release();
   c->cmask.release(); c->rmask.release(); c->cval.release(); c->fext.release(); c->fint.release(); c->nvol.release();
-  c->work.release(); c->val.release(); c->dinv.release(); c->pdat.release(); c->pdat3.release(); c->jc3_ws.release(); c->gbuf.release(); c->rrec.release();
+  c->work.release(); c->val.release(); c->dinv.release(); c->pdat.release(); c->pdat3.release(); c->jc3_ws.release(); c->jl3_ws.release(); c->jf3_ws.release(); c->gbuf.release(); c->rrec.release();
   c->kx.release(); c->kr.release(); c->krh.release(); c->kp.release(); c->kv.release(); c->ks.release();
   c->kt.release(); c->kph.release(); c->ksh.release(); c->kb.release(); c->part.release(); c->simsc.release();
   c->simflag.release(); c->du_base.release(); c->alpha.release();
@@ -222,6 +231,19 @@ int mpm_jacobian_bsr(mpm_ctx* c, const mpm_problem* pb, const double* du, int32_
   return MPM_OK;
 }
 
+int mpm_jv(mpm_ctx* c, const mpm_problem* pb, const double* du, const double* x, double* y, int32_t flags) {
+  if (!c) return MPM_E_INVALID;
+  c->err.clear();
+  GUARD(check_prepared(c, pb));
+  if (c->n_row && (!x || !y)) return c->fail(MPM_E_INVALID, "x and y are required");
+  const bool reuse = (flags & MPM_JV_REUSE) != 0;
+  if (!reuse && !du && c->n_row) return c->fail(MPM_E_INVALID, "du is NULL");
+  if (x == y && c->n_row) return c->fail(MPM_E_INVALID, "x and y must not alias");
+  HIPC(c, hipSetDevice(c->device));
+  if (!reuse) HIPC(c, hipMemsetAsync(c->flag.p, 0, sizeof(int32_t), c->stream));
+  return launch_jv(c, pb, du, !reuse, x, y, (flags & MPM_JAC_RAW) == 0);
+}
+
 int mpm_update(mpm_ctx* c, const mpm_problem* pb, const double* du, double* x_out, double* F_out, double* be_out) {
   if (!c) return MPM_E_INVALID;
   c->err.clear();
@@ -254,8 +276,6 @@ int mpm_newton_step(mpm_ctx* c, const mpm_problem* pb, const mpm_newton_opts* op
   const int kmax = opts->krylov_max_iter > 0 ? opts->krylov_max_iter : 20000;
   if (opts->krylov_method < 0 || opts->krylov_method > 3) return c->fail(MPM_E_INVALID, "unknown krylov_method");
   const bool use_mg = opts->krylov_method >= 2;
-  if (use_mg && (c->dim != 2 || c->up))
-    return c->fail(MPM_E_INVALID, "krylov_method 2 and 3 (multigrid) cover 2-D single-phase problems");
   c->kmethod = opts->krylov_method;
   if (use_mg && !c->mg_ready) GUARD(mg_build(c, pb));
   const double stall = opts->stall_factor > 0 ? opts->stall_factor : 0.0;

@@ -14,7 +14,7 @@ namespace mpm {
 
 struct AsmArgs {
   int64_t np;
-  int nd, up, dp, match;
+  int nd, up, dp, match, nsim;
   const double *xs, *vs, *Fs, *bes, *Es, *phis;   // sorted SoA (Es/phis may be null)
   const int32_t* psim;
   const SimDev* sims;
@@ -91,17 +91,29 @@ __device__ __forceinline__ void load_particle(const AsmArgs& A, int64_t i, const
       }
     }
   } else {
-    for (int a = 0; a < Stencil<DIM>::NN; ++a) {
-      int32_t r = A.node_map[L.st.node(S, a)];
-      L.row[a] = r;
-      double g[DIM];
-      L.st.grad(a, g);
-      const double* u = du + (int64_t)r * nd;
+    // one z-layer of nine nodes at a time: its node-map loads, then its
+    // increment loads, then the sums, all unrolled (the stencil arrays stay
+    // in registers)
 #pragma unroll
-      for (int q = 0; q < DIM; ++q) {
-        double uq = u[q];
+    for (int az = 0; az < 3; ++az) {
+      int32_t rr[9];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) L.dF[q][k] += uq * g[k];
+      for (int a9 = 0; a9 < 9; ++a9) rr[a9] = A.node_map[L.st.node(S, a9 + 9 * az)];
+      double uu[9][3];
+#pragma unroll
+      for (int a9 = 0; a9 < 9; ++a9)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) uu[a9][q] = du[(int64_t)rr[a9] * nd + q];
+#pragma unroll
+      for (int a9 = 0; a9 < 9; ++a9) {
+        const int a = a9 + 9 * az;
+        L.row[a] = rr[a9];
+        double g[DIM];
+        L.st.grad(a, g);
+#pragma unroll
+        for (int q = 0; q < DIM; ++q)
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) L.dF[q][k] += uu[a9][q] * g[k];
       }
     }
   }
@@ -231,130 +243,6 @@ __device__ __forceinline__ void tangent2_col(const AsmArgs& A, const PLoad<2>& L
   mech2<dnum>(m, F, bd, dnum(L.Jn), NIO == 7, u, pp, gp, o, nullptr);
   Tc[0] = o.P[0][0].d; Tc[1] = o.P[0][1].d; Tc[2] = o.P[1][0].d; Tc[3] = o.P[1][1].d;
   if constexpr (NIO == 7) { Tc[4] = o.s1.d; Tc[5] = o.vv[0].d; Tc[6] = o.vv[1].d; }
-}
-
-// ---------------------------------------------- group-cooperative 2-D ------
-// Particles of one stencil group (same origin) are adjacent after sorting.
-// A workgroup stages per-particle data in LDS, finds the group starts with a
-// ballot scan, and then one thread per (group, node) sums the group's
-// contributions in registers before a single atomic per entry.
-constexpr int GP = 128;   // particles (threads) per workgroup
-
-__device__ __forceinline__ int32_t origin_key2(const SimDev& S, const Stencil<2>& st) {
-  return (int32_t)(S.okey_base + (st.o[0] + 1) + (int64_t)S.noa[0] * (st.o[1] + 1));
-}
-
-// Group starts of the workgroup's particles (n valid).  Returns the number of
-// groups; gstart[g] = first local index of group g, gstart[G] = n.
-__device__ __forceinline__ int group_starts(const int32_t* key, int n, int32_t* gstart, int32_t* wave_cnt) {
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  bool head = t < n && (t == 0 || key[t] != key[t - 1]);
-  unsigned long long m = __ballot(head);
-  int before = __popcll(m & ((1ull << lane) - 1ull));
-  if (lane == 0) wave_cnt[wv] = __popcll(m);
-  __syncthreads();
-  int off = 0;
-  for (int w = 0; w < wv; ++w) off += wave_cnt[w];
-  if (head) gstart[off + before] = t;
-  int G = 0;
-  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) G += wave_cnt[w];
-  if (t == 0) gstart[G] = n;
-  __syncthreads();
-  return G;
-}
-
-// 2-D Jacobian.  Phase 1: LP lanes per particle, lane q computes tangent
-// column q (one forward pass each), so a workgroup holds JP particles and a
-// small problem still fills the chip.  Phase 2: one thread per (group,
-// column node b, row of 3 nodes a) sums the group's contributions to its
-// three local blocks in registers, then adds each entry once.
-constexpr int JT = 256;                       // threads per workgroup
-
-template <int NIO>
-__global__ void __launch_bounds__(JT) k_jac2g(AsmArgs A, const double* __restrict__ du,
-                                             const int32_t* __restrict__ rowptr, const int8_t* __restrict__ slot,
-                                             double* __restrict__ val) {
-  constexpr int ND = NIO == 7 ? 3 : 2;
-  constexpr int LP = NIO == 7 ? 8 : 4;       // lanes per particle in phase 1
-  constexpr int JP = JT / LP;                 // particles per workgroup
-  __shared__ double sT[JP][NIO * NIO];        // V0 * tangent table
-  __shared__ double sW[JP][2][3], sD[JP][2][3];
-  __shared__ int32_t sKey[JP], sRow[JP][9], sG[JP + 1], sWc[JT / 64];
-  const int64_t base = (int64_t)blockIdx.x * JP;
-  const int n = (int)min<int64_t>(JP, A.np - base);
-  const int t = threadIdx.x;
-  const int lp = t / LP, q = t % LP;
-  if (lp < n && q < NIO) {
-    const int64_t i = base + lp;
-    PLoad<2> L;
-    load_particle<2>(A, i, du, L);
-    double Tc[NIO];
-    tangent2_col<NIO>(A, L, load_be2(A, i), q, Tc);
-#pragma unroll
-    for (int o = 0; o < NIO; ++o) sT[lp][o * NIO + q] = L.v0 * Tc[o];
-    if (q == 0) {
-#pragma unroll
-      for (int k = 0; k < 2; ++k)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) { sW[lp][k][a] = L.st.w[k][a]; sD[lp][k][a] = L.st.dw[k][a]; }
-#pragma unroll
-      for (int a = 0; a < 9; ++a) sRow[lp][a] = L.row[a];
-      sKey[lp] = origin_key2(A.sims[A.psim[i]], L.st);
-    }
-  }
-  __syncthreads();
-  const int G = group_starts(sKey, n, sG, sWc);
-  for (int task = t; task < 27 * G; task += JT) {
-    const int g = task / 27, rem = task % 27, b = rem % 9, ay = rem / 9;
-    const int bx = b % 3, by = b / 3;
-    double acc[3][ND][ND];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int r = 0; r < ND; ++r)
-#pragma unroll
-        for (int c = 0; c < ND; ++c) acc[a][r][c] = 0.0;
-    for (int p = sG[g]; p < sG[g + 1]; ++p) {
-      const double* T = sT[p];
-      const double gb0 = sD[p][0][bx] * sW[p][1][by], gb1 = sW[p][0][bx] * sD[p][1][by];
-      double Tb[NIO][ND];
-#pragma unroll
-      for (int o = 0; o < NIO; ++o) {
-#pragma unroll
-        for (int m = 0; m < 2; ++m) Tb[o][m] = T[o * NIO + m * 2] * gb0 + T[o * NIO + m * 2 + 1] * gb1;
-        if constexpr (ND == 3) {
-          const double wb = sW[p][0][bx] * sW[p][1][by];
-          Tb[o][2] = T[o * NIO + 4] * wb + T[o * NIO + 5] * gb0 + T[o * NIO + 6] * gb1;
-        }
-      }
-      const double wy = sW[p][1][ay], dy = sD[p][1][ay];
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        const double ga0 = sD[p][0][ax] * wy, ga1 = sW[p][0][ax] * dy;
-#pragma unroll
-        for (int c = 0; c < ND; ++c) {
-#pragma unroll
-          for (int r = 0; r < 2; ++r) acc[ax][r][c] += ga0 * Tb[r * 2][c] + ga1 * Tb[r * 2 + 1][c];
-          if constexpr (ND == 3) {
-            const double wa = sW[p][0][ax] * wy;
-            acc[ax][2][c] += wa * Tb[4][c] + ga0 * Tb[5][c] + ga1 * Tb[6][c];
-          }
-        }
-      }
-    }
-    const int p0 = sG[g];
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      const int a = ay * 3 + ax;
-      const int32_t ra = sRow[p0][a];
-      const int s = slot[(int64_t)ra * 25 + nb_index<2>(a, b)];
-      double* blk = val + ((int64_t)rowptr[ra] + s) * (ND * ND);
-#pragma unroll
-      for (int r = 0; r < ND; ++r)
-#pragma unroll
-        for (int c = 0; c < ND; ++c) atomicAdd(&blk[r * ND + c], acc[ax][r][c]);
-    }
-  }
 }
 
 // 2-D single-phase Jacobian without atomics, in two deterministic passes.
@@ -509,6 +397,138 @@ __global__ void __launch_bounds__(256) k_jac2_rows(int64_t n_row, const int32_t*
   }
 }
 
+// u-p Jacobian without atomics, the same two passes with 3x3 blocks.
+// k_tan2up: eight lanes per particle, lane q < 7 writes column q of the 7x7
+// table V0 d(P, s1, vv)/d(dF, p, grad p) (output-major), and lane 7 the
+// stencil's weights and derivatives per axis.
+__global__ void __launch_bounds__(256) k_tan2up(AsmArgs A, const double* __restrict__ du, double* __restrict__ pdat) {
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = gid >> 3;
+  const int q = (int)(gid & 7);
+  if (i >= A.np) return;
+  PLoad<2> L;
+  load_particle<2>(A, i, du, L);
+  double* P = pdat + i * PU2;
+  if (q < 7) {
+    double Tc[7];
+    tangent2_col<7>(A, L, load_be2(A, i), q, Tc);
+#pragma unroll
+    for (int o = 0; o < 7; ++o) P[o * 7 + q] = L.v0 * Tc[o];
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      P[49 + a] = L.st.w[0][a];
+      P[52 + a] = L.st.dw[0][a];
+      P[55 + a] = L.st.w[1][a];
+      P[58 + a] = L.st.dw[1][a];
+    }
+  }
+}
+
+// k_jac2up_rows: JRU rows of 16 lanes; lane q < 9 of row a takes the q-th
+// stencil group holding node a and accumulates the nine 3x3 blocks (a, b) of
+// its particles, in order, in LDS.  Node a's side is contracted first: with
+// (ga0, ga1) = grad w_a and wa = w_a, U[r][k] = sum over the outputs o of row
+// component r (P rows for r < 2, the fluid outputs (s1, vv) for r = 2) of
+// their weight times T[o][k]; then K_ab[r][c] sums U[r][k] over the inputs k
+// of column component c with node b's weights (dF entries for c < 2,
+// (p, grad p) for c = 2).  The block pass sums the groups holding both nodes
+// in group order and writes each block once, Dirichlet from the row codes.
+constexpr int JRU = 8;                          // rows per workgroup (16 lanes each)
+constexpr int JBU = (JRU * 25 + JRU * 16 - 1) / (JRU * 16);   // stencil offsets per thread
+__global__ void __launch_bounds__(JRU * 16) k_jac2up_rows(int64_t n_row, const int32_t* __restrict__ rgrp,
+                                                         const double* __restrict__ pdat,
+                                                         const int32_t* __restrict__ rowptr,
+                                                         const int8_t* __restrict__ slot,
+                                                         const uint8_t* __restrict__ bcode, double* __restrict__ val) {
+  constexpr int NT = JRU * 16;
+  __shared__ double part[JRU][9][81];   // [row][group q][local node b][3x3]
+  const int rl = threadIdx.x / 16, q = threadIdx.x % 16;
+  const int64_t row0 = (int64_t)blockIdx.x * JRU;
+  int32_t sl[JBU], rp[JBU];
+  uint32_t code[JBU];
+#pragma unroll
+  for (int h = 0; h < JBU; ++h) {
+    const int t = threadIdx.x + NT * h;
+    const int64_t row = row0 + t / 25;
+    sl[h] = -1;
+    rp[h] = 0;
+    code[h] = 0;
+    if (t < JRU * 25 && row < n_row) {
+      sl[h] = slot[row * 25 + t % 25];
+      rp[h] = rowptr[row];
+      if (bcode) code[h] = bcode[row * 25 + t % 25];
+    }
+  }
+  {
+    const int64_t row = row0 + rl;
+    if (row < n_row && q < 9) {
+      const int p0 = rgrp[(row * 9 + q) * 2], p1 = rgrp[(row * 9 + q) * 2 + 1];
+      const int ax = 2 - q % 3, ay = 2 - q / 3;   // node a's place in the group's 3x3 stencil
+      double* K = part[rl][q];
+      for (int e = 0; e < 81; ++e) K[e] = 0.0;
+      for (int p = p0; p < p1; ++p) {
+        const double* P = pdat + (int64_t)p * PU2;
+        double w[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) w[k] = P[49 + k];
+        // w: wx 0..2, dwx 3..5, wy 6..8, dwy 9..11
+        const double wxa = sel3(ax, w[0], w[1], w[2]), dwxa = sel3(ax, w[3], w[4], w[5]);
+        const double wya = sel3(ay, w[6], w[7], w[8]), dwya = sel3(ay, w[9], w[10], w[11]);
+        const double ga0 = dwxa * wya, ga1 = wxa * dwya, wa = wxa * wya;
+        double U[3][7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+          U[0][k] = fma(ga1, P[1 * 7 + k], ga0 * P[0 * 7 + k]);
+          U[1][k] = fma(ga1, P[3 * 7 + k], ga0 * P[2 * 7 + k]);
+          U[2][k] = fma(ga1, P[6 * 7 + k], fma(ga0, P[5 * 7 + k], wa * P[4 * 7 + k]));
+        }
+#pragma unroll
+        for (int lb = 0; lb < 9; ++lb) {
+          const int bx = lb % 3, by = lb / 3;
+          const double gb0 = w[3 + bx] * w[6 + by], gb1 = w[bx] * w[9 + by], wb = w[bx] * w[6 + by];
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            double* k9 = K + lb * 9 + r * 3;
+            k9[0] = fma(U[r][1], gb1, fma(U[r][0], gb0, k9[0]));
+            k9[1] = fma(U[r][3], gb1, fma(U[r][2], gb0, k9[1]));
+            k9[2] = fma(U[r][6], gb1, fma(U[r][5], gb0, fma(U[r][4], wb, k9[2])));
+          }
+        }
+      }
+    }
+  }
+  // groups off the grid (empty ranges) leave zeros; lanes of rows past the end write nothing that is read
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < JBU; ++h) {
+    if (sl[h] < 0) continue;
+    const int t = threadIdx.x + NT * h;
+    const int r2 = t / 25, o = t % 25;
+    const int dx = o % 5 - 2, dy = o / 5 - 2;
+    double acc[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) acc[e] = 0.0;
+    for (int qy = max(0, dy); qy <= min(2, dy + 2); ++qy)
+      for (int qx = max(0, dx); qx <= min(2, dx + 2); ++qx) {
+        const int qq = qy * 3 + qx;
+        const int lb = (dx + 2 - qx) + 3 * (dy + 2 - qy);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) acc[e] += part[r2][qq][lb * 9 + e];
+      }
+    if (code[h]) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          if (((code[h] >> (3 + i)) | (code[h] >> j)) & 1) acc[i * 3 + j] = (o == 12 && i == j) ? 1.0 : 0.0;
+    }
+    double* blk = val + ((int64_t)rp[h] + sl[h]) * 9;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) blk[e] = acc[e];
+  }
+}
+
 // 32 lanes per BSR row (two rows per wave); lane k < row length owns slot k.
 // With cmask, constrained rows and columns are written as the identity's.
 __global__ void __launch_bounds__(256) k_jac2_blocks(int64_t n_row, const int64_t* __restrict__ active_nodes,
@@ -636,170 +656,315 @@ __global__ void __launch_bounds__(256, 8) k_fint2_rows(int64_t n_row, int nd, in
 // ---------------------------------------------- group-cooperative 3-D ------
 constexpr int GP3 = 64;   // particles (threads) per workgroup in 3-D
 
-// 3-D Jacobian without atomics.  k_tan3: one thread per particle writes its
-// tangent table (V0 dP/dF, 81 entries, from 9 forward passes) and its
-// stencil weights and derivatives to a record.  k_jac3c: stencil groups of
-// one colour (origin index mod 3 per axis) hold pairwise disjoint node sets,
-// so one workgroup per group adds its 729 3x3 blocks with plain
-// read-modify-writes; the 27 colours run in a fixed order, every group's
-// particles in order, so the result is deterministic.
-constexpr int PD3 = 100;   // doubles per 3-D record: T 0..80 ((r*3+c)*9 + q), w 81..89 [axis][a], dw 90..98
-constexpr int JC3 = 32;    // records staged in LDS at a time
+// 3-D Jacobian, each 3x3 block written once.
+//
+// k_tan3v: nine lanes per particle, lane q = 3c + j carrying the direction
+// dF_cj, write the particle's tangent record: V0 dP_ri/dF_cj at
+// [(r*3 + c)*9 + i*3 + j].
+//
+// k_jac3_lines: one workgroup owns a segment of JL_SEG consecutive rows of one
+// x-line of nodes (fixed iy, iz) and sweeps the stencil-group origins ox along
+// x.  At step ox the nine groups (ox, iy - ly, iz - lz), ly, lz in 0..2, are
+// the only ones holding rows ox .. ox+2 of the line; their particles' tangent
+// records are staged in LDS beside their stencil weights (evaluated there:
+// the x-axis weights and derivatives and the yz products of the other two
+// axes, so that stencil node b = (bx, by, bz) has the gradient
+//   g_b = (dwx[bx] P0[by,bz], wx[bx] P1[by,bz], wx[bx] P2[by,bz])),
+// every (group, row, r, c) lane contracts its group's particles into the 27
+// blocks of its row, the nine groups' partial blocks meet in LDS and are
+// added to the rows' accumulators in a fixed group order, and row ox, which
+// no later step touches, is written to its BSR row with the Dirichlet rows
+// and columns applied.  So the matrix needs no clearing, no colour passes and
+// no second pass for the boundary conditions, and the result does not depend
+// on the launch.  A multigrid level runs the same kernel on its own grid and
+// particle order, reading the finest level's tangent records through a map.
+// Origins of colour (cx, cy, cz) along one axis: v = o + 1 in [0, n] with v = c mod 3.
+__device__ __host__ __forceinline__ int colour_count(int n, int c) { return c > n ? 0 : (n - c) / 3 + 1; }
 
-__global__ void __launch_bounds__(GP3) k_tan3(AsmArgs A, const double* __restrict__ du, double* __restrict__ rec,
-                                              int32_t* __restrict__ flag) {
-  const int64_t i = (int64_t)blockIdx.x * GP3 + threadIdx.x;
+constexpr int PW3 = 33;    // staged stencil data per particle: wx 0..2, dwx 3..5, P0 6..14, P1 15..23, P2 24..32
+constexpr int TL3 = 256;   // k_tan3v threads: 4 waves of 7 particles x 9 directions (63 of 64 lanes)
+constexpr int TP3 = 28;    // particles per k_tan3v workgroup
+
+__global__ void __launch_bounds__(TL3) k_tan3v(AsmArgs A, const double* __restrict__ du, double* __restrict__ rec,
+                                               int32_t* __restrict__ flag) {
+  const int wl = threadIdx.x % 64;
+  if (wl >= 63) return;
+  const int64_t i = (int64_t)blockIdx.x * TP3 + (threadIdx.x / 64) * 7 + wl / 9;
+  const int q = wl % 9;
   if (i >= A.np) return;
   PLoad<3> L;
   load_particle<3>(A, i, du, L);
   Mat<dnum> m = make_mat<dnum>(dnum(L.E), A.nu, dnum(L.phi), A.c, A.psi, A.dp, A.match, A.apex_reg);
   Sym3<double> be = load_be3(A, i);
-  double* R = rec + i * PD3;
-  int rerr = 0;
-  for (int q = 0; q < 9; ++q) {
-    dnum F[3][3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) F[r][c] = dnum(L.dF[r][c], q == r * 3 + c ? 1.0 : 0.0);
-    Sym3<dnum> bd;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) bd.a[k] = dnum(be.a[k]);
-    Out3<dnum> o;
-    mech3<dnum>(m, F, bd, o, nullptr, &rerr);
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) R[(r * 3 + c) * 9 + q] = L.v0 * o.P[r][c].d;
-  }
-  if (rerr) atomicOr(flag, 4);
-#pragma unroll
-  for (int k = 0; k < 3; ++k)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      R[81 + k * 3 + a] = L.st.w[k][a];
-      R[90 + k * 3 + a] = L.st.dw[k][a];
-    }
-}
-
-// Origins of colour (cx, cy, cz) along one axis: v = o + 1 in [0, n] with v = c mod 3.
-__device__ __host__ __forceinline__ int colour_count(int n, int c) { return c > n ? 0 : (n - c) / 3 + 1; }
-
-constexpr int JC3T = 256;   // threads: task t < 243 is (column node b, z-layer of a, block row r)
-__global__ void __launch_bounds__(JC3T) k_jac3c(int colour, const int64_t* __restrict__ wstart, int nsim,
-                                                const SimDev* __restrict__ sims, const int32_t* __restrict__ gstart,
-                                                const int32_t* __restrict__ node_map, const double* __restrict__ rec,
-                                                const int32_t* __restrict__ rowptr, const int8_t* __restrict__ slot,
-                                                double* __restrict__ val) {
-  __shared__ double sT[JC3][81];
-  __shared__ double sW[JC3][3][3], sD[JC3][3][3];
-  __shared__ int32_t sRow[27];
-  const int64_t w = blockIdx.x;
-  int s = 0;
-  while (s + 1 < nsim && wstart[s + 1] <= w) ++s;   // workgroup-uniform
-  const SimDev& S = sims[s];
-  const int cx = colour % 3, cy = (colour / 3) % 3, cz = colour / 9;
-  const int nx = colour_count(S.n[0], cx), ny = colour_count(S.n[1], cy);
-  const int64_t loc = w - wstart[s];
-  const int ox = cx + 3 * (int)(loc % nx) - 1, oy = cy + 3 * (int)((loc / nx) % ny) - 1,
-            oz = cz + 3 * (int)(loc / ((int64_t)nx * ny)) - 1;
-  const int64_t key = S.okey_base + (ox + 1) + (int64_t)S.noa[0] * ((oy + 1) + (int64_t)S.noa[1] * (oz + 1));
-  const int p0 = gstart[key], p1 = gstart[key + 1];
-  if (p0 == p1) return;   // empty origin (uniform over the workgroup)
-  const int t = threadIdx.x;
-  if (t < 27) {
-    const int ax = t % 3, ay = (t / 3) % 3, az = t / 9;
-    sRow[t] = node_map[S.node_base + (ox + ax + 1) + (int64_t)S.nna[0] * ((oy + ay + 1) + (int64_t)S.nna[1] * (oz + az + 1))];
-  }
-  const bool task = t < 243;
-  const int r = t % 3, az = (t / 3) % 3, b = t / 9;
-  const int bx = b % 3, by = (b / 3) % 3, bz = b / 9;
-  double acc[9][3];
-#pragma unroll
-  for (int a = 0; a < 9; ++a)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) acc[a][c] = 0.0;
-  for (int c0 = p0; c0 < p1; c0 += JC3) {
-    const int nc = min(JC3, p1 - c0);
-    __syncthreads();   // the previous chunk is consumed
-    for (int e = t; e < nc * 99; e += JC3T) {
-      const int q = e / 99, k = e % 99;
-      const double v = rec[(int64_t)(c0 + q) * PD3 + k];
-      if (k < 81) sT[q][k] = v;
-      else if (k < 90) sW[q][(k - 81) / 3][(k - 81) % 3] = v;
-      else sD[q][(k - 90) / 3][(k - 90) % 3] = v;
-    }
-    __syncthreads();
-    if (task) {
-      for (int p = 0; p < nc; ++p) {
-        const double* T = sT[p];
-        const double gb0 = sD[p][0][bx] * sW[p][1][by] * sW[p][2][bz];
-        const double gb1 = sW[p][0][bx] * sD[p][1][by] * sW[p][2][bz];
-        const double gb2 = sW[p][0][bx] * sW[p][1][by] * sD[p][2][bz];
-        double Tb[3][3];   // Tb[i][c] = sum_j dP_{r i}/dF_{c j} grad_j w_b
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const double* Tq = T + (r * 3 + i) * 9 + c * 3;
-            Tb[i][c] = Tq[0] * gb0 + Tq[1] * gb1 + Tq[2] * gb2;
-          }
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-          const int ax = a % 3, ay = a / 3;
-          const double ga0 = sD[p][0][ax] * sW[p][1][ay] * sW[p][2][az];
-          const double ga1 = sW[p][0][ax] * sD[p][1][ay] * sW[p][2][az];
-          const double ga2 = sW[p][0][ax] * sW[p][1][ay] * sD[p][2][az];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) acc[a][c] += ga0 * Tb[0][c] + ga1 * Tb[1][c] + ga2 * Tb[2][c];
-        }
-      }
-    }
-  }
-  if (task) {
-#pragma unroll
-    for (int a9 = 0; a9 < 9; ++a9) {
-      const int a = a9 + 9 * az;
-      const int32_t ra = sRow[a];
-      const int sl = slot[(int64_t)ra * 125 + nb_index<3>(a, b)];
-      double* blk = val + ((int64_t)rowptr[ra] + sl) * 9 + r * 3;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) blk[c] += acc[a9][c];   // one writer per entry in this colour
-    }
-  }
-}
-
-// 3-D internal force without atomics: k_fint3_rec writes per particle V0 P
-// and the stencil weights and derivatives; k_p2g3c (shared with the
-// external force) gives one workgroup to each stencil group of a colour and
-// adds the group's sum over its particles, in order, to each of its 27
-// nodes with a plain read-modify-write.
-constexpr int PR3 = 28;    // doubles per 3-D force record: V0 P 0..8 (or the force 0..2), w 9..17 [axis][a], dw 18..26
-
-__global__ void __launch_bounds__(256) k_fint3_rec(AsmArgs A, const double* __restrict__ du, double* __restrict__ rec,
-                                                  int32_t* __restrict__ flag) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= A.np) return;
-  PLoad<3> L;
-  load_particle<3>(A, i, du, L);
-  Mat<double> m = make_mat<double>(L.E, A.nu, L.phi, A.c, A.psi, A.dp, A.match, A.apex_reg);
-  Out3<double> o;
-  int rerr = 0;
-  mech3<double>(m, L.dF, load_be3(A, i), o, nullptr, &rerr);
-  if (rerr) atomicOr(flag, 4);
-  double* R = rec + i * PR3;
+  dnum F[3][3];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) R[r * 3 + c] = L.v0 * o.P[r][c];
+    for (int c = 0; c < 3; ++c) F[r][c] = dnum(L.dF[r][c], q == r * 3 + c ? 1.0 : 0.0);
+  Sym3<dnum> bd;
 #pragma unroll
-  for (int k = 0; k < 3; ++k)
+  for (int k = 0; k < 6; ++k) bd.a[k] = dnum(be.a[k]);
+  Out3<dnum> o;
+  int rerr = 0;
+  mech3<dnum>(m, F, bd, o, nullptr, &rerr);
+  if (rerr) atomicOr(flag, 4);
+  double* R = rec + i * PT3;
+  const int c = q / 3, j = q % 3;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      R[9 + k * 3 + a] = L.st.w[k][a];
-      R[18 + k * 3 + a] = L.st.dw[k][a];
-    }
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii) R[(r * 3 + c) * 9 + ii * 3 + j] = L.v0 * o.P[r][ii].d;
 }
+
+constexpr int JL_T = 256;    // threads; lane t < 243 is (group q, row la_x, r, c), c fastest
+constexpr int JL_SEG = 16;   // rows of a line per workgroup
+constexpr int JL_PART = 6561;            // doubles of the nine groups' partial blocks (9 x 3 rows x 27 x 9)
+constexpr int JL_CH = JL_PART / (PT3 + PW3);   // records staged per chunk in the same buffer (57)
+constexpr int JL_ACC = 3375;             // row accumulators: 3 rows x 125 blocks x 9
+constexpr int JL_FL = (1125 + JL_T - 1) / JL_T;   // entries of the finished row per thread
+
+__device__ __forceinline__ int imod3(int v) { return ((v % 3) + 3) % 3; }
+
+// Particle range [a, b) of group k of sweep step ox: origin (ox, iy - k % 3, iz - k / 3).
+__device__ __forceinline__ void line_group_range(const SimDev& S, const int32_t* __restrict__ gstart, int ox, int iy,
+                                                 int iz, int k, int& a, int& b) {
+  const int oy = iy - (k % 3), oz = iz - (k / 3);
+  a = 0;
+  b = 0;
+  if (oy >= -1 && oy <= S.n[1] - 1 && oz >= -1 && oz <= S.n[2] - 1) {
+    const int64_t key = S.okey_base + (ox + 1) + (int64_t)S.noa[0] * ((oy + 1) + (int64_t)S.noa[1] * (oz + 1));
+    a = gstart[key];
+    b = gstart[key + 1];
+  }
+}
+
+// Each step of the sweep loads nothing that it waits for at once except the
+// records it stages: the next step's group ranges and the finished row's
+// slots and Dirichlet codes are loaded a step ahead, or at the step's start
+// and used at its end.
+__global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restrict__ wstart, int nsim,
+                                                        const SimDev* __restrict__ sims,
+                                                        const int32_t* __restrict__ gstart,
+                                                        const int32_t* __restrict__ node_map,
+                                                        const double* __restrict__ xs, int64_t np,
+                                                        const double* __restrict__ rec,
+                                                        const int32_t* __restrict__ pmap,
+                                                        const int32_t* __restrict__ rowptr,
+                                                        const int8_t* __restrict__ slot,
+                                                        const uint8_t* __restrict__ bcode, double* __restrict__ val) {
+  __shared__ double sbuf[JL_PART];   // staged records [JL_CH][PT3] and stencil data [JL_CH][PW3]; then the
+                                     // nine groups' partial blocks
+  __shared__ double sacc[JL_ACC];    // rows in flight, slot imod3(ix): [slot][block 125][r*3+c]
+  __shared__ int32_t rng[2][9][2];   // group ranges of this step and the next: first particle, count
+  __shared__ int32_t srow[JL_SEG];
+  // Workgroups are dealt to the 8 XCDs in turn; XCD x takes the x-th
+  // contiguous eighth of the lines (z fastest), so lines that share stencil
+  // groups run side by side on one L2.
+  const unsigned nwg = gridDim.x, xcd = blockIdx.x % 8, kq = blockIdx.x / 8;
+  const unsigned q8 = nwg / 8, r8 = nwg % 8;
+  const int64_t w = (int64_t)xcd * q8 + min(xcd, r8) + kq;   // a bijection of [0, nwg)
+  int s = 0;
+  while (s + 1 < nsim && wstart[s + 1] <= w) ++s;   // workgroup-uniform
+  const SimDev& S = sims[s];
+  const int64_t loc = w - wstart[s];
+  const int iz = (int)(loc % S.nna[2]) - 1;
+  const int iy = (int)((loc / S.nna[2]) % S.nna[1]) - 1;
+  const int seg = (int)(loc / ((int64_t)S.nna[2] * S.nna[1]));
+  const int x0 = -1 + seg * JL_SEG;
+  const int x1 = min(x0 + JL_SEG, S.n[0] + 2);   // rows x0 .. x1-1 (nodes run to n+1)
+  const int t = threadIdx.x;
+  const int64_t line_base = S.node_base + (int64_t)S.nna[0] * ((iy + 1) + (int64_t)S.nna[1] * (iz + 1));
+  if (t < x1 - x0) srow[t] = node_map[line_base + (x0 + t + 1)];
+  for (int e = t; e < JL_ACC; e += JL_T) sacc[e] = 0.0;
+  const int ox_lo = max(x0 - 2, -1), ox_hi = min(x1 - 1, S.n[0] - 1);
+  int ra = 0, rb = 0;   // thread k < 9: range of group k, one step ahead
+  if (t < 9 && ox_lo <= ox_hi) line_group_range(S, gstart, ox_lo, iy, iz, t, ra, rb);
+  __syncthreads();
+  {
+    int any = 0;
+    for (int k = 0; k < x1 - x0; ++k) any |= srow[k] >= 0;
+    if (!any) return;   // no active row in this segment (uniform)
+  }
+  const bool lane = t < 243;
+  const int c = t % 3, r = (t / 3) % 3, la_x = (t / 9) % 3, q = t / 27;
+  const int yz = (q % 3) * 3 + q / 3;   // (ly, lz) of group q as a yz-product index
+
+  for (int ox = ox_lo; ox <= ox_hi + 2; ++ox) {
+    const int cur = ox & 1;
+    if (t < 9) {
+      rng[cur][t][0] = ra;
+      rng[cur][t][1] = rb - ra;
+      if (ox + 1 <= ox_hi) line_group_range(S, gstart, ox + 1, iy, iz, t, ra, rb);
+    }
+    // row ox is finished after this step: its slots and codes, in flight meanwhile
+    const int32_t frow = (ox >= x0 && ox < x1) ? srow[ox - x0] : -1;
+    int32_t fsp[JL_FL];
+    uint32_t fcode[JL_FL];
+    int64_t frp = 0;
+    if (frow >= 0) {
+      frp = rowptr[frow];
+#pragma unroll
+      for (int k = 0; k < JL_FL; ++k) {
+        const int l = t + JL_T * k;
+        fsp[k] = -1;
+        fcode[k] = 0;
+        if (l < 1125) {
+          fsp[k] = slot[(int64_t)frow * 125 + l / 9];
+          if (bcode) fcode[k] = bcode[(int64_t)frow * 125 + l / 9];
+        }
+      }
+    }
+    __syncthreads();   // this step's ranges are visible; the last row flush and clear are done
+    if (ox <= ox_hi) {
+      int g0[9], goff[10];
+      goff[0] = 0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        g0[k] = rng[cur][k][0];
+        goff[k + 1] = goff[k] + rng[cur][k][1];
+      }
+      const int ntot = goff[9];
+      if (ntot > 0) {
+        double acc[27];
+#pragma unroll
+        for (int b = 0; b < 27; ++b) acc[b] = 0.0;
+        const int ixr = ox + la_x;
+        const bool mine = lane && ixr >= x0 && ixr < x1 && srow[ixr - x0] >= 0;
+        int qb = 0, qe = 0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+          if (lane && q == k) { qb = goff[k]; qe = goff[k + 1]; }
+        for (int c0 = 0; c0 < ntot; c0 += JL_CH) {
+          const int nc = min(JL_CH, ntot - c0);
+          // four threads per staged particle: one evaluates its stencil on this
+          // level, three copy its tangent record
+          {
+            const int k = t >> 2, part = t & 3;
+            if (k < nc) {
+              const int gpos = c0 + k;
+              int qq = 0;
+#pragma unroll
+              for (int u = 1; u < 9; ++u) qq += gpos >= goff[u];
+              int gbase = g0[0], gstart_q = goff[0];
+#pragma unroll
+              for (int u = 1; u < 9; ++u)
+                if (qq == u) { gbase = g0[u]; gstart_q = goff[u]; }
+              const int64_t p = gbase + gpos - gstart_q;
+              if (part == 0) {
+                Stencil<3> st;
+                make_stencil<3>(S, xs, np, p, st);
+                double* W = sbuf + JL_CH * PT3 + k * PW3;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) { W[a] = st.w[0][a]; W[3 + a] = st.dw[0][a]; }
+#pragma unroll
+                for (int by = 0; by < 3; ++by)
+#pragma unroll
+                  for (int bz = 0; bz < 3; ++bz) {
+                    W[6 + by * 3 + bz] = st.w[1][by] * st.w[2][bz];
+                    W[15 + by * 3 + bz] = st.dw[1][by] * st.w[2][bz];
+                    W[24 + by * 3 + bz] = st.w[1][by] * st.dw[2][bz];
+                  }
+              } else {
+                const double* src = rec + (int64_t)(pmap ? pmap[p] : p) * PT3;
+                double v[27];
+#pragma unroll
+                for (int m = 0; m < 27; ++m) v[m] = src[(part - 1) + 3 * m];
+#pragma unroll
+                for (int m = 0; m < 27; ++m) sbuf[k * PT3 + (part - 1) + 3 * m] = v[m];
+              }
+            }
+          }
+          __syncthreads();
+          if (mine) {
+            const int kb = max(qb, c0) - c0, ke = min(qe, c0 + nc) - c0;
+            for (int k = kb; k < ke; ++k) {
+              const double* T = sbuf + k * PT3 + (r * 3 + c) * 9;
+              const double* R = sbuf + JL_CH * PT3 + k * PW3;
+              double wx[3], dwx[3];
+#pragma unroll
+              for (int u = 0; u < 3; ++u) { wx[u] = R[u]; dwx[u] = R[3 + u]; }
+              const double wxa = la_x == 0 ? wx[0] : (la_x == 1 ? wx[1] : wx[2]);
+              const double dwxa = la_x == 0 ? dwx[0] : (la_x == 1 ? dwx[1] : dwx[2]);
+              const double ga0 = dwxa * R[6 + yz], ga1 = wxa * R[15 + yz], ga2 = wxa * R[24 + yz];
+              double ta[3];
+#pragma unroll
+              for (int jj = 0; jj < 3; ++jj) ta[jj] = fma(ga0, T[jj], fma(ga1, T[3 + jj], ga2 * T[6 + jj]));
+              double u0[3], u1[3], u2[3];
+#pragma unroll
+              for (int bx = 0; bx < 3; ++bx) { u0[bx] = ta[0] * dwx[bx]; u1[bx] = ta[1] * wx[bx]; u2[bx] = ta[2] * wx[bx]; }
+#pragma unroll
+              for (int byz = 0; byz < 9; ++byz) {
+                const double p0 = R[6 + byz], p1 = R[15 + byz], p2 = R[24 + byz];
+                const int by = byz / 3, bz = byz % 3;
+#pragma unroll
+                for (int bx = 0; bx < 3; ++bx) {
+                  const int b = bx + 3 * by + 9 * bz;
+                  acc[b] = fma(u0[bx], p0, fma(u1[bx], p1, fma(u2[bx], p2, acc[b])));
+                }
+              }
+            }
+          }
+          __syncthreads();   // chunk consumed (and, after the last one, the buffer is free)
+        }
+        if (lane) {
+#pragma unroll
+          for (int b = 0; b < 27; ++b) sbuf[((q * 3 + la_x) * 27 + b) * 9 + r * 3 + c] = mine ? acc[b] : 0.0;
+        }
+        __syncthreads();
+        // accumulator block (slot sl, offset d) adds the nine groups' partials in
+        // group order, all nine entries at once
+        for (int it = t; it < 375; it += JL_T) {
+          const int sl = it / 125, d = it - sl * 125;
+          const int lx = imod3(sl - ox);   // row ox + lx sits in slot sl
+          const int dx = d % 5 - 2, dy = (d / 5) % 5 - 2, dz = d / 25 - 2;
+          const int bx = lx + dx;
+          if (bx < 0 || bx > 2) continue;
+          double sum[9];
+#pragma unroll
+          for (int e = 0; e < 9; ++e) sum[e] = 0.0;
+#pragma unroll
+          for (int qq = 0; qq < 9; ++qq) {
+            const int by = qq % 3 + dy, bz = qq / 3 + dz;
+            if (by >= 0 && by <= 2 && bz >= 0 && bz <= 2) {
+              const double* src = sbuf + ((qq * 3 + lx) * 27 + bx + 3 * by + 9 * bz) * 9;
+#pragma unroll
+              for (int e = 0; e < 9; ++e) sum[e] += src[e];
+            }
+          }
+          double* dst = sacc + sl * 1125 + d * 9;
+#pragma unroll
+          for (int e = 0; e < 9; ++e) dst[e] += sum[e];
+        }
+        __syncthreads();   // partials consumed; row ox is complete
+      }
+    }
+    // row ox is finished (the last two steps only flush): write it, clear its slot
+    if (ox >= x0 && ox < x1) {
+      const int sl0 = imod3(ox);
+      if (frow >= 0) {
+#pragma unroll
+        for (int k = 0; k < JL_FL; ++k) {
+          const int l = t + JL_T * k;
+          if (l < 1125 && fsp[k] >= 0) {
+            const int d = l / 9, rc = l - d * 9;
+            double out = sacc[sl0 * 1125 + l];
+            const int rr = rc / 3, cc = rc - rr * 3;
+            if (((fcode[k] >> (3 + rr)) | (fcode[k] >> cc)) & 1u) out = (d == 62 && rr == cc) ? 1.0 : 0.0;
+            val[(frp + fsp[k]) * 9 + rc] = out;
+          }
+        }
+      }
+      for (int l = t; l < 1125; l += JL_T) sacc[sl0 * 1125 + l] = 0.0;
+    }
+  }
+}
+
+// 3-D external force without atomics: per particle a force record (the
+// particle's force and its stencil weights and derivatives, written by the
+// pattern build), then k_p2g3c gives one workgroup to each stencil group of a
+// colour and adds the group's sum over its particles, in order, to each of
+// its 27 nodes with a plain read-modify-write.
+constexpr int PR3 = 28;    // doubles per 3-D force record: V0 P 0..8 (or the force 0..2), w 9..17 [axis][a], dw 18..26
 
 // mode 0: f_a += sum_p V0 P_p grad w_a(x_p) (internal force);
 // mode 1: f_a += sum_p w_a(x_p) f_p (external force).
@@ -857,23 +1022,305 @@ __global__ void __launch_bounds__(64) k_p2g3c(int colour, int mode, const int64_
   }
 }
 
-// Dirichlet rows/columns: zero them, 1 on the diagonal (structure unchanged).
-__global__ void k_jac_bc(int64_t n_row, int nd, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
-                         const uint8_t* __restrict__ cmask, double* __restrict__ val) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n_row) return;
-  for (int32_t k = rowptr[r]; k < rowptr[r + 1]; ++k) {
-    int32_t c = colind[k];
-    double* blk = val + (int64_t)k * nd * nd;
-    for (int i = 0; i < nd; ++i)
-      for (int j = 0; j < nd; ++j)
-        if (cmask[r * nd + i] || cmask[(int64_t)c * nd + j]) blk[i * nd + j] = (r == c && i == j) ? 1.0 : 0.0;
+// 3-D internal force in one pass per colour, without particle records:
+// a workgroup takes FG3 consecutive stencil groups of one colour (no two of
+// them share a node), evaluates their particles' stresses into LDS (64 at a
+// time) and then adds each group's sum over its particles, in order, to each
+// of the group's 27 nodes with a plain read-modify-write.  Every particle is
+// evaluated once, and f_int is deterministic.
+constexpr int FG3 = 8;    // stencil groups per workgroup
+constexpr int FT3 = 64;   // threads (particles evaluated at a time)
+
+__global__ void __launch_bounds__(FT3) k_fint3c(AsmArgs A, const double* __restrict__ du, int colour,
+                                                const int64_t* __restrict__ wstart, const int32_t* __restrict__ gstart,
+                                                double* __restrict__ fint, int32_t* __restrict__ flag) {
+  __shared__ double sP[FT3][9];              // V0 P of the staged particles
+  __shared__ double sW[FT3][3][2][3];        // per axis: weights, derivatives
+  __shared__ int32_t gp0[FG3], goff[FG3 + 1];
+  __shared__ int32_t gox[FG3], goy[FG3], goz[FG3];
+  const int64_t w = blockIdx.x;
+  int s = 0;
+  while (s + 1 < A.nsim && wstart[s + 1] <= w) ++s;   // workgroup-uniform
+  const SimDev& S = A.sims[s];
+  const int cx = colour % 3, cy = (colour / 3) % 3, cz = colour / 9;
+  const int nx = colour_count(S.n[0], cx), ny = colour_count(S.n[1], cy), nz = colour_count(S.n[2], cz);
+  const int64_t ngr = (int64_t)nx * ny * nz;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    int acc = 0;
+    for (int k = 0; k < FG3; ++k) {
+      const int64_t g = (w - wstart[s]) * FG3 + k;
+      int a = 0, b = 0, ox = 0, oy = 0, oz = 0;
+      if (g < ngr) {
+        ox = cx + 3 * (int)(g % nx) - 1;
+        oy = cy + 3 * (int)((g / nx) % ny) - 1;
+        oz = cz + 3 * (int)(g / ((int64_t)nx * ny)) - 1;
+        const int64_t key = S.okey_base + (ox + 1) + (int64_t)S.noa[0] * ((oy + 1) + (int64_t)S.noa[1] * (oz + 1));
+        a = gstart[key];
+        b = gstart[key + 1];
+      }
+      gp0[k] = a; goff[k] = acc; acc += b - a;
+      gox[k] = ox; goy[k] = oy; goz[k] = oz;
+    }
+    goff[FG3] = acc;
+  }
+  __syncthreads();
+  const int ntot = goff[FG3];
+  if (ntot == 0) return;   // uniform
+  // tasks: (group k, stencil node a), FG3 * 27 = 216 of them over 64 threads
+  constexpr int NTK = (FG3 * 27 + FT3 - 1) / FT3;
+  double f[NTK][3];
+#pragma unroll
+  for (int j = 0; j < NTK; ++j) f[j][0] = f[j][1] = f[j][2] = 0.0;
+  int rerr = 0;
+  for (int c0 = 0; c0 < ntot; c0 += FT3) {
+    const int nc = min(FT3, ntot - c0);
+    if (t < nc) {
+      const int gpos = c0 + t;
+      int k = 0;
+#pragma unroll
+      for (int u = 1; u < FG3; ++u) k += gpos >= goff[u];
+      const int64_t i = gp0[k] + (gpos - goff[k]);
+      PLoad<3> L;
+      load_particle<3>(A, i, du, L);
+      Mat<double> m = make_mat<double>(L.E, A.nu, L.phi, A.c, A.psi, A.dp, A.match, A.apex_reg);
+      Out3<double> o;
+      mech3<double>(m, L.dF, load_be3(A, i), o, nullptr, &rerr);
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) sP[t][r * 3 + cc] = L.v0 * o.P[r][cc];
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) { sW[t][ax][0][a] = L.st.w[ax][a]; sW[t][ax][1][a] = L.st.dw[ax][a]; }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NTK; ++j) {
+      const int tk = t + FT3 * j;
+      if (tk >= FG3 * 27) continue;
+      const int k = tk / 27, a = tk % 27;
+      const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
+      const int kb = max(goff[k], c0) - c0, ke = min(goff[k + 1], c0 + nc) - c0;
+      for (int p = kb; p < ke; ++p) {
+        const double ga0 = sW[p][0][1][ax] * sW[p][1][0][ay] * sW[p][2][0][az];
+        const double ga1 = sW[p][0][0][ax] * sW[p][1][1][ay] * sW[p][2][0][az];
+        const double ga2 = sW[p][0][0][ax] * sW[p][1][0][ay] * sW[p][2][1][az];
+        const double* P = sP[p];
+        f[j][0] += P[0] * ga0 + P[1] * ga1 + P[2] * ga2;
+        f[j][1] += P[3] * ga0 + P[4] * ga1 + P[5] * ga2;
+        f[j][2] += P[6] * ga0 + P[7] * ga1 + P[8] * ga2;
+      }
+    }
+    __syncthreads();   // the staged particles are consumed
+  }
+  if (rerr) atomicOr(flag, 4);
+#pragma unroll
+  for (int j = 0; j < NTK; ++j) {
+    const int tk = t + FT3 * j;
+    if (tk >= FG3 * 27) continue;
+    const int k = tk / 27, a = tk % 27;
+    if (goff[k + 1] == goff[k]) continue;   // empty group: its nodes may be inactive
+    const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
+    const int32_t ra = A.node_map[S.node_base + (gox[k] + ax + 1) +
+                                  (int64_t)S.nna[0] * ((goy[k] + ay + 1) + (int64_t)S.nna[1] * (goz[k] + az + 1))];
+    double* fo = fint + (int64_t)ra * 3;
+    fo[0] += f[j][0];   // one writer per node in this colour
+    fo[1] += f[j][1];
+    fo[2] += f[j][2];
   }
 }
 
+// Matrix-free Jacobian-vector product (the matrix-free Newton-Krylov variant
+// of Sec. 2.2, Remark 2): y = J x from the per-particle tangent records
+// (V0 dP/dF) without forming the BSR matrix.  Per particle the increment
+// gradient dF = sum_b x_b (x) grad w_b, the stress increment dP = T : dF,
+// then dP grad w_a scattered like the internal force.  Constrained unknowns
+// of x are read as zero when cm is given (the Dirichlet-modified matrix).
+//
+// 3-D: per colour, FG3 stencil groups per workgroup as in k_fint3c.
+__global__ void __launch_bounds__(FT3) k_jv3c(int colour, const int64_t* __restrict__ wstart, int nsim,
+                                              const SimDev* __restrict__ sims, const int32_t* __restrict__ gstart,
+                                              const int32_t* __restrict__ node_map, const double* __restrict__ xs,
+                                              int64_t np, const double* __restrict__ rec,
+                                              const uint8_t* __restrict__ cm, const double* __restrict__ x,
+                                              double* __restrict__ y) {
+  __shared__ double sP[FT3][9];
+  __shared__ double sW[FT3][3][2][3];
+  __shared__ int32_t gp0[FG3], goff[FG3 + 1];
+  __shared__ int32_t gox[FG3], goy[FG3], goz[FG3];
+  const int64_t w = blockIdx.x;
+  int s = 0;
+  while (s + 1 < nsim && wstart[s + 1] <= w) ++s;   // workgroup-uniform
+  const SimDev& S = sims[s];
+  const int cx = colour % 3, cy = (colour / 3) % 3, cz = colour / 9;
+  const int nx = colour_count(S.n[0], cx), ny = colour_count(S.n[1], cy), nz = colour_count(S.n[2], cz);
+  const int64_t ngr = (int64_t)nx * ny * nz;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    int acc = 0;
+    for (int k = 0; k < FG3; ++k) {
+      const int64_t g = (w - wstart[s]) * FG3 + k;
+      int a = 0, b = 0, ox = 0, oy = 0, oz = 0;
+      if (g < ngr) {
+        ox = cx + 3 * (int)(g % nx) - 1;
+        oy = cy + 3 * (int)((g / nx) % ny) - 1;
+        oz = cz + 3 * (int)(g / ((int64_t)nx * ny)) - 1;
+        const int64_t key = S.okey_base + (ox + 1) + (int64_t)S.noa[0] * ((oy + 1) + (int64_t)S.noa[1] * (oz + 1));
+        a = gstart[key];
+        b = gstart[key + 1];
+      }
+      gp0[k] = a; goff[k] = acc; acc += b - a;
+      gox[k] = ox; goy[k] = oy; goz[k] = oz;
+    }
+    goff[FG3] = acc;
+  }
+  __syncthreads();
+  const int ntot = goff[FG3];
+  if (ntot == 0) return;   // uniform
+  constexpr int NTK = (FG3 * 27 + FT3 - 1) / FT3;
+  double f[NTK][3];
+#pragma unroll
+  for (int j = 0; j < NTK; ++j) f[j][0] = f[j][1] = f[j][2] = 0.0;
+  for (int c0 = 0; c0 < ntot; c0 += FT3) {
+    const int nc = min(FT3, ntot - c0);
+    if (t < nc) {
+      const int gpos = c0 + t;
+      int k = 0;
+#pragma unroll
+      for (int u = 1; u < FG3; ++u) k += gpos >= goff[u];
+      const int64_t i = gp0[k] + (gpos - goff[k]);
+      Stencil<3> st;
+      make_stencil<3>(S, xs, np, i, st);
+      double dF[3][3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dF[r][c] = 0.0;
+#pragma unroll
+      for (int az = 0; az < 3; ++az) {
+        int32_t rr[9];
+#pragma unroll
+        for (int a9 = 0; a9 < 9; ++a9) rr[a9] = node_map[st.node(S, a9 + 9 * az)];
+#pragma unroll
+        for (int a9 = 0; a9 < 9; ++a9) {
+          double g[3];
+          st.grad(a9 + 9 * az, g);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const int64_t e = (int64_t)rr[a9] * 3 + c;
+            const double xv = (cm && cm[e]) ? 0.0 : x[e];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) dF[c][j] += xv * g[j];
+          }
+        }
+      }
+      const double* T = rec + i * PT3;
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) {
+          double a = 0.0;
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) a += T[(r * 3 + c) * 9 + ii * 3 + j] * dF[c][j];
+          sP[t][r * 3 + ii] = a;
+        }
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) { sW[t][ax][0][a] = st.w[ax][a]; sW[t][ax][1][a] = st.dw[ax][a]; }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NTK; ++j) {
+      const int tk = t + FT3 * j;
+      if (tk >= FG3 * 27) continue;
+      const int k = tk / 27, a = tk % 27;
+      const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
+      const int kb = max(goff[k], c0) - c0, ke = min(goff[k + 1], c0 + nc) - c0;
+      for (int p = kb; p < ke; ++p) {
+        const double ga0 = sW[p][0][1][ax] * sW[p][1][0][ay] * sW[p][2][0][az];
+        const double ga1 = sW[p][0][0][ax] * sW[p][1][1][ay] * sW[p][2][0][az];
+        const double ga2 = sW[p][0][0][ax] * sW[p][1][0][ay] * sW[p][2][1][az];
+        const double* P = sP[p];
+        f[j][0] += P[0] * ga0 + P[1] * ga1 + P[2] * ga2;
+        f[j][1] += P[3] * ga0 + P[4] * ga1 + P[5] * ga2;
+        f[j][2] += P[6] * ga0 + P[7] * ga1 + P[8] * ga2;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < NTK; ++j) {
+    const int tk = t + FT3 * j;
+    if (tk >= FG3 * 27) continue;
+    const int k = tk / 27, a = tk % 27;
+    if (goff[k + 1] == goff[k]) continue;
+    const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
+    const int32_t ra = node_map[S.node_base + (gox[k] + ax + 1) +
+                                (int64_t)S.nna[0] * ((goy[k] + ay + 1) + (int64_t)S.nna[1] * (goz[k] + az + 1))];
+    double* yo = y + (int64_t)ra * 3;
+    yo[0] += f[j][0];   // one writer per node in this colour
+    yo[1] += f[j][1];
+    yo[2] += f[j][2];
+  }
+}
+
+// 2-D: per particle the stress increment dP = T : dF from its tangent record
+// (k_tan2 layout), written as a residual record (k_fint2_rec layout) so the
+// row gather of the internal force forms y.
+__global__ void __launch_bounds__(256) k_jv2_rec(int64_t np, const SimDev* __restrict__ sims,
+                                                 const int32_t* __restrict__ psim, const int32_t* __restrict__ node_map,
+                                                 const double* __restrict__ pdat, const uint8_t* __restrict__ cm,
+                                                 const double* __restrict__ xs, const double* __restrict__ x,
+                                                 double* __restrict__ rec) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= np) return;
+  const SimDev& S = sims[psim[i]];
+  const double* P = pdat + i * PD2;
+  const double u0 = (xs[i] - S.x0[0]) / S.h, u1 = (xs[np + i] - S.x0[1]) / S.h;
+  const int o0 = (int)floor(u0 - 0.5), o1 = (int)floor(u1 - 0.5);
+  double dF[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+  for (int b = 0; b < 9; ++b) {
+    const int bx = b % 3, by = b / 3;
+    const int32_t r = node_map[S.node_base + (o0 + bx + 1) + (int64_t)S.nna[0] * (o1 + by + 1)];
+    const double g0 = P[19 + bx] * P[22 + by], g1 = P[16 + bx] * P[25 + by];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int64_t e = (int64_t)r * 2 + c;
+      const double xv = (cm && cm[e]) ? 0.0 : x[e];
+      dF[c][0] += xv * g0;
+      dF[c][1] += xv * g1;
+    }
+  }
+  double* R = rec + i * RD2;
+#pragma unroll
+  for (int o = 0; o < 4; ++o)
+    R[o] = P[o * 4 + 0] * dF[0][0] + P[o * 4 + 1] * dF[0][1] + P[o * 4 + 2] * dF[1][0] + P[o * 4 + 3] * dF[1][1];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    R[8 + a] = P[16 + a];
+    R[11 + a] = P[19 + a];
+    R[14 + a] = P[22 + a];
+    R[17 + a] = P[25 + a];
+  }
+}
+
+// Dirichlet rows of J_mod x: y = x on constrained unknowns.
+__global__ void k_jv_bc(int64_t nv, const uint8_t* __restrict__ cm, const double* __restrict__ x,
+                        double* __restrict__ y) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nv && cm[e]) y[e] = x[e];
+}
+
+
 // ------------------------------------------------------------- update ------
 template <int DIM>
-__global__ void k_update(AsmArgs A, const double* __restrict__ du, const int32_t* __restrict__ perm,
+__global__ void __launch_bounds__(256) k_update(AsmArgs A, const double* __restrict__ du, const int32_t* __restrict__ perm,
                          double* __restrict__ x_out, double* __restrict__ F_out, double* __restrict__ be_out,
                          int32_t* __restrict__ flag) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -908,21 +1355,19 @@ __global__ void k_update(AsmArgs A, const double* __restrict__ du, const int32_t
     }
   if constexpr (DIM == 2) {
     Out2<double> o;
-    Sym2<double> ee;
+    Sym2<double> b;
     double F[2][2] = {{L.dF[0][0], L.dF[0][1]}, {L.dF[1][0], L.dF[1][1]}};
     double gp0[2] = {0.0, 0.0};
-    mech2<double>(m, F, load_be2(A, i), L.Jn, 0, up_par(A), 0.0, gp0, o, &ee);
-    Sym2<double> b = exp2eps2(ee);
+    mech2<double>(m, F, load_be2(A, i), L.Jn, 0, up_par(A), 0.0, gp0, o, &b);
     if (be_out) {
       be_out[0 * np + p] = b.xx; be_out[1 * np + p] = b.yy; be_out[2 * np + p] = b.xy; be_out[3 * np + p] = b.zz;
     }
   } else {
     Out3<double> o;
-    Sym3<double> ee;
+    Sym3<double> b;
     int rerr = 0;
-    mech3<double>(m, L.dF, load_be3(A, i), o, &ee, &rerr);
+    mech3<double>(m, L.dF, load_be3(A, i), o, &b, &rerr);
     if (rerr) atomicOr(flag, 4);
-    Sym3<double> b = exp2eps3(ee);
     if (be_out)
 #pragma unroll
       for (int t = 0; t < 6; ++t) be_out[t * np + p] = b.a[t];
@@ -943,6 +1388,7 @@ using namespace mpm;
 static AsmArgs make_args(mpm_ctx* c, const mpm_problem* pb) {
   AsmArgs A;
   A.np = c->np;
+  A.nsim = c->nsim;
   A.nd = c->nd;
   A.up = c->up;
   A.dp = c->dp;
@@ -981,6 +1427,29 @@ int build_colour_table(mpm_ctx* c) {
   if (c->jc3_ws.ensure(c->jc3_ws_h.size()) != hipSuccess) return c->fail(MPM_E_NOMEM, "colour table allocation failed");
   HIPC(c, hipMemcpyAsync(c->jc3_ws.p, c->jc3_ws_h.data(), c->jc3_ws_h.size() * sizeof(int64_t), hipMemcpyHostToDevice,
                          c->stream));
+  // per colour and sim the first workgroup of the fused 3-D internal force (FG3 groups each)
+  c->jf3_ws_h.assign(27 * (size_t)(nsim + 1), 0);
+  for (int col = 0; col < 27; ++col) {
+    int64_t* ws = &c->jf3_ws_h[(size_t)col * (nsim + 1)];
+    for (int s = 0; s < nsim; ++s) {
+      const SimDev& S = c->sims_h[s];
+      const int64_t ng = (int64_t)colour_count(S.n[0], col % 3) * colour_count(S.n[1], (col / 3) % 3) *
+                         colour_count(S.n[2], col / 9);
+      ws[s + 1] = ws[s] + (ng + FG3 - 1) / FG3;
+    }
+  }
+  if (c->jf3_ws.ensure(c->jf3_ws_h.size()) != hipSuccess) return c->fail(MPM_E_NOMEM, "colour table allocation failed");
+  HIPC(c, hipMemcpyAsync(c->jf3_ws.p, c->jf3_ws_h.data(), c->jf3_ws_h.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                         c->stream));
+  // per sim the first workgroup of the 3-D line sweep: (n+3)^2 lines of ceil((n+3)/JL_SEG) segments
+  c->jl3_ws_h.assign(nsim + 1, 0);
+  for (int s = 0; s < nsim; ++s) {
+    const SimDev& S = c->sims_h[s];
+    c->jl3_ws_h[s + 1] = c->jl3_ws_h[s] + (int64_t)((S.nna[0] + JL_SEG - 1) / JL_SEG) * S.nna[1] * S.nna[2];
+  }
+  if (c->jl3_ws.ensure(nsim + 1) != hipSuccess) return c->fail(MPM_E_NOMEM, "line table allocation failed");
+  HIPC(c, hipMemcpyAsync(c->jl3_ws.p, c->jl3_ws_h.data(), (nsim + 1) * sizeof(int64_t), hipMemcpyHostToDevice,
+                         c->stream));
   return MPM_OK;
 }
 
@@ -999,7 +1468,7 @@ int launch_p2g3(mpm_ctx* c, int mode, const double* rec, double* out) {
 }
 
 // Doubles per particle of the residual's force records.
-int64_t fint_record_doubles(int dim) { return dim == 2 ? RD2 : PR3; }
+int64_t fint_record_doubles(int dim) { return dim == 2 ? RD2 : 0; }
 
 // f_int into c->fint.  rec: the force records (np * fint_record_doubles
 // doubles); null uses the context's own buffer (allocated on first use).
@@ -1025,10 +1494,16 @@ int launch_fint(mpm_ctx* c, const mpm_problem* pb, const double* du, double* rec
   }
   HIPC(c, hipMemsetAsync(c->fint.p, 0, c->n_row * c->nd * sizeof(double), c->stream));
   if (c->np == 0) return MPM_OK;
-  // force records, then the 27 colours of stencil groups in order
-  k_fint3_rec<<<(unsigned)((c->np + 255) / 256), 256, 0, c->stream>>>(A, du, rec, c->flag.p);
-  LAUNCH_CHECK(c, "k_fint3_rec");
-  return launch_p2g3(c, 0, rec, c->fint.p);
+  // the 27 colours of stencil groups in order, stresses evaluated in place (no records)
+  const int nsim = c->nsim;
+  for (int col = 0; col < 27; ++col) {
+    const int64_t nwg = c->jf3_ws_h[(size_t)col * (nsim + 1) + nsim];
+    if (nwg == 0) continue;
+    k_fint3c<<<(unsigned)nwg, FT3, 0, c->stream>>>(A, du, col, c->jf3_ws.p + (size_t)col * (nsim + 1), c->gstart.p,
+                                                    c->fint.p, c->flag.p);
+    LAUNCH_CHECK(c, "k_fint3c");
+  }
+  return MPM_OK;
 }
 
 // Residual with per-sim ||r||^2 -> simsc[s*16+0], reaction -> simsc[s*16+1].
@@ -1066,6 +1541,16 @@ int launch_jac2_records(mpm_ctx* c, double* val, bool apply_bc) {
   return MPM_OK;
 }
 
+// u-p BSR blocks of context c from its u-p records rec (c's sorted order).
+int launch_jac2up_records(mpm_ctx* c, const double* rec, double* val, bool apply_bc, const int32_t* rgrp) {
+  if (c->n_row > 0) {
+    k_jac2up_rows<<<(unsigned)((c->n_row + JRU - 1) / JRU), JRU * 16, 0, c->stream>>>(
+        c->n_row, rgrp ? rgrp : c->rgrp.p, rec, c->rowptr.p, c->slot.p, apply_bc ? c->bcode.p : nullptr, val);
+    LAUNCH_CHECK(c, "k_jac2up_rows");
+  }
+  return MPM_OK;
+}
+
 // BSR blocks from the group blocks already in c->gbuf.
 int launch_jac2_blocks(mpm_ctx* c, double* val, bool apply_bc) {
   if (c->n_row > 0) {
@@ -1073,6 +1558,20 @@ int launch_jac2_blocks(mpm_ctx* c, double* val, bool apply_bc) {
         c->n_row, c->active_nodes.p, c->row_sim.p, c->sims.p, c->gstart.p, c->rowptr.p, c->colind.p, c->gbuf.p,
         apply_bc ? c->cmask.p : nullptr, val);
     LAUNCH_CHECK(c, "k_jac2_blocks");
+  }
+  return MPM_OK;
+}
+
+// 3-D BSR blocks of context c from tangent records rec (indexed through pmap
+// when given: record pmap[p] belongs to c's sorted particle p).
+int launch_jac3_lines(mpm_ctx* c, const double* rec, const int32_t* pmap, double* val, bool apply_bc,
+                      const int32_t* gstart, const double* xs, int64_t np) {
+  const int64_t nwg = c->jl3_ws_h.empty() ? 0 : c->jl3_ws_h[c->nsim];
+  if (nwg > 0 && c->n_row > 0) {
+    k_jac3_lines<<<(unsigned)nwg, JL_T, 0, c->stream>>>(
+        c->jl3_ws.p, c->nsim, c->sims.p, gstart ? gstart : c->gstart.p, c->node_map.p, xs ? xs : c->xs.p,
+        np >= 0 ? np : c->np, rec, pmap, c->rowptr.p, c->slot.p, apply_bc ? c->bcode.p : nullptr, val);
+    LAUNCH_CHECK(c, "k_jac3_lines");
   }
   return MPM_OK;
 }
@@ -1088,34 +1587,90 @@ int launch_jacobian(mpm_ctx* c, const mpm_problem* pb, const double* du, double*
       k_tan2<<<(unsigned)((4 * c->np + 255) / 256), 256, 0, c->stream>>>(A, du, c->pdat.p);
       LAUNCH_CHECK(c, "k_tan2");
     }
+    c->tan_ready = true;
     GUARD(launch_jac2_records(c, val, apply_bc));
+  } else if (c->dim == 2) {
+    // u-p: 7x7 tangent records, then one writer per 3x3 block
+    if (c->pdat.ensure(std::max<int64_t>(1, c->np) * PU2) != hipSuccess)
+      return c->fail(MPM_E_NOMEM, "particle tangent records allocation failed");
+    if (c->np > 0) {
+      k_tan2up<<<(unsigned)((8 * c->np + 255) / 256), 256, 0, c->stream>>>(A, du, c->pdat.p);
+      LAUNCH_CHECK(c, "k_tan2up");
+    }
+    GUARD(launch_jac2up_records(c, c->pdat.p, val, apply_bc));
+  }
+  if (c->dim == 3) {
+    // tangent records, then the row segments of every x-line (each block written once)
+    if (c->np > 0) {
+      if (c->pdat3.ensure(c->np * PT3) != hipSuccess)
+        return c->fail(MPM_E_NOMEM, "3-D tangent records allocation failed");
+      k_tan3v<<<(unsigned)((c->np + TP3 - 1) / TP3), TL3, 0, c->stream>>>(A, du, c->pdat3.p, c->flag.p);
+      LAUNCH_CHECK(c, "k_tan3v");
+    }
+    c->tan_ready = true;
+    GUARD(launch_jac3_lines(c, c->pdat3.p, nullptr, val, apply_bc));
+  }
+  return MPM_OK;
+}
+
+// y = J x without the matrix (see k_jv3c).  records: compute the tangent
+// records at du first (else reuse those of the last assembly at the same du).
+int launch_jv(mpm_ctx* c, const mpm_problem* pb, const double* du, bool records, const double* x, double* y,
+              bool apply_bc) {
+  if (c->up) return c->fail(MPM_E_INVALID, "the matrix-free product covers single-phase problems");
+  AsmArgs A = make_args(c, pb);
+  const int nd = c->nd;
+  const int64_t nv = c->n_row * nd;
+  const uint8_t* cm = apply_bc ? c->cmask.p : nullptr;
+  if (c->dim == 2) {
+    if (records) {
+      if (c->pdat.ensure(std::max<int64_t>(1, c->np) * PD2) != hipSuccess)
+        return c->fail(MPM_E_NOMEM, "particle tangent records allocation failed");
+      if (c->np > 0) {
+        k_tan2<<<(unsigned)((4 * c->np + 255) / 256), 256, 0, c->stream>>>(A, du, c->pdat.p);
+        LAUNCH_CHECK(c, "k_tan2");
+      }
+      c->tan_ready = true;
+    } else if (!c->tan_ready) {
+      return c->fail(MPM_E_INVALID, "no tangent records of this prepare to reuse");
+    }
+    if (c->rrec.ensure(std::max<int64_t>(1, c->np) * RD2) != hipSuccess)
+      return c->fail(MPM_E_NOMEM, "residual records allocation failed");
+    if (c->np > 0) {
+      k_jv2_rec<<<nb256(c->np), 256, 0, c->stream>>>(c->np, c->sims.p, c->psim.p, c->node_map.p, c->pdat.p, cm,
+                                                    c->xs.p, x, c->rrec.p);
+      LAUNCH_CHECK(c, "k_jv2_rec");
+    }
+    if (c->n_row > 0) {
+      k_fint2_rows<<<(unsigned)((c->n_row * RL2 + 255) / 256), 256, 0, c->stream>>>(c->n_row, nd, 0, c->rgrp.p,
+                                                                                    c->rrec.p, y);
+      LAUNCH_CHECK(c, "k_fint2_rows");
+    }
   } else {
-    HIPC(c, hipMemsetAsync(val, 0, c->nnzb * nd * nd * sizeof(double), c->stream));
-  }
-  if (c->np > 0 && c->dim == 2 && c->up) {
-    const unsigned g8 = (unsigned)((c->np + JT / 8 - 1) / (JT / 8));
-    k_jac2g<7><<<g8, JT, 0, c->stream>>>(A, du, c->rowptr.p, c->slot.p, val);
-    LAUNCH_CHECK(c, "k_jac2g");
-  }
-  if (c->np > 0 && c->dim == 3) {
-    // tangent records, then the 27 colours of stencil groups in order
-    if (c->pdat3.ensure(c->np * PD3) != hipSuccess)
-      return c->fail(MPM_E_NOMEM, "3-D tangent records allocation failed");
-    k_tan3<<<(unsigned)((c->np + GP3 - 1) / GP3), GP3, 0, c->stream>>>(A, du, c->pdat3.p, c->flag.p);
-    LAUNCH_CHECK(c, "k_tan3");
+    if (records) {
+      if (c->pdat3.ensure(std::max<int64_t>(1, c->np) * PT3) != hipSuccess)
+        return c->fail(MPM_E_NOMEM, "3-D tangent records allocation failed");
+      if (c->np > 0) {
+        k_tan3v<<<(unsigned)((c->np + TP3 - 1) / TP3), TL3, 0, c->stream>>>(A, du, c->pdat3.p, c->flag.p);
+        LAUNCH_CHECK(c, "k_tan3v");
+      }
+      c->tan_ready = true;
+    } else if (!c->tan_ready) {
+      return c->fail(MPM_E_INVALID, "no tangent records of this prepare to reuse");
+    }
+    HIPC(c, hipMemsetAsync(y, 0, nv * sizeof(double), c->stream));
     const int nsim = c->nsim;
-    for (int col = 0; col < 27; ++col) {
-      const int64_t nwg = c->jc3_ws_h[(size_t)col * (nsim + 1) + nsim];
+    for (int col = 0; col < 27 && c->np > 0; ++col) {
+      const int64_t nwg = c->jf3_ws_h[(size_t)col * (nsim + 1) + nsim];
       if (nwg == 0) continue;
-      k_jac3c<<<(unsigned)nwg, JC3T, 0, c->stream>>>(col, c->jc3_ws.p + (size_t)col * (nsim + 1), nsim, c->sims.p,
-                                                      c->gstart.p, c->node_map.p, c->pdat3.p, c->rowptr.p, c->slot.p,
-                                                      val);
-      LAUNCH_CHECK(c, "k_jac3c");
+      k_jv3c<<<(unsigned)nwg, FT3, 0, c->stream>>>(col, c->jf3_ws.p + (size_t)col * (nsim + 1), nsim, c->sims.p,
+                                                   c->gstart.p, c->node_map.p, c->xs.p, c->np, c->pdat3.p, cm, x, y);
+      LAUNCH_CHECK(c, "k_jv3c");
     }
   }
-  if (apply_bc && c->n_row > 0 && !(c->dim == 2 && !c->up)) {   // the 2-D single-phase writer applies it itself
-    k_jac_bc<<<nb256(c->n_row), 256, 0, c->stream>>>(c->n_row, nd, c->rowptr.p, c->colind.p, c->cmask.p, val);
-    LAUNCH_CHECK(c, "k_jac_bc");
+  if (apply_bc && nv > 0) {
+    k_jv_bc<<<nb256(nv), 256, 0, c->stream>>>(nv, c->cmask.p, x, y);
+    LAUNCH_CHECK(c, "k_jv_bc");
   }
   return MPM_OK;
 }

@@ -82,6 +82,35 @@ __device__ __forceinline__ void bspline3(S xi, double inv_h, S w[3], S dw[3]) {
   dw[2] = inv_h * r2;
 }
 
+// cpGIMP along one axis (Sec. 2.2): the weight of node o+a is the average of
+// its linear hat function over the particle domain, half-width l cells
+// (l <= 1/2), around the particle at signed distance r = xi - a from it:
+//   |r| < l: 1 - (r^2 + l^2)/(2l);  l <= |r| < 1-l: 1 - |r|;
+//   1-l <= |r| < 1+l: (1 + l - |r|)^2/(4l);  else 0.
+__device__ __forceinline__ void gimp3(double xi, double l, double inv_h, double w[3], double dw[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double r = xi - a, ar = fabs(r), sg = r < 0.0 ? -1.0 : 1.0;
+    double wa, da;
+    if (ar < l) {
+      wa = 1.0 - (r * r + l * l) / (2.0 * l);
+      da = -r / l;
+    } else if (ar < 1.0 - l) {
+      wa = 1.0 - ar;
+      da = -sg;
+    } else if (ar < 1.0 + l) {
+      const double e = 1.0 + l - ar;
+      wa = e * e / (4.0 * l);
+      da = -sg * e / (2.0 * l);
+    } else {
+      wa = 0.0;
+      da = 0.0;
+    }
+    w[a] = wa;
+    dw[a] = da * inv_h;
+  }
+}
+
 // ---------------------------------------------------- material constants ---
 template <class S>
 struct Mat {
@@ -106,6 +135,13 @@ __device__ __forceinline__ Mat<S> make_mat(S E, double nu, S phi, double c, doub
   const double r3 = 1.7320508075688772935;
   const bool assoc = (match & 4) != 0;
   match &= 3;
+  if (match == 3) {
+    // J2: sqrt(2 J2) <= c, the pressure-independent cone (radial return)
+    m.eta = S(0.0) * phi;
+    m.xi = S(0.70710678118654752440) + 0.0 * phi;
+    m.etab = S(0.0) * phi;
+    return m;
+  }
   if (match == 1) {
     S t = s_tan(phi);
     S den = s_sqrt(9.0 + 12.0 * t * t);
@@ -206,7 +242,7 @@ __device__ __forceinline__ int stress2(const Mat<S>& m, const Sym2<S>& eps, Sym2
   S g2 = 2.0 * m.G;
   tau.xx = lt + g2 * eps.xx; tau.yy = lt + g2 * eps.yy; tau.zz = lt + g2 * eps.zz; tau.xy = g2 * eps.xy;
   ee = eps;
-  if (!m.dp) return 0;
+  if (m.dp != 1) return 0;
   S p = (tau.xx + tau.yy + tau.zz) * (1.0 / 3.0);
   Sym2<S> s{tau.xx - p, tau.yy - p, tau.xy, tau.zz - p};
   double sv = vv(s.xx) * vv(s.xx) + vv(s.yy) * vv(s.yy) + vv(s.zz) * vv(s.zz) + 2.0 * vv(s.xy) * vv(s.xy);
@@ -366,7 +402,7 @@ __device__ __forceinline__ int stress3(const Mat<S>& m, const Sym3<S>& eps, Sym3
 #pragma unroll
   for (int t = 0; t < 3; ++t) tau.a[t] = tau.a[t] + lt;
   ee = eps;
-  if (!m.dp) return 0;
+  if (m.dp != 1) return 0;
   S p = (tau.a[0] + tau.a[1] + tau.a[2]) * (1.0 / 3.0);
   Sym3<S> s = tau;
 #pragma unroll
@@ -423,7 +459,7 @@ struct Out2 { S P[2][2]; S s1; S vv[2]; };
 
 template <class S>
 __device__ __forceinline__ int mech2(const Mat<S>& m, const S F[2][2], const Sym2<S>& be, S Jn, int up, const UpPar& u,
-                                     S pp, const S gp[2], Out2<S>& o, Sym2<S>* ee_out) {
+                                     S pp, const S gp[2], Out2<S>& o, Sym2<S>* be_out) {
   S m00 = F[0][0] * be.xx + F[0][1] * be.xy, m01 = F[0][0] * be.xy + F[0][1] * be.yy;
   S m10 = F[1][0] * be.xx + F[1][1] * be.xy, m11 = F[1][0] * be.xy + F[1][1] * be.yy;
   Sym2<S> bt;
@@ -431,9 +467,17 @@ __device__ __forceinline__ int mech2(const Mat<S>& m, const S F[2][2], const Sym
   bt.yy = m10 * F[1][0] + m11 * F[1][1];
   bt.xy = m00 * F[1][0] + m01 * F[1][1];
   bt.zz = be.zz;
-  Sym2<S> eps = hencky2(bt);
   Sym2<S> tau, ee;
-  int reg = stress2(m, eps, tau, ee);
+  int reg = 0;
+  if (m.dp == 2) {
+    // compressible Neo-Hookean: tau = mu (b - 1) + lambda ln J 1, J^2 = det b
+    S lnJ = 0.5 * s_log((bt.xx * bt.yy - bt.xy * bt.xy) * bt.zz);
+    S lj = m.lam * lnJ;
+    tau.xx = m.G * (bt.xx - 1.0) + lj; tau.yy = m.G * (bt.yy - 1.0) + lj;
+    tau.zz = m.G * (bt.zz - 1.0) + lj; tau.xy = m.G * bt.xy;
+  } else {
+    reg = stress2(m, hencky2(bt), tau, ee);
+  }
   S det = F[0][0] * F[1][1] - F[0][1] * F[1][0];
   S idet = 1.0 / det;
   S it00 = F[1][1] * idet, it01 = -1.0 * F[1][0] * idet, it10 = -1.0 * F[0][1] * idet, it11 = F[0][0] * idet;
@@ -453,7 +497,7 @@ __device__ __forceinline__ int mech2(const Mat<S>& m, const S F[2][2], const Sym
     o.vv[0] = u.dt * (it00 * q0 + it10 * q1) * J;
     o.vv[1] = u.dt * (it01 * q0 + it11 * q1) * J;
   }
-  if (ee_out) *ee_out = ee;
+  if (be_out) *be_out = (m.dp == 2) ? bt : exp2eps2(ee);   // b^e at the end of the step
   return reg;
 }
 
@@ -462,7 +506,7 @@ template <class S>
 struct Out3 { S P[3][3]; };
 
 template <class S>
-__device__ __forceinline__ int mech3(const Mat<S>& m, const S F[3][3], const Sym3<S>& be, Out3<S>& o, Sym3<S>* ee_out,
+__device__ __forceinline__ int mech3(const Mat<S>& m, const S F[3][3], const Sym3<S>& be, Out3<S>& o, Sym3<S>* be_out,
                                      int* range_err) {
   S M[3][3];
 #pragma unroll
@@ -474,9 +518,18 @@ __device__ __forceinline__ int mech3(const Mat<S>& m, const S F[3][3], const Sym
 #pragma unroll
   for (int t = 0; t < 6; ++t)
     bt.a[t] = M[I[t]][0] * F[Jx[t]][0] + M[I[t]][1] * F[Jx[t]][1] + M[I[t]][2] * F[Jx[t]][2];
-  Sym3<S> eps = hencky3(bt, range_err);
   Sym3<S> tau, ee;
-  int reg = stress3(m, eps, tau, ee);
+  int reg = 0;
+  if (m.dp == 2) {
+    // compressible Neo-Hookean: tau = mu (b - 1) + lambda ln J 1, J^2 = det b
+    S lj = m.lam * (0.5 * s_log(sdet(bt)));
+#pragma unroll
+    for (int t = 0; t < 6; ++t) tau.a[t] = m.G * bt.a[t];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) tau.a[t] = tau.a[t] - m.G + lj;
+  } else {
+    reg = stress3(m, hencky3(bt, range_err), tau, ee);
+  }
   // dF^-T = cofactor(dF) / det
   S cof[3][3];
   cof[0][0] = F[1][1] * F[2][2] - F[1][2] * F[2][1];
@@ -495,7 +548,7 @@ __device__ __forceinline__ int mech3(const Mat<S>& m, const S F[3][3], const Sym
 #pragma unroll
     for (int j = 0; j < 3; ++j)
       o.P[i][j] = (sget(tau, i, 0) * cof[0][j] + sget(tau, i, 1) * cof[1][j] + sget(tau, i, 2) * cof[2][j]) * idet;
-  if (ee_out) *ee_out = ee;
+  if (be_out) *be_out = (m.dp == 2) ? bt : exp2eps3(ee);   // b^e at the end of the step
   return reg;
 }
 

@@ -66,7 +66,13 @@ __device__ __forceinline__ void make_stencil(const SimDev& S, const double* __re
     double u = (xs[k * np + i] - S.x0[k]) / S.h;
     double of = floor(u - 0.5);
     st.o[k] = (int32_t)of;
-    bspline3<double>(u - of, S.inv_h, st.w[k], st.dw[k]);
+    if (S.shape == 1) {
+      // the particle domain follows the stretch of its axis: l = lp0 F_kk
+      const double l = S.lp0[k] * S.Fs[(k * DIM + k) * np + i] * S.inv_h;
+      gimp3(u - of, l, S.inv_h, st.w[k], st.dw[k]);
+    } else {
+      bspline3<double>(u - of, S.inv_h, st.w[k], st.dw[k]);
+    }
   }
   if (DIM == 2) {
     st.o[2] = 0;
@@ -88,6 +94,8 @@ __device__ __forceinline__ int nb_index(int a, int b) {
 
 namespace mpm {
 constexpr int PD2 = 32;       // doubles per 2-D particle record: V0 T 0..15, wx 16..18, dwx 19..21, wy 22..24, dwy 25..27
+constexpr int PT3 = 81;       // doubles per 3-D tangent record: V0 dP_ri/dF_cj at (r * 3 + c) * 9 + i * 3 + j
+constexpr int PU2 = 64;       // doubles per u-p record: V0 T 0..48 (7x7), wx 49..51, dwx 52..54, wy 55..57, dwy 58..60
 constexpr int GB2 = 81 * 4;   // doubles per origin in the 2-D group-block buffer
 }  // namespace mpm
 
@@ -103,18 +111,30 @@ int launch_fint(mpm_ctx* c, const mpm_problem* pb, const double* du, double* rec
 int launch_residual(mpm_ctx* c, const mpm_problem* pb, const double* du, double* r, double* r_raw,
                     double* rec = nullptr);
 int launch_jacobian(mpm_ctx* c, const mpm_problem* pb, const double* du, double* val, bool apply_bc);
+// gstart, xs, np: particle ranges per origin, positions and count to use in
+// place of c's own (the quadrature particles of a multigrid level)
+int launch_jac3_lines(mpm_ctx* c, const double* rec, const int32_t* pmap, double* val, bool apply_bc,
+                      const int32_t* gstart = nullptr, const double* xs = nullptr, int64_t np = -1);
+int launch_row_groups(mpm_ctx* c, const int32_t* gstart, int32_t* rgrp);
+int launch_jv(mpm_ctx* c, const mpm_problem* pb, const double* du, bool records, const double* x, double* y,
+              bool apply_bc);
 int launch_update(mpm_ctx* c, const mpm_problem* pb, const double* du, double* x, double* F, double* be);
 int launch_bj_inv(mpm_ctx* c, const double* val);
 int launch_spmv(mpm_ctx* c, const double* val, const double* x, double* y, const double* z);
 int krylov_solve(mpm_ctx* c, const double* val, double rtol, int max_iter, std::vector<int>& iters_out);
 int launch_jac2_records(mpm_ctx* c, double* val, bool apply_bc);
+int launch_jac2up_records(mpm_ctx* c, const double* rec, double* val, bool apply_bc, const int32_t* rgrp = nullptr);
 int build_colour_table(mpm_ctx* c);
 int launch_p2g3(mpm_ctx* c, int mode, const double* rec, double* out);
 int launch_jac2_blocks(mpm_ctx* c, double* val, bool apply_bc);
 void ctx_release(mpm_ctx* c);
-// multigrid preconditioner (2-D single-phase)
+// multigrid preconditioner (single-phase; the 3-D levels in mpm_mg3.hip)
 int mg_build(mpm_ctx* c, const mpm_problem* pb);
 int mg_setup(mpm_ctx* c);
 int mg_vcycle(mpm_ctx* c, const double* b, double* x);
 void mg_release(mpm_ctx* c);
 void mg_drop_graphs(mpm_ctx* c);
+void mg_level_release(mpm::MgLevel* L);
+int mg3_build(mpm_ctx* c, const mpm_problem* pb);
+int mg3_setup(mpm_ctx* c);
+int mg3_vcycle(mpm_ctx* c, const double* b, double* x);

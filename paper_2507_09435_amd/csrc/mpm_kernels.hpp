@@ -23,6 +23,9 @@ struct SimDev {
   int64_t okey_base;   // first origin key of this sim
   int64_t row_base;    // first compact row of this sim (after prepare)
   int64_t p_begin, p_end;
+  int32_t shape;       // 0 quadratic B-spline, 1 cpGIMP
+  double lp0[3];       // cpGIMP: initial half-width of the particle domain per axis
+  const double* Fs;    // cpGIMP: sorted deformation gradients (the domain follows F_kk)
 };
 
 // Row blocks of the Krylov / elementwise kernels: a block never spans two sims.
@@ -85,6 +88,16 @@ struct MgLevel {
   DBuf<double> part;         // per chunk: 81 partial 2x2 blocks
   int64_t n_chunks = 0;
   int32_t max_key_chunks = 0;   // most chunks of one origin key
+  // 3x3-block levels: quadrature particles, NG per non-empty origin (at the
+  // Gauss points of the origin's dual cell), carrying the origin's summed
+  // tangent tables / NG
+  DBuf<int32_t> pg;          // per origin key: first quadrature particle (n_okeys + 1)
+  DBuf<int32_t> nek;         // non-empty origin keys
+  DBuf<double> pxs;          // quadrature particle positions [dim][npp]
+  DBuf<double> prec;         // quadrature particle records [npp][record]
+  DBuf<int32_t> qsim;        // sim of each quadrature particle
+  DBuf<int32_t> prgrp;       // plane strain: row group table over the quadrature particles
+  int64_t npp = 0, n_nek = 0;
 };
 }  // namespace mpm
 
@@ -129,8 +142,13 @@ struct mpm_ctx {
   mpm::DBuf<double> val, dinv;
   mpm::DBuf<double> pdat;                      // per-particle tangent records (2-D assembly)
   mpm::DBuf<double> pdat3;                     // per-particle tangent records (3-D assembly)
+  bool tan_ready = false;                      // pdat / pdat3 hold this prepare's tangent records
   mpm::DBuf<int64_t> jc3_ws;                   // 3-D colour passes: per colour and sim, first workgroup
   std::vector<int64_t> jc3_ws_h;               // host staging of jc3_ws
+  mpm::DBuf<int64_t> jf3_ws;                   // fused 3-D internal force: per colour and sim, first workgroup
+  std::vector<int64_t> jf3_ws_h;               // host staging of jf3_ws
+  mpm::DBuf<int64_t> jl3_ws;                   // 3-D line sweep: per sim, first workgroup
+  std::vector<int64_t> jl3_ws_h;               // host staging of jl3_ws
   mpm::DBuf<double> gbuf;                      // per-origin group blocks (2-D assembly)
   mpm::DBuf<double> rrec;                      // per-particle residual records (2-D)
   // Krylov
@@ -169,6 +187,8 @@ struct mpm_ctx {
   mpm::DBuf<double> mg_dense;                  // coarsest level: per sim dense matrix and inverse
   mpm::DBuf<int32_t> mg_doff;                  // per sim: first coarsest row, rows
   mpm::DBuf<mpm::SimDev> mg_sims;              // staging of a child level's descriptors
+  std::vector<double> mg3_lmax;                // 3-D levels: lambda_max(D^-1 A) for the Chebyshev smoother
+  mpm::DBuf<double> mg3_part;                  // 3-D levels: power-iteration partial sums
   int mg_nmax = 0;                             // largest coarsest system (unknowns)
   bool mg_ready = false;                       // hierarchy built for the current prepare
   bool mg_on = false;                          // precondition the current solve with a V-cycle

@@ -837,18 +837,19 @@ using namespace mpm;
 
 static unsigned nb256(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + 255) / 256); }
 
-static void level_release(MgLevel* L) {
+void mg_level_release(MgLevel* L) {
   if (L->sub) { ctx_release(L->sub); delete L->sub; }
   L->mask.release(); L->pmap.release(); L->vec.release(); L->chunk.release(); L->key_chunk.release();
-  L->part.release();
+  L->part.release(); L->pg.release(); L->nek.release(); L->pxs.release(); L->prec.release(); L->qsim.release();
+  L->prgrp.release();
   delete L;
 }
 
 void mg_release(mpm_ctx* c) {
-  for (MgLevel* L : c->mgl) level_release(L);
+  for (MgLevel* L : c->mgl) mg_level_release(L);
   c->mgl.clear();
   c->mg_zero.release(); c->mg_inv.release(); c->mg_fine.release(); c->mg_dense.release(); c->mg_doff.release();
-  c->mg_sims.release(); c->mg_tail.release(); c->mg_tab.release(); c->mg_tabw.release();
+  c->mg_sims.release(); c->mg_tail.release(); c->mg_tab.release(); c->mg_tabw.release(); c->mg3_part.release();
   c->mg_tail_first = -1;
   mg_drop_graphs(c);
   if (c->cap_stream) { (void)hipStreamDestroy(c->cap_stream); c->cap_stream = nullptr; }
@@ -888,7 +889,8 @@ static int build_chunks(mpm_ctx* c, MgLevel* L) {
 // Build (or re-prepare) the levels for the current prepare of c; pb is the
 // fine problem.  Level contexts and their buffers are kept between prepares.
 int mg_build(mpm_ctx* c, const mpm_problem* pb) {
-  if (c->dim != 2 || c->up) return c->fail(MPM_E_INVALID, "the multigrid preconditioner covers 2-D single-phase problems");
+  if (c->dim == 3 || c->up) return mg3_build(c, pb);
+  if (c->dim != 2 || c->up) return c->fail(MPM_E_INVALID, "the multigrid preconditioner covers single-phase problems");
   const int nsim = c->nsim;
   const int64_t np = c->np;
   if (c->mg_inv.ensure(std::max<int64_t>(1, np)) != hipSuccess ||
@@ -954,6 +956,7 @@ int mg_build(mpm_ctx* c, const mpm_problem* pb) {
                                                       L->mask.p);
     LAUNCH_CHECK(c, "k_mg_mask");
     mpm_problem cp = *pb;
+    cp.mat.shape = 0;   // coarse levels are rediscretized with quadratic B-splines (a preconditioner only)
     cp.grids = L->grids.data();
     cp.bc_mask = L->mask.p;
     cp.bc_value = c->mg_zero.p;
@@ -974,7 +977,7 @@ int mg_build(mpm_ctx* c, const mpm_problem* pb) {
     fmask = L->mask.p;
     nl = l;
   }
-  while (c->mgl.size() > nl) { level_release(c->mgl.back()); c->mgl.pop_back(); }
+  while (c->mgl.size() > nl) { mg_level_release(c->mgl.back()); c->mgl.pop_back(); }
   // fused coarse tail: from the first level whose sims all have at most
   // MG_TAIL_ROWS rows, when at least one smoothed level lies above the dense solve
   c->mg_tail_first = -1;
@@ -1064,6 +1067,7 @@ int mg_build(mpm_ctx* c, const mpm_problem* pb) {
 // Per Newton iteration, after the fine Jacobian (records in c->pdat) and its
 // block-Jacobi inverse: level records, matrices, inverses, coarsest inverse.
 int mg_setup(mpm_ctx* c) {
+  if (c->dim == 3 || c->up) return mg3_setup(c);
   const int64_t np = c->np;
   for (MgLevel* L : c->mgl) {
     mpm_ctx* sub = L->sub;
@@ -1240,6 +1244,7 @@ void mg_drop_graphs(mpm_ctx* c) {
 // stream: the caller's may be the null stream) and replayed with a single
 // launch; the kernels read the Krylov flags at run time.
 int mg_vcycle(mpm_ctx* c, const double* b, double* x) {
+  if (c->dim == 3 || c->up) return mg3_vcycle(c, b, x);
   c->lstream = c->stream;
   if (!c->mg_graph) return vcycle(c, 0, b, x);
   const void* key[5] = {b, x, c->val.p, c->dinv.p, c->simflag.p};

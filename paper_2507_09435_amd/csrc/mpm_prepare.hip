@@ -229,6 +229,19 @@ __global__ void k_gather(int64_t np, int dim, const int32_t* __restrict__ perm, 
   psim[i] = psim_in[p];
 }
 
+// cpGIMP: every particle domain half-width l = lp0 F_kk must lie in (0, h/2]
+// (the 3-node stencil then holds every node it touches).  flag[0] |= 32.
+__global__ void k_gimp_check(int64_t np, int dim, const int32_t* __restrict__ psim, const SimDev* __restrict__ sims,
+                             const double* __restrict__ Fs, int32_t* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const SimDev& S = sims[psim[i]];
+  for (int k = 0; k < dim; ++k) {
+    const double l = S.lp0[k] * Fs[(k * dim + k) * np + i] * S.inv_h;
+    if (!(l > 0.0 && l <= 0.5)) atomicOr(flag, 32);
+  }
+}
+
 // --------------------------------------------------------- node activity --
 __device__ __forceinline__ int find_sim_node(const SimDev* __restrict__ sims, int nsim, int64_t node) {
   int lo = 0, hi = nsim - 1;
@@ -379,23 +392,24 @@ __global__ void k_row_groups(int64_t n_row, const int64_t* __restrict__ active, 
   rgrp[2 * t + 1] = p1;
 }
 
-// 2-D with two unknowns per node: per row and stencil offset o (the slot
-// table's order), bits 0 and 1 mark the column node's constrained unknowns,
-// bits 2 and 3 the row's; 0 where the row has no block at o.
-__global__ void k_row_bc(int64_t n_row, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
-                         const int8_t* __restrict__ slot, const uint8_t* __restrict__ cmask,
-                         uint8_t* __restrict__ bcode) {
+// Per row and stencil offset o (the slot table's order, nb = 5^d offsets),
+// with nd (2 or 3) unknowns per node: bits 0 .. nd-1 mark the column node's
+// constrained unknowns, bits nd .. 2nd-1 the row's; 0 where the row has no
+// block at o.
+__global__ void k_row_bc(int64_t n_row, int nb, int nd, const int32_t* __restrict__ rowptr,
+                         const int32_t* __restrict__ colind, const int8_t* __restrict__ slot,
+                         const uint8_t* __restrict__ cmask, uint8_t* __restrict__ bcode) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_row * 25) return;
-  const int64_t row = t / 25;
+  if (t >= n_row * nb) return;
+  const int64_t row = t / nb;
   const int s = slot[t];
-  uint8_t code = 0;
+  unsigned code = 0;
   if (s >= 0) {
     const int64_t col = colind[rowptr[row] + s];
-    code = (uint8_t)((cmask[col * 2] ? 1 : 0) | (cmask[col * 2 + 1] ? 2 : 0) | (cmask[row * 2] ? 4 : 0) |
-                     (cmask[row * 2 + 1] ? 8 : 0));
+    for (int k = 0; k < nd; ++k)
+      code |= (cmask[col * nd + k] ? 1u << k : 0u) | (cmask[row * nd + k] ? 1u << (nd + k) : 0u);
   }
-  bcode[t] = code;
+  bcode[t] = (uint8_t)code;
 }
 
 // Sum of w * V0 per row (a row whose sum is zero carries no material).
@@ -518,10 +532,22 @@ __global__ void k_fext2_rows(int64_t n_row, int nd, const int64_t* __restrict__ 
 
 using namespace mpm;
 
+// Row group table of context c over the particle ranges gstart (plane strain).
+int launch_row_groups(mpm_ctx* c, const int32_t* gstart, int32_t* rgrp) {
+  if (c->n_row > 0) {
+    k_row_groups<<<(unsigned)((c->n_row * 9 + 255) / 256), 256, 0, c->stream>>>(c->n_row, c->active_nodes.p,
+                                                                              c->row_sim.p, c->sims.p, gstart, rgrp);
+    LAUNCH_CHECK(c, "k_row_groups");
+  }
+  return MPM_OK;
+}
+
+
 // ======================================================================
 int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row_out, int64_t* nnzb_out, int32_t* nd_out) {
   c->prepared = false;
   c->tpos_ready = false;
+  c->tan_ready = false;
   int rc = validate_problem(c, pb);
   if (rc) return rc;
   const int dim = pb->grids[0].dim;
@@ -530,7 +556,7 @@ int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row_out, int6
   c->dim = dim;
   c->nsim = nsim;
   c->up = pb->mat.up ? 1 : 0;
-  c->dp = pb->mat.dp ? 1 : 0;
+  c->dp = pb->mat.dp ? 1 : (pb->mat.elastic == 1 ? 2 : 0);   // 0 Hencky, 1 Hencky + return map, 2 Neo-Hookean
   c->nd = dim + c->up;
   c->np = np;
   const int nd = c->nd;
@@ -544,6 +570,9 @@ int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row_out, int6
     S.dim = dim;
     S.h = g.h;
     S.inv_h = 1.0 / g.h;
+    S.shape = pb->mat.shape;
+    for (int k = 0; k < 3; ++k) S.lp0[k] = pb->mat.lp0[k];
+    S.Fs = nullptr;
     int64_t nn = 1, no = 1;
     for (int k = 0; k < 3; ++k) {
       S.n[k] = k < dim ? g.ncell[k] : 0;
@@ -579,6 +608,7 @@ int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row_out, int6
             c->bes.ensure((dim == 2 ? 4 : 6) * np) == hipSuccess &&
             c->Es.ensure(pb->P.E ? np : 1) == hipSuccess && c->phis.ensure(pb->P.phi ? np : 1) == hipSuccess;
   if (!ok) return c->fail(MPM_E_NOMEM, "device allocation failed in prepare");
+  for (int s = 0; s < nsim; ++s) c->sims_h[s].Fs = c->Fs.p;
   HIPC(c, hipMemcpyAsync(c->sims.p, c->sims_h.data(), nsim * sizeof(SimDev), hipMemcpyHostToDevice, c->stream));
   HIPC(c, hipMemcpyAsync(c->sim_start.p, ss.data(), (nsim + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
   HIPC(c, hipMemsetAsync(c->flag.p, 0, 8 * sizeof(int32_t), c->stream));
@@ -635,6 +665,14 @@ int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row_out, int6
                                               pb->P.E, pb->P.phi, c->xs.p, c->vol0s.p, c->Fs.p, c->bes.p, c->Es.p,
                                               c->phis.p, c->psim.p);
     LAUNCH_CHECK(c, "sort/gather");
+    if (pb->mat.shape == 1) {
+      k_gimp_check<<<nblk(np), TPB, 0, c->stream>>>(np, dim, c->psim.p, c->sims.p, c->Fs.p, c->flag.p);
+      LAUNCH_CHECK(c, "k_gimp_check");
+      int32_t gflag = 0;
+      HIPC(c, hipMemcpyAsync(&gflag, c->flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+      HIPC(c, hipStreamSynchronize(c->stream));
+      if (gflag & 32) return c->fail(MPM_E_RANGE, "a cpGIMP particle domain is not within (0, h/2] on some axis");
+    }
   }
 
   // active nodes and rows
@@ -727,12 +765,13 @@ int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row_out, int6
                                                 pb->react_mask, c->nvol.p, c->cmask.p, c->cval.p, c->rmask.p);
     LAUNCH_CHECK(c, "k_cmask");
   }
-  if (dim == 2 && nd == 2) {
-    if (c->bcode.ensure(std::max<int64_t>(1, n_row) * 25) != hipSuccess)
+  {
+    const int nb = dim == 2 ? 25 : 125;
+    if (c->bcode.ensure(std::max<int64_t>(1, n_row) * nb) != hipSuccess)
       return c->fail(MPM_E_NOMEM, "row constraint table allocation failed");
     if (n_row > 0) {
-      k_row_bc<<<nblk(n_row * 25), TPB, 0, c->stream>>>(n_row, c->rowptr.p, c->colind.p, c->slot.p, c->cmask.p,
-                                                        c->bcode.p);
+      k_row_bc<<<nblk(n_row * nb), TPB, 0, c->stream>>>(n_row, nb, nd, c->rowptr.p, c->colind.p, c->slot.p,
+                                                        c->cmask.p, c->bcode.p);
       LAUNCH_CHECK(c, "k_row_bc");
     }
   }

@@ -35,10 +35,11 @@ class mpm_grid(C.Structure):
 
 
 class mpm_material(C.Structure):
-    _fields_ = [("up", C.c_int32), ("dp", C.c_int32), ("dp_match", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("up", C.c_int32), ("dp", C.c_int32), ("dp_match", C.c_int32), ("shape", C.c_int32),
                 ("E", C.c_double), ("nu", C.c_double), ("phi", C.c_double), ("c", C.c_double), ("psi", C.c_double),
                 ("rho0", C.c_double), ("g", C.c_double * 3), ("perm", C.c_double), ("mu_f", C.c_double),
-                ("biot", C.c_double), ("rho_f", C.c_double), ("dt", C.c_double), ("apex_reg", C.c_double)]
+                ("biot", C.c_double), ("rho_f", C.c_double), ("dt", C.c_double), ("apex_reg", C.c_double),
+                ("lp0", C.c_double * 3), ("elastic", C.c_int32), ("reserved", C.c_int32)]
 
 
 class mpm_particles(C.Structure):
@@ -70,7 +71,7 @@ class mpm_newton_report(C.Structure):
 
 EXPORTS = ["mpm_create", "mpm_destroy", "mpm_last_error", "mpm_prepare", "mpm_residual", "mpm_jacobian_bsr",
            "mpm_newton_step", "mpm_update", "mpm_spmv", "mpm_spmv_lanes", "mpm_spmv_set_lanes",
-           "mpm_adjoint_step", "mpm_residual_noalloc"]
+           "mpm_adjoint_step", "mpm_residual_noalloc", "mpm_jv"]
 MPM_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 _lib = None
@@ -98,6 +99,7 @@ def load():
                              C.POINTER(mpm_newton_report)], C.c_int),
         "mpm_update": ([P, C.POINTER(mpm_problem), P, P, P, P], C.c_int),
         "mpm_spmv": ([P, P, P, P, P], C.c_int),
+        "mpm_jv": ([P, C.POINTER(mpm_problem), P, P, P, C.c_int32], C.c_int),
         "mpm_spmv_lanes": ([P], C.c_int),
         "mpm_spmv_set_lanes": ([P, C.c_int32], C.c_int),
         "mpm_adjoint_step": ([P, C.POINTER(mpm_problem), P, C.POINTER(C.c_double), P, P, P, C.c_double,
@@ -193,6 +195,11 @@ def make_problem(sims, bcs, device="cuda", react_masks=None) -> DeviceProblem:
         m.g[k] = float(P0.g[k]) if k < len(P0.g) else 0.0
     m.perm, m.mu_f, m.biot, m.rho_f, m.dt = P0.perm, P0.mu_f, P0.biot, P0.rho_f, P0.dt
     m.apex_reg = float(getattr(P0, "apex_reg", 0.0))
+    m.shape = int(getattr(P0, "shape", 0))
+    m.elastic = int(getattr(P0, "elastic", 0))
+    lp0 = getattr(P0, "lp0", (0.0, 0.0, 0.0))
+    for k in range(3):
+        m.lp0[k] = float(lp0[k]) if k < len(lp0) else 0.0
 
     pr = mpm_problem()
     pr.nsim = nsim
@@ -284,6 +291,14 @@ def mpm_newton_step(ctx, dp: DeviceProblem, du, tol=1e-10, max_iter=25, commit=T
 
 def mpm_update(ctx, dp: DeviceProblem, du, x_out, F_out, be_out):
     _check(ctx, load().mpm_update(ctx, C.byref(dp.struct), _ptr(du), _ptr(x_out), _ptr(F_out), _ptr(be_out)))
+
+
+MPM_JV_REUSE = 2
+
+
+def mpm_jv(ctx, dp: DeviceProblem, du, x, y, raw=False, reuse=False):
+    flags = (MPM_JAC_RAW if raw else 0) | (MPM_JV_REUSE if reuse else 0)
+    _check(ctx, load().mpm_jv(ctx, C.byref(dp.struct), _ptr(du), _ptr(x), _ptr(y), flags))
 
 
 def mpm_spmv(ctx, val, x, y, z=None):

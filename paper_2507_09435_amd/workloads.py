@@ -59,6 +59,7 @@ class Problem:
     dt: float = 1.0
     apex_reg: float = 1e-6          # tangent scale of apex returns (values are exact)
     shape: int = 0                # 0 quadratic B-splines, 1 cpGIMP
+    elastic: int = 0              # 0 Hencky, 1 compressible Neo-Hookean (elastic only)
     lp0: tuple = (0.0, 0.0, 0.0)  # cpGIMP: initial half-width of the particle domain per axis
     name: str = ""
 

@@ -286,12 +286,14 @@ def test_invalid_options_and_arguments(ctx):
     dpb.sim_start[1] = n0
     dpb.sim_start[2] = 2 * n0 - 1                       # does not end at np
     assert code(M.mpm_prepare, ctx, dpb) == M.MPM_E_INVALID
-    # multigrid covers 2-D single-phase problems only
-    for wb in (W.make_c3(n=8, n_steps=1), W.make_c4(n=8, n_steps=1, width_cells=4, dt=1.0)):
+    # the Neo-Hookean law is elastic; J2 needs a yield strength
+    for change in ({"elastic": 1, "dp": 1}, {"dp": 1, "dp_match": 3, "c": 0.0}, {"elastic": 2}, {"shape": 2},
+                   {"shape": 1, "lp0": (0.0, 0.0, 0.0)}):
+        wb = W.small_footing(n_y=4)
+        for k, v in change.items():
+            setattr(wb.prob, k, v)
         dpb = M.make_problem([(wb.prob, wb.particles)], [wb.bc(1)])
-        nr, _, ndb = M.mpm_prepare(ctx, dpb)
-        dub = torch.zeros(nr * ndb, dtype=torch.float64, device="cuda")
-        assert code(M.mpm_newton_step, ctx, dpb, dub, krylov_method=2) == M.MPM_E_INVALID
+        assert code(M.mpm_prepare, ctx, dpb) == M.MPM_E_INVALID, change
     # a device that does not exist
     with pytest.raises(M.MPMError):
         M.mpm_create(torch.cuda.device_count() + 3, stream=0)

@@ -121,7 +121,7 @@ def test_c4_first_load_step_newton(c4):
     P, st = w.prob, w.particles
     print("[c4] first load step newton", flush=True)
     du = torch.zeros(n_row * nd, dtype=torch.float64, device="cuda")
-    rep = M.mpm_newton_step(ctx, dp, du, tol=1e-10, commit=False, krylov_rtol=1e-12)
+    rep = M.mpm_newton_step(ctx, dp, du, tol=1e-10, commit=False, krylov_rtol=1e-12, krylov_method=2)
     torch.cuda.synchronize()
     print(f"  newton {rep['iters']} krylov {rep['krylov']} ms {rep['ms_total']:.1f}", flush=True)
     assert rep["converged"], rep

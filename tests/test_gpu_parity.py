@@ -146,7 +146,9 @@ def test_jacobian_parity(ctx, name, raw):
 NEWTON_CASES = [("c1", 1, 0), ("footing", 0, 0), ("footing_elastic", 1, 0), ("up", 1, 0), ("c3small", 0, 0),
                 ("c3small_stiff", 0, 0), ("c1", 1, 1), ("footing_elastic", 1, 1), ("up", 1, 1), ("c3small", 0, 1),
                 ("c1", 1, 2), ("footing", 0, 2), ("footing_elastic", 1, 2), ("footing_big", 0, 2),
-                ("footing_ps", 0, 0), ("footing_ps_assoc", 1, 2), ("up_gravity", 1, 0)]
+                ("footing_ps", 0, 0), ("footing_ps_assoc", 1, 2), ("up_gravity", 1, 0),
+                ("c3small", 0, 2), ("c3small_stiff", 0, 2), ("c3mid", 0, 2), ("up", 1, 2), ("up_gravity", 1, 2),
+                ("up_column", 1, 2)]
 
 
 @pytest.mark.parametrize("name", ["footing_big", "batch"])
@@ -215,10 +217,10 @@ def test_spmv_does_not_depend_on_its_shape(ctx, name):
 
 
 @pytest.mark.parametrize("name,method", [("footing_big", 2), ("footing_elastic", 0), ("footing_elastic", 1),
-                                         ("c3small", 0)])
+                                         ("c3small", 0), ("up_gravity", 0)])
 def test_newton_does_not_depend_on_spmv_shape(ctx, name, method):
-    """Plane-strain single-phase and 3-D solves (assembled without atomics,
-    so each prepare rebuilds the same residual and matrix bits): the Newton
+    """Plane-strain single-phase, u-p and 3-D solves (assembled without
+    atomics, so each prepare rebuilds the same residual and matrix bits): the Newton
     increments and the Newton and Krylov iteration counts are bitwise the
     same for every SpMV shape, including the Krylov dot products the product
     fuses."""
@@ -226,7 +228,7 @@ def test_newton_does_not_depend_on_spmv_shape(ctx, name, method):
     w = _newton_case(name)
     P = w.prob
     P.dp = 0
-    step = 1 if name == "footing_elastic" else 0
+    step = 1 if name in ("footing_elastic", "up_gravity") else 0
     outs = []
     try:
         for lanes in (4, 8, 16):
@@ -249,6 +251,12 @@ def test_newton_does_not_depend_on_spmv_shape(ctx, name, method):
 
 
 def _newton_case(name):
+    if name == "c3mid":
+        # a 16^3 cube: three multigrid levels above the dense solve
+        return W.make_c3(n=16, n_steps=1)
+    if name == "up_column":
+        # a 32 x 32 u-p block: four multigrid levels above the dense solve
+        return W.make_c4(n=32, n_steps=1, width_cells=32, dt=1.0)
     if name == "c3small_stiff":
         w = W.make_c3(n=8, n_steps=1)
         w.particles.phi = np.full(w.particles.np, np.radians(40.0))   # geostatic state stays elastic
@@ -417,3 +425,54 @@ def test_line_search_follows_the_oracle(ctx, push, iters):
     e = rel_err(got, dof[pat.active])
     print(f"  du rel err {e:.3e}", flush=True)
     assert e <= 1e-9, e
+
+
+def test_multigrid_up_cuts_krylov_iterations(ctx):
+    """The multigrid V-cycle on the u-p block (64 x 64 cells, first load
+    step): the same Newton solution as block-Jacobi (to the solve's
+    tolerance) with at least five times fewer BiCGStab iterations per Newton
+    iteration."""
+    from paper_2507_09435_amd import mpm as M
+    w = W.make_c4(n=64, n_steps=1, width_cells=64, dt=1.0)
+    out = {}
+    for method in (0, 2):
+        print(f"[mg-up] krylov_method={method}", flush=True)
+        dp = M.make_problem([(w.prob, w.particles)], [w.bc(1)])
+        n_row, nnzb, nd = M.mpm_prepare(ctx, dp)
+        du = torch.zeros(n_row * nd, dtype=torch.float64, device="cuda")
+        rep = M.mpm_newton_step(ctx, dp, du, tol=1e-12, max_iter=25, commit=False, krylov_rtol=1e-12,
+                                krylov_method=method)
+        torch.cuda.synchronize()
+        assert rep["converged"], rep
+        out[method] = (du.cpu().numpy().reshape(-1, nd), rep)
+        print(f"  newton {rep['iters']}  krylov per newton {rep['krylov'][:rep['iters']]}", flush=True)
+    a, b = out[2][0], out[0][0]
+    assert max(rel_err(a[:, :2], b[:, :2]), rel_err(a[:, 2], b[:, 2])) <= 1e-9
+    kb = max(out[0][1]["krylov"][:out[0][1]["iters"]])
+    km = max(out[2][1]["krylov"][:out[2][1]["iters"]])
+    assert km * 5 <= kb, (km, kb)
+
+
+def test_multigrid_3d_cuts_krylov_iterations(ctx):
+    """The 3-D V-cycle preconditioner on the 16^3 cube's geostatic step:
+    the same Newton solution as block-Jacobi (to the solve's tolerance) with
+    far fewer BiCGStab iterations per Newton iteration."""
+    from paper_2507_09435_amd import mpm as M
+    w = _newton_case("c3mid")
+    out = {}
+    for method in (0, 2):
+        print(f"[mg3] krylov_method={method}", flush=True)
+        dp = _dev(w, 0)
+        n_row, nnzb, nd = M.mpm_prepare(ctx, dp)
+        du = torch.zeros(n_row * nd, dtype=torch.float64, device="cuda")
+        rep = M.mpm_newton_step(ctx, dp, du, tol=1e-12, max_iter=25, commit=False, krylov_rtol=1e-12,
+                                krylov_method=method)
+        torch.cuda.synchronize()
+        assert rep["converged"], rep
+        out[method] = (du.cpu().numpy(), rep)
+        print(f"  newton {rep['iters']}  krylov per newton {rep['krylov'][:rep['iters']]}", flush=True)
+    e = rel_err(out[2][0], out[0][0])
+    assert e <= 1e-9, e
+    kb = max(out[0][1]["krylov"][:out[0][1]["iters"]])
+    km = max(out[2][1]["krylov"][:out[2][1]["iters"]])
+    assert km * 3 <= kb, (km, kb)
