@@ -718,10 +718,12 @@ __global__ void __launch_bounds__(TL3) k_tan3v(AsmArgs A, const double* __restri
 
 constexpr int JL_T = 256;    // threads; lane t < 243 is (group q, row la_x, r, c), c fastest
 constexpr int JL_SEG = 16;   // rows of a line per workgroup
-constexpr int JL_PART = 6561;            // doubles of the nine groups' partial blocks (9 x 3 rows x 27 x 9)
-constexpr int JL_CH = JL_PART / (PT3 + PW3);   // records staged per chunk in the same buffer (57)
-constexpr int JL_ACC = 3375;             // row accumulators: 3 rows x 125 blocks x 9
-constexpr int JL_FL = (1125 + JL_T - 1) / JL_T;   // entries of the finished row per thread
+constexpr int JL_CH = 72;    // records staged per chunk: a step's nine groups of eight particles
+constexpr int JL_BUF = JL_CH * (PT3 + PW3);   // staged records and stencil data; then the partial blocks
+constexpr int JL_PART = 6561;                 // doubles of the nine groups' partial blocks (9 x 3 rows x 27 x 9)
+constexpr int JL_IT = 2;                      // accumulator blocks per thread: (slot, offset) items t, t + 256
+static_assert(JL_PART <= JL_BUF, "the partial blocks reuse the staging buffer");
+static_assert(JL_IT * JL_T >= 375, "every (slot, offset) item has an owner");
 
 __device__ __forceinline__ int imod3(int v) { return ((v % 3) + 3) % 3; }
 
@@ -738,8 +740,12 @@ __device__ __forceinline__ void line_group_range(const SimDev& S, const int32_t*
   }
 }
 
-// Each step of the sweep loads nothing that it waits for at once except the
-// records it stages: the next step's group ranges and the finished row's
+// The three rows in flight live in registers: thread t owns the 3x3 blocks
+// of (slot, offset) items t and t + 256 of the 3 x 125 (slot imod3(ix) of
+// row ix, offset d of the 5^3 neighbourhood), adds the nine groups' partials
+// to them in group order after every step, and writes the finished row's
+// blocks itself.  Each step loads nothing that it waits for at once except
+// the records it stages: the next step's group ranges and the finished row's
 // slots and Dirichlet codes are loaded a step ahead, or at the step's start
 // and used at its end.
 __global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restrict__ wstart, int nsim,
@@ -752,9 +758,8 @@ __global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restric
                                                         const int32_t* __restrict__ rowptr,
                                                         const int8_t* __restrict__ slot,
                                                         const uint8_t* __restrict__ bcode, double* __restrict__ val) {
-  __shared__ double sbuf[JL_PART];   // staged records [JL_CH][PT3] and stencil data [JL_CH][PW3]; then the
+  __shared__ double sbuf[JL_BUF];    // staged records [JL_CH][PT3] and stencil data [JL_CH][PW3]; then the
                                      // nine groups' partial blocks
-  __shared__ double sacc[JL_ACC];    // rows in flight, slot imod3(ix): [slot][block 125][r*3+c]
   __shared__ int32_t rng[2][9][2];   // group ranges of this step and the next: first particle, count
   __shared__ int32_t srow[JL_SEG];
   // Workgroups are dealt to the 8 XCDs in turn; XCD x takes the x-th
@@ -775,7 +780,6 @@ __global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restric
   const int t = threadIdx.x;
   const int64_t line_base = S.node_base + (int64_t)S.nna[0] * ((iy + 1) + (int64_t)S.nna[1] * (iz + 1));
   if (t < x1 - x0) srow[t] = node_map[line_base + (x0 + t + 1)];
-  for (int e = t; e < JL_ACC; e += JL_T) sacc[e] = 0.0;
   const int ox_lo = max(x0 - 2, -1), ox_hi = min(x1 - 1, S.n[0] - 1);
   int ra = 0, rb = 0;   // thread k < 9: range of group k, one step ahead
   if (t < 9 && ox_lo <= ox_hi) line_group_range(S, gstart, ox_lo, iy, iz, t, ra, rb);
@@ -788,6 +792,12 @@ __global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restric
   const bool lane = t < 243;
   const int c = t % 3, r = (t / 3) % 3, la_x = (t / 9) % 3, q = t / 27;
   const int yz = (q % 3) * 3 + q / 3;   // (ly, lz) of group q as a yz-product index
+  // owned accumulator items: slot sl, offset d
+  double racc[JL_IT][9];
+#pragma unroll
+  for (int h = 0; h < JL_IT; ++h)
+#pragma unroll
+    for (int e = 0; e < 9; ++e) racc[h][e] = 0.0;
 
   for (int ox = ox_lo; ox <= ox_hi + 2; ++ox) {
     const int cur = ox & 1;
@@ -796,25 +806,28 @@ __global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restric
       rng[cur][t][1] = rb - ra;
       if (ox + 1 <= ox_hi) line_group_range(S, gstart, ox + 1, iy, iz, t, ra, rb);
     }
-    // row ox is finished after this step: its slots and codes, in flight meanwhile
+    // row ox is finished after this step: the slots and codes of its owned
+    // blocks, in flight meanwhile
+    const int sl0 = imod3(ox);
     const int32_t frow = (ox >= x0 && ox < x1) ? srow[ox - x0] : -1;
-    int32_t fsp[JL_FL];
-    uint32_t fcode[JL_FL];
+    int32_t fsp[JL_IT];
+    uint32_t fcode[JL_IT];
     int64_t frp = 0;
+#pragma unroll
+    for (int h = 0; h < JL_IT; ++h) { fsp[h] = -1; fcode[h] = 0; }
     if (frow >= 0) {
       frp = rowptr[frow];
 #pragma unroll
-      for (int k = 0; k < JL_FL; ++k) {
-        const int l = t + JL_T * k;
-        fsp[k] = -1;
-        fcode[k] = 0;
-        if (l < 1125) {
-          fsp[k] = slot[(int64_t)frow * 125 + l / 9];
-          if (bcode) fcode[k] = bcode[(int64_t)frow * 125 + l / 9];
+      for (int h = 0; h < JL_IT; ++h) {
+        const int it = t + JL_T * h;
+        if (it < 375 && it / 125 == sl0) {
+          const int d = it - sl0 * 125;
+          fsp[h] = slot[(int64_t)frow * 125 + d];
+          if (bcode) fcode[h] = bcode[(int64_t)frow * 125 + d];
         }
       }
     }
-    __syncthreads();   // this step's ranges are visible; the last row flush and clear are done
+    __syncthreads();   // this step's ranges are visible; the last step's partials are consumed
     if (ox <= ox_hi) {
       int g0[9], goff[10];
       goff[0] = 0;
@@ -836,42 +849,41 @@ __global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restric
           if (lane && q == k) { qb = goff[k]; qe = goff[k + 1]; }
         for (int c0 = 0; c0 < ntot; c0 += JL_CH) {
           const int nc = min(JL_CH, ntot - c0);
+          if (c0 > 0) __syncthreads();   // the previous chunk is consumed
           // four threads per staged particle: one evaluates its stencil on this
-          // level, three copy its tangent record
-          {
-            const int k = t >> 2, part = t & 3;
-            if (k < nc) {
-              const int gpos = c0 + k;
-              int qq = 0;
+          // level, three copy its tangent record (JL_CH * 4 > JL_T: two rounds)
+          for (int u4 = t; u4 < 4 * nc; u4 += JL_T) {
+            const int k = u4 >> 2, part = u4 & 3;
+            const int gpos = c0 + k;
+            int qq = 0;
 #pragma unroll
-              for (int u = 1; u < 9; ++u) qq += gpos >= goff[u];
-              int gbase = g0[0], gstart_q = goff[0];
+            for (int u = 1; u < 9; ++u) qq += gpos >= goff[u];
+            int gbase = g0[0], gstart_q = goff[0];
 #pragma unroll
-              for (int u = 1; u < 9; ++u)
-                if (qq == u) { gbase = g0[u]; gstart_q = goff[u]; }
-              const int64_t p = gbase + gpos - gstart_q;
-              if (part == 0) {
-                Stencil<3> st;
-                make_stencil<3>(S, xs, np, p, st);
-                double* W = sbuf + JL_CH * PT3 + k * PW3;
+            for (int u = 1; u < 9; ++u)
+              if (qq == u) { gbase = g0[u]; gstart_q = goff[u]; }
+            const int64_t p = gbase + gpos - gstart_q;
+            if (part == 0) {
+              Stencil<3> st;
+              make_stencil<3>(S, xs, np, p, st);
+              double* W = sbuf + JL_CH * PT3 + k * PW3;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) { W[a] = st.w[0][a]; W[3 + a] = st.dw[0][a]; }
+              for (int a = 0; a < 3; ++a) { W[a] = st.w[0][a]; W[3 + a] = st.dw[0][a]; }
 #pragma unroll
-                for (int by = 0; by < 3; ++by)
+              for (int by = 0; by < 3; ++by)
 #pragma unroll
-                  for (int bz = 0; bz < 3; ++bz) {
-                    W[6 + by * 3 + bz] = st.w[1][by] * st.w[2][bz];
-                    W[15 + by * 3 + bz] = st.dw[1][by] * st.w[2][bz];
-                    W[24 + by * 3 + bz] = st.w[1][by] * st.dw[2][bz];
-                  }
-              } else {
-                const double* src = rec + (int64_t)(pmap ? pmap[p] : p) * PT3;
-                double v[27];
+                for (int bz = 0; bz < 3; ++bz) {
+                  W[6 + by * 3 + bz] = st.w[1][by] * st.w[2][bz];
+                  W[15 + by * 3 + bz] = st.dw[1][by] * st.w[2][bz];
+                  W[24 + by * 3 + bz] = st.w[1][by] * st.dw[2][bz];
+                }
+            } else {
+              const double* src = rec + (int64_t)(pmap ? pmap[p] : p) * PT3;
+              double v[27];
 #pragma unroll
-                for (int m = 0; m < 27; ++m) v[m] = src[(part - 1) + 3 * m];
+              for (int m = 0; m < 27; ++m) v[m] = src[(part - 1) + 3 * m];
 #pragma unroll
-                for (int m = 0; m < 27; ++m) sbuf[k * PT3 + (part - 1) + 3 * m] = v[m];
-              }
+              for (int m = 0; m < 27; ++m) sbuf[k * PT3 + (part - 1) + 3 * m] = v[m];
             }
           }
           __syncthreads();
@@ -904,16 +916,18 @@ __global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restric
               }
             }
           }
-          __syncthreads();   // chunk consumed (and, after the last one, the buffer is free)
         }
+        __syncthreads();   // the staged records are consumed
         if (lane) {
 #pragma unroll
           for (int b = 0; b < 27; ++b) sbuf[((q * 3 + la_x) * 27 + b) * 9 + r * 3 + c] = mine ? acc[b] : 0.0;
         }
         __syncthreads();
-        // accumulator block (slot sl, offset d) adds the nine groups' partials in
-        // group order, all nine entries at once
-        for (int it = t; it < 375; it += JL_T) {
+        // owned items add the nine groups' partials in group order
+#pragma unroll
+        for (int h = 0; h < JL_IT; ++h) {
+          const int it = t + JL_T * h;
+          if (it >= 375) continue;
           const int sl = it / 125, d = it - sl * 125;
           const int lx = imod3(sl - ox);   // row ox + lx sits in slot sl
           const int dx = d % 5 - 2, dy = (d / 5) % 5 - 2, dz = d / 25 - 2;
@@ -931,30 +945,32 @@ __global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restric
               for (int e = 0; e < 9; ++e) sum[e] += src[e];
             }
           }
-          double* dst = sacc + sl * 1125 + d * 9;
 #pragma unroll
-          for (int e = 0; e < 9; ++e) dst[e] += sum[e];
+          for (int e = 0; e < 9; ++e) racc[h][e] += sum[e];
         }
-        __syncthreads();   // partials consumed; row ox is complete
       }
     }
-    // row ox is finished (the last two steps only flush): write it, clear its slot
+    // row ox is finished (the last two steps only flush): write its owned
+    // blocks, clear them
     if (ox >= x0 && ox < x1) {
-      const int sl0 = imod3(ox);
-      if (frow >= 0) {
 #pragma unroll
-        for (int k = 0; k < JL_FL; ++k) {
-          const int l = t + JL_T * k;
-          if (l < 1125 && fsp[k] >= 0) {
-            const int d = l / 9, rc = l - d * 9;
-            double out = sacc[sl0 * 1125 + l];
+      for (int h = 0; h < JL_IT; ++h) {
+        const int it = t + JL_T * h;
+        if (it >= 375 || it / 125 != sl0) continue;
+        const int d = it - sl0 * 125;
+        if (frow >= 0 && fsp[h] >= 0) {
+          double* blk = val + (frp + fsp[h]) * 9;
+#pragma unroll
+          for (int rc = 0; rc < 9; ++rc) {
+            double out = racc[h][rc];
             const int rr = rc / 3, cc = rc - rr * 3;
-            if (((fcode[k] >> (3 + rr)) | (fcode[k] >> cc)) & 1u) out = (d == 62 && rr == cc) ? 1.0 : 0.0;
-            val[(frp + fsp[k]) * 9 + rc] = out;
+            if (((fcode[h] >> (3 + rr)) | (fcode[h] >> cc)) & 1u) out = (d == 62 && rr == cc) ? 1.0 : 0.0;
+            blk[rc] = out;
           }
         }
+#pragma unroll
+        for (int e = 0; e < 9; ++e) racc[h][e] = 0.0;
       }
-      for (int l = t; l < 1125; l += JL_T) sacc[sl0 * 1125 + l] = 0.0;
     }
   }
 }

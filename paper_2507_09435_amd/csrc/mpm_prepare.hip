@@ -750,13 +750,17 @@ int mpm_prepare_impl(mpm_ctx* c, const mpm_problem* pb, int64_t* n_row_out, int6
     } else {
       k_node_volume<3><<<nblk(np), TPB, 0, c->stream>>>(np, c->xs.p, c->vol0s.p, c->psim.p, c->sims.p, c->node_map.p,
                                                         c->nvol.p);
-      // force records, then the coloured P2G (deterministic, no atomics)
-      if (c->rrec.ensure(np * 28) != hipSuccess) return c->fail(MPM_E_NOMEM, "external force records allocation failed");
-      k_fext3_rec<<<nblk(np), TPB, 0, c->stream>>>(np, c->xs.p, c->vol0s.p, pb->P.fp, c->perm.p, c->psim.p, c->sims.p,
-                                                   pb->mat.rho0, pb->mat.g[0], pb->mat.g[1], pb->mat.g[2], c->rrec.p);
-      LAUNCH_CHECK(c, "k_fext3_rec");
       GUARD(build_colour_table(c));
-      GUARD(launch_p2g3(c, 1, c->rrec.p, c->fext.p));
+      if (!c->mg_level) {   // a multigrid level needs no external force
+        // force records, then the coloured P2G (deterministic, no atomics)
+        if (c->rrec.ensure(np * 28) != hipSuccess)
+          return c->fail(MPM_E_NOMEM, "external force records allocation failed");
+        k_fext3_rec<<<nblk(np), TPB, 0, c->stream>>>(np, c->xs.p, c->vol0s.p, pb->P.fp, c->perm.p, c->psim.p,
+                                                     c->sims.p, pb->mat.rho0, pb->mat.g[0], pb->mat.g[1],
+                                                     pb->mat.g[2], c->rrec.p);
+        LAUNCH_CHECK(c, "k_fext3_rec");
+        GUARD(launch_p2g3(c, 1, c->rrec.p, c->fext.p));
+      }
     }
     LAUNCH_CHECK(c, "node volume / fext");
   }
