@@ -326,10 +326,10 @@ def c5_full(M, W, torch, args):
         print(f"[c5]   adjoint step {step}: krylov max {max(kit)}", file=sys.stderr, flush=True)
 
     # backtracking line search: cone/elastic switching can make full Newton steps cycle
-    # Newton to 1e-12, stopping at the round-off floor only within 10x of it:
+    # Newton to 1e-12, stopping at the round-off floor only within 100x of it:
     # central differences with a 1e-5 relative perturbation magnify a
     # residual left at ||r|| / ||r_0|| = e into an error of about e / 1e-5
-    opts = dict(tol=1e-12, stall_factor=10.0, krylov_rtol=1e-12, max_iter=50, krylov_method=2, line_search=4,
+    opts = dict(tol=1e-12, stall_factor=100.0, krylov_rtol=1e-12, max_iter=50, krylov_method=2, line_search=4,
                 progress=progress, adjoint_progress=adjoint_progress)
     E0 = torch.tensor([float(w.particles.E[0]) for w in sims], dtype=torch.float64)
     phi0 = torch.tensor([float(w.particles.phi[0]) for w in sims], dtype=torch.float64)

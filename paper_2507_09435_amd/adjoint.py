@@ -71,7 +71,12 @@ def forward(ctx, dp, sims, steps, tol=1e-10, krylov_rtol=1e-12, max_iter=25, lin
         n_row, nnzb, nd = M.mpm_prepare(ctx, dp)
         du = torch.zeros(n_row * nd, dtype=torch.float64, device=T["x"].device)
         rep = M.mpm_newton_step(ctx, dp, du, tol=tol, max_iter=max_iter, commit=True, krylov_rtol=krylov_rtol,
-                                line_search=line_search, krylov_method=krylov_method, stall_factor=stall_factor)
+                                line_search=line_search, krylov_method=krylov_method, stall_factor=stall_factor,
+                                raise_on_fail=False)
+        if rep["status"] != M.MPM_OK:
+            bad = [(s, rep["sim_iters"][s], rep["sim_rel"][s]) for s in range(dp.nsim) if not rep["sim_converged"][s]]
+            raise M.MPMError(rep["status"], f"load step {step}: {M.STATUS_NAMES.get(rep['status'], rep['status'])}; "
+                                            f"sims not converged (sim, iterations, ||r||/||r0||): {bad[:8]}")
         R.append(rep["sim_reaction"])
         rel.append(max(rep["sim_rel"]) if rep["sim_rel"] else 0.0)
         dus.append(du)
