@@ -54,6 +54,14 @@ def rel_err(a, b, scale=None):
     return np.linalg.norm(a - b) / max(s, 1e-300)
 
 
+def row_errors(got, ref, fint, fext):
+    """Per row: ||r_gpu - r_ref|| / (||f_int,row|| + ||f_ext,row|| + 1e-12 max over rows of both)
+    (rows whose forces all vanish, as where a node's weight is exactly zero, count as 0 / tiny)."""
+    g, r = np.asarray(got).reshape(ref.shape), np.asarray(ref)
+    fi, fe = np.linalg.norm(fint, axis=1), np.linalg.norm(fext, axis=1)
+    return np.linalg.norm(g - r, axis=1) / (fi + fe + 1e-12 * max(fi.max(), fe.max()) + 1e-300)
+
+
 def block_errors(val_gpu, val_ref):
     """Per-block ||B_gpu - B_ref||_F / max(||B_ref||_F, 1e-12 max ||B_ref||_F)."""
     nb = val_ref.shape[0]

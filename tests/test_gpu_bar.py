@@ -10,7 +10,7 @@ import pytest
 from oracle import oracle as O
 from paper_2507_09435_amd import workloads as W
 
-from gpu_common import block_errors, compact_to_full, rel_err, seeded_du
+from gpu_common import row_errors, block_errors, compact_to_full, rel_err, seeded_du
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -62,6 +62,7 @@ def test_bar_residual_and_jacobian_parity(ctx, kappa):
     ref = (fint - fext)[pat.active]
     scale = max(np.linalg.norm(ref), np.linalg.norm(fint[pat.active]), np.linalg.norm(fext[pat.active]))
     e = rel_err(rr.cpu().numpy().reshape(-1, nd), ref, scale)
+    assert row_errors(rr.cpu().numpy(), ref, fint[pat.active], fext[pat.active]).max() <= 1e-10
     reg = O.regimes(Pk, st, full)
     print(f"  residual {e:.2e}, plastic particles {int((reg > 0).sum())} of {st.np}", flush=True)
     assert e <= 1e-10

@@ -10,7 +10,7 @@ import pytest
 from oracle import oracle as O
 from paper_2507_09435_amd import workloads as W
 
-from gpu_common import (block_errors, compact_to_full, oracle_pattern_batch, react_mask, rel_err, seeded_du)
+from gpu_common import (row_errors, block_errors, compact_to_full, oracle_pattern_batch, react_mask, rel_err, seeded_du)
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -68,6 +68,7 @@ def _check_parity(ctx, w, step, seed):
     ref = (fint - fext)[pat.active]
     scale = max(np.linalg.norm(ref), np.linalg.norm(fint[pat.active]), np.linalg.norm(fext[pat.active]))
     assert rel_err(rr.cpu().numpy().reshape(-1, nd), ref, scale) <= 1e-10
+    assert row_errors(rr.cpu().numpy(), ref, fint[pat.active], fext[pat.active]).max() <= 1e-10
     jref = O.jacobian_bsr(P, st, full, pat)
     assert block_errors(val.cpu().numpy(), jref).max() <= 1e-9
 

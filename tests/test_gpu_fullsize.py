@@ -8,7 +8,7 @@ import pytest
 from oracle import oracle as O
 from paper_2507_09435_amd import workloads as W
 
-from gpu_common import block_errors, compact_to_full, react_mask, rel_err, seeded_du
+from gpu_common import row_errors, block_errors, compact_to_full, react_mask, rel_err, seeded_du
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -60,6 +60,9 @@ def test_full_residual_and_jacobian(c2):
     ref = (fint - fext)[pat.active]
     scale = max(np.linalg.norm(ref), np.linalg.norm(fint[pat.active]), np.linalg.norm(fext[pat.active]))
     assert rel_err(rr.cpu().numpy().reshape(-1, nd), ref, scale) <= 1e-10
+    re = row_errors(rr.cpu().numpy(), ref, fint[pat.active], fext[pat.active])
+    print(f"  worst row {re.max():.2e}", flush=True)
+    assert re.max() <= 1e-10, (re.max(), int(re.argmax()))
     errs = block_errors(val.cpu().numpy(), O.jacobian_bsr(P, st, full, pat))
     assert errs.max() <= 1e-9, errs.max()
 

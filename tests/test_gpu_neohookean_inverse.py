@@ -9,7 +9,7 @@ import pytest
 from oracle import oracle as O
 from paper_2507_09435_amd import workloads as W
 
-from gpu_common import block_errors, compact_to_full, react_mask, rel_err, seeded_du
+from gpu_common import row_errors, block_errors, compact_to_full, react_mask, rel_err, seeded_du
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -61,6 +61,7 @@ def test_neohookean_residual_and_jacobian_parity(ctx, name):
     ref = (fint - fext)[pat.active]
     scale = max(np.linalg.norm(ref), np.linalg.norm(fint[pat.active]), np.linalg.norm(fext[pat.active]))
     e = rel_err(rr.cpu().numpy().reshape(-1, nd), ref, scale)
+    assert row_errors(rr.cpu().numpy(), ref, fint[pat.active], fext[pat.active]).max() <= 1e-10
     be = block_errors(val.cpu().numpy(), O.jacobian_bsr(P, st, full, pat)).max()
     print(f"  residual {e:.2e}, worst Jacobian block {be:.2e}", flush=True)
     assert e <= 1e-10 and be <= 1e-9

@@ -7,7 +7,7 @@ import pytest
 from oracle import oracle as O
 from paper_2507_09435_amd import workloads as W
 
-from gpu_common import (block_errors, compact_to_full, dirichlet_bsr, oracle_pattern_batch, react_mask, rel_err,
+from gpu_common import (row_errors, block_errors, compact_to_full, dirichlet_bsr, oracle_pattern_batch, react_mask, rel_err,
                         seeded_du)
 
 pytestmark = pytest.mark.gpu
@@ -54,13 +54,6 @@ def _case(name):
 
 
 CASES = ["c1", "footing", "footing_geo", "up", "c3small", "footing_ps", "footing_ps_assoc", "up_gravity"]
-
-
-def row_errors(got, ref, fint, fext):
-    """Per row: ||r_gpu - r_ref|| / (||f_int,row|| + ||f_ext,row|| + 1e-12 max_row ||f_int,row||)."""
-    g, r = np.asarray(got).reshape(ref.shape), np.asarray(ref)
-    fi, fe = np.linalg.norm(fint, axis=1), np.linalg.norm(fext, axis=1)
-    return np.linalg.norm(g - r, axis=1) / (fi + fe + 1e-12 * fi.max())
 
 
 def _dev(w, step):
