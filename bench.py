@@ -12,8 +12,9 @@ plane-strain footing (256 x 128 cells, 131,072 particles) instead.
 Prints one JSON line: the metric is the residual + Jacobian assembly rate
 (Mparticles/s); it also carries ms per Newton iteration, the roofline of the
 BSR SpMV (the HBM-bound product of the Krylov solve, timed with HIP events
-on the library's stream), the batched-vs-sequential comparison and the CPU
-oracle timed on a bounded sample.
+on the library's stream), with the cube the plane-strain footing's figures
+under "c2", the batched-vs-sequential comparison and the CPU oracle timed on
+a bounded sample.
 """
 from __future__ import annotations
 
@@ -70,6 +71,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c2", action="store_true", help="with the cube: skip the plane-strain footing key")
     ap.add_argument("--krylov-rtol", type=float, default=1e-12)
     ap.add_argument("--krylov-method", type=int, default=None,
                     help="0 block-Jacobi BiCGStab (GMRES fallback), 1 GMRES, 2 multigrid-preconditioned BiCGStab "
@@ -256,6 +258,12 @@ def main():
                            "vs_bsr_spmv": round(spmv_us / jv_us, 3),
                            "note": "y = J x from the per-particle tangent tables (no matrix), Dirichlet-modified"},
     }
+    if args.workload == "c3" and not args.no_c2:
+        M.mpm_destroy(ctx)
+        del dp, val, xv, zv, yv
+        torch.cuda.empty_cache()
+        ctx = M.mpm_create(0, stream.cuda_stream)
+        out["c2"] = c2_extra(M, W, torch, ctx, stream, args)
     if args.batch_sims > 0:
         # the plane-strain footings of the batched set: multigrid-preconditioned BiCGStab
         out["batched"] = batched_vs_sequential(ctx, args.batch_sims, args.batch_steps, args.krylov_rtol, 2)
@@ -263,6 +271,68 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w, args.workload)
     M.mpm_destroy(ctx)
     print(json.dumps(out))
+
+
+def c2_extra(M, W, torch, ctx, stream, args, steps=5, warmup=1):
+    """The plane-strain footing (256 x 128 cells, 131,072 particles) beside
+    the cube: its geostatic load step with multigrid-preconditioned BiCGStab
+    (assembly rate, ms per Newton iteration and per load step) and its SpMV
+    (200 back-to-back launches of the autotuner's shape)."""
+    w = W.make_c2(n_steps=1)
+    P = w.prob
+    react = np.zeros((P.n_nodes, P.ndof), dtype=np.uint8)
+    react[w.footing_nodes(), P.dim - 1] = 1
+    dp = M.make_problem([(P, w.particles)], [w.bc(0)], react_masks=[react])
+    x_out = torch.empty_like(dp.tensors["x"])
+    F_out = torch.empty_like(dp.tensors["F"])
+    be_out = torch.empty_like(dp.tensors["be"])
+    reps = []
+    torch.cuda.synchronize()
+    for k in range(warmup + steps):
+        if k == warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        n_row, nnzb, nd = M.mpm_prepare(ctx, dp)
+        du = torch.zeros(n_row * nd, dtype=torch.float64, device="cuda")
+        rep = M.mpm_newton_step(ctx, dp, du, tol=w.tol, max_iter=25, commit=False, krylov_rtol=args.krylov_rtol,
+                                krylov_method=2)
+        M.mpm_update(ctx, dp, du, x_out, F_out, be_out)
+        if k >= warmup:
+            reps.append(rep)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n_res = sum(r["iters"] + 1 for r in reps)
+    n_jac = sum(r["iters"] for r in reps)
+    t_asm_ms = sum(r["ms_residual"] for r in reps) / n_res + sum(r["ms_jacobian"] for r in reps) / n_jac
+    val = torch.zeros(nnzb * nd * nd, dtype=torch.float64, device="cuda")
+    M.mpm_jacobian_bsr(ctx, dp, du, val=val)
+    xv = torch.randn(n_row * nd, dtype=torch.float64, device="cuda")
+    zv = torch.randn_like(xv)
+    yv = torch.empty_like(xv)
+    for _ in range(10):
+        M.mpm_spmv(ctx, val, xv, yv, zv)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(200):
+        M.mpm_spmv(ctx, val, xv, yv, zv)
+    e1.record(stream)
+    e1.synchronize()
+    spmv_us = e0.elapsed_time(e1) * 1e3 / 200
+    lanes = M.mpm_spmv_lanes(ctx)
+    achieved = spmv_bytes(n_row, nnzb, nd) / (spmv_us * 1e-6) / 1e9
+    print(f"[bench] c2: {w.particles.np / t_asm_ms / 1e3:.1f} Mparticles/s, "
+          f"{sum(r['ms_total'] for r in reps) / n_jac:.2f} ms per Newton iteration", file=sys.stderr, flush=True)
+    return {"workload": "2D plane-strain Drucker-Prager footing layer, 256x128 cells, 131072 particles, geostatic "
+                        "load step, multigrid-preconditioned BiCGStab",
+            "assembly_mparticles_per_s": round(w.particles.np / t_asm_ms / 1e3, 3),
+            "ms_residual_per_eval": round(sum(r["ms_residual"] for r in reps) / n_res, 4),
+            "ms_jacobian_per_eval": round(sum(r["ms_jacobian"] for r in reps) / n_jac, 4),
+            "newton_step_ms": round(sum(r["ms_total"] for r in reps) / n_jac, 3),
+            "ms_per_load_step": round(wall * 1e3 / steps, 3),
+            "spmv": {"kernel": f"k_spmv<{nd},{lanes}>", "avg_launch_us": round(spmv_us, 3),
+                     "achieved_GBps": round(achieved, 1), "frac_of_hbm_peak": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": spmv_traffic(lanes, "c2")}}
 
 
 def batched_vs_sequential(ctx, nsims, nsteps, krylov_rtol, krylov_method):
