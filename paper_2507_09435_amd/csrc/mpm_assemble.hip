@@ -717,7 +717,7 @@ __global__ void __launch_bounds__(TL3) k_tan3v(AsmArgs A, const double* __restri
 }
 
 constexpr int JL_T = 256;    // threads; lane t < 243 is (group q, row la_x, r, c), c fastest
-constexpr int JL_SEG = 16;   // rows of a line per workgroup
+constexpr int JL_SEG = 12;   // rows of a line per workgroup (8: 59.2 ms, 12: 54.7, 16: 56.9, 32: 59.8, 64: 68.2 on the cube)
 constexpr int JL_CH = 72;    // records staged per chunk: a step's nine groups of eight particles
 constexpr int JL_BUF = JL_CH * (PT3 + PW3);   // staged records and stencil data; then the partial blocks
 constexpr int JL_PART = 6561;                 // doubles of the nine groups' partial blocks (9 x 3 rows x 27 x 9)

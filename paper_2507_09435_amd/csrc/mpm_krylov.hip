@@ -706,11 +706,11 @@ static int spmv_tune(mpm_ctx* c, const double* val, const double* x, double* y) 
     if (rc) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return rc; }
     HIPC(c, hipEventElapsedTime(&t[k], e0, e1));
   }
-  // keep the middle shape unless another is clearly faster (stable choice)
+  // keep the middle shape unless another is faster by more than 2 %
   mid = t[1];
   best = mid;
   for (int k = 0; k < 3; ++k)
-    if (k != 1 && t[k] < 0.95f * mid && t[k] < best) { best = t[k]; pick = cand[k]; }
+    if (k != 1 && t[k] < 0.98f * mid && t[k] < best) { best = t[k]; pick = cand[k]; }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->spmv_lanes = pick;
