@@ -187,8 +187,13 @@ struct mpm_ctx {
   mpm::DBuf<double> mg_dense;                  // coarsest level: per sim dense matrix and inverse
   mpm::DBuf<int32_t> mg_doff;                  // per sim: first coarsest row, rows
   mpm::DBuf<mpm::SimDev> mg_sims;              // staging of a child level's descriptors
-  std::vector<double> mg3_lmax;                // 3-D levels: lambda_max(D^-1 A) for the Chebyshev smoother
-  mpm::DBuf<double> mg3_part;                  // 3-D levels: power-iteration partial sums
+  std::vector<double> mg3_lmax;                // 3x3-block levels: lambda_max(D^-1 A) per level and sim
+  mpm::DBuf<double> mg3_lam;                   // (device copy)
+  mpm::DBuf<double> mg3_inv;                   // power iteration: per sim 1 / ||w||
+  mpm::DBuf<double> mg3_part;                  // power iteration: per row w.w
+  mpm::DBuf<double> mg3_coef;                  // Chebyshev (c0, c1) per level, step and sim
+  mpm::DBuf<int32_t> mg3_depth;                // 3x3-block levels: per sim, the level solved densely
+  std::vector<int32_t> mg3_depth_h;            // (host copy; finer levels smooth the sim, coarser skip it)
   int mg_nmax = 0;                             // largest coarsest system (unknowns)
   bool mg_ready = false;                       // hierarchy built for the current prepare
   bool mg_on = false;                          // precondition the current solve with a V-cycle

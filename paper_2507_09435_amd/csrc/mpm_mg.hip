@@ -850,6 +850,7 @@ void mg_release(mpm_ctx* c) {
   c->mgl.clear();
   c->mg_zero.release(); c->mg_inv.release(); c->mg_fine.release(); c->mg_dense.release(); c->mg_doff.release();
   c->mg_sims.release(); c->mg_tail.release(); c->mg_tab.release(); c->mg_tabw.release(); c->mg3_part.release();
+  c->mg3_depth.release(); c->mg3_lam.release(); c->mg3_inv.release(); c->mg3_coef.release();
   c->mg_tail_first = -1;
   mg_drop_graphs(c);
   if (c->cap_stream) { (void)hipStreamDestroy(c->cap_stream); c->cap_stream = nullptr; }

@@ -15,11 +15,21 @@
 // material as on every level.  Smoothing: a Chebyshev polynomial of degree
 // MG3_DEG in the block-Jacobi-scaled operator D^-1 A (3x3 blocks) over
 // [MG3_LO, MG3_HI] x lambda_max before and after the coarse correction, with
-// lambda_max estimated per level by power iteration whenever the operators
-// change.  (Damped block-Jacobi, which suits the plane-strain levels, diverges
+// lambda_max estimated per level and simulation by power iteration whenever
+// the operators change.  (Damped block-Jacobi, which suits the plane-strain levels, diverges
 // here: lambda_max(D^-1 A) is about 6 for these 3-D operators, so w = 0.6
-// amplifies the stiff modes.)  The coarsest level is inverted densely
-// (Gauss-Jordan with partial pivoting) per simulation.
+// amplifies the stiff modes.)  Each simulation's coarsest level is inverted
+// densely (Gauss-Jordan with partial pivoting).
+//
+// Depth per simulation: a simulation's coarsest level is the first on which
+// it has at most MG3_DENSE_MAX unknowns, as if it were solved alone; the
+// hierarchy goes as deep as the largest simulation needs, and the levels
+// below a simulation's own coarsest carry its rows without touching them
+// (smoothing, residuals, transfers and the power iteration skip them).  A
+// batch then preconditions every simulation as its single solve does.  This
+// matters for the u-p operators: coarsened past the consolidation length
+// sqrt(c_v dt) the rediscretized operator stops approximating the fine one,
+// and a small simulation taken to a large one's depth no longer converges.
 //
 // Quadrature particles: a coarse level's stencil groups hold 2^(dim l) times
 // the particles of a fine group, so the level is not assembled from every
@@ -31,6 +41,7 @@
 // pattern is unchanged; the coarse operator is a coarser quadrature of the
 // same rediscretization (a preconditioner only), and its assembly costs
 // about 1/2^dim of the finer level's.
+#include <algorithm>
 #include <cmath>
 
 #include "mpm_internal.hpp"
@@ -48,6 +59,12 @@ constexpr double MG3_HI_3D = 1.1, MG3_HI_UP = 1.3;
 constexpr int MG3_MAX_LEVELS = 12;
 constexpr int MG3_DENSE_MAX = 384;        // coarsest unknowns per simulation (inverted in global memory)
 constexpr int MG3_LPR = 8;                // lanes per row in the sweeps
+
+// Rows of level lev that are smoothed (their simulation's coarsest level is deeper).
+__device__ __forceinline__ bool mg3_smooths(const int32_t* __restrict__ row_sim, const int32_t* __restrict__ depth,
+                                            int64_t row, int lev) {
+  return depth[row_sim[row]] > lev;
+}
 
 __device__ __forceinline__ int sim_of_node3(const SimDev* sims, int nsim, int64_t node) {
   int s = 0;
@@ -189,38 +206,44 @@ __device__ __forceinline__ void mg3_row_product(int64_t row, int lane, const int
 }
 
 // One Chebyshev step per row: z = D^-1 (b - A x_in) (x_in null: x = 0),
-// d = c0 d + c1 z, x_out = x_in + d.  d is updated in place (row-local).
-__global__ void __launch_bounds__(256) k_mg3_cheb(int64_t n_row, const int32_t* __restrict__ rowptr,
+// d = c0 d + c1 z, x_out = x_in + d, with (c0, c1) = coef[2 s .. 2 s + 1]
+// of the row's simulation s.  d is updated in place (row-local).  Rows of
+// simulations not smoothed on this level are left alone.
+__global__ void __launch_bounds__(256) k_mg3_cheb(int64_t n_row, int lev, const int32_t* __restrict__ row_sim,
+                                                  const int32_t* __restrict__ depth, const int32_t* __restrict__ rowptr,
                                                   const int32_t* __restrict__ colind, const double* __restrict__ val,
                                                   const double* __restrict__ dinv, const double* __restrict__ b,
                                                   const double* __restrict__ x_in, double* __restrict__ x_out,
-                                                  double* __restrict__ d, double c0, double c1) {
+                                                  double* __restrict__ d, const double* __restrict__ coef, bool first) {
   const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / MG3_LPR;
   const int lane = threadIdx.x % MG3_LPR;
-  if (row >= n_row) return;   // a row's lanes leave together
+  if (row >= n_row || !mg3_smooths(row_sim, depth, row, lev)) return;   // a row's lanes leave together
   double y0 = 0.0, y1 = 0.0, y2 = 0.0;
   if (x_in) mg3_row_product(row, lane, rowptr, colind, val, x_in, y0, y1, y2);
   if (lane != 0) return;
+  const int s = row_sim[row];
+  const double c0 = coef[2 * s], c1 = coef[2 * s + 1];
   const double r0 = b[row * 3] - y0, r1 = b[row * 3 + 1] - y1, r2 = b[row * 3 + 2] - y2;
   const double* D = dinv + row * 9;
   const double z[3] = {D[0] * r0 + D[1] * r1 + D[2] * r2, D[3] * r0 + D[4] * r1 + D[5] * r2,
                        D[6] * r0 + D[7] * r1 + D[8] * r2};
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double dn = (c0 != 0.0 ? c0 * d[row * 3 + c] : 0.0) + c1 * z[c];
+    const double dn = (first ? 0.0 : c0 * d[row * 3 + c]) + c1 * z[c];
     d[row * 3 + c] = dn;
     x_out[row * 3 + c] = (x_in ? x_in[row * 3 + c] : 0.0) + dn;
   }
 }
 
-// r = b - A x.
-__global__ void __launch_bounds__(256) k_mg3_resid(int64_t n_row, const int32_t* __restrict__ rowptr,
+// r = b - A x on the smoothed rows.
+__global__ void __launch_bounds__(256) k_mg3_resid(int64_t n_row, int lev, const int32_t* __restrict__ row_sim,
+                                                   const int32_t* __restrict__ depth, const int32_t* __restrict__ rowptr,
                                                    const int32_t* __restrict__ colind, const double* __restrict__ val,
                                                    const double* __restrict__ b, const double* __restrict__ x,
                                                    double* __restrict__ r) {
   const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / MG3_LPR;
   const int lane = threadIdx.x % MG3_LPR;
-  if (row >= n_row) return;
+  if (row >= n_row || !mg3_smooths(row_sim, depth, row, lev)) return;
   double y0, y1, y2;
   mg3_row_product(row, lane, rowptr, colind, val, x, y0, y1, y2);
   if (lane != 0) return;
@@ -229,76 +252,91 @@ __global__ void __launch_bounds__(256) k_mg3_resid(int64_t n_row, const int32_t*
   r[row * 3 + 2] = b[row * 3 + 2] - y2;
 }
 
-// Power iteration for lambda_max(D^-1 A): w = D^-1 A v, and per workgroup of
-// 32 rows the partial sums of v.w and w.w (fixed order).
-constexpr int PW_ROWS = 256 / MG3_LPR;
-__global__ void __launch_bounds__(256) k_mg3_pow(int64_t n_row, const int32_t* __restrict__ rowptr,
+// Power iteration for lambda_max(D^-1 A), per simulation: w = D^-1 A v on
+// the smoothed rows (0 on the others), and per row w.w.
+__global__ void __launch_bounds__(256) k_mg3_pow(int64_t n_row, int lev, const int32_t* __restrict__ row_sim,
+                                                 const int32_t* __restrict__ depth, const int32_t* __restrict__ rowptr,
                                                  const int32_t* __restrict__ colind, const double* __restrict__ val,
                                                  const double* __restrict__ dinv, const double* __restrict__ v,
-                                                 double* __restrict__ w, double* __restrict__ part) {
-  __shared__ double s_vw[PW_ROWS], s_ww[PW_ROWS];
+                                                 double* __restrict__ w, double* __restrict__ rowww) {
   const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / MG3_LPR;
-  const int lane = threadIdx.x % MG3_LPR, lr = threadIdx.x / MG3_LPR;
-  double vw = 0.0, ww = 0.0;
-  if (row < n_row) {
+  const int lane = threadIdx.x % MG3_LPR;
+  if (row >= n_row) return;
+  double z0 = 0.0, z1 = 0.0, z2 = 0.0;
+  if (mg3_smooths(row_sim, depth, row, lev)) {
     double y0, y1, y2;
     mg3_row_product(row, lane, rowptr, colind, val, v, y0, y1, y2);
     const double* D = dinv + row * 9;
-    const double z0 = D[0] * y0 + D[1] * y1 + D[2] * y2, z1 = D[3] * y0 + D[4] * y1 + D[5] * y2,
-                 z2 = D[6] * y0 + D[7] * y1 + D[8] * y2;
-    if (lane == 0) {
-      w[row * 3] = z0; w[row * 3 + 1] = z1; w[row * 3 + 2] = z2;
-      vw = v[row * 3] * z0 + v[row * 3 + 1] * z1 + v[row * 3 + 2] * z2;
-      ww = z0 * z0 + z1 * z1 + z2 * z2;
-    }
+    z0 = D[0] * y0 + D[1] * y1 + D[2] * y2;
+    z1 = D[3] * y0 + D[4] * y1 + D[5] * y2;
+    z2 = D[6] * y0 + D[7] * y1 + D[8] * y2;
   }
-  if (lane == 0) { s_vw[lr] = vw; s_ww[lr] = ww; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double a = 0.0, bb = 0.0;
-    for (int k = 0; k < PW_ROWS; ++k) { a += s_vw[k]; bb += s_ww[k]; }
-    part[2 * blockIdx.x] = a;
-    part[2 * blockIdx.x + 1] = bb;
-  }
+  if (lane != 0) return;
+  w[row * 3] = z0;
+  w[row * 3 + 1] = z1;
+  w[row * 3 + 2] = z2;
+  rowww[row] = z0 * z0 + z1 * z1 + z2 * z2;
 }
 
-// Sum the partials (one workgroup, fixed order): out[0] = v.w, out[1] = w.w.
-__global__ void __launch_bounds__(256) k_mg3_pow_sum(int64_t nblk, const double* __restrict__ part,
-                                                     double* __restrict__ out) {
-  __shared__ double sa[256], sb[256];
-  double a = 0.0, b = 0.0;
-  for (int64_t k = threadIdx.x; k < nblk; k += 256) { a += part[2 * k]; b += part[2 * k + 1]; }
+// One workgroup per simulation: ||w||^2 over its rows (fixed order), then
+// lambda[s] = ||w|| and inv[s] = 1 / ||w|| (the next vector's scale).  A zero
+// or non-finite norm keeps lambda[s] and zeroes the simulation's vector.
+// first: lambda[s] starts at 1.
+__global__ void __launch_bounds__(256) k_mg3_pow_sim(int64_t n_row, int nsim, const SimDev* __restrict__ sims,
+                                                     const double* __restrict__ rowww, double* __restrict__ inv,
+                                                     double* __restrict__ lambda, bool first) {
+  __shared__ double sa[256];
+  const int s = blockIdx.x;
+  const int64_t r0 = sims[s].row_base, r1 = s + 1 < nsim ? sims[s + 1].row_base : n_row;
+  double a = 0.0;
+  for (int64_t k = r0 + threadIdx.x; k < r1; k += 256) a += rowww[k];
   sa[threadIdx.x] = a;
-  sb[threadIdx.x] = b;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) { sa[threadIdx.x] += sa[threadIdx.x + off]; sb[threadIdx.x] += sb[threadIdx.x + off]; }
+    if ((int)threadIdx.x < off) sa[threadIdx.x] += sa[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) { out[0] = sa[0]; out[1] = sb[0]; }
+  if (threadIdx.x == 0) {
+    const double ww = sa[0];
+    if (first) lambda[s] = 1.0;
+    if (ww > 0.0 && isfinite(ww)) {
+      const double nw = sqrt(ww);
+      lambda[s] = nw;
+      inv[s] = 1.0 / nw;
+    } else {
+      inv[s] = 0.0;
+    }
+  }
 }
 
-// v = w / ||w|| (s = 1 / ||w|| from the host); the first vector: a fixed
-// pseudo-random field (row and component hash), the same on every run.
-__global__ void k_mg3_scale(int64_t n, const double* __restrict__ w, double s, double* __restrict__ v) {
+// v = inv[s] w on the rows of simulation s; the first vector (w null): a
+// fixed pseudo-random field hashed from the row's index within its
+// simulation and the component, so a simulation starts from the same vector
+// alone or in any batch.
+__global__ void k_mg3_scale(int64_t n, const int32_t* __restrict__ row_sim, const SimDev* __restrict__ sims,
+                            const double* __restrict__ w, const double* __restrict__ inv, double* __restrict__ v) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
-  if (w) { v[e] = s * w[e]; return; }
-  uint64_t h = (uint64_t)e * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+  const int s = row_sim[e / 3];
+  if (w) { v[e] = inv[s] * w[e]; return; }
+  const uint64_t el = (uint64_t)(e - 3 * sims[s].row_base);
+  uint64_t h = el * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
   h ^= h >> 31; h *= 0xBF58476D1CE4E5B9ull; h ^= h >> 29;
   v[e] = (double)(h >> 11) * (1.0 / 9007199254740992.0) + 0.5;
 }
 
-// Restriction (transpose of trilinear interpolation): coarse row (I, J, K)
-// gathers the fine rows at 2I + {-1, 0, 1} per axis with weights 1/2, 1, 1/2;
-// constrained coarse unknowns get 0.
-__global__ void k_mg3_restrict(int64_t n_crow, int dim, const int64_t* __restrict__ c_active,
+// Restriction (transpose of trilinear interpolation) from level lev: coarse
+// row (I, J, K) gathers the fine rows at 2I + {-1, 0, 1} per axis with
+// weights 1/2, 1, 1/2; constrained coarse unknowns get 0.  Rows of
+// simulations not smoothed on level lev are skipped.
+__global__ void k_mg3_restrict(int64_t n_crow, int dim, int lev, const int32_t* __restrict__ depth,
+                               const int64_t* __restrict__ c_active,
                                const int32_t* __restrict__ c_rowsim, const SimDev* __restrict__ csims,
                                const SimDev* __restrict__ fsims, const int32_t* __restrict__ f_node_map,
                                const double* __restrict__ rf, const uint8_t* __restrict__ c_cmask,
                                double* __restrict__ bc) {
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= n_crow) return;
+  if (row >= n_crow || !mg3_smooths(c_rowsim, depth, row, lev)) return;
   const int s = c_rowsim[row];
   const SimDev& C = csims[s];
   const SimDev& F = fsims[s];
@@ -329,16 +367,17 @@ __global__ void k_mg3_restrict(int64_t n_crow, int dim, const int64_t* __restric
   bc[row * 3 + 2] = c_cmask[row * 3 + 2] ? 0.0 : a2;
 }
 
-// Prolongation added to x: fine node (i, j, k) takes, per axis, coarse node
-// i/2 (i even) or the mean of (i-1)/2 and (i+1)/2 (i odd); constrained fine
-// unknowns are left alone.
-__global__ void k_mg3_prolong_add(int64_t n_frow, int dim, const int64_t* __restrict__ f_active,
+// Prolongation added to x on level lev: fine node (i, j, k) takes, per
+// axis, coarse node i/2 (i even) or the mean of (i-1)/2 and (i+1)/2 (i odd);
+// constrained fine unknowns, and rows not smoothed on lev, are left alone.
+__global__ void k_mg3_prolong_add(int64_t n_frow, int dim, int lev, const int32_t* __restrict__ depth,
+                                  const int64_t* __restrict__ f_active,
                                   const int32_t* __restrict__ f_rowsim, const SimDev* __restrict__ fsims,
                                   const SimDev* __restrict__ csims, const int32_t* __restrict__ c_node_map,
                                   const double* __restrict__ xc, const uint8_t* __restrict__ f_cmask,
                                   double* __restrict__ x) {
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= n_frow) return;
+  if (row >= n_frow || !mg3_smooths(f_rowsim, depth, row, lev)) return;
   const int s = f_rowsim[row];
   const SimDev& F = fsims[s];
   const SimDev& C = csims[s];
@@ -370,14 +409,17 @@ __global__ void k_mg3_prolong_add(int64_t n_frow, int dim, const int64_t* __rest
 }
 
 // Coarsest matrix, dense per sim: [A | I] of nmax x 2 nmax (row-major), the
-// sim's rows first.  dense must be zeroed before.
-__global__ void k_mg3_dense_fill(int64_t n_row, const int32_t* __restrict__ row_sim,
+// sim's rows first, from the rows of level lev whose simulation is solved
+// there.  dense must be zeroed before.
+__global__ void k_mg3_dense_fill(int64_t n_row, int lev, const int32_t* __restrict__ depth,
+                                 const int32_t* __restrict__ row_sim,
                                  const int32_t* __restrict__ doff, const int32_t* __restrict__ rowptr,
                                  const int32_t* __restrict__ colind, const double* __restrict__ val, int nmax,
                                  double* __restrict__ dense) {
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= n_row) return;
   const int s = row_sim[row];
+  if (depth[s] != lev) return;
   const int r0 = doff[2 * s];
   double* M = dense + (int64_t)s * nmax * 2 * nmax;
   const int rl = (int)(row - r0);
@@ -450,10 +492,13 @@ __global__ void __launch_bounds__(GJ3) k_mg3_gauss_jordan(const int32_t* __restr
   }
 }
 
-// x = A^-1 b on the coarsest level (per sim: the right half of its dense block).
-__global__ void k_mg3_dense_apply(const int32_t* __restrict__ doff, int nmax, const double* __restrict__ dense,
-                                  const double* __restrict__ b, double* __restrict__ x) {
+// x = A^-1 b for the simulations whose coarsest level is lev (vectors of
+// that level; per sim the right half of its dense block).
+__global__ void k_mg3_dense_apply(int lev, const int32_t* __restrict__ depth, const int32_t* __restrict__ doff,
+                                  int nmax, const double* __restrict__ dense, const double* __restrict__ b,
+                                  double* __restrict__ x) {
   const int s = blockIdx.x;
+  if (depth[s] != lev) return;
   const int r0 = doff[2 * s], n = 3 * doff[2 * s + 1];
   const double* M = dense + (int64_t)s * nmax * 2 * nmax;
   const double* bb = b + (int64_t)r0 * 3;
@@ -470,8 +515,8 @@ using namespace mpm;
 
 static unsigned nb256_3(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + 255) / 256); }
 
-static int level_lmax(mpm_ctx* c, const mpm_ctx* L, const double* val, const double* dinv, double* v, double* w,
-                      double& lmax);
+static int level_lmax(mpm_ctx* c, int lev, const mpm_ctx* L, const double* val, const double* dinv, double* v,
+                      double* w, double* lambda);
 
 // Quadrature particles of level L (see the top of this file): per origin key
 // its chunks of at most MG3_CHUNK sorted particles and its first quadrature
@@ -641,20 +686,31 @@ int mg3_build(mpm_ctx* c, const mpm_problem* pb) {
   }
   while (c->mgl.size() > nl) { mg_level_release(c->mgl.back()); c->mgl.pop_back(); }
   c->mg_tail_first = -1;
-  const mpm_ctx* C = nl ? c->mgl.back()->sub : c;
+  // per sim: its coarsest level (the first with at most MG3_DENSE_MAX
+  // unknowns, else the last) and its rows there
   std::vector<int32_t> doff(2 * nsim);
+  c->mg3_depth_h.assign(nsim, (int32_t)nl);
   int nmax = 3;
   for (int s = 0; s < nsim; ++s) {
-    doff[2 * s] = (int32_t)C->sim_row_start[s];
-    doff[2 * s + 1] = (int32_t)(C->sim_row_start[s + 1] - C->sim_row_start[s]);
+    for (size_t l = 0; l <= nl; ++l) {
+      const mpm_ctx* C = l ? c->mgl[l - 1]->sub : c;
+      if (3 * (C->sim_row_start[s + 1] - C->sim_row_start[s]) <= MG3_DENSE_MAX || l == nl) {
+        c->mg3_depth_h[s] = (int32_t)l;
+        doff[2 * s] = (int32_t)C->sim_row_start[s];
+        doff[2 * s + 1] = (int32_t)(C->sim_row_start[s + 1] - C->sim_row_start[s]);
+        break;
+      }
+    }
     nmax = std::max(nmax, 3 * doff[2 * s + 1]);
   }
   if (nmax > MG3_DENSE_MAX) return c->fail(MPM_E_INVALID, "multigrid coarsest level too large for the dense solve");
   c->mg_nmax = nmax;
-  if (c->mg_doff.ensure(2 * nsim) != hipSuccess ||
+  if (c->mg_doff.ensure(2 * nsim) != hipSuccess || c->mg3_depth.ensure(nsim) != hipSuccess ||
       c->mg_dense.ensure((size_t)nsim * 2 * nmax * nmax) != hipSuccess)
     return c->fail(MPM_E_NOMEM, "multigrid dense allocation failed");
   HIPC(c, hipMemcpyAsync(c->mg_doff.p, doff.data(), doff.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  HIPC(c, hipMemcpyAsync(c->mg3_depth.p, c->mg3_depth_h.data(), nsim * sizeof(int32_t), hipMemcpyHostToDevice,
+                         c->stream));
   HIPC(c, hipStreamSynchronize(c->stream));
   ++c->mg_gen;
   c->mg_ready = true;
@@ -685,23 +741,66 @@ int mg3_setup(mpm_ctx* c) {
     if (!rc) rc = launch_bj_inv(sub, sub->val.p);
     if (rc) return c->fail(rc, "multigrid level setup: " + sub->err);
   }
-  // lambda_max(D^-1 A) of every smoothed level (the level's own vectors as scratch)
-  c->mg3_lmax.assign(c->mgl.size() + 1, 1.0);
-  for (size_t l = 0; l < c->mgl.size(); ++l) {
-    const mpm_ctx* L = l == 0 ? c : c->mgl[l - 1]->sub;
-    const double* val = l == 0 ? c->val.p : L->val.p;
-    const double* dinv = l == 0 ? c->dinv.p : L->dinv.p;
-    const int64_t nv = L->n_row * 3;
-    double* v = l == 0 ? c->mg_fine.p : c->mgl[l - 1]->vec.p;
-    GUARD(level_lmax(c, L, val, dinv, v, v + nv, c->mg3_lmax[l]));
+  // lambda_max(D^-1 A) of every smoothed level and sim (the level's own
+  // vectors as scratch), then the Chebyshev coefficients of every step
+  const size_t nl = c->mgl.size();
+  const int nsim = c->nsim;
+  if (nl) {
+    int64_t most_rows = c->n_row;
+    for (MgLevel* L : c->mgl) most_rows = std::max(most_rows, L->sub->n_row);
+    if (c->mg3_lam.ensure(nl * nsim) != hipSuccess || c->mg3_inv.ensure(nsim) != hipSuccess ||
+        c->mg3_part.ensure(std::max<int64_t>(1, most_rows)) != hipSuccess ||
+        c->mg3_coef.ensure(nl * MG3_DEG * nsim * 2) != hipSuccess)
+      return c->fail(MPM_E_NOMEM, "multigrid allocation failed");
+    for (size_t l = 0; l < nl; ++l) {
+      const mpm_ctx* L = l == 0 ? c : c->mgl[l - 1]->sub;
+      const double* val = l == 0 ? c->val.p : L->val.p;
+      const double* dinv = l == 0 ? c->dinv.p : L->dinv.p;
+      const int64_t nv = L->n_row * 3;
+      double* v = l == 0 ? c->mg_fine.p : c->mgl[l - 1]->vec.p;
+      GUARD(level_lmax(c, (int)l, L, val, dinv, v, v + nv, c->mg3_lam.p + l * nsim));
+    }
+    c->mg3_lmax.assign(nl * nsim, 1.0);
+    HIPC(c, hipMemcpyAsync(c->mg3_lmax.data(), c->mg3_lam.p, nl * nsim * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+    HIPC(c, hipStreamSynchronize(c->stream));
+    // step k: x_k = x_{k-1} + d_k, d_k = c0 d_{k-1} + c1 D^-1 r (the three-term
+    // Chebyshev recurrence on [lo, hi] = [MG3_LO, MG3_HI] x lambda_max)
+    std::vector<double> coef(nl * MG3_DEG * nsim * 2);
+    for (size_t l = 0; l < nl; ++l)
+      for (int q = 0; q < nsim; ++q) {
+        const double lmax = c->mg3_lmax[l * nsim + q];
+        const double lo = MG3_LO * lmax, hi = (c->up ? MG3_HI_UP : MG3_HI_3D) * lmax;
+        const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+        double rho = 1.0 / sigma;
+        for (int k = 0; k < MG3_DEG; ++k) {
+          double c0 = 0.0, c1 = 1.0 / theta;
+          if (k > 0) {
+            const double rn = 1.0 / (2.0 * sigma - rho);
+            c0 = rn * rho;
+            c1 = 2.0 * rn / delta;
+            rho = rn;
+          }
+          double* e = coef.data() + ((l * MG3_DEG + k) * nsim + q) * 2;
+          e[0] = c0;
+          e[1] = c1;
+        }
+      }
+    HIPC(c, hipMemcpyAsync(c->mg3_coef.p, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice,
+                           c->stream));
+    HIPC(c, hipStreamSynchronize(c->stream));   // coef goes out of scope
   }
-  const mpm_ctx* C = c->mgl.empty() ? c : c->mgl.back()->sub;
-  const double* Cval = c->mgl.empty() ? c->val.p : C->val.p;
+  // every sim's dense block from its own coarsest level
   const int nmax = c->mg_nmax;
   HIPC(c, hipMemsetAsync(c->mg_dense.p, 0, (size_t)c->nsim * 2 * nmax * nmax * sizeof(double), c->stream));
-  if (C->n_row) {
-    k_mg3_dense_fill<<<nb256_3(C->n_row), 256, 0, c->stream>>>(C->n_row, C->row_sim.p, c->mg_doff.p, C->rowptr.p,
-                                                               C->colind.p, Cval, nmax, c->mg_dense.p);
+  for (size_t l = 0; l <= c->mgl.size(); ++l) {
+    if (std::find(c->mg3_depth_h.begin(), c->mg3_depth_h.end(), (int32_t)l) == c->mg3_depth_h.end()) continue;
+    const mpm_ctx* C = l == 0 ? c : c->mgl[l - 1]->sub;
+    const double* Cval = l == 0 ? c->val.p : C->val.p;
+    if (!C->n_row) continue;
+    k_mg3_dense_fill<<<nb256_3(C->n_row), 256, 0, c->stream>>>(C->n_row, (int)l, c->mg3_depth.p, C->row_sim.p,
+                                                               c->mg_doff.p, C->rowptr.p, C->colind.p, Cval, nmax,
+                                                               c->mg_dense.p);
     LAUNCH_CHECK(c, "k_mg3_dense_fill");
   }
   k_mg3_gauss_jordan<<<(unsigned)c->nsim, GJ3, 0, c->stream>>>(c->mg_doff.p, nmax, c->mg_dense.p, c->flag.p);
@@ -711,14 +810,12 @@ int mg3_setup(mpm_ctx* c) {
 
 static unsigned rows_grid(int64_t n_row) { return (unsigned)((n_row * MG3_LPR + 255) / 256); }
 
-// Chebyshev smoothing of level ctx from x_in (null: 0) into x; d is scratch.
-static int cheb3(mpm_ctx* c, const mpm_ctx* L, const double* val, const double* dinv, double lmax, const double* b,
+// Chebyshev smoothing of level lev (context L) from x_in (null: 0) into x,
+// with every sim's own coefficients; d is scratch.
+static int cheb3(mpm_ctx* c, int lev, const mpm_ctx* L, const double* val, const double* dinv, const double* b,
                  double* x, double* xs, double* d, bool from_zero) {
   const int64_t n_row = L->n_row;
   if (!n_row) return MPM_OK;
-  const double lo = MG3_LO * lmax, hi = (c->up ? MG3_HI_UP : MG3_HI_3D) * lmax;
-  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
-  double rho = 1.0 / sigma;
   // step k writes x when DEG-1-k is even, else xs, so the last lands in x;
   // no step reads the vector it writes (the products need the old iterate)
   const double* xin = nullptr;
@@ -731,56 +828,56 @@ static int cheb3(mpm_ctx* c, const mpm_ctx* L, const double* val, const double* 
     }
   }
   for (int k = 0; k < MG3_DEG; ++k) {
-    double c0 = 0.0, c1 = 1.0 / theta;
-    if (k > 0) {
-      const double rn = 1.0 / (2.0 * sigma - rho);
-      c0 = rn * rho;
-      c1 = 2.0 * rn / delta;
-      rho = rn;
-    }
     double* out = ((MG3_DEG - 1 - k) % 2 == 0) ? x : xs;
-    k_mg3_cheb<<<rows_grid(n_row), 256, 0, c->stream>>>(n_row, L->rowptr.p, L->colind.p, val, dinv, b, xin, out, d,
-                                                         c0, c1);
+    k_mg3_cheb<<<rows_grid(n_row), 256, 0, c->stream>>>(n_row, lev, L->row_sim.p, c->mg3_depth.p, L->rowptr.p,
+                                                         L->colind.p, val, dinv, b, xin, out, d,
+                                                         c->mg3_coef.p + ((size_t)lev * MG3_DEG + k) * c->nsim * 2,
+                                                         k == 0);
     LAUNCH_CHECK(c, "k_mg3_cheb");
     xin = out;
   }
   return MPM_OK;
 }
 
-// lambda_max(D^-1 A) of a level by power iteration (deterministic sums).
-static int level_lmax(mpm_ctx* c, const mpm_ctx* L, const double* val, const double* dinv, double* v, double* w,
-                      double& lmax) {
+// lambda_max(D^-1 A) of level lev's smoothed rows, per sim, by power
+// iteration (deterministic sums, no host round trip): lambda[s] on the device.
+static int level_lmax(mpm_ctx* c, int lev, const mpm_ctx* L, const double* val, const double* dinv, double* v,
+                      double* w, double* lambda) {
   const int64_t n_row = L->n_row;
-  lmax = 1.0;
-  if (!n_row) return MPM_OK;
-  const int64_t nv = n_row * 3;
-  const int64_t nblk = (n_row + PW_ROWS - 1) / PW_ROWS;
-  if (c->mg3_part.ensure(2 * nblk + 2) != hipSuccess) return c->fail(MPM_E_NOMEM, "multigrid allocation failed");
-  k_mg3_scale<<<nb256_3(nv), 256, 0, c->stream>>>(nv, nullptr, 1.0, v);
-  double host[2] = {0.0, 0.0};
-  for (int it = 0; it < MG3_POWER; ++it) {
-    k_mg3_pow<<<(unsigned)nblk, 256, 0, c->stream>>>(n_row, L->rowptr.p, L->colind.p, val, dinv, v, w, c->mg3_part.p);
-    k_mg3_pow_sum<<<1, 256, 0, c->stream>>>(nblk, c->mg3_part.p, c->mg3_part.p + 2 * nblk);
-    LAUNCH_CHECK(c, "k_mg3_pow");
-    HIPC(c, hipMemcpyAsync(host, c->mg3_part.p + 2 * nblk, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (!n_row) {
+    std::vector<double> one(c->nsim, 1.0);
+    HIPC(c, hipMemcpyAsync(lambda, one.data(), one.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     HIPC(c, hipStreamSynchronize(c->stream));
-    if (!(host[1] > 0.0) || !std::isfinite(host[1])) break;
-    const double nw = std::sqrt(host[1]);
-    k_mg3_scale<<<nb256_3(nv), 256, 0, c->stream>>>(nv, w, 1.0 / nw, v);
+    return MPM_OK;
+  }
+  const int64_t nv = n_row * 3;
+  k_mg3_scale<<<nb256_3(nv), 256, 0, c->stream>>>(nv, L->row_sim.p, L->sims.p, nullptr, nullptr, v);
+  LAUNCH_CHECK(c, "k_mg3_scale");
+  for (int it = 0; it < MG3_POWER; ++it) {
+    k_mg3_pow<<<rows_grid(n_row), 256, 0, c->stream>>>(n_row, lev, L->row_sim.p, c->mg3_depth.p, L->rowptr.p,
+                                                        L->colind.p, val, dinv, v, w, c->mg3_part.p);
+    LAUNCH_CHECK(c, "k_mg3_pow");
+    k_mg3_pow_sim<<<(unsigned)c->nsim, 256, 0, c->stream>>>(n_row, c->nsim, L->sims.p, c->mg3_part.p, c->mg3_inv.p,
+                                                            lambda, it == 0);
+    LAUNCH_CHECK(c, "k_mg3_pow_sim");
+    // lambda = ||D^-1 A v|| with ||v|| = 1 (after the first step)
+    k_mg3_scale<<<nb256_3(nv), 256, 0, c->stream>>>(nv, L->row_sim.p, L->sims.p, w, c->mg3_inv.p, v);
     LAUNCH_CHECK(c, "k_mg3_scale");
-    lmax = nw;   // ||D^-1 A v|| with ||v|| = 1 (after the first step)
   }
   return MPM_OK;
 }
 
-// out = M^-1 b on level l.
+// out = M^-1 b on level l: the dense solve of the simulations whose
+// coarsest level is l, a V-cycle for those with deeper ones.
 static int vcycle3(mpm_ctx* c, size_t l, const double* b, double* out) {
   const size_t nl = c->mgl.size();
-  if (l == nl) {
-    k_mg3_dense_apply<<<(unsigned)c->nsim, 256, 0, c->stream>>>(c->mg_doff.p, c->mg_nmax, c->mg_dense.p, b, out);
+  const std::vector<int32_t>& dep = c->mg3_depth_h;
+  if (std::find(dep.begin(), dep.end(), (int32_t)l) != dep.end()) {
+    k_mg3_dense_apply<<<(unsigned)c->nsim, 256, 0, c->stream>>>((int)l, c->mg3_depth.p, c->mg_doff.p, c->mg_nmax,
+                                                               c->mg_dense.p, b, out);
     LAUNCH_CHECK(c, "k_mg3_dense_apply");
-    return MPM_OK;
   }
+  if (l == nl) return MPM_OK;
   const mpm_ctx* ctx = l == 0 ? c : c->mgl[l - 1]->sub;
   const double* val = l == 0 ? c->val.p : ctx->val.p;
   const double* dinv = l == 0 ? c->dinv.p : ctx->dinv.p;
@@ -788,10 +885,10 @@ static int vcycle3(mpm_ctx* c, size_t l, const double* b, double* out) {
   double* y = l == 0 ? c->mg_fine.p : c->mgl[l - 1]->vec.p;            // iterate partner
   double* r = l == 0 ? c->mg_fine.p + nv : c->mgl[l - 1]->vec.p + nv;  // residual
   double* d = l == 0 ? c->mg_fine.p + 2 * nv : c->mgl[l - 1]->vec.p + 4 * nv;   // Chebyshev direction
-  const double lmax = c->mg3_lmax[l];
-  GUARD(cheb3(c, ctx, val, dinv, lmax, b, out, y, d, true));
+  GUARD(cheb3(c, (int)l, ctx, val, dinv, b, out, y, d, true));
   if (ctx->n_row) {
-    k_mg3_resid<<<rows_grid(ctx->n_row), 256, 0, c->stream>>>(ctx->n_row, ctx->rowptr.p, ctx->colind.p, val, b, out, r);
+    k_mg3_resid<<<rows_grid(ctx->n_row), 256, 0, c->stream>>>(ctx->n_row, (int)l, ctx->row_sim.p, c->mg3_depth.p,
+                                                              ctx->rowptr.p, ctx->colind.p, val, b, out, r);
     LAUNCH_CHECK(c, "k_mg3_resid");
   }
   MgLevel* CL = c->mgl[l];
@@ -799,18 +896,19 @@ static int vcycle3(mpm_ctx* c, size_t l, const double* b, double* out) {
   double* xc = CL->vec.p + 2 * C->n_row * 3;
   double* bc = CL->vec.p + 3 * C->n_row * 3;
   if (C->n_row) {
-    k_mg3_restrict<<<nb256_3(C->n_row), 256, 0, c->stream>>>(C->n_row, c->dim, C->active_nodes.p, C->row_sim.p, C->sims.p,
-                                                             ctx->sims.p, ctx->node_map.p, r, C->cmask.p, bc);
+    k_mg3_restrict<<<nb256_3(C->n_row), 256, 0, c->stream>>>(C->n_row, c->dim, (int)l, c->mg3_depth.p,
+                                                             C->active_nodes.p, C->row_sim.p, C->sims.p, ctx->sims.p,
+                                                             ctx->node_map.p, r, C->cmask.p, bc);
     LAUNCH_CHECK(c, "k_mg3_restrict");
   }
   GUARD(vcycle3(c, l + 1, bc, xc));
   if (ctx->n_row) {
-    k_mg3_prolong_add<<<nb256_3(ctx->n_row), 256, 0, c->stream>>>(ctx->n_row, c->dim, ctx->active_nodes.p, ctx->row_sim.p,
-                                                                  ctx->sims.p, C->sims.p, C->node_map.p, xc,
-                                                                  ctx->cmask.p, out);
+    k_mg3_prolong_add<<<nb256_3(ctx->n_row), 256, 0, c->stream>>>(ctx->n_row, c->dim, (int)l, c->mg3_depth.p,
+                                                                  ctx->active_nodes.p, ctx->row_sim.p, ctx->sims.p,
+                                                                  C->sims.p, C->node_map.p, xc, ctx->cmask.p, out);
     LAUNCH_CHECK(c, "k_mg3_prolong_add");
   }
-  GUARD(cheb3(c, ctx, val, dinv, lmax, b, out, y, d, false));
+  GUARD(cheb3(c, (int)l, ctx, val, dinv, b, out, y, d, false));
   return MPM_OK;
 }
 

@@ -386,6 +386,61 @@ def test_batched_newton_parity(ctx, method):
         off += pat.n_row
 
 
+@pytest.mark.parametrize("kind", ["up", "cube"])
+def test_batched_multigrid_3x3(ctx, kind):
+    """Two sims of different size in one batch under the 3x3-block multigrid
+    (each sim coarsened to its own depth, with its own dense coarsest
+    solve): each sim's converged increment equals its own oracle Newton
+    solution, and the batch's first Krylov solve takes no more than twice
+    the iterations of the slower single-sim solve (the u-p pair: the smaller
+    sim taken to the larger one's depth stops converging)."""
+    from paper_2507_09435_amd import mpm as M
+    if kind == "up":
+        ws = [W.make_c4(n=n, n_steps=1, width_cells=n, dt=1.0) for n in (16, 24)]
+        step, bound = 1, 1e-10
+    else:
+        ws = [W.make_c3(n=n, n_steps=1) for n in (8, 12)]
+        for w in ws:
+            w.particles.phi = np.full(w.particles.np, np.radians(40.0))   # the geostatic state stays elastic
+        step, bound = 0, 1e-10
+    print(f"[mg-batch] kind={kind} sims={[w.particles.np for w in ws]}", flush=True)
+
+    def solve(batch):
+        dp = M.make_problem([(w.prob, w.particles) for w in batch], [w.bc(step) for w in batch])
+        n_row, nnzb, nd = M.mpm_prepare(ctx, dp)
+        du = torch.zeros(n_row * nd, dtype=torch.float64, device="cuda")
+        rep = M.mpm_newton_step(ctx, dp, du, tol=1e-12, max_iter=25, commit=False, krylov_rtol=1e-12,
+                                krylov_method=2)
+        torch.cuda.synchronize()
+        assert rep["converged"] and all(rep["sim_converged"]), rep
+        return du, nd, rep
+
+    single = [solve([w])[2]["krylov"][0] for w in ws]
+    du, nd, rep = solve(ws)
+    print(f"  newton {rep['iters']}  krylov per newton {rep['krylov'][:rep['iters']]}, "
+          f"first solve alone {single}", flush=True)
+    assert rep["krylov"][0] <= 2 * max(single), (rep["krylov"][0], single)
+    got = du.cpu().numpy().reshape(-1, nd)
+    off = 0
+    for k, w in enumerate(ws):
+        bc = w.bc(step)
+        dof, orep, pat = O.newton(w.prob, w.particles, bc.mask, bc.value, tol=1e-12)
+        assert orep.converged
+        # widened only to 10x the oracle's own spread at its round-off floor
+        more, _, _ = O.newton(w.prob, w.particles, bc.mask, bc.value, tol=1e-30, stall_factor=0.0,
+                              maxit=orep.iters + 4, dof0_full=dof)
+        g, r, m = got[off:off + pat.n_row], dof[pat.active], more[pat.active]
+        if kind == "up":
+            e = max(rel_err(g[:, :2], r[:, :2]), rel_err(g[:, 2], r[:, 2]))
+            spread = max(rel_err(m[:, :2], r[:, :2]), rel_err(m[:, 2], r[:, 2]))
+        else:
+            e, spread = rel_err(g, r), rel_err(m, r)
+        b = max(bound, 10.0 * spread)
+        print(f"  sim {k}: du rel err {e:.3e} (oracle spread {spread:.1e}, bound {b:.1e})", flush=True)
+        assert e <= b
+        off += pat.n_row
+
+
 @pytest.mark.parametrize("push,iters", [(-1e-3, 4), (-3e-3, 3)])
 def test_line_search_follows_the_oracle(ctx, push, iters):
     """Backtracking on ||r||: step lengths 1, 1/2 (two trials), then the full
