@@ -127,6 +127,65 @@ __device__ __forceinline__ void load_particle(const AsmArgs& A, int64_t i, const
   L.phi = A.phis ? A.phis[i] : A.phi;
 }
 
+// The 3-D load of load_particle without the stencil's rows (L.row is left
+// unset), for kernels that evaluate the stress only: the z-layers are taken
+// one at a time in a loop, so at most one layer's nine node-map and 27
+// increment loads are in flight and the register budget leaves room for a
+// second wave per SIMD.  Same sums in the same order as load_particle<3>.
+__device__ __forceinline__ void load_particle3_lean(const AsmArgs& A, int64_t i, const double* __restrict__ du,
+                                                    PLoad<3>& L) {
+  const SimDev& S = A.sims[A.psim[i]];
+  make_stencil<3>(S, A.xs, A.np, i, L.st);
+  double w0[3], w1[3], d0[3], d1[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) { w0[a] = L.st.w[0][a]; w1[a] = L.st.w[1][a]; d0[a] = L.st.dw[0][a]; d1[a] = L.st.dw[1][a]; }
+  double dF[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dF[r][c] = (r == c) ? 1.0 : 0.0;
+  const int nd = A.nd;
+  const int64_t sy = S.nna[0], sz = (int64_t)S.nna[0] * S.nna[1];
+  const int64_t base = S.node_base + (L.st.o[0] + 1) + sy * (L.st.o[1] + 1) + sz * (L.st.o[2] + 1);
+  const double wz3[3] = {L.st.w[2][0], L.st.w[2][1], L.st.w[2][2]};
+  const double dz3[3] = {L.st.dw[2][0], L.st.dw[2][1], L.st.dw[2][2]};
+#pragma unroll 1
+  for (int az = 0; az < 3; ++az) {
+    const double wz = az == 0 ? wz3[0] : (az == 1 ? wz3[1] : wz3[2]);
+    const double dwz = az == 0 ? dz3[0] : (az == 1 ? dz3[1] : dz3[2]);
+    int32_t rr[9];
+#pragma unroll
+    for (int a9 = 0; a9 < 9; ++a9) rr[a9] = A.node_map[base + sz * az + (a9 % 3) + sy * (a9 / 3)];
+    double uu[9][3];
+#pragma unroll
+    for (int a9 = 0; a9 < 9; ++a9)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) uu[a9][q] = du[(int64_t)rr[a9] * nd + q];
+#pragma unroll
+    for (int a9 = 0; a9 < 9; ++a9) {
+      const int ax = a9 % 3, ay = a9 / 3;
+      const double g0 = d0[ax] * w1[ay] * wz, g1 = w0[ax] * d1[ay] * wz, g2 = w0[ax] * w1[ay] * dwz;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        dF[q][0] += uu[a9][q] * g0;
+        dF[q][1] += uu[a9][q] * g1;
+        dF[q][2] += uu[a9][q] * g2;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) L.dF[r][c] = dF[r][c];
+  L.pp = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) L.gp[k] = 0.0;
+  L.v0 = A.vs[i];
+  L.Jn = 1.0;
+  L.E = A.Es ? A.Es[i] : A.E;
+  L.phi = A.phis ? A.phis[i] : A.phi;
+}
+
 __device__ __forceinline__ Sym2<double> load_be2(const AsmArgs& A, int64_t i) {
   return Sym2<double>{A.bes[0 * A.np + i], A.bes[1 * A.np + i], A.bes[2 * A.np + i], A.bes[3 * A.np + i]};
 }
@@ -693,7 +752,7 @@ __global__ void __launch_bounds__(TL3) k_tan3v(AsmArgs A, const double* __restri
   const int q = wl % 9;
   if (i >= A.np) return;
   PLoad<3> L;
-  load_particle<3>(A, i, du, L);
+  load_particle3_lean(A, i, du, L);
   Mat<dnum> m = make_mat<dnum>(dnum(L.E), A.nu, dnum(L.phi), A.c, A.psi, A.dp, A.match, A.apex_reg);
   Sym3<double> be = load_be3(A, i);
   dnum F[3][3];
@@ -1047,11 +1106,12 @@ __global__ void __launch_bounds__(64) k_p2g3c(int colour, int mode, const int64_
 constexpr int FG3 = 8;    // stencil groups per workgroup
 constexpr int FT3 = 64;   // threads (particles evaluated at a time)
 
-__global__ void __launch_bounds__(FT3) k_fint3c(AsmArgs A, const double* __restrict__ du, int colour,
+__global__ void __launch_bounds__(FT3) __attribute__((amdgpu_waves_per_eu(2))) k_fint3c(AsmArgs A, const double* __restrict__ du, int colour,
                                                 const int64_t* __restrict__ wstart, const int32_t* __restrict__ gstart,
                                                 double* __restrict__ fint, int32_t* __restrict__ flag) {
   __shared__ double sP[FT3][9];              // V0 P of the staged particles
   __shared__ double sW[FT3][3][2][3];        // per axis: weights, derivatives
+  __shared__ double sF[FG3 * 27][3];         // per (group, stencil node) task: its force so far
   __shared__ int32_t gp0[FG3], goff[FG3 + 1];
   __shared__ int32_t gox[FG3], goy[FG3], goz[FG3];
   const int64_t w = blockIdx.x;
@@ -1083,11 +1143,11 @@ __global__ void __launch_bounds__(FT3) k_fint3c(AsmArgs A, const double* __restr
   __syncthreads();
   const int ntot = goff[FG3];
   if (ntot == 0) return;   // uniform
-  // tasks: (group k, stencil node a), FG3 * 27 = 216 of them over 64 threads
+  // tasks: (group k, stencil node a), FG3 * 27 = 216 of them over 64 threads;
+  // their sums live in LDS between chunks (no registers held across the
+  // stress evaluation)
   constexpr int NTK = (FG3 * 27 + FT3 - 1) / FT3;
-  double f[NTK][3];
-#pragma unroll
-  for (int j = 0; j < NTK; ++j) f[j][0] = f[j][1] = f[j][2] = 0.0;
+  for (int e = t; e < FG3 * 27 * 3; e += FT3) (&sF[0][0])[e] = 0.0;
   int rerr = 0;
   for (int c0 = 0; c0 < ntot; c0 += FT3) {
     const int nc = min(FT3, ntot - c0);
@@ -1098,7 +1158,7 @@ __global__ void __launch_bounds__(FT3) k_fint3c(AsmArgs A, const double* __restr
       for (int u = 1; u < FG3; ++u) k += gpos >= goff[u];
       const int64_t i = gp0[k] + (gpos - goff[k]);
       PLoad<3> L;
-      load_particle<3>(A, i, du, L);
+      load_particle3_lean(A, i, du, L);
       Mat<double> m = make_mat<double>(L.E, A.nu, L.phi, A.c, A.psi, A.dp, A.match, A.apex_reg);
       Out3<double> o;
       mech3<double>(m, L.dF, load_be3(A, i), o, nullptr, &rerr);
@@ -1119,15 +1179,20 @@ __global__ void __launch_bounds__(FT3) k_fint3c(AsmArgs A, const double* __restr
       const int k = tk / 27, a = tk % 27;
       const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
       const int kb = max(goff[k], c0) - c0, ke = min(goff[k + 1], c0 + nc) - c0;
+      if (kb >= ke) continue;
+      double f0 = sF[tk][0], f1 = sF[tk][1], f2 = sF[tk][2];
       for (int p = kb; p < ke; ++p) {
         const double ga0 = sW[p][0][1][ax] * sW[p][1][0][ay] * sW[p][2][0][az];
         const double ga1 = sW[p][0][0][ax] * sW[p][1][1][ay] * sW[p][2][0][az];
         const double ga2 = sW[p][0][0][ax] * sW[p][1][0][ay] * sW[p][2][1][az];
         const double* P = sP[p];
-        f[j][0] += P[0] * ga0 + P[1] * ga1 + P[2] * ga2;
-        f[j][1] += P[3] * ga0 + P[4] * ga1 + P[5] * ga2;
-        f[j][2] += P[6] * ga0 + P[7] * ga1 + P[8] * ga2;
+        f0 += P[0] * ga0 + P[1] * ga1 + P[2] * ga2;
+        f1 += P[3] * ga0 + P[4] * ga1 + P[5] * ga2;
+        f2 += P[6] * ga0 + P[7] * ga1 + P[8] * ga2;
       }
+      sF[tk][0] = f0;   // task tk belongs to this thread alone
+      sF[tk][1] = f1;
+      sF[tk][2] = f2;
     }
     __syncthreads();   // the staged particles are consumed
   }
@@ -1142,9 +1207,9 @@ __global__ void __launch_bounds__(FT3) k_fint3c(AsmArgs A, const double* __restr
     const int32_t ra = A.node_map[S.node_base + (gox[k] + ax + 1) +
                                   (int64_t)S.nna[0] * ((goy[k] + ay + 1) + (int64_t)S.nna[1] * (goz[k] + az + 1))];
     double* fo = fint + (int64_t)ra * 3;
-    fo[0] += f[j][0];   // one writer per node in this colour
-    fo[1] += f[j][1];
-    fo[2] += f[j][2];
+    fo[0] += sF[tk][0];   // one writer per node in this colour
+    fo[1] += sF[tk][1];
+    fo[2] += sF[tk][2];
   }
 }
 
