@@ -726,8 +726,10 @@ constexpr int GP3 = 64;   // particles (threads) per workgroup in 3-D
 // x.  At step ox the nine groups (ox, iy - ly, iz - lz), ly, lz in 0..2, are
 // the only ones holding rows ox .. ox+2 of the line; their particles' tangent
 // records are staged in LDS beside their stencil weights (evaluated there:
-// the x-axis weights and derivatives and the yz products of the other two
-// axes, so that stencil node b = (bx, by, bz) has the gradient
+// the weights and derivatives per axis; a lane forms the yz products
+// P0[by,bz] = wy[by] wz[bz], P1 = dwy[by] wz[bz], P2 = wy[by] dwz[bz] itself,
+// which reads 12 staged values instead of 27, so that stencil node
+// b = (bx, by, bz) has the gradient
 //   g_b = (dwx[bx] P0[by,bz], wx[bx] P1[by,bz], wx[bx] P2[by,bz])),
 // every (group, row, r, c) lane contracts its group's particles into the 27
 // blocks of its row, the nine groups' partial blocks meet in LDS and are
@@ -740,7 +742,7 @@ constexpr int GP3 = 64;   // particles (threads) per workgroup in 3-D
 // Origins of colour (cx, cy, cz) along one axis: v = o + 1 in [0, n] with v = c mod 3.
 __device__ __host__ __forceinline__ int colour_count(int n, int c) { return c > n ? 0 : (n - c) / 3 + 1; }
 
-constexpr int PW3 = 33;    // staged stencil data per particle: wx 0..2, dwx 3..5, P0 6..14, P1 15..23, P2 24..32
+constexpr int PW3 = 18;    // staged stencil data per particle: w, dw per axis (x 0..5, y 6..11, z 12..17)
 constexpr int TL3 = 256;   // k_tan3v threads: 4 waves of 7 particles x 9 directions (63 of 64 lanes)
 constexpr int TP3 = 28;    // particles per k_tan3v workgroup
 
@@ -786,6 +788,24 @@ static_assert(JL_IT * JL_T >= 375, "every (slot, offset) item has an owner");
 
 __device__ __forceinline__ int imod3(int v) { return ((v % 3) + 3) % 3; }
 
+// Owned accumulator items (slot sl of the three rows in flight, offset d of
+// the 5^3 neighbourhood) in an order that keeps the work of a wave uniform:
+// the 25 (dy, dz) layers by the number of the nine groups that can hold both
+// nodes ((3 - |dy|)(3 - |dz|): 9, then 6, 4, 3, 2, 1), 15 items (sl, dx) each.
+// Thread t owns position 64 c + (t mod 64) for chunk c = t / 64 (h = 0) and
+// c = 7 - t / 64 (h = 1), so the wave with the nine-group layer gets no
+// second chunk.  Returns the item sl * 125 + d, or -1.
+__device__ __forceinline__ int jl_item(int t, int h) {
+  constexpr int8_t LDY[25] = {0, 0, 0, -1, 1, -1, -1, 1, 1, 0, 0, -2, 2, -1, -1, 1, 1, -2, -2, 2, 2, -2, -2, 2, 2};
+  constexpr int8_t LDZ[25] = {0, -1, 1, 0, 0, -1, 1, -1, 1, -2, 2, 0, 0, -2, 2, -2, 2, -1, 1, -1, 1, -2, 2, -2, 2};
+  const int w = t >> 6, chunk = h == 0 ? w : 7 - w;
+  const int pos = chunk * 64 + (t & 63);
+  if (pos >= 375) return -1;
+  const int layer = pos / 15, within = pos - layer * 15;
+  const int sl = within / 5, dx = within - sl * 5 - 2;
+  return sl * 125 + (dx + 2) + 5 * (LDY[layer] + 2) + 25 * (LDZ[layer] + 2);
+}
+
 // Particle range [a, b) of group k of sweep step ox: origin (ox, iy - k % 3, iz - k / 3).
 __device__ __forceinline__ void line_group_range(const SimDev& S, const int32_t* __restrict__ gstart, int ox, int iy,
                                                  int iz, int k, int& a, int& b) {
@@ -800,10 +820,10 @@ __device__ __forceinline__ void line_group_range(const SimDev& S, const int32_t*
 }
 
 // The three rows in flight live in registers: thread t owns the 3x3 blocks
-// of (slot, offset) items t and t + 256 of the 3 x 125 (slot imod3(ix) of
-// row ix, offset d of the 5^3 neighbourhood), adds the nine groups' partials
-// to them in group order after every step, and writes the finished row's
-// blocks itself.  Each step loads nothing that it waits for at once except
+// of two of the 3 x 125 (slot, offset) items (slot imod3(ix) of row ix,
+// offset d of the 5^3 neighbourhood; jl_item), adds the nine groups'
+// partials to them in group order after every step, and writes the finished
+// row's blocks itself.  Each step loads nothing that it waits for at once except
 // the records it stages: the next step's group ranges and the finished row's
 // slots and Dirichlet codes are loaded a step ahead, or at the step's start
 // and used at its end.
@@ -850,7 +870,7 @@ __global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restric
   }
   const bool lane = t < 243;
   const int c = t % 3, r = (t / 3) % 3, la_x = (t / 9) % 3, q = t / 27;
-  const int yz = (q % 3) * 3 + q / 3;   // (ly, lz) of group q as a yz-product index
+  const int ly = q % 3, lz = q / 3;   // row node's place in group q's stencil along y and z
   // owned accumulator items: slot sl, offset d
   double racc[JL_IT][9];
 #pragma unroll
@@ -878,8 +898,8 @@ __global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restric
       frp = rowptr[frow];
 #pragma unroll
       for (int h = 0; h < JL_IT; ++h) {
-        const int it = t + JL_T * h;
-        if (it < 375 && it / 125 == sl0) {
+        const int it = jl_item(t, h);
+        if (it >= 0 && it / 125 == sl0) {
           const int d = it - sl0 * 125;
           fsp[h] = slot[(int64_t)frow * 125 + d];
           if (bcode) fcode[h] = bcode[(int64_t)frow * 125 + d];
@@ -927,15 +947,9 @@ __global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restric
               make_stencil<3>(S, xs, np, p, st);
               double* W = sbuf + JL_CH * PT3 + k * PW3;
 #pragma unroll
-              for (int a = 0; a < 3; ++a) { W[a] = st.w[0][a]; W[3 + a] = st.dw[0][a]; }
+              for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
-              for (int by = 0; by < 3; ++by)
-#pragma unroll
-                for (int bz = 0; bz < 3; ++bz) {
-                  W[6 + by * 3 + bz] = st.w[1][by] * st.w[2][bz];
-                  W[15 + by * 3 + bz] = st.dw[1][by] * st.w[2][bz];
-                  W[24 + by * 3 + bz] = st.w[1][by] * st.dw[2][bz];
-                }
+                for (int a = 0; a < 3; ++a) { W[6 * ax + a] = st.w[ax][a]; W[6 * ax + 3 + a] = st.dw[ax][a]; }
             } else {
               const double* src = rec + (int64_t)(pmap ? pmap[p] : p) * PT3;
               double v[27];
@@ -951,12 +965,21 @@ __global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restric
             for (int k = kb; k < ke; ++k) {
               const double* T = sbuf + k * PT3 + (r * 3 + c) * 9;
               const double* R = sbuf + JL_CH * PT3 + k * PW3;
-              double wx[3], dwx[3];
+              double wx[3], dwx[3], wy[3], dwy[3], wz[3], dwz[3];
 #pragma unroll
-              for (int u = 0; u < 3; ++u) { wx[u] = R[u]; dwx[u] = R[3 + u]; }
+              for (int u = 0; u < 3; ++u) {
+                wx[u] = R[u]; dwx[u] = R[3 + u];
+                wy[u] = R[6 + u]; dwy[u] = R[9 + u];
+                wz[u] = R[12 + u]; dwz[u] = R[15 + u];
+              }
               const double wxa = la_x == 0 ? wx[0] : (la_x == 1 ? wx[1] : wx[2]);
               const double dwxa = la_x == 0 ? dwx[0] : (la_x == 1 ? dwx[1] : dwx[2]);
-              const double ga0 = dwxa * R[6 + yz], ga1 = wxa * R[15 + yz], ga2 = wxa * R[24 + yz];
+              // node a: (la_x, ly, lz) of the group's stencil, ly = q mod 3, lz = q / 3
+              const double wya = ly == 0 ? wy[0] : (ly == 1 ? wy[1] : wy[2]);
+              const double dwya = ly == 0 ? dwy[0] : (ly == 1 ? dwy[1] : dwy[2]);
+              const double wza = lz == 0 ? wz[0] : (lz == 1 ? wz[1] : wz[2]);
+              const double dwza = lz == 0 ? dwz[0] : (lz == 1 ? dwz[1] : dwz[2]);
+              const double ga0 = dwxa * (wya * wza), ga1 = wxa * (dwya * wza), ga2 = wxa * (wya * dwza);
               double ta[3];
 #pragma unroll
               for (int jj = 0; jj < 3; ++jj) ta[jj] = fma(ga0, T[jj], fma(ga1, T[3 + jj], ga2 * T[6 + jj]));
@@ -965,8 +988,8 @@ __global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restric
               for (int bx = 0; bx < 3; ++bx) { u0[bx] = ta[0] * dwx[bx]; u1[bx] = ta[1] * wx[bx]; u2[bx] = ta[2] * wx[bx]; }
 #pragma unroll
               for (int byz = 0; byz < 9; ++byz) {
-                const double p0 = R[6 + byz], p1 = R[15 + byz], p2 = R[24 + byz];
                 const int by = byz / 3, bz = byz % 3;
+                const double p0 = wy[by] * wz[bz], p1 = dwy[by] * wz[bz], p2 = wy[by] * dwz[bz];
 #pragma unroll
                 for (int bx = 0; bx < 3; ++bx) {
                   const int b = bx + 3 * by + 9 * bz;
@@ -982,11 +1005,13 @@ __global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restric
           for (int b = 0; b < 27; ++b) sbuf[((q * 3 + la_x) * 27 + b) * 9 + r * 3 + c] = mine ? acc[b] : 0.0;
         }
         __syncthreads();
-        // owned items add the nine groups' partials in group order
+        // owned items add the nine groups' partials in group order, visiting
+        // only the groups that hold both nodes (the same count across most
+        // of a wave, by the item order)
 #pragma unroll
         for (int h = 0; h < JL_IT; ++h) {
-          const int it = t + JL_T * h;
-          if (it >= 375) continue;
+          const int it = jl_item(t, h);
+          if (it < 0) continue;
           const int sl = it / 125, d = it - sl * 125;
           const int lx = imod3(sl - ox);   // row ox + lx sits in slot sl
           const int dx = d % 5 - 2, dy = (d / 5) % 5 - 2, dz = d / 25 - 2;
@@ -995,15 +1020,14 @@ __global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restric
           double sum[9];
 #pragma unroll
           for (int e = 0; e < 9; ++e) sum[e] = 0.0;
-#pragma unroll
-          for (int qq = 0; qq < 9; ++qq) {
-            const int by = qq % 3 + dy, bz = qq / 3 + dz;
-            if (by >= 0 && by <= 2 && bz >= 0 && bz <= 2) {
-              const double* src = sbuf + ((qq * 3 + lx) * 27 + bx + 3 * by + 9 * bz) * 9;
+          const int qy0 = max(0, -dy), qy1 = min(2, 2 - dy), qz0 = max(0, -dz), qz1 = min(2, 2 - dz);
+          for (int qz = qz0; qz <= qz1; ++qz)
+            for (int qy = qy0; qy <= qy1; ++qy) {
+              const int qq = qy + 3 * qz;
+              const double* src = sbuf + ((qq * 3 + lx) * 27 + bx + 3 * (qy + dy) + 9 * (qz + dz)) * 9;
 #pragma unroll
               for (int e = 0; e < 9; ++e) sum[e] += src[e];
             }
-          }
 #pragma unroll
           for (int e = 0; e < 9; ++e) racc[h][e] += sum[e];
         }
@@ -1014,8 +1038,8 @@ __global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restric
     if (ox >= x0 && ox < x1) {
 #pragma unroll
       for (int h = 0; h < JL_IT; ++h) {
-        const int it = t + JL_T * h;
-        if (it >= 375 || it / 125 != sl0) continue;
+        const int it = jl_item(t, h);
+        if (it < 0 || it / 125 != sl0) continue;
         const int d = it - sl0 * 125;
         if (frow >= 0 && fsp[h] >= 0) {
           double* blk = val + (frp + fsp[h]) * 9;
