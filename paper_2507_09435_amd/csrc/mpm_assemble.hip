@@ -719,18 +719,19 @@ constexpr int GP3 = 64;   // particles (threads) per workgroup in 3-D
 //
 // k_tan3v: nine lanes per particle, lane q = 3c + j carrying the direction
 // dF_cj, write the particle's tangent record: V0 dP_ri/dF_cj at
-// [(r*3 + c)*9 + i*3 + j].
+// [(r*3 + c)*9 + i*3 + j], then its stencil's weights and derivatives per
+// axis (evaluated once here instead of at every staging below).
 //
 // k_jac3_lines: one workgroup owns a segment of JL_SEG consecutive rows of one
 // x-line of nodes (fixed iy, iz) and sweeps the stencil-group origins ox along
 // x.  At step ox the nine groups (ox, iy - ly, iz - lz), ly, lz in 0..2, are
 // the only ones holding rows ox .. ox+2 of the line; their particles' tangent
-// records are staged in LDS beside their stencil weights (evaluated there:
-// the weights and derivatives per axis; a lane forms the yz products
-// P0[by,bz] = wy[by] wz[bz], P1 = dwy[by] wz[bz], P2 = wy[by] dwz[bz] itself,
-// which reads 12 staged values instead of 27, so that stencil node
-// b = (bx, by, bz) has the gradient
-//   g_b = (dwx[bx] P0[by,bz], wx[bx] P1[by,bz], wx[bx] P2[by,bz])),
+// records (table, then the stencil's weights and derivatives per axis) are
+// staged in LDS; a lane forms the yz products P0[by,bz] = wy[by] wz[bz],
+// P1 = dwy[by] wz[bz], P2 = wy[by] dwz[bz] itself, which reads 12 staged
+// values instead of 27, so that stencil node b = (bx, by, bz) has the
+// gradient
+//   g_b = (dwx[bx] P0[by,bz], wx[bx] P1[by,bz], wx[bx] P2[by,bz]),
 // every (group, row, r, c) lane contracts its group's particles into the 27
 // blocks of its row, the nine groups' partial blocks meet in LDS and are
 // added to the rows' accumulators in a fixed group order, and row ox, which
@@ -742,7 +743,6 @@ constexpr int GP3 = 64;   // particles (threads) per workgroup in 3-D
 // Origins of colour (cx, cy, cz) along one axis: v = o + 1 in [0, n] with v = c mod 3.
 __device__ __host__ __forceinline__ int colour_count(int n, int c) { return c > n ? 0 : (n - c) / 3 + 1; }
 
-constexpr int PW3 = 18;    // staged stencil data per particle: w, dw per axis (x 0..5, y 6..11, z 12..17)
 constexpr int TL3 = 256;   // k_tan3v threads: 4 waves of 7 particles x 9 directions (63 of 64 lanes)
 constexpr int TP3 = 28;    // particles per k_tan3v workgroup
 
@@ -769,18 +769,24 @@ __global__ void __launch_bounds__(TL3) k_tan3v(AsmArgs A, const double* __restri
   int rerr = 0;
   mech3<dnum>(m, F, bd, o, nullptr, &rerr);
   if (rerr) atomicOr(flag, 4);
-  double* R = rec + i * PT3;
+  double* R = rec + i * PTW3;
   const int c = q / 3, j = q % 3;
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int ii = 0; ii < 3; ++ii) R[(r * 3 + c) * 9 + ii * 3 + j] = L.v0 * o.P[r][ii].d;
+  // the stencil's weights and derivatives, two entries per lane
+#pragma unroll
+  for (int e = 0; e < 18; ++e) {
+    const int ax = e / 6, a = e % 3;
+    if (e / 2 == q) R[PT3 + e] = (e % 6) < 3 ? L.st.w[ax][a] : L.st.dw[ax][a];
+  }
 }
 
 constexpr int JL_T = 256;    // threads; lane t < 243 is (group q, row la_x, r, c), c fastest
 constexpr int JL_SEG = 12;   // rows of a line per workgroup (8: 59.2 ms, 12: 54.7, 16: 56.9, 32: 59.8, 64: 68.2 on the cube)
 constexpr int JL_CH = 72;    // records staged per chunk: a step's nine groups of eight particles
-constexpr int JL_BUF = JL_CH * (PT3 + PW3);   // staged records and stencil data; then the partial blocks
+constexpr int JL_BUF = JL_CH * PTW3;         // staged records (table and stencil data); then the partial blocks
 constexpr int JL_PART = 6561;                 // doubles of the nine groups' partial blocks (9 x 3 rows x 27 x 9)
 constexpr int JL_IT = 2;                      // accumulator blocks per thread: (slot, offset) items t, t + 256
 static_assert(JL_PART <= JL_BUF, "the partial blocks reuse the staging buffer");
@@ -831,14 +837,12 @@ __global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restric
                                                         const SimDev* __restrict__ sims,
                                                         const int32_t* __restrict__ gstart,
                                                         const int32_t* __restrict__ node_map,
-                                                        const double* __restrict__ xs, int64_t np,
                                                         const double* __restrict__ rec,
                                                         const int32_t* __restrict__ pmap,
                                                         const int32_t* __restrict__ rowptr,
                                                         const int8_t* __restrict__ slot,
                                                         const uint8_t* __restrict__ bcode, double* __restrict__ val) {
-  __shared__ double sbuf[JL_BUF];    // staged records [JL_CH][PT3] and stencil data [JL_CH][PW3]; then the
-                                     // nine groups' partial blocks
+  __shared__ double sbuf[JL_BUF];    // staged records [JL_CH][PTW3]; then the nine groups' partial blocks
   __shared__ int32_t rng[2][9][2];   // group ranges of this step and the next: first particle, count
   __shared__ int32_t srow[JL_SEG];
   // Workgroups are dealt to the 8 XCDs in turn; XCD x takes the x-th
@@ -929,8 +933,8 @@ __global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restric
         for (int c0 = 0; c0 < ntot; c0 += JL_CH) {
           const int nc = min(JL_CH, ntot - c0);
           if (c0 > 0) __syncthreads();   // the previous chunk is consumed
-          // four threads per staged particle: one evaluates its stencil on this
-          // level, three copy its tangent record (JL_CH * 4 > JL_T: two rounds)
+          // four threads per staged particle copy its record, entries
+          // part + 4 m (JL_CH * 4 > JL_T: two rounds)
           for (int u4 = t; u4 < 4 * nc; u4 += JL_T) {
             const int k = u4 >> 2, part = u4 & 3;
             const int gpos = c0 + k;
@@ -942,29 +946,21 @@ __global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restric
             for (int u = 1; u < 9; ++u)
               if (qq == u) { gbase = g0[u]; gstart_q = goff[u]; }
             const int64_t p = gbase + gpos - gstart_q;
-            if (part == 0) {
-              Stencil<3> st;
-              make_stencil<3>(S, xs, np, p, st);
-              double* W = sbuf + JL_CH * PT3 + k * PW3;
+            const double* src = rec + (int64_t)(pmap ? pmap[p] : p) * PTW3;
+            constexpr int NM = (PTW3 + 3) / 4;   // 25: entries part + 4 m < PTW3
+            double v[NM];
 #pragma unroll
-              for (int ax = 0; ax < 3; ++ax)
+            for (int m = 0; m < NM; ++m) v[m] = (part + 4 * m < PTW3) ? src[part + 4 * m] : 0.0;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) { W[6 * ax + a] = st.w[ax][a]; W[6 * ax + 3 + a] = st.dw[ax][a]; }
-            } else {
-              const double* src = rec + (int64_t)(pmap ? pmap[p] : p) * PT3;
-              double v[27];
-#pragma unroll
-              for (int m = 0; m < 27; ++m) v[m] = src[(part - 1) + 3 * m];
-#pragma unroll
-              for (int m = 0; m < 27; ++m) sbuf[k * PT3 + (part - 1) + 3 * m] = v[m];
-            }
+            for (int m = 0; m < NM; ++m)
+              if (part + 4 * m < PTW3) sbuf[k * PTW3 + part + 4 * m] = v[m];
           }
           __syncthreads();
           if (mine) {
             const int kb = max(qb, c0) - c0, ke = min(qe, c0 + nc) - c0;
             for (int k = kb; k < ke; ++k) {
-              const double* T = sbuf + k * PT3 + (r * 3 + c) * 9;
-              const double* R = sbuf + JL_CH * PT3 + k * PW3;
+              const double* T = sbuf + k * PTW3 + (r * 3 + c) * 9;
+              const double* R = sbuf + k * PTW3 + PT3;
               double wx[3], dwx[3], wy[3], dwy[3], wz[3], dwz[3];
 #pragma unroll
               for (int u = 0; u < 3; ++u) {
@@ -1321,7 +1317,7 @@ __global__ void __launch_bounds__(FT3) k_jv3c(int colour, const int64_t* __restr
           }
         }
       }
-      const double* T = rec + i * PT3;
+      const double* T = rec + i * PTW3;
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -1670,12 +1666,12 @@ int launch_jac2_blocks(mpm_ctx* c, double* val, bool apply_bc) {
 // 3-D BSR blocks of context c from tangent records rec (indexed through pmap
 // when given: record pmap[p] belongs to c's sorted particle p).
 int launch_jac3_lines(mpm_ctx* c, const double* rec, const int32_t* pmap, double* val, bool apply_bc,
-                      const int32_t* gstart, const double* xs, int64_t np) {
+                      const int32_t* gstart) {
   const int64_t nwg = c->jl3_ws_h.empty() ? 0 : c->jl3_ws_h[c->nsim];
   if (nwg > 0 && c->n_row > 0) {
     k_jac3_lines<<<(unsigned)nwg, JL_T, 0, c->stream>>>(
-        c->jl3_ws.p, c->nsim, c->sims.p, gstart ? gstart : c->gstart.p, c->node_map.p, xs ? xs : c->xs.p,
-        np >= 0 ? np : c->np, rec, pmap, c->rowptr.p, c->slot.p, apply_bc ? c->bcode.p : nullptr, val);
+        c->jl3_ws.p, c->nsim, c->sims.p, gstart ? gstart : c->gstart.p, c->node_map.p, rec, pmap, c->rowptr.p,
+        c->slot.p, apply_bc ? c->bcode.p : nullptr, val);
     LAUNCH_CHECK(c, "k_jac3_lines");
   }
   return MPM_OK;
@@ -1707,7 +1703,7 @@ int launch_jacobian(mpm_ctx* c, const mpm_problem* pb, const double* du, double*
   if (c->dim == 3) {
     // tangent records, then the row segments of every x-line (each block written once)
     if (c->np > 0) {
-      if (c->pdat3.ensure(c->np * PT3) != hipSuccess)
+      if (c->pdat3.ensure(c->np * PTW3) != hipSuccess)
         return c->fail(MPM_E_NOMEM, "3-D tangent records allocation failed");
       k_tan3v<<<(unsigned)((c->np + TP3 - 1) / TP3), TL3, 0, c->stream>>>(A, du, c->pdat3.p, c->flag.p);
       LAUNCH_CHECK(c, "k_tan3v");
@@ -1753,7 +1749,7 @@ int launch_jv(mpm_ctx* c, const mpm_problem* pb, const double* du, bool records,
     }
   } else {
     if (records) {
-      if (c->pdat3.ensure(std::max<int64_t>(1, c->np) * PT3) != hipSuccess)
+      if (c->pdat3.ensure(std::max<int64_t>(1, c->np) * PTW3) != hipSuccess)
         return c->fail(MPM_E_NOMEM, "3-D tangent records allocation failed");
       if (c->np > 0) {
         k_tan3v<<<(unsigned)((c->np + TP3 - 1) / TP3), TL3, 0, c->stream>>>(A, du, c->pdat3.p, c->flag.p);

@@ -94,7 +94,9 @@ __device__ __forceinline__ int nb_index(int a, int b) {
 
 namespace mpm {
 constexpr int PD2 = 32;       // doubles per 2-D particle record: V0 T 0..15, wx 16..18, dwx 19..21, wy 22..24, dwy 25..27
-constexpr int PT3 = 81;       // doubles per 3-D tangent record: V0 dP_ri/dF_cj at (r * 3 + c) * 9 + i * 3 + j
+constexpr int PT3 = 81;       // 3-D tangent table: V0 dP_ri/dF_cj at (r * 3 + c) * 9 + i * 3 + j
+constexpr int PTW3 = 99;      // doubles per 3-D tangent record: the table, then per axis k the weights
+                              // at PT3 + 6 k + 0..2 and their derivatives at PT3 + 6 k + 3..5
 constexpr int PU2 = 64;       // doubles per u-p record: V0 T 0..48 (7x7), wx 49..51, dwx 52..54, wy 55..57, dwy 58..60
 constexpr int GB2 = 81 * 4;   // doubles per origin in the 2-D group-block buffer
 }  // namespace mpm
@@ -111,10 +113,10 @@ int launch_fint(mpm_ctx* c, const mpm_problem* pb, const double* du, double* rec
 int launch_residual(mpm_ctx* c, const mpm_problem* pb, const double* du, double* r, double* r_raw,
                     double* rec = nullptr);
 int launch_jacobian(mpm_ctx* c, const mpm_problem* pb, const double* du, double* val, bool apply_bc);
-// gstart, xs, np: particle ranges per origin, positions and count to use in
-// place of c's own (the quadrature particles of a multigrid level)
+// gstart: particle ranges per origin to use in place of c's own (the
+// quadrature particles of a multigrid level, whose records are in level order)
 int launch_jac3_lines(mpm_ctx* c, const double* rec, const int32_t* pmap, double* val, bool apply_bc,
-                      const int32_t* gstart = nullptr, const double* xs = nullptr, int64_t np = -1);
+                      const int32_t* gstart = nullptr);
 int launch_row_groups(mpm_ctx* c, const int32_t* gstart, int32_t* rgrp);
 int launch_jv(mpm_ctx* c, const mpm_problem* pb, const double* du, bool records, const double* x, double* y,
               bool apply_bc);

@@ -163,6 +163,24 @@ __global__ void k_mgup_qweights(int64_t npp, const double* __restrict__ pxs, con
   }
 }
 
+// 3-D quadrature particles: their level weights and derivatives per axis
+// (record entries PT3 .. PTW3 - 1), fixed for the prepare.
+__global__ void k_mg3_qweights(int64_t npp, const double* __restrict__ pxs, const int32_t* __restrict__ psim_q,
+                               const SimDev* __restrict__ sims, double* __restrict__ prec) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npp) return;
+  Stencil<3> st;
+  make_stencil<3>(sims[psim_q[i]], pxs, npp, i, st);
+  double* C = prec + i * PTW3 + PT3;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      C[6 * ax + a] = st.w[ax][a];
+      C[6 * ax + 3 + a] = st.dw[ax][a];
+    }
+}
+
 // Coarse full-grid mask from the next finer one (the fine node at the same
 // position, clamped into the fine grid).
 __global__ void k_mg3_mask(int64_t n_cnodes, int nsim, int dim, const SimDev* __restrict__ csims,
@@ -565,7 +583,7 @@ static int build_quadrature(mpm_ctx* c, MgLevel* L, int dim) {
   L->n_chunks = (int64_t)(ch.size() / 2);
   L->npp = npp;
   L->n_nek = (int64_t)nek.size();
-  const int stride = dim == 3 ? PT3 : PU2;
+  const int stride = dim == 3 ? PTW3 : PU2;
   const int nent = dim == 3 ? PT3 : 49;
   if (L->chunk.ensure(std::max<size_t>(2, ch.size())) != hipSuccess || L->key_chunk.ensure(nk + 1) != hipSuccess ||
       L->pg.ensure(nk + 1) != hipSuccess || L->nek.ensure(std::max<size_t>(1, nek.size())) != hipSuccess ||
@@ -592,6 +610,9 @@ static int build_quadrature(mpm_ctx* c, MgLevel* L, int dim) {
       k_mgup_qweights<<<nb256_3(npp), 256, 0, c->stream>>>(npp, L->pxs.p, L->qsim.p, sub->sims.p, L->prec.p);
       LAUNCH_CHECK(c, "k_mgup_qweights");
     }
+  } else if (npp) {
+    k_mg3_qweights<<<nb256_3(npp), 256, 0, c->stream>>>(npp, L->pxs.p, L->qsim.p, sub->sims.p, L->prec.p);
+    LAUNCH_CHECK(c, "k_mg3_qweights");
   }
   HIPC(c, hipStreamSynchronize(c->stream));   // the host tables above go out of scope
   return MPM_OK;
@@ -724,7 +745,7 @@ int mg3_setup(mpm_ctx* c) {
   for (MgLevel* L : c->mgl) {
     mpm_ctx* sub = L->sub;
     // quadrature particle tables: the finest tables summed per origin of this level
-    const int stride = c->up ? PU2 : PT3, nent = c->up ? 49 : PT3, ng = c->up ? 4 : 8;
+    const int stride = c->up ? PU2 : PTW3, nent = c->up ? 49 : PT3, ng = c->up ? 4 : 8;
     if (L->n_chunks) {
       k_mg3_chunk_sum<<<(unsigned)L->n_chunks, 128, 0, c->stream>>>(L->n_chunks, L->chunk.p, L->pmap.p,
                                                                    c->up ? c->pdat.p : c->pdat3.p, stride, nent,
@@ -737,7 +758,7 @@ int mg3_setup(mpm_ctx* c) {
       LAUNCH_CHECK(c, "k_mg3_qrec");
     }
     int rc = c->up ? launch_jac2up_records(sub, L->prec.p, sub->val.p, true, L->prgrp.p)
-                   : launch_jac3_lines(sub, L->prec.p, nullptr, sub->val.p, true, L->pg.p, L->pxs.p, L->npp);
+                   : launch_jac3_lines(sub, L->prec.p, nullptr, sub->val.p, true, L->pg.p);
     if (!rc) rc = launch_bj_inv(sub, sub->val.p);
     if (rc) return c->fail(rc, "multigrid level setup: " + sub->err);
   }
