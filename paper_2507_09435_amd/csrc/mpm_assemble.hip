@@ -784,7 +784,9 @@ __global__ void __launch_bounds__(TL3) k_tan3v(AsmArgs A, const double* __restri
 }
 
 constexpr int JL_T = 256;    // threads; lane t < 243 is (group q, row la_x, r, c), c fastest
-constexpr int JL_SEG = 12;   // rows of a line per workgroup (8: 59.2 ms, 12: 54.7, 16: 56.9, 32: 59.8, 64: 68.2 on the cube)
+constexpr int JL_SEG = 12;   // rows of a line per workgroup (cube Jacobian with its tangent records, ms:
+                             // 10: 43.0, 12: 40.2, 16: 42.0, 20: 40.5, 24: 40.9; LDS strides padded
+                             // against bank conflicts measured 40.9)
 constexpr int JL_CH = 72;    // records staged per chunk: a step's nine groups of eight particles
 constexpr int JL_BUF = JL_CH * PTW3;         // staged records (table and stencil data); then the partial blocks
 constexpr int JL_PART = 6561;                 // doubles of the nine groups' partial blocks (9 x 3 rows x 27 x 9)
