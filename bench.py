@@ -88,6 +88,9 @@ def main():
                     help="only the SpMV launches and a plain copy of known size, for counter passes")
     ap.add_argument("--workload", choices=["c3", "c2"], default="c3",
                     help="c3: the 128^3 footing cube (default); c2: the 256x128 plane-strain footing")
+    ap.add_argument("--peaks", action="store_true",
+                    help="only measure the chip's reachable peaks: HBM copy and triad bandwidth (torch), FP64 "
+                         "DGEMM throughput (the vendor BLAS on the FP64 matrix cores); one JSON line")
     ap.add_argument("--c3-probe", action="store_true",
                     help="the 128^3 footing cube: one residual, one Jacobian and timed BSR SpMV launches "
                          "(the HBM-bound regime of the SpMV), one JSON line")
@@ -116,6 +119,9 @@ def main():
         return
     if args.c3_probe:
         print(json.dumps(c3_probe(M, W, torch)))
+        return
+    if args.peaks:
+        print(json.dumps(peak_probe(torch)))
         return
 
     if args.workload == "c3":
@@ -511,6 +517,44 @@ def c3_probe(M, W, torch):
                      "timed_launches": nrep, "algorithmic_bytes_per_launch": nbytes,
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4)}}
+
+
+def peak_probe(torch):
+    """What the chip reaches outside this library, to set the measured
+    kernels against: a device-to-device copy and a triad a = b + s c over
+    2 GiB FP64 arrays (HBM bytes read + written per second), and an FP64
+    matrix product of order 8192 (2 n^3 flop per second; the vendor BLAS
+    runs it on the FP64 matrix cores, whose published peak equals the FP64
+    vector peak on this chip)."""
+    dev = "cuda"
+    n = (2 << 30) // 8
+    a = torch.empty(n, dtype=torch.float64, device=dev)
+    b = torch.rand(n, dtype=torch.float64, device=dev)
+    c = torch.rand(n, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    t_copy = timed(lambda: a.copy_(b), 20)
+    t_triad = timed(lambda: torch.add(b, c, alpha=1.5, out=a), 20)
+    m = 8192
+    A = torch.rand(m, m, dtype=torch.float64, device=dev)
+    B = torch.rand(m, m, dtype=torch.float64, device=dev)
+    C = torch.empty(m, m, dtype=torch.float64, device=dev)
+    t_gemm = timed(lambda: torch.matmul(A, B, out=C), 10)
+    return {"probe": "peaks", "hbm_copy_GBps": round(2 * 8 * n / t_copy / 1e9, 1),
+            "hbm_triad_GBps": round(3 * 8 * n / t_triad / 1e9, 1), "hbm_peak_GBps": HBM_PEAK_GBS,
+            "dgemm_TFlops": round(2 * m ** 3 / t_gemm / 1e12, 2), "fp64_peak_TFlops": 78.6,
+            "sizes": {"copy_triad_bytes_per_array": 8 * n, "dgemm_order": m}}
 
 
 def pmc_probe(M, W, torch, workload):
