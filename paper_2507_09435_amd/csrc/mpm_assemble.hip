@@ -727,19 +727,18 @@ constexpr int GP3 = 64;   // particles (threads) per workgroup in 3-D
 // x.  At step ox the nine groups (ox, iy - ly, iz - lz), ly, lz in 0..2, are
 // the only ones holding rows ox .. ox+2 of the line; their particles' tangent
 // records (table, then the stencil's weights and derivatives per axis) are
-// staged in LDS; a lane forms the yz products P0[by,bz] = wy[by] wz[bz],
-// P1 = dwy[by] wz[bz], P2 = wy[by] dwz[bz] itself, which reads 12 staged
-// values instead of 27, so that stencil node b = (bx, by, bz) has the
-// gradient
-//   g_b = (dwx[bx] P0[by,bz], wx[bx] P1[by,bz], wx[bx] P2[by,bz]),
+// staged in LDS; stencil node b = (bx, by, bz) has the gradient
+//   g_b = (dwx[bx] wy[by] wz[bz], wx[bx] dwy[by] wz[bz], wx[bx] wy[by] dwz[bz]),
+// and a lane forms ta . g_b as (u0 wy + u1 dwy) wz + (u2 wy) dwz with
+// u = (ta0 dwx, ta1 wx, ta2 wx), two FMAs per block entry,
 // every (group, row, r, c) lane contracts its group's particles into the 27
 // blocks of its row, the nine groups' partial blocks meet in LDS and are
 // added to the rows' accumulators in a fixed group order, and row ox, which
 // no later step touches, is written to its BSR row with the Dirichlet rows
 // and columns applied.  So the matrix needs no clearing, no colour passes and
 // no second pass for the boundary conditions, and the result does not depend
-// on the launch.  A multigrid level runs the same kernel on its own grid and
-// particle order, reading the finest level's tangent records through a map.
+// on the launch.  A multigrid level runs the same kernel on its own grid
+// over its quadrature particles' records.
 // Origins of colour (cx, cy, cz) along one axis: v = o + 1 in [0, n] with v = c mod 3.
 __device__ __host__ __forceinline__ int colour_count(int n, int c) { return c > n ? 0 : (n - c) / 3 + 1; }
 
@@ -970,13 +969,10 @@ __global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restric
                 wy[u] = R[6 + u]; dwy[u] = R[9 + u];
                 wz[u] = R[12 + u]; dwz[u] = R[15 + u];
               }
-              const double wxa = la_x == 0 ? wx[0] : (la_x == 1 ? wx[1] : wx[2]);
-              const double dwxa = la_x == 0 ? dwx[0] : (la_x == 1 ? dwx[1] : dwx[2]);
-              // node a: (la_x, ly, lz) of the group's stencil, ly = q mod 3, lz = q / 3
-              const double wya = ly == 0 ? wy[0] : (ly == 1 ? wy[1] : wy[2]);
-              const double dwya = ly == 0 ? dwy[0] : (ly == 1 ? dwy[1] : dwy[2]);
-              const double wza = lz == 0 ? wz[0] : (lz == 1 ? wz[1] : wz[2]);
-              const double dwza = lz == 0 ? dwz[0] : (lz == 1 ? dwz[1] : dwz[2]);
+              // node a: (la_x, ly, lz) of the group's stencil, ly = q mod 3,
+              // lz = q / 3; its weights read at lane-dependent addresses
+              const double wxa = R[la_x], dwxa = R[3 + la_x], wya = R[6 + ly], dwya = R[9 + ly],
+                           wza = R[12 + lz], dwza = R[15 + lz];
               const double ga0 = dwxa * (wya * wza), ga1 = wxa * (dwya * wza), ga2 = wxa * (wya * dwza);
               double ta[3];
 #pragma unroll
@@ -984,16 +980,18 @@ __global__ void __launch_bounds__(JL_T, 2) k_jac3_lines(const int64_t* __restric
               double u0[3], u1[3], u2[3];
 #pragma unroll
               for (int bx = 0; bx < 3; ++bx) { u0[bx] = ta[0] * dwx[bx]; u1[bx] = ta[1] * wx[bx]; u2[bx] = ta[2] * wx[bx]; }
+              // ta . g_b = (u0 wy + u1 dwy) wz + (u2 wy) dwz over (bx, by), bz
 #pragma unroll
-              for (int byz = 0; byz < 9; ++byz) {
-                const int by = byz / 3, bz = byz % 3;
-                const double p0 = wy[by] * wz[bz], p1 = dwy[by] * wz[bz], p2 = wy[by] * dwz[bz];
+              for (int by = 0; by < 3; ++by)
 #pragma unroll
                 for (int bx = 0; bx < 3; ++bx) {
-                  const int b = bx + 3 * by + 9 * bz;
-                  acc[b] = fma(u0[bx], p0, fma(u1[bx], p1, fma(u2[bx], p2, acc[b])));
+                  const double X = fma(u1[bx], dwy[by], u0[bx] * wy[by]), Y = u2[bx] * wy[by];
+#pragma unroll
+                  for (int bz = 0; bz < 3; ++bz) {
+                    const int b = bx + 3 * by + 9 * bz;
+                    acc[b] = fma(X, wz[bz], fma(Y, dwz[bz], acc[b]));
+                  }
                 }
-              }
             }
           }
         }
