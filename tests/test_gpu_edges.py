@@ -123,9 +123,13 @@ def test_particles_on_origin_switch_lines(ctx):
 
 # ------------------------------------------------------------ empty sims ---
 def _empty_like(w):
+    """w without particles (per-particle loads kept as empty arrays, so that
+    a batch keeps the other sims' loads)."""
     P = w.prob
     st = W.Particles(np.zeros((P.dim, 0)), np.zeros(0), np.zeros((P.dim * P.dim, 0)),
                      np.zeros((4 if P.dim == 2 else 6, 0)))
+    if w.particles.fp is not None:
+        st.fp = np.zeros((w.particles.fp.shape[0], 0))
     return W.Workload(P, st, w.n_steps, w.geostatic, w.walls, w.footing, w.p_drained)
 
 
@@ -189,6 +193,56 @@ def test_empty_sims_in_batch(ctx, method):
         print(f"  sim {k}: du rel err {e:.3e}", flush=True)
         assert e <= 1e-10
         off += pat.n_row
+
+
+@pytest.mark.parametrize("kind", ["cube", "up"])
+def test_empty_sims_under_3x3_multigrid(ctx, kind):
+    """Sims without particles around two sims of different size under the
+    3x3-block multigrid (3-D and u-p): the empty sims own no rows, get no
+    levels and converge at iteration 0 (their dense coarsest block is
+    empty), and each other sim's increment matches its own oracle Newton
+    solution."""
+    from paper_2507_09435_amd import mpm as M
+    print(f"[edge] empty sims under the 3x3-block multigrid, kind={kind}", flush=True)
+    if kind == "cube":
+        full = [W.make_c3(n=n, n_steps=1) for n in (8, 10)]
+        for w in full:
+            w.particles.phi = np.full(w.particles.np, np.radians(40.0))   # the geostatic state stays elastic
+        step = 0
+    else:
+        full = [W.make_c4(n=n, n_steps=1, width_cells=n, dt=1.0) for n in (12, 16)]
+        step = 1
+    ws = [_empty_like(full[0]), full[0], _empty_like(full[1]), full[1], _empty_like(full[0])]
+    dp = M.make_problem([(w.prob, w.particles) for w in ws], [w.bc(step) for w in ws])
+    n_row, nnzb, nd = M.mpm_prepare(ctx, dp)
+    du = torch.zeros(n_row * nd, dtype=torch.float64, device="cuda")
+    rep = M.mpm_newton_step(ctx, dp, du, tol=1e-12, max_iter=25, commit=False, krylov_rtol=1e-12, krylov_method=2)
+    torch.cuda.synchronize()
+    assert rep["converged"] and all(rep["sim_converged"]), rep
+    print(f"  newton {rep['iters']}  krylov {rep['krylov'][:rep['iters']]}", flush=True)
+    got = du.cpu().numpy().reshape(-1, nd)
+    off = 0
+    for k, w in enumerate(ws):
+        if w.particles.np == 0:
+            assert rep["sim_iters"][k] == 0
+            continue
+        bc = w.bc(step)
+        dof, orep, pat = O.newton(w.prob, w.particles, bc.mask, bc.value, tol=1e-12)
+        assert orep.converged
+        # bound widened only to 10x the oracle's own spread at its round-off floor
+        more, _, _ = O.newton(w.prob, w.particles, bc.mask, bc.value, tol=1e-30, stall_factor=0.0,
+                              maxit=orep.iters + 4, dof0_full=dof)
+        g, r, m = got[off:off + pat.n_row], dof[pat.active], more[pat.active]
+        if kind == "up":
+            e = max(rel_err(g[:, :2], r[:, :2]), rel_err(g[:, 2], r[:, 2]))
+            spread = max(rel_err(m[:, :2], r[:, :2]), rel_err(m[:, 2], r[:, 2]))
+        else:
+            e, spread = rel_err(g, r), rel_err(m, r)
+        b = max(1e-10, 10.0 * spread)
+        print(f"  sim {k}: du rel err {e:.3e} (bound {b:.1e})", flush=True)
+        assert e <= b
+        off += pat.n_row
+    assert off == n_row
 
 
 @pytest.mark.parametrize("method", [0, 2])
