@@ -124,7 +124,7 @@ void ctx_release(mpm_ctx* c) {
   c->colind.release(); c->slot.release(); c->rgrp.release(); c->bcode.release(); c->blocks.release(); c->blk_first.release(); c->flag.release();
   c->xs.release(); c->vol0s.release(); c->Fs.release(); c->bes.release(); c->Es.release(); c->phis.release();
   c->cmask.release(); c->rmask.release(); c->cval.release(); c->fext.release(); c->fint.release(); c->nvol.release();
-  c->work.release(); c->val.release(); c->dinv.release(); c->pdat.release(); c->pdat3.release(); c->jc3_ws.release(); c->jl3_ws.release(); c->jf3_ws.release(); c->gbuf.release(); c->rrec.release();
+  c->work.release(); c->val.release(); c->dinv.release(); c->pdat.release(); c->pdat3.release(); c->pdF3.release(); c->jc3_ws.release(); c->jl3_ws.release(); c->jf3_ws.release(); c->gbuf.release(); c->rrec.release();
   c->kx.release(); c->kr.release(); c->krh.release(); c->kp.release(); c->kv.release(); c->ks.release();
   c->kt.release(); c->kph.release(); c->ksh.release(); c->kb.release(); c->part.release(); c->simsc.release();
   c->simflag.release(); c->du_base.release(); c->alpha.release();

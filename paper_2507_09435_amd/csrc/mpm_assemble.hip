@@ -717,10 +717,14 @@ constexpr int GP3 = 64;   // particles (threads) per workgroup in 3-D
 
 // 3-D Jacobian, each 3x3 block written once.
 //
+// k_dF3: one thread per particle gathers du over its 27 nodes once: the
+// increment gradient dF [9][np] for k_tan3v, and the stencil's weights and
+// derivatives per axis into the tail of the particle's tangent record
+// (evaluated once here instead of at every staging below).
+//
 // k_tan3v: nine lanes per particle, lane q = 3c + j carrying the direction
-// dF_cj, write the particle's tangent record: V0 dP_ri/dF_cj at
-// [(r*3 + c)*9 + i*3 + j], then its stencil's weights and derivatives per
-// axis (evaluated once here instead of at every staging below).
+// dF_cj, read dF and write the particle's tangent table: V0 dP_ri/dF_cj at
+// [(r*3 + c)*9 + i*3 + j].
 //
 // k_jac3_lines: one workgroup owns a segment of JL_SEG consecutive rows of one
 // x-line of nodes (fixed iy, iz) and sweeps the stencil-group origins ox along
@@ -745,22 +749,41 @@ __device__ __host__ __forceinline__ int colour_count(int n, int c) { return c > 
 constexpr int TL3 = 256;   // k_tan3v threads: 4 waves of 7 particles x 9 directions (63 of 64 lanes)
 constexpr int TP3 = 28;    // particles per k_tan3v workgroup
 
-__global__ void __launch_bounds__(TL3) k_tan3v(AsmArgs A, const double* __restrict__ du, double* __restrict__ rec,
+__global__ void __launch_bounds__(256) k_dF3(AsmArgs A, const double* __restrict__ du, double* __restrict__ dF,
+                                             double* __restrict__ rec) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.np) return;
+  PLoad<3> L;
+  load_particle3_lean(A, i, du, L);
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dF[(r * 3 + c) * A.np + i] = L.dF[r][c];
+  double* W = rec + i * PTW3 + PT3;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      W[6 * ax + a] = L.st.w[ax][a];
+      W[6 * ax + 3 + a] = L.st.dw[ax][a];
+    }
+}
+
+__global__ void __launch_bounds__(TL3) k_tan3v(AsmArgs A, const double* __restrict__ dFs, double* __restrict__ rec,
                                                int32_t* __restrict__ flag) {
   const int wl = threadIdx.x % 64;
   if (wl >= 63) return;
   const int64_t i = (int64_t)blockIdx.x * TP3 + (threadIdx.x / 64) * 7 + wl / 9;
   const int q = wl % 9;
   if (i >= A.np) return;
-  PLoad<3> L;
-  load_particle3_lean(A, i, du, L);
-  Mat<dnum> m = make_mat<dnum>(dnum(L.E), A.nu, dnum(L.phi), A.c, A.psi, A.dp, A.match, A.apex_reg);
+  const double v0 = A.vs[i], E = A.Es ? A.Es[i] : A.E, phi = A.phis ? A.phis[i] : A.phi;
+  Mat<dnum> m = make_mat<dnum>(dnum(E), A.nu, dnum(phi), A.c, A.psi, A.dp, A.match, A.apex_reg);
   Sym3<double> be = load_be3(A, i);
   dnum F[3][3];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) F[r][c] = dnum(L.dF[r][c], q == r * 3 + c ? 1.0 : 0.0);
+    for (int c = 0; c < 3; ++c) F[r][c] = dnum(dFs[(r * 3 + c) * A.np + i], q == r * 3 + c ? 1.0 : 0.0);
   Sym3<dnum> bd;
 #pragma unroll
   for (int k = 0; k < 6; ++k) bd.a[k] = dnum(be.a[k]);
@@ -773,13 +796,7 @@ __global__ void __launch_bounds__(TL3) k_tan3v(AsmArgs A, const double* __restri
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int ii = 0; ii < 3; ++ii) R[(r * 3 + c) * 9 + ii * 3 + j] = L.v0 * o.P[r][ii].d;
-  // the stencil's weights and derivatives, two entries per lane
-#pragma unroll
-  for (int e = 0; e < 18; ++e) {
-    const int ax = e / 6, a = e % 3;
-    if (e / 2 == q) R[PT3 + e] = (e % 6) < 3 ? L.st.w[ax][a] : L.st.dw[ax][a];
-  }
+    for (int ii = 0; ii < 3; ++ii) R[(r * 3 + c) * 9 + ii * 3 + j] = v0 * o.P[r][ii].d;
 }
 
 constexpr int JL_T = 256;    // threads; lane t < 243 is (group q, row la_x, r, c), c fastest
@@ -1677,6 +1694,20 @@ int launch_jac3_lines(mpm_ctx* c, const double* rec, const int32_t* pmap, double
   return MPM_OK;
 }
 
+// 3-D tangent records at du into c->pdat3: the increment gradients and
+// stencil weights once per particle, then the nine forward-mode lanes.
+static int launch_tan3(mpm_ctx* c, const AsmArgs& A, const double* du) {
+  if (c->pdat3.ensure(std::max<int64_t>(1, c->np) * PTW3) != hipSuccess ||
+      c->pdF3.ensure(std::max<int64_t>(1, c->np) * 9) != hipSuccess)
+    return c->fail(MPM_E_NOMEM, "3-D tangent records allocation failed");
+  if (c->np == 0) return MPM_OK;
+  k_dF3<<<nb256(c->np), 256, 0, c->stream>>>(A, du, c->pdF3.p, c->pdat3.p);
+  LAUNCH_CHECK(c, "k_dF3");
+  k_tan3v<<<(unsigned)((c->np + TP3 - 1) / TP3), TL3, 0, c->stream>>>(A, c->pdF3.p, c->pdat3.p, c->flag.p);
+  LAUNCH_CHECK(c, "k_tan3v");
+  return MPM_OK;
+}
+
 int launch_jacobian(mpm_ctx* c, const mpm_problem* pb, const double* du, double* val, bool apply_bc) {
   AsmArgs A = make_args(c, pb);
   const int nd = c->nd;
@@ -1702,12 +1733,7 @@ int launch_jacobian(mpm_ctx* c, const mpm_problem* pb, const double* du, double*
   }
   if (c->dim == 3) {
     // tangent records, then the row segments of every x-line (each block written once)
-    if (c->np > 0) {
-      if (c->pdat3.ensure(c->np * PTW3) != hipSuccess)
-        return c->fail(MPM_E_NOMEM, "3-D tangent records allocation failed");
-      k_tan3v<<<(unsigned)((c->np + TP3 - 1) / TP3), TL3, 0, c->stream>>>(A, du, c->pdat3.p, c->flag.p);
-      LAUNCH_CHECK(c, "k_tan3v");
-    }
+    GUARD(launch_tan3(c, A, du));
     c->tan_ready = true;
     GUARD(launch_jac3_lines(c, c->pdat3.p, nullptr, val, apply_bc));
   }
@@ -1749,12 +1775,7 @@ int launch_jv(mpm_ctx* c, const mpm_problem* pb, const double* du, bool records,
     }
   } else {
     if (records) {
-      if (c->pdat3.ensure(std::max<int64_t>(1, c->np) * PTW3) != hipSuccess)
-        return c->fail(MPM_E_NOMEM, "3-D tangent records allocation failed");
-      if (c->np > 0) {
-        k_tan3v<<<(unsigned)((c->np + TP3 - 1) / TP3), TL3, 0, c->stream>>>(A, du, c->pdat3.p, c->flag.p);
-        LAUNCH_CHECK(c, "k_tan3v");
-      }
+      GUARD(launch_tan3(c, A, du));
       c->tan_ready = true;
     } else if (!c->tan_ready) {
       return c->fail(MPM_E_INVALID, "no tangent records of this prepare to reuse");

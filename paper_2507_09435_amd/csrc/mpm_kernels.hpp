@@ -142,6 +142,7 @@ struct mpm_ctx {
   mpm::DBuf<double> val, dinv;
   mpm::DBuf<double> pdat;                      // per-particle tangent records (2-D assembly)
   mpm::DBuf<double> pdat3;                     // per-particle tangent records (3-D assembly)
+  mpm::DBuf<double> pdF3;                      // 3-D increment gradients dF per particle [9][np]
   bool tan_ready = false;                      // pdat / pdat3 hold this prepare's tangent records
   mpm::DBuf<int64_t> jc3_ws;                   // 3-D colour passes: per colour and sim, first workgroup
   std::vector<int64_t> jc3_ws_h;               // host staging of jc3_ws
