@@ -207,8 +207,10 @@ typedef struct {
                              BiCGStab: plane-strain single-phase levels smoothed by damped
                              block-Jacobi and replayed from a captured HIP graph; 3-D and u-p
                              levels (3x3 blocks) smoothed by Chebyshev polynomials and launched
-                             eagerly; 3: as 2 with the plane-strain V-cycle launched kernel by
-                             kernel (same arithmetic) */
+                             eagerly, every sim of a batch coarsened to its own depth (its
+                             coarsest level as if solved alone) with its own spectral
+                             estimate; 3: as 2 with the plane-strain V-cycle launched kernel
+                             by kernel (same arithmetic) */
 } mpm_newton_opts;
 
 #define MPM_MAX_REPORT 32
