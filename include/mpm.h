@@ -205,12 +205,12 @@ typedef struct {
                              2: as 0, with a geometric multigrid V-cycle (coarse levels
                              rediscretized from the particles on grids of 2^l h) preconditioning
                              BiCGStab: plane-strain single-phase levels smoothed by damped
-                             block-Jacobi and replayed from a captured HIP graph; 3-D and u-p
-                             levels (3x3 blocks) smoothed by Chebyshev polynomials and launched
-                             eagerly, every sim of a batch coarsened to its own depth (its
-                             coarsest level as if solved alone) with its own spectral
-                             estimate; 3: as 2 with the plane-strain V-cycle launched kernel
-                             by kernel (same arithmetic) */
+                             block-Jacobi; 3-D and u-p levels (3x3 blocks) smoothed by
+                             Chebyshev polynomials, every sim of a batch coarsened to its own
+                             depth (its coarsest level as if solved alone) with its own
+                             spectral estimate; the V-cycle replayed from a captured HIP graph;
+                             3: as 2 with the V-cycle launched kernel by kernel (same
+                             arithmetic) */
 } mpm_newton_opts;
 
 #define MPM_MAX_REPORT 32

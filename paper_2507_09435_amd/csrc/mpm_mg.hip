@@ -1243,12 +1243,13 @@ void mg_drop_graphs(mpm_ctx* c) {
 // x = M^-1 b.  The V-cycle's launch sequence is fixed for a hierarchy and a
 // pair of vectors, so it is captured once into a HIP graph (on a private
 // stream: the caller's may be the null stream) and replayed with a single
-// launch; the kernels read the Krylov flags at run time.
+// launch; the kernels read the Krylov flags, the level matrices and (3x3
+// blocks) the Chebyshev coefficients at run time.
 int mg_vcycle(mpm_ctx* c, const double* b, double* x) {
-  if (c->dim == 3 || c->up) return mg3_vcycle(c, b, x);
+  const bool blk3 = c->dim == 3 || c->up;
   c->lstream = c->stream;
-  if (!c->mg_graph) return vcycle(c, 0, b, x);
-  const void* key[5] = {b, x, c->val.p, c->dinv.p, c->simflag.p};
+  if (!c->mg_graph) return blk3 ? mg3_vcycle(c, b, x) : vcycle(c, 0, b, x);
+  const void* key[5] = {b, x, c->val.p, c->dinv.p, blk3 ? (const void*)c->mg3_coef.p : (const void*)c->simflag.p};
   mpm_ctx::MgGraph* hit = nullptr;
   for (auto& g : c->mg_exec)
     if (g.exec && g.gen == c->mg_gen && std::equal(key, key + 5, g.key)) hit = &g;
@@ -1262,9 +1263,10 @@ int mg_vcycle(mpm_ctx* c, const double* b, double* x) {
     drop_graph(g);
     if (!c->cap_stream) HIPC(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     HIPC(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    c->lstream = c->cap_stream;
-    int rc = vcycle(c, 0, b, x);
-    c->lstream = c->stream;
+    const hipStream_t saved = c->stream;
+    c->lstream = c->stream = c->cap_stream;   // every launch of the cycle goes to the capture
+    int rc = blk3 ? mg3_vcycle(c, b, x) : vcycle(c, 0, b, x);
+    c->lstream = c->stream = saved;
     hipGraph_t graph = nullptr;
     hipError_t ec = hipStreamEndCapture(c->cap_stream, &graph);
     if (rc || ec != hipSuccess) {

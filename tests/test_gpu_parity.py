@@ -144,15 +144,25 @@ NEWTON_CASES = [("c1", 1, 0), ("footing", 0, 0), ("footing_elastic", 1, 0), ("up
                 ("up_column", 1, 2)]
 
 
-@pytest.mark.parametrize("name", ["footing_big", "batch"])
+@pytest.mark.parametrize("name", ["footing_big", "batch", "up", "cube"])
 def test_multigrid_graph_replays_match_eager(ctx, name):
     """BiCGStab with the V-cycle replayed from captured HIP graphs (method 2)
     and launched kernel by kernel (method 3) does the same arithmetic: the
     Newton increments, iteration counts and Krylov counts agree bit for bit,
     over every replay of both graphs within each solve, with the solver's
-    own launches and synchronizations between replays."""
+    own launches and synchronizations between replays.  Plane-strain
+    hierarchies (one sim, a batch) and 3x3-block ones (a u-p pair of
+    different depth, a 3-D pair)."""
     from paper_2507_09435_amd import mpm as M
-    if name == "batch":
+    step = 1
+    if name == "up":
+        ws = [W.make_c4(n=n, n_steps=1, width_cells=n, dt=1.0) for n in (16, 24)]
+    elif name == "cube":
+        ws = [W.make_c3(n=n, n_steps=1) for n in (8, 12)]
+        for w in ws:
+            w.particles.phi = np.full(w.particles.np, np.radians(40.0))   # the geostatic state stays elastic
+        step = 0
+    elif name == "batch":
         ws = [W.small_footing(n_y=k) for k in (12, 20, 16)]
         for k, w in enumerate(ws):
             w.prob.dp = 0
@@ -163,7 +173,7 @@ def test_multigrid_graph_replays_match_eager(ctx, name):
     outs = []
     for method in (3, 2, 2):
         print(f"[mg-graph] case={name} krylov_method={method}", flush=True)
-        dp = M.make_problem([(w.prob, w.particles) for w in ws], [w.bc(1) for w in ws],
+        dp = M.make_problem([(w.prob, w.particles) for w in ws], [w.bc(step) for w in ws],
                             react_masks=[react_mask(w) for w in ws])
         n_row, nnzb, nd = M.mpm_prepare(ctx, dp)
         du = torch.zeros(n_row * nd, dtype=torch.float64, device="cuda")
