@@ -260,6 +260,7 @@ def main():
                      "avg_launch_us_by_lanes_per_row": {str(k): round(v, 3) for k, v in by_shape.items()},
                      "in_loop_event_us": round(loop_ms * 1e3 / max(loop_n, 1), 3),
                      "algorithmic_bytes_per_launch": nbytes},
+        "assembly_roofline": assembly_roofline(npart, nd, ms_jac / max(n_jac, 1)),
         "matrix_free_jv": {"avg_us": round(jv_us, 3), "timed_calls": njv,
                            "vs_bsr_spmv": round(spmv_us / jv_us, 3),
                            "note": "y = J x from the per-particle tangent tables (no matrix), Dirichlet-modified"},
@@ -277,6 +278,23 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w, args.workload)
     M.mpm_destroy(ctx)
     print(json.dumps(out))
+
+
+FP64_PEAK_TFLOPS = 78.6
+
+
+def assembly_roofline(npart, nd, ms_jac):
+    """The Jacobian evaluation against the FP64 peak: the local-block
+    contraction of each particle, K_ab = sum_ij g_ai T_(r i)(c j) g_bj over
+    its 3^d x 3^d node pairs and nd^2 entries with d FMAs each once the
+    row side T g_a is formed (2 flop per FMA), per measured evaluation in
+    the Newton loop (tangent tables, stencil data and the block sweep)."""
+    nn = 3 ** nd
+    flop = 2.0 * nn * nn * nd * nd * nd
+    achieved = npart * flop / (ms_jac * 1e-3) / 1e12
+    return {"kernels": "Jacobian evaluation (increment gradients, tangent tables, block sweep)", "bound": "alu",
+            "flop_per_particle": flop, "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP64_PEAK_TFLOPS, 4)}
 
 
 def c2_extra(M, W, torch, ctx, stream, args, steps=5, warmup=1):
