@@ -777,7 +777,8 @@ __global__ void __launch_bounds__(TL3) k_tan3v(AsmArgs A, const double* __restri
   const int q = wl % 9;
   if (i >= A.np) return;
   const double v0 = A.vs[i], E = A.Es ? A.Es[i] : A.E, phi = A.phis ? A.phis[i] : A.phi;
-  Mat<dnum> m = make_mat<dnum>(dnum(E), A.nu, dnum(phi), A.c, A.psi, A.dp, A.match, A.apex_reg);
+  // the material constants carry no derivative here
+  const Mat<double> m = make_mat<double>(E, A.nu, phi, A.c, A.psi, A.dp, A.match, A.apex_reg);
   Sym3<double> be = load_be3(A, i);
   dnum F[3][3];
 #pragma unroll
@@ -789,7 +790,7 @@ __global__ void __launch_bounds__(TL3) k_tan3v(AsmArgs A, const double* __restri
   for (int k = 0; k < 6; ++k) bd.a[k] = dnum(be.a[k]);
   Out3<dnum> o;
   int rerr = 0;
-  mech3<dnum>(m, F, bd, o, nullptr, &rerr);
+  mech3<dnum, double>(m, F, bd, o, nullptr, &rerr);
   if (rerr) atomicOr(flag, 4);
   double* R = rec + i * PTW3;
   const int c = q / 3, j = q % 3;

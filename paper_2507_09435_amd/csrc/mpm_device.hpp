@@ -392,11 +392,14 @@ __device__ __forceinline__ Sym3<S> exp2eps3(const Sym3<S>& e) {
   return sum;
 }
 
-template <class S>
-__device__ __forceinline__ int stress3(const Mat<S>& m, const Sym3<S>& eps, Sym3<S>& tau, Sym3<S>& ee) {
+// MS: the scalar type of the material constants (plain double when only the
+// state carries derivatives, as in the tangent tables; S when the
+// derivatives with respect to E and the friction angle are wanted).
+template <class S, class MS = S>
+__device__ __forceinline__ int stress3(const Mat<MS>& m, const Sym3<S>& eps, Sym3<S>& tau, Sym3<S>& ee) {
   S trc = eps.a[0] + eps.a[1] + eps.a[2];
   S lt = m.lam * trc;
-  S g2 = 2.0 * m.G;
+  const MS g2 = 2.0 * m.G;
 #pragma unroll
   for (int t = 0; t < 6; ++t) tau.a[t] = g2 * eps.a[t];
 #pragma unroll
@@ -435,7 +438,8 @@ __device__ __forceinline__ int stress3(const Mat<S>& m, const Sym3<S>& eps, Sym3
     for (int t = 0; t < 6; ++t) s.a[t] = s.a[t] * 0.0;
     pn = m.xi * m.c / m.eta;
   }
-  S i2g = 0.5 / m.G, i3k = pn / (3.0 * m.K);
+  const MS i2g = 0.5 / m.G;
+  const S i3k = pn / (3.0 * m.K);
   const Sym3<S> ttr = tau;
 #pragma unroll
   for (int t = 0; t < 6; ++t) { tau.a[t] = s.a[t]; ee.a[t] = s.a[t] * i2g; }
@@ -505,9 +509,9 @@ __device__ __forceinline__ int mech2(const Mat<S>& m, const S F[2][2], const Sym
 template <class S>
 struct Out3 { S P[3][3]; };
 
-template <class S>
-__device__ __forceinline__ int mech3(const Mat<S>& m, const S F[3][3], const Sym3<S>& be, Out3<S>& o, Sym3<S>* be_out,
-                                     int* range_err) {
+template <class S, class MS = S>
+__device__ __forceinline__ int mech3(const Mat<MS>& m, const S F[3][3], const Sym3<S>& be, Out3<S>& o,
+                                     Sym3<S>* be_out, int* range_err) {
   S M[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -528,7 +532,7 @@ __device__ __forceinline__ int mech3(const Mat<S>& m, const S F[3][3], const Sym
 #pragma unroll
     for (int t = 0; t < 3; ++t) tau.a[t] = tau.a[t] - m.G + lj;
   } else {
-    reg = stress3(m, hencky3(bt, range_err), tau, ee);
+    reg = stress3<S, MS>(m, hencky3(bt, range_err), tau, ee);
   }
   // dF^-T = cofactor(dF) / det
   S cof[3][3];
