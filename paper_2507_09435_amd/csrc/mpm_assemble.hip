@@ -288,7 +288,8 @@ __global__ void __launch_bounds__(64) k_sim_sum_res(const int32_t* __restrict__ 
 template <int NIO>
 __device__ __forceinline__ void tangent2_col(const AsmArgs& A, const PLoad<2>& L, const Sym2<double>& be, int q,
                                              double Tc[NIO]) {
-  Mat<dnum> m = make_mat<dnum>(dnum(L.E), A.nu, dnum(L.phi), A.c, A.psi, A.dp, A.match, A.apex_reg);
+  // the material constants carry no derivative here
+  const Mat<double> m = make_mat<double>(L.E, A.nu, L.phi, A.c, A.psi, A.dp, A.match, A.apex_reg);
   UpPar u = up_par(A);
   dnum F[2][2];
 #pragma unroll
@@ -299,7 +300,7 @@ __device__ __forceinline__ void tangent2_col(const AsmArgs& A, const PLoad<2>& L
   dnum gp[2] = {dnum(L.gp[0], q == 5 ? 1.0 : 0.0), dnum(L.gp[1], q == 6 ? 1.0 : 0.0)};
   Sym2<dnum> bd{dnum(be.xx), dnum(be.yy), dnum(be.xy), dnum(be.zz)};
   Out2<dnum> o;
-  mech2<dnum>(m, F, bd, dnum(L.Jn), NIO == 7, u, pp, gp, o, nullptr);
+  mech2<dnum, double>(m, F, bd, dnum(L.Jn), NIO == 7, u, pp, gp, o, nullptr);
   Tc[0] = o.P[0][0].d; Tc[1] = o.P[0][1].d; Tc[2] = o.P[1][0].d; Tc[3] = o.P[1][1].d;
   if constexpr (NIO == 7) { Tc[4] = o.s1.d; Tc[5] = o.vv[0].d; Tc[6] = o.vv[1].d; }
 }

@@ -235,11 +235,12 @@ __device__ __forceinline__ Sym2<S> exp2eps2(const Sym2<S>& e) {
 // Hencky stress and Drucker-Prager return (perfect plasticity, tension
 // positive, p = tr(tau)/3, f = sqrt(J2) + eta p - xi c, potential
 // sqrt(J2) + etab p).  Returns 0 elastic, 1 cone, 2 apex.
-template <class S>
-__device__ __forceinline__ int stress2(const Mat<S>& m, const Sym2<S>& eps, Sym2<S>& tau, Sym2<S>& ee) {
+// MS: the scalar type of the material constants (see stress3).
+template <class S, class MS = S>
+__device__ __forceinline__ int stress2(const Mat<MS>& m, const Sym2<S>& eps, Sym2<S>& tau, Sym2<S>& ee) {
   S trc = eps.xx + eps.yy + eps.zz;
   S lt = m.lam * trc;
-  S g2 = 2.0 * m.G;
+  const MS g2 = 2.0 * m.G;
   tau.xx = lt + g2 * eps.xx; tau.yy = lt + g2 * eps.yy; tau.zz = lt + g2 * eps.zz; tau.xy = g2 * eps.xy;
   ee = eps;
   if (m.dp != 1) return 0;
@@ -273,7 +274,8 @@ __device__ __forceinline__ int stress2(const Mat<S>& m, const Sym2<S>& eps, Sym2
   }
   const Sym2<S> ttr = tau;
   tau.xx = s.xx + pn; tau.yy = s.yy + pn; tau.zz = s.zz + pn; tau.xy = s.xy;
-  S i2g = 0.5 / m.G, i3k = pn / (3.0 * m.K);
+  const MS i2g = 0.5 / m.G;
+  const S i3k = pn / (3.0 * m.K);
   ee.xx = s.xx * i2g + i3k; ee.yy = s.yy * i2g + i3k; ee.zz = s.zz * i2g + i3k; ee.xy = s.xy * i2g;
   if (reg == 2) {
     // zero exact tangent at the apex of a cohesionless cone: keep the value,
@@ -461,9 +463,9 @@ struct UpPar { double biot, mob, dt, rho_f, g[3]; };
 template <class S>
 struct Out2 { S P[2][2]; S s1; S vv[2]; };
 
-template <class S>
-__device__ __forceinline__ int mech2(const Mat<S>& m, const S F[2][2], const Sym2<S>& be, S Jn, int up, const UpPar& u,
-                                     S pp, const S gp[2], Out2<S>& o, Sym2<S>* be_out) {
+template <class S, class MS = S>
+__device__ __forceinline__ int mech2(const Mat<MS>& m, const S F[2][2], const Sym2<S>& be, S Jn, int up,
+                                     const UpPar& u, S pp, const S gp[2], Out2<S>& o, Sym2<S>* be_out) {
   S m00 = F[0][0] * be.xx + F[0][1] * be.xy, m01 = F[0][0] * be.xy + F[0][1] * be.yy;
   S m10 = F[1][0] * be.xx + F[1][1] * be.xy, m11 = F[1][0] * be.xy + F[1][1] * be.yy;
   Sym2<S> bt;
@@ -480,7 +482,7 @@ __device__ __forceinline__ int mech2(const Mat<S>& m, const S F[2][2], const Sym
     tau.xx = m.G * (bt.xx - 1.0) + lj; tau.yy = m.G * (bt.yy - 1.0) + lj;
     tau.zz = m.G * (bt.zz - 1.0) + lj; tau.xy = m.G * bt.xy;
   } else {
-    reg = stress2(m, hencky2(bt), tau, ee);
+    reg = stress2<S, MS>(m, hencky2(bt), tau, ee);
   }
   S det = F[0][0] * F[1][1] - F[0][1] * F[1][0];
   S idet = 1.0 / det;
