@@ -1142,7 +1142,7 @@ __global__ void __launch_bounds__(64) k_p2g3c(int colour, int mode, const int64_
 // time) and then adds each group's sum over its particles, in order, to each
 // of the group's 27 nodes with a plain read-modify-write.  Every particle is
 // evaluated once, and f_int is deterministic.
-constexpr int FG3 = 8;    // stencil groups per workgroup
+constexpr int FG3 = 7;    // stencil groups per workgroup (seven: one scatter task (group, x-node, y-node) per thread)
 constexpr int FT3 = 64;   // threads (particles evaluated at a time)
 
 __global__ void __launch_bounds__(FT3) __attribute__((amdgpu_waves_per_eu(2))) k_fint3c(AsmArgs A, const double* __restrict__ du, int colour,
@@ -1182,10 +1182,13 @@ __global__ void __launch_bounds__(FT3) __attribute__((amdgpu_waves_per_eu(2))) k
   __syncthreads();
   const int ntot = goff[FG3];
   if (ntot == 0) return;   // uniform
-  // tasks: (group k, stencil node a), FG3 * 27 = 216 of them over 64 threads;
-  // their sums live in LDS between chunks (no registers held across the
+  // scatter tasks: (group k, stencil x-node ax, y-node ay), FG3 * 9 of them,
+  // one per thread; each sums its three z-nodes with the weights factored as
+  //   P grad w_a = (P0 dwx wy + P1 wx dwy) wz + (P2 wx wy) dwz,
+  // and keeps the sums in LDS between chunks (no registers held across the
   // stress evaluation)
-  constexpr int NTK = (FG3 * 27 + FT3 - 1) / FT3;
+  static_assert(FG3 * 9 <= FT3, "one scatter task per thread");
+  constexpr int NTK = (FG3 * 27 + FT3 - 1) / FT3;   // (group, node) items per thread in the final write
   for (int e = t; e < FG3 * 27 * 3; e += FT3) (&sF[0][0])[e] = 0.0;
   int rerr = 0;
   for (int c0 = 0; c0 < ntot; c0 += FT3) {
@@ -1211,27 +1214,31 @@ __global__ void __launch_bounds__(FT3) __attribute__((amdgpu_waves_per_eu(2))) k
         for (int a = 0; a < 3; ++a) { sW[t][ax][0][a] = L.st.w[ax][a]; sW[t][ax][1][a] = L.st.dw[ax][a]; }
     }
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < NTK; ++j) {
-      const int tk = t + FT3 * j;
-      if (tk >= FG3 * 27) continue;
-      const int k = tk / 27, a = tk % 27;
-      const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
+    if (t < FG3 * 9) {
+      const int k = t / 9, axy = t - 9 * k, ax = axy % 3, ay = axy / 3;
       const int kb = max(goff[k], c0) - c0, ke = min(goff[k + 1], c0 + nc) - c0;
-      if (kb >= ke) continue;
-      double f0 = sF[tk][0], f1 = sF[tk][1], f2 = sF[tk][2];
-      for (int p = kb; p < ke; ++p) {
-        const double ga0 = sW[p][0][1][ax] * sW[p][1][0][ay] * sW[p][2][0][az];
-        const double ga1 = sW[p][0][0][ax] * sW[p][1][1][ay] * sW[p][2][0][az];
-        const double ga2 = sW[p][0][0][ax] * sW[p][1][0][ay] * sW[p][2][1][az];
-        const double* P = sP[p];
-        f0 += P[0] * ga0 + P[1] * ga1 + P[2] * ga2;
-        f1 += P[3] * ga0 + P[4] * ga1 + P[5] * ga2;
-        f2 += P[6] * ga0 + P[7] * ga1 + P[8] * ga2;
+      if (kb < ke) {
+        double f[3][3];   // [az][component]
+#pragma unroll
+        for (int az = 0; az < 3; ++az)
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) f[az][cc] = sF[k * 27 + ax + 3 * ay + 9 * az][cc];
+        for (int p = kb; p < ke; ++p) {
+          const double wxy0 = sW[p][0][1][ax] * sW[p][1][0][ay], wxy1 = sW[p][0][0][ax] * sW[p][1][1][ay],
+                       wxy2 = sW[p][0][0][ax] * sW[p][1][0][ay];
+          const double* P = sP[p];
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) {
+            const double X = fma(P[3 * cc + 1], wxy1, P[3 * cc] * wxy0), Y = P[3 * cc + 2] * wxy2;
+#pragma unroll
+            for (int az = 0; az < 3; ++az) f[az][cc] = fma(X, sW[p][2][0][az], fma(Y, sW[p][2][1][az], f[az][cc]));
+          }
+        }
+#pragma unroll
+        for (int az = 0; az < 3; ++az)
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) sF[k * 27 + ax + 3 * ay + 9 * az][cc] = f[az][cc];   // this thread's alone
       }
-      sF[tk][0] = f0;   // task tk belongs to this thread alone
-      sF[tk][1] = f1;
-      sF[tk][2] = f2;
     }
     __syncthreads();   // the staged particles are consumed
   }
