@@ -260,7 +260,7 @@ def main():
                      "avg_launch_us_by_lanes_per_row": {str(k): round(v, 3) for k, v in by_shape.items()},
                      "in_loop_event_us": round(loop_ms * 1e3 / max(loop_n, 1), 3),
                      "algorithmic_bytes_per_launch": nbytes},
-        "assembly_roofline": assembly_roofline(npart, nd, ms_jac / max(n_jac, 1)),
+        "assembly_roofline": assembly_roofline(npart, nd, ms_jac / max(n_jac, 1), args.workload),
         "matrix_free_jv": {"avg_us": round(jv_us, 3), "timed_calls": njv,
                            "vs_bsr_spmv": round(spmv_us / jv_us, 3),
                            "note": "y = J x from the per-particle tangent tables (no matrix), Dirichlet-modified"},
@@ -283,18 +283,39 @@ def main():
 FP64_PEAK_TFLOPS = 78.6
 
 
-def assembly_roofline(npart, nd, ms_jac):
+def jacobian_traffic(workload):
+    """HBM bytes per 3-D Jacobian evaluation on the cube (its three kernels),
+    from the committed counter passes (profiles/k_jac3_cube_pmc.md), or None
+    for another workload or when the assembly source has changed since."""
+    import hashlib
+    if workload != "c3":
+        return None
+    try:
+        text = open(os.path.join(ROOT, "profiles", "k_jac3_cube_pmc.md")).read()
+        code = open(os.path.join(ROOT, "paper_2507_09435_amd", "csrc", "mpm_assemble.hip")).read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines()
+                  if line.startswith(("traffic_", "assembly_source_sha1")))
+    if fields.get("assembly_source_sha1", "").strip() != hashlib.sha1(code.encode()).hexdigest():
+        return None
+    v = fields.get("traffic_bytes_per_jacobian")
+    return int(float(v)) if v else None
+
+
+def assembly_roofline(npart, nd, ms_jac, workload):
     """The Jacobian evaluation against the FP64 peak: the local-block
     contraction of each particle, K_ab = sum_ij g_ai T_(r i)(c j) g_bj over
     its 3^d x 3^d node pairs and nd^2 entries with d FMAs each once the
     row side T g_a is formed (2 flop per FMA), per measured evaluation in
-    the Newton loop (tangent tables, stencil data and the block sweep)."""
+    the Newton loop (tangent tables, stencil data and the block sweep).
+    traffic: counted HBM bytes of one evaluation, where measured."""
     nn = 3 ** nd
     flop = 2.0 * nn * nn * nd * nd * nd
     achieved = npart * flop / (ms_jac * 1e-3) / 1e12
     return {"kernels": "Jacobian evaluation (increment gradients, tangent tables, block sweep)", "bound": "alu",
             "flop_per_particle": flop, "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / FP64_PEAK_TFLOPS, 4)}
+            "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": jacobian_traffic(workload)}
 
 
 def c2_extra(M, W, torch, ctx, stream, args, steps=5, warmup=1):
