@@ -1171,7 +1171,7 @@ __global__ void __launch_bounds__(FT3) __attribute__((amdgpu_waves_per_eu(2))) k
   __shared__ double sP[FT3][9];              // V0 P of the staged particles
   __shared__ double sW[FT3][3][2][3];        // per axis: weights, derivatives
   __shared__ double sF[FG3 * 27][3];         // per (group, stencil node) task: its force so far
-  __shared__ int32_t gp0[FG3], goff[FG3 + 1];
+  __shared__ int32_t gp0[FG3], gcn[FG3], goff[FG3 + 1];
   __shared__ int32_t gox[FG3], goy[FG3], goz[FG3];
   const int64_t w = blockIdx.x;
   int s = 0;
@@ -1181,22 +1181,25 @@ __global__ void __launch_bounds__(FT3) __attribute__((amdgpu_waves_per_eu(2))) k
   const int nx = colour_count(S.n[0], cx), ny = colour_count(S.n[1], cy), nz = colour_count(S.n[2], cz);
   const int64_t ngr = (int64_t)nx * ny * nz;
   const int t = threadIdx.x;
+  if (t < FG3) {   // lane k finds group k's particles (all FG3 lookups in flight at once)
+    const int64_t g = (w - wstart[s]) * FG3 + t;
+    int a = 0, b = 0, ox = 0, oy = 0, oz = 0;
+    if (g < ngr) {
+      ox = cx + 3 * (int)(g % nx) - 1;
+      oy = cy + 3 * (int)((g / nx) % ny) - 1;
+      oz = cz + 3 * (int)(g / ((int64_t)nx * ny)) - 1;
+      const int64_t key = S.okey_base + (ox + 1) + (int64_t)S.noa[0] * ((oy + 1) + (int64_t)S.noa[1] * (oz + 1));
+      a = gstart[key];
+      b = gstart[key + 1];
+    }
+    gp0[t] = a; gcn[t] = b - a;
+    gox[t] = ox; goy[t] = oy; goz[t] = oz;
+  }
+  __syncthreads();
   if (t == 0) {
     int acc = 0;
-    for (int k = 0; k < FG3; ++k) {
-      const int64_t g = (w - wstart[s]) * FG3 + k;
-      int a = 0, b = 0, ox = 0, oy = 0, oz = 0;
-      if (g < ngr) {
-        ox = cx + 3 * (int)(g % nx) - 1;
-        oy = cy + 3 * (int)((g / nx) % ny) - 1;
-        oz = cz + 3 * (int)(g / ((int64_t)nx * ny)) - 1;
-        const int64_t key = S.okey_base + (ox + 1) + (int64_t)S.noa[0] * ((oy + 1) + (int64_t)S.noa[1] * (oz + 1));
-        a = gstart[key];
-        b = gstart[key + 1];
-      }
-      gp0[k] = a; goff[k] = acc; acc += b - a;
-      gox[k] = ox; goy[k] = oy; goz[k] = oz;
-    }
+#pragma unroll
+    for (int k = 0; k < FG3; ++k) { goff[k] = acc; acc += gcn[k]; }
     goff[FG3] = acc;
   }
   __syncthreads();
