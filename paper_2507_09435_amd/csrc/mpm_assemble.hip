@@ -1165,24 +1165,19 @@ __global__ void __launch_bounds__(64) k_p2g3c(int colour, int mode, const int64_
 constexpr int FG3 = 7;    // stencil groups per workgroup (seven: one scatter task (group, x-node, y-node) per thread)
 constexpr int FT3 = 64;   // threads (particles evaluated at a time)
 
-__global__ void __launch_bounds__(FT3) __attribute__((amdgpu_waves_per_eu(2))) k_fint3c(AsmArgs A, const double* __restrict__ du, int colour,
-                                                const int64_t* __restrict__ wstart, const int32_t* __restrict__ gstart,
-                                                double* __restrict__ fint, int32_t* __restrict__ flag) {
-  __shared__ double sP[FT3][9];              // V0 P of the staged particles
-  __shared__ double sW[FT3][3][2][3];        // per axis: weights, derivatives
-  __shared__ double sF[FG3 * 27][3];         // per (group, stencil node) task: its force so far
-  __shared__ int32_t gp0[FG3], gcn[FG3], goff[FG3 + 1];
-  __shared__ int32_t gox[FG3], goy[FG3], goz[FG3];
-  const int64_t w = blockIdx.x;
-  int s = 0;
-  while (s + 1 < A.nsim && wstart[s + 1] <= w) ++s;   // workgroup-uniform
-  const SimDev& S = A.sims[s];
+// The FG3 consecutive stencil groups (of one colour) that workgroup wl of a
+// sim takes: lane k < FG3 looks up group k's particle range, all lookups in
+// flight at once, then lane 0 forms the offsets goff (goff[FG3]: the
+// workgroup's particle count).  Groups past the colour's count are empty.
+// Ends with the workgroup synchronised.
+__device__ __forceinline__ void fg3_groups(const SimDev& S, const int32_t* __restrict__ gstart, int64_t wl,
+                                           int colour, int t, int32_t* gp0, int32_t* gcn, int32_t* goff,
+                                           int32_t* gox, int32_t* goy, int32_t* goz) {
   const int cx = colour % 3, cy = (colour / 3) % 3, cz = colour / 9;
   const int nx = colour_count(S.n[0], cx), ny = colour_count(S.n[1], cy), nz = colour_count(S.n[2], cz);
   const int64_t ngr = (int64_t)nx * ny * nz;
-  const int t = threadIdx.x;
-  if (t < FG3) {   // lane k finds group k's particles (all FG3 lookups in flight at once)
-    const int64_t g = (w - wstart[s]) * FG3 + t;
+  if (t < FG3) {
+    const int64_t g = wl * FG3 + t;
     int a = 0, b = 0, ox = 0, oy = 0, oz = 0;
     if (g < ngr) {
       ox = cx + 3 * (int)(g % nx) - 1;
@@ -1203,6 +1198,22 @@ __global__ void __launch_bounds__(FT3) __attribute__((amdgpu_waves_per_eu(2))) k
     goff[FG3] = acc;
   }
   __syncthreads();
+}
+
+__global__ void __launch_bounds__(FT3) __attribute__((amdgpu_waves_per_eu(2))) k_fint3c(AsmArgs A, const double* __restrict__ du, int colour,
+                                                const int64_t* __restrict__ wstart, const int32_t* __restrict__ gstart,
+                                                double* __restrict__ fint, int32_t* __restrict__ flag) {
+  __shared__ double sP[FT3][9];              // V0 P of the staged particles
+  __shared__ double sW[FT3][3][2][3];        // per axis: weights, derivatives
+  __shared__ double sF[FG3 * 27][3];         // per (group, stencil node) task: its force so far
+  __shared__ int32_t gp0[FG3], gcn[FG3], goff[FG3 + 1];
+  __shared__ int32_t gox[FG3], goy[FG3], goz[FG3];
+  const int64_t w = blockIdx.x;
+  int s = 0;
+  while (s + 1 < A.nsim && wstart[s + 1] <= w) ++s;   // workgroup-uniform
+  const SimDev& S = A.sims[s];
+  const int t = threadIdx.x;
+  fg3_groups(S, gstart, w - wstart[s], colour, t, gp0, gcn, goff, gox, goy, goz);
   const int ntot = goff[FG3];
   if (ntot == 0) return;   // uniform
   // scatter tasks: (group k, stencil x-node ax, y-node ay), FG3 * 9 of them,
@@ -1298,35 +1309,14 @@ __global__ void __launch_bounds__(FT3) k_jv3c(int colour, const int64_t* __restr
                                               double* __restrict__ y) {
   __shared__ double sP[FT3][9];
   __shared__ double sW[FT3][3][2][3];
-  __shared__ int32_t gp0[FG3], goff[FG3 + 1];
+  __shared__ int32_t gp0[FG3], gcn[FG3], goff[FG3 + 1];
   __shared__ int32_t gox[FG3], goy[FG3], goz[FG3];
   const int64_t w = blockIdx.x;
   int s = 0;
   while (s + 1 < nsim && wstart[s + 1] <= w) ++s;   // workgroup-uniform
   const SimDev& S = sims[s];
-  const int cx = colour % 3, cy = (colour / 3) % 3, cz = colour / 9;
-  const int nx = colour_count(S.n[0], cx), ny = colour_count(S.n[1], cy), nz = colour_count(S.n[2], cz);
-  const int64_t ngr = (int64_t)nx * ny * nz;
   const int t = threadIdx.x;
-  if (t == 0) {
-    int acc = 0;
-    for (int k = 0; k < FG3; ++k) {
-      const int64_t g = (w - wstart[s]) * FG3 + k;
-      int a = 0, b = 0, ox = 0, oy = 0, oz = 0;
-      if (g < ngr) {
-        ox = cx + 3 * (int)(g % nx) - 1;
-        oy = cy + 3 * (int)((g / nx) % ny) - 1;
-        oz = cz + 3 * (int)(g / ((int64_t)nx * ny)) - 1;
-        const int64_t key = S.okey_base + (ox + 1) + (int64_t)S.noa[0] * ((oy + 1) + (int64_t)S.noa[1] * (oz + 1));
-        a = gstart[key];
-        b = gstart[key + 1];
-      }
-      gp0[k] = a; goff[k] = acc; acc += b - a;
-      gox[k] = ox; goy[k] = oy; goz[k] = oz;
-    }
-    goff[FG3] = acc;
-  }
-  __syncthreads();
+  fg3_groups(S, gstart, w - wstart[s], colour, t, gp0, gcn, goff, gox, goy, goz);
   const int ntot = goff[FG3];
   if (ntot == 0) return;   // uniform
   constexpr int NTK = (FG3 * 27 + FT3 - 1) / FT3;
