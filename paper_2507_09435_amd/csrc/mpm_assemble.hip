@@ -782,43 +782,36 @@ __global__ void __launch_bounds__(256) k_dF3(AsmArgs A, const double* __restrict
 
 __global__ void __launch_bounds__(TL3) k_tan3v(AsmArgs A, const double* __restrict__ dFs, double* __restrict__ rec,
                                                int32_t* __restrict__ flag) {
-  // the workgroup's 28 tables are gathered in LDS and leave as one run of
-  // 81 doubles per particle
-  __shared__ double sT[TP3 * PT3];
+  // each lane writes its nine entries straight to the record: staging the
+  // tables in LDS behind a workgroup barrier measured slower in the Newton
+  // loop, where plastic returns make the waves' work uneven
   const int wl = threadIdx.x % 64;
-  const int lp = (threadIdx.x / 64) * 7 + wl / 9;
-  const int64_t p0 = (int64_t)blockIdx.x * TP3, i = p0 + lp;
+  if (wl >= 63) return;
+  const int64_t i = (int64_t)blockIdx.x * TP3 + (threadIdx.x / 64) * 7 + wl / 9;
   const int q = wl % 9;
-  if (wl < 63 && i < A.np) {
-    const double v0 = A.vs[i], E = A.Es ? A.Es[i] : A.E, phi = A.phis ? A.phis[i] : A.phi;
-    // the material constants carry no derivative here
-    const Mat<double> m = make_mat<double>(E, A.nu, phi, A.c, A.psi, A.dp, A.match, A.apex_reg);
-    Sym3<double> be = load_be3(A, i);
-    dnum F[3][3];
+  if (i >= A.np) return;
+  const double v0 = A.vs[i], E = A.Es ? A.Es[i] : A.E, phi = A.phis ? A.phis[i] : A.phi;
+  // the material constants carry no derivative here
+  const Mat<double> m = make_mat<double>(E, A.nu, phi, A.c, A.psi, A.dp, A.match, A.apex_reg);
+  Sym3<double> be = load_be3(A, i);
+  dnum F[3][3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
+  for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) F[r][c] = dnum(dFs[(r * 3 + c) * A.np + i], q == r * 3 + c ? 1.0 : 0.0);
-    Sym3<dnum> bd;
+    for (int c = 0; c < 3; ++c) F[r][c] = dnum(dFs[(r * 3 + c) * A.np + i], q == r * 3 + c ? 1.0 : 0.0);
+  Sym3<dnum> bd;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) bd.a[k] = dnum(be.a[k]);
-    Out3<dnum> o;
-    int rerr = 0;
-    mech3<dnum, double>(m, F, bd, o, nullptr, &rerr);
-    if (rerr) atomicOr(flag, 4);
-    double* R = sT + lp * PT3;
-    const int c = q / 3, j = q % 3;
+  for (int k = 0; k < 6; ++k) bd.a[k] = dnum(be.a[k]);
+  Out3<dnum> o;
+  int rerr = 0;
+  mech3<dnum, double>(m, F, bd, o, nullptr, &rerr);
+  if (rerr) atomicOr(flag, 4);
+  double* R = rec + i * PTW3;
+  const int c = q / 3, j = q % 3;
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
+  for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int ii = 0; ii < 3; ++ii) R[(r * 3 + c) * 9 + ii * 3 + j] = v0 * o.P[r][ii].d;
-  }
-  __syncthreads();
-  const int n = (int)min((int64_t)TP3, A.np - p0);
-  for (int e = threadIdx.x; e < n * PT3; e += TL3) {
-    const int p = e / PT3;
-    rec[(p0 + p) * PTW3 + (e - PT3 * p)] = sT[e];
-  }
+    for (int ii = 0; ii < 3; ++ii) R[(r * 3 + c) * 9 + ii * 3 + j] = v0 * o.P[r][ii].d;
 }
 
 constexpr int JL_T = 256;    // threads; lane t < 243 is (group q, row la_x, r, c), c fastest
