@@ -1216,6 +1216,22 @@ __global__ void __launch_bounds__(FT3) __attribute__((amdgpu_waves_per_eu(2))) k
   // stress evaluation)
   static_assert(FG3 * 9 <= FT3, "one scatter task per thread");
   constexpr int NTK = (FG3 * 27 + FT3 - 1) / FT3;   // (group, node) items per thread in the final write
+  // the rows of this thread's final-write items, fetched now so that their
+  // latency hides behind the stress evaluation (-1: no item)
+  int32_t rw[NTK];
+#pragma unroll
+  for (int j = 0; j < NTK; ++j) {
+    const int tk = t + FT3 * j;
+    rw[j] = -1;
+    if (tk < FG3 * 27) {
+      const int k = tk / 27, a = tk % 27;
+      if (goff[k + 1] != goff[k]) {   // an empty group's nodes may be inactive
+        const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
+        rw[j] = A.node_map[S.node_base + (gox[k] + ax + 1) +
+                           (int64_t)S.nna[0] * ((goy[k] + ay + 1) + (int64_t)S.nna[1] * (goz[k] + az + 1))];
+      }
+    }
+  }
   for (int e = t; e < FG3 * 27 * 3; e += FT3) (&sF[0][0])[e] = 0.0;
   int rerr = 0;
   for (int c0 = 0; c0 < ntot; c0 += FT3) {
@@ -1272,14 +1288,9 @@ __global__ void __launch_bounds__(FT3) __attribute__((amdgpu_waves_per_eu(2))) k
   if (rerr) atomicOr(flag, 4);
 #pragma unroll
   for (int j = 0; j < NTK; ++j) {
+    if (rw[j] < 0) continue;
     const int tk = t + FT3 * j;
-    if (tk >= FG3 * 27) continue;
-    const int k = tk / 27, a = tk % 27;
-    if (goff[k + 1] == goff[k]) continue;   // empty group: its nodes may be inactive
-    const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
-    const int32_t ra = A.node_map[S.node_base + (gox[k] + ax + 1) +
-                                  (int64_t)S.nna[0] * ((goy[k] + ay + 1) + (int64_t)S.nna[1] * (goz[k] + az + 1))];
-    double* fo = fint + (int64_t)ra * 3;
+    double* fo = fint + (int64_t)rw[j] * 3;
     fo[0] += sF[tk][0];   // one writer per node in this colour
     fo[1] += sF[tk][1];
     fo[2] += sF[tk][2];
