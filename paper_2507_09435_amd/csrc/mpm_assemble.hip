@@ -1313,6 +1313,7 @@ __global__ void __launch_bounds__(FT3) k_jv3c(int colour, const int64_t* __restr
                                               double* __restrict__ y) {
   __shared__ double sP[FT3][9];
   __shared__ double sW[FT3][3][2][3];
+  __shared__ double sF[FG3 * 27][3];         // per (group, stencil node) task: its sum so far
   __shared__ int32_t gp0[FG3], gcn[FG3], goff[FG3 + 1];
   __shared__ int32_t gox[FG3], goy[FG3], goz[FG3];
   const int64_t w = blockIdx.x;
@@ -1323,10 +1324,26 @@ __global__ void __launch_bounds__(FT3) k_jv3c(int colour, const int64_t* __restr
   fg3_groups(S, gstart, w - wstart[s], colour, t, gp0, gcn, goff, gox, goy, goz);
   const int ntot = goff[FG3];
   if (ntot == 0) return;   // uniform
+  // the scatter as in k_fint3c: one task (group, x-node, y-node) per thread
+  // summing its three z-nodes with factored weights, sums in LDS, and the
+  // rows of the final writes fetched before the first chunk
+  static_assert(FG3 * 9 <= FT3, "one scatter task per thread");
   constexpr int NTK = (FG3 * 27 + FT3 - 1) / FT3;
-  double f[NTK][3];
+  int32_t rw[NTK];
 #pragma unroll
-  for (int j = 0; j < NTK; ++j) f[j][0] = f[j][1] = f[j][2] = 0.0;
+  for (int j = 0; j < NTK; ++j) {
+    const int tk = t + FT3 * j;
+    rw[j] = -1;
+    if (tk < FG3 * 27) {
+      const int k = tk / 27, a = tk % 27;
+      if (goff[k + 1] != goff[k]) {   // an empty group's nodes may be inactive
+        const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
+        rw[j] = node_map[S.node_base + (gox[k] + ax + 1) +
+                         (int64_t)S.nna[0] * ((goy[k] + ay + 1) + (int64_t)S.nna[1] * (goz[k] + az + 1))];
+      }
+    }
+  }
+  for (int e = t; e < FG3 * 27 * 3; e += FT3) (&sF[0][0])[e] = 0.0;
   for (int c0 = 0; c0 < ntot; c0 += FT3) {
     const int nc = min(FT3, ntot - c0);
     if (t < nc) {
@@ -1378,38 +1395,42 @@ __global__ void __launch_bounds__(FT3) k_jv3c(int colour, const int64_t* __restr
         for (int a = 0; a < 3; ++a) { sW[t][ax][0][a] = st.w[ax][a]; sW[t][ax][1][a] = st.dw[ax][a]; }
     }
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < NTK; ++j) {
-      const int tk = t + FT3 * j;
-      if (tk >= FG3 * 27) continue;
-      const int k = tk / 27, a = tk % 27;
-      const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
+    if (t < FG3 * 9) {
+      const int k = t / 9, axy = t - 9 * k, ax = axy % 3, ay = axy / 3;
       const int kb = max(goff[k], c0) - c0, ke = min(goff[k + 1], c0 + nc) - c0;
-      for (int p = kb; p < ke; ++p) {
-        const double ga0 = sW[p][0][1][ax] * sW[p][1][0][ay] * sW[p][2][0][az];
-        const double ga1 = sW[p][0][0][ax] * sW[p][1][1][ay] * sW[p][2][0][az];
-        const double ga2 = sW[p][0][0][ax] * sW[p][1][0][ay] * sW[p][2][1][az];
-        const double* P = sP[p];
-        f[j][0] += P[0] * ga0 + P[1] * ga1 + P[2] * ga2;
-        f[j][1] += P[3] * ga0 + P[4] * ga1 + P[5] * ga2;
-        f[j][2] += P[6] * ga0 + P[7] * ga1 + P[8] * ga2;
+      if (kb < ke) {
+        double f[3][3];   // [az][component]
+#pragma unroll
+        for (int az = 0; az < 3; ++az)
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) f[az][cc] = sF[k * 27 + ax + 3 * ay + 9 * az][cc];
+        for (int p = kb; p < ke; ++p) {
+          const double wxy0 = sW[p][0][1][ax] * sW[p][1][0][ay], wxy1 = sW[p][0][0][ax] * sW[p][1][1][ay],
+                       wxy2 = sW[p][0][0][ax] * sW[p][1][0][ay];
+          const double* P = sP[p];
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) {
+            const double X = fma(P[3 * cc + 1], wxy1, P[3 * cc] * wxy0), Y = P[3 * cc + 2] * wxy2;
+#pragma unroll
+            for (int az = 0; az < 3; ++az) f[az][cc] = fma(X, sW[p][2][0][az], fma(Y, sW[p][2][1][az], f[az][cc]));
+          }
+        }
+#pragma unroll
+        for (int az = 0; az < 3; ++az)
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) sF[k * 27 + ax + 3 * ay + 9 * az][cc] = f[az][cc];   // this thread's alone
       }
     }
-    __syncthreads();
+    __syncthreads();   // the staged particles are consumed
   }
 #pragma unroll
   for (int j = 0; j < NTK; ++j) {
+    if (rw[j] < 0) continue;
     const int tk = t + FT3 * j;
-    if (tk >= FG3 * 27) continue;
-    const int k = tk / 27, a = tk % 27;
-    if (goff[k + 1] == goff[k]) continue;
-    const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
-    const int32_t ra = node_map[S.node_base + (gox[k] + ax + 1) +
-                                (int64_t)S.nna[0] * ((goy[k] + ay + 1) + (int64_t)S.nna[1] * (goz[k] + az + 1))];
-    double* yo = y + (int64_t)ra * 3;
-    yo[0] += f[j][0];   // one writer per node in this colour
-    yo[1] += f[j][1];
-    yo[2] += f[j][2];
+    double* yo = y + (int64_t)rw[j] * 3;
+    yo[0] += sF[tk][0];   // one writer per node in this colour
+    yo[1] += sF[tk][1];
+    yo[2] += sF[tk][2];
   }
 }
 
