@@ -283,21 +283,36 @@ def main():
 FP64_PEAK_TFLOPS = 78.6
 
 
+def jacobian_source_sha1():
+    """SHA-1 of the source the 3-D Jacobian kernels are built from (None if unreadable)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2507_09435_amd", "csrc")
+    try:
+        code = open(os.path.join(csrc, "mpm_assemble.hip")).read()
+        dev = open(os.path.join(csrc, "mpm_device.hpp")).read()
+    except OSError:
+        return None
+    j = code.find("// The FG3 consecutive stencil groups")
+    if j < 0:
+        return None
+    return hashlib.sha1((code[:j] + dev).encode()).hexdigest()
+
+
 def jacobian_traffic(workload):
     """HBM bytes per 3-D Jacobian evaluation on the cube (its three kernels),
     from the committed counter passes (profiles/k_jac3_cube_pmc.md), or None
-    for another workload or when the assembly source has changed since."""
-    import hashlib
+    for another workload or when the kernels' source has changed since: the
+    device code of mpm_assemble.hip up to the residual's kernels, and the
+    constitutive code of mpm_device.hpp."""
     if workload != "c3":
         return None
     try:
         text = open(os.path.join(ROOT, "profiles", "k_jac3_cube_pmc.md")).read()
-        code = open(os.path.join(ROOT, "paper_2507_09435_amd", "csrc", "mpm_assemble.hip")).read()
     except OSError:
         return None
     fields = dict(line.split(": ", 1) for line in text.splitlines()
-                  if line.startswith(("traffic_", "assembly_source_sha1")))
-    if fields.get("assembly_source_sha1", "").strip() != hashlib.sha1(code.encode()).hexdigest():
+                  if line.startswith(("traffic_", "jacobian_source_sha1")))
+    if fields.get("jacobian_source_sha1", "").strip() != jacobian_source_sha1():
         return None
     v = fields.get("traffic_bytes_per_jacobian")
     return int(float(v)) if v else None
